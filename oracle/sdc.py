@@ -1,0 +1,217 @@
+"""Generic SDC step and sweep drivers (oracle; test infrastructure only).
+
+A problem object supplies the three right-hand-side pieces and the implicit
+sub-solves used by the schemes of section 3 of the paper:
+
+    FA(phi), FD(phi), FR(phi)    advection, diffusion, reaction terms
+    solve_D(c, rhs, lag)         phi - c * FD_lag(phi) = rhs, where FD_lag is the
+                                 diffusion operator with its coefficients frozen
+                                 at the state ``lag`` (the lagged flux of the
+                                 species-update step S3, eq. lagged_diffusion_flux)
+    solve_R(c, b, guess)         phi - c * FR(phi) = b (reaction step, S5)
+    solve_DR(c, rhs, guess, lag) phi - c * (FD_lag + FR)(phi) = rhs (IMEXQ only)
+
+States are NumPy arrays of any shape; the drivers only add, scale and copy
+them.  Every update below is written bracket by bracket in the order the paper
+prints it, with no folding of terms.
+
+Schemes
+-------
+"misdc"   node-to-node MISDC, eqs. update_equation_misdc_discrete_form_D/R,
+          with backward-Euler diffusion/reaction and forward-Euler advection
+          over each sub-interval and the node-to-node quadrature S^{m:m+1}.
+"misdcq"  MISDCQ, eqs. update_equation_misdcq_discrete_form_D/R: Q-form with
+          the LU-trick implicit weights Q~I and forward-Euler weights Q~E.
+"cisdcq"  CISDCQ-nu, eqs. update_equation_amisdcq_discrete_form_D and
+          update_equation_amisdcq_discrete_form_R_alt, with the lag
+          initialisation initial_lagged_values_A/D/R and nu nested iterations.
+"imexq"   IMEXQ: explicit advection, fully coupled implicit diffusion+reaction
+          with the LU-trick weights (the comparison scheme of section 3.2.2).
+"""
+import numpy as np
+
+from .coefficients import sdc_tables, node_to_node_weights
+
+
+class _F:
+    """Operator values (FA, FD, FR) at one node."""
+    __slots__ = ("A", "D", "R")
+
+    def __init__(self, A, D, R):
+        self.A, self.D, self.R = A, D, R
+
+    def total(self):
+        return self.A + self.D + self.R
+
+
+def _evalF(prob, phi):
+    return _F(prob.FA(phi), prob.FD(phi), prob.FR(phi))
+
+
+def scheme_tables(n_nodes, scheme, qe="cumulative"):
+    return sdc_tables(n_nodes, qi="be" if scheme == "misdc" else "lu", qe=qe)
+
+
+def sweep_misdc(prob, phi, F, dt, tab, S):
+    """One node-to-node MISDC sweep.  phi, F: lists over nodes 0..M (sweep k)."""
+    M = tab["M"]
+    new_phi = [phi[0]] + [None] * M
+    new_F = [F[0]] + [None] * M
+    for m in range(M):
+        p = m + 1
+        dtm = dt * tab["dtau"][m]
+        quad = dt * sum(S[m, j] * F[j].total() for j in range(M + 1))
+        # phi_AD^{m+1} = phi^{m,(k+1)} + dt^m [FA(phi^{m,(k+1)}) - FA(phi^{m,(k)})
+        #                + FD(phi_AD^{m+1}) - FD(phi^{m+1,(k)})] + dt S^{m:m+1} F^{(k)}
+        rhs = new_phi[m] + dtm * (new_F[m].A - F[m].A) - dtm * F[p].D + quad
+        phi_ad = prob.solve_D(dtm, rhs, phi[p])
+        # phi^{m+1} = phi_AD^{m+1} + dt^m [FR(phi^{m+1}) - FR(phi^{m+1,(k)})]
+        b = phi_ad - dtm * F[p].R
+        new_phi[p] = prob.solve_R(dtm, b, phi[p])
+        new_F[p] = _evalF(prob, new_phi[p])
+    return new_phi, new_F
+
+
+def sweep_misdcq(prob, phi, F, dt, tab):
+    """One MISDCQ sweep (Q-form, serial diffusion then reaction per node)."""
+    M = tab["M"]
+    Q, QI, QE = tab["Q"], tab["QI"], tab["QE"]
+    phi0 = phi[0]
+    new_phi = [phi0] + [None] * M
+    new_F = [F[0]] + [None] * M
+    for p in range(1, M + 1):
+        m = p - 1
+        # Q^{0:m+1}(F(phi^{(k)}))
+        quad = sum(Q[p - 1, j] * F[j].total() for j in range(M + 1))
+        rhs = phi0 + dt * quad
+        for j in range(1, m + 1):
+            rhs = rhs + dt * QE[p - 1, j - 1] * (new_F[j].A - F[j].A)
+        for j in range(1, m + 1):
+            rhs = rhs + dt * QI[p - 1, j - 1] * (new_F[j].D - F[j].D)
+        c = dt * QI[p - 1, p - 1]
+        rhs = rhs - c * F[p].D                       # known half of the implicit bracket
+        phi_ad = prob.solve_D(c, rhs, phi[p])
+        # reaction update = (MISDCQ-R) - (MISDCQ-D): the reaction brackets
+        b = phi_ad
+        for j in range(1, m + 1):
+            b = b + dt * QI[p - 1, j - 1] * (new_F[j].R - F[j].R)
+        b = b - c * F[p].R
+        new_phi[p] = prob.solve_R(c, b, phi[p])
+        new_F[p] = _evalF(prob, new_phi[p])
+    return new_phi, new_F
+
+
+def sweep_cisdcq(prob, phi, F, dt, tab, nu):
+    """One CISDCQ-nu sweep: nu nested iterations over the nodes.
+
+    Buffers: ``prev`` holds the values of nested iteration l (l = 0 is the lag
+    initialisation), ``cur`` those of iteration l+1 being computed.  The
+    diffusion update at node m+1 uses iteration-(l+1) values at nodes
+    j <= m-1 and iteration-l (lagged) values at nodes m and m+1; the reaction
+    update is the correction form of eq. ..._R_alt.
+    """
+    M = tab["M"]
+    Q, QI, QE = tab["Q"], tab["QI"], tab["QE"]
+    phi0 = phi[0]
+    # S1 / eq. initial_lagged_values_R: iteration-0 state and reaction terms
+    # are those of sweep k.
+    prev_phi = list(phi)
+    prev_F = list(F)
+    ad_F = [None] * (M + 1)         # FA, FD at phi_AD^{m,(k+1,1)} (lag init A/D)
+    for ell in range(nu):
+        cur_phi = [phi0] + [None] * M
+        cur_F = [F[0]] + [None] * M
+        for p in range(1, M + 1):
+            m = p - 1
+            # ---- diffusion step at node m+1, iteration l+1 ----
+            quad = sum(Q[p - 1, j] * F[j].total() for j in range(M + 1))
+            rhs = phi0 + dt * quad
+            for j in range(1, m):        # j = 1..m-1: values of iteration l+1
+                rhs = rhs + dt * QE[p - 1, j - 1] * (cur_F[j].A - F[j].A)
+            for j in range(1, m):
+                rhs = rhs + dt * QI[p - 1, j - 1] * (cur_F[j].D - F[j].D + cur_F[j].R - F[j].R)
+            if m >= 1:
+                if ell == 0:
+                    # eqs. initial_lagged_values_A/D: the most recent AD update at
+                    # node m, i.e. phi_AD^{m,(k+1,1)} of this pass
+                    lagA, lagD = ad_F[m].A, ad_F[m].D
+                else:
+                    lagA, lagD = prev_F[m].A, prev_F[m].D
+                lagR = prev_F[m].R
+                rhs = rhs + dt * QE[p - 1, m - 1] * (lagA - F[m].A)
+                rhs = rhs + dt * QI[p - 1, m - 1] * (lagD - F[m].D + lagR - F[m].R)
+            c = dt * QI[p - 1, p - 1]
+            rhs = rhs + c * (prev_F[p].R - F[p].R) - c * F[p].D
+            lag_state = phi[p] if ell == 0 else prev_phi[p]      # eq. lagged_diffusion_flux
+            phi_ad = prob.solve_D(c, rhs, lag_state)
+            if ell == 0:
+                ad_F[p] = _F(prob.FA(phi_ad), prob.FD(phi_ad), None)
+            # ---- reaction step at node m+1, iteration l+1 (eq. ..._R_alt) ----
+            b = phi_ad
+            if m >= 1:
+                b = b + dt * QI[p - 1, m - 1] * (cur_F[m].R - prev_F[m].R)
+            b = b - c * prev_F[p].R
+            cur_phi[p] = prob.solve_R(c, b, prev_phi[p])
+            cur_F[p] = _evalF(prob, cur_phi[p])
+        prev_phi, prev_F = cur_phi, cur_F
+    return prev_phi, prev_F          # S7
+
+
+def sweep_imexq(prob, phi, F, dt, tab):
+    """One IMEXQ sweep: explicit advection, coupled implicit diffusion+reaction."""
+    M = tab["M"]
+    Q, QI, QE = tab["Q"], tab["QI"], tab["QE"]
+    phi0 = phi[0]
+    new_phi = [phi0] + [None] * M
+    new_F = [F[0]] + [None] * M
+    for p in range(1, M + 1):
+        m = p - 1
+        quad = sum(Q[p - 1, j] * F[j].total() for j in range(M + 1))
+        rhs = phi0 + dt * quad
+        for j in range(1, m + 1):
+            rhs = rhs + dt * QE[p - 1, j - 1] * (new_F[j].A - F[j].A)
+            rhs = rhs + dt * QI[p - 1, j - 1] * (new_F[j].D - F[j].D + new_F[j].R - F[j].R)
+        c = dt * QI[p - 1, p - 1]
+        rhs = rhs - c * (F[p].D + F[p].R)
+        new_phi[p] = prob.solve_DR(c, rhs, phi[p], phi[p])
+        new_F[p] = _evalF(prob, new_phi[p])
+    return new_phi, new_F
+
+
+def sdc_step(prob, phi_n, dt, n_nodes, sweeps, scheme, nu=1, qe="cumulative",
+             increments=None, stop_tol=None, norm=None):
+    """Advance phi_n by one step of size dt.
+
+    I1-I2: node 0 and every node of sweep 0 hold phi^n; I4: the operator values
+    at phi^n serve for the first sweep's quadrature.  After each sweep the
+    increment |phi^{M,(k+1)} - phi^{M,(k)}| (``norm``, default max-abs) is
+    appended to ``increments``.  With ``stop_tol`` the step stops at the first
+    sweep whose increment is <= stop_tol.  Returns (phi^{n+1}, sweeps done).
+    """
+    tab = scheme_tables(n_nodes, scheme, qe)
+    S = node_to_node_weights(n_nodes) if scheme == "misdc" else None
+    M = tab["M"]
+    phi = [np.array(phi_n, dtype=np.float64, copy=True) for _ in range(M + 1)]
+    F0 = _evalF(prob, phi[0])
+    F = [F0] * (M + 1)
+    norm = norm or (lambda x: float(np.max(np.abs(x))))
+    done = 0
+    for _k in range(sweeps):
+        if scheme == "misdc":
+            new_phi, new_F = sweep_misdc(prob, phi, F, dt, tab, S)
+        elif scheme == "misdcq":
+            new_phi, new_F = sweep_misdcq(prob, phi, F, dt, tab)
+        elif scheme == "cisdcq":
+            new_phi, new_F = sweep_cisdcq(prob, phi, F, dt, tab, nu)
+        elif scheme == "imexq":
+            new_phi, new_F = sweep_imexq(prob, phi, F, dt, tab)
+        else:
+            raise ValueError(scheme)
+        inc = norm(new_phi[M] - phi[M])
+        if increments is not None:
+            increments.append(inc)
+        phi, F = new_phi, new_F
+        done += 1
+        if stop_tol is not None and inc <= stop_tol:
+            break
+    return phi[M], done

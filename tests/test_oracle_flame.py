@@ -1,0 +1,94 @@
+"""Pins of the oracle sweeps on nonlinear problems.
+
+* P-5: on tiny flame grids, many sweeps of every scheme reach the collocation
+  solution computed independently by a dense Newton solve;
+* P-6: temporal order on the paper's nonlinear test PDE: k sweeps give order
+  min(k, 2M) (section 5.2: order 2 with two sweeps, 4 with four);
+* P-7: conservation over a flame step (sum of mass fractions per cell, domain
+  totals of elements and enthalpy).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.adr import FlameProblem, relaxed_initial_state
+from oracle.collocation import collocation_solve
+from oracle.nagumo import Nagumo
+from oracle.sdc import sdc_step
+
+
+@pytest.fixture(scope="module")
+def mild_flame():
+    m = synth.make_mechanism(9, 21, 0, A_range=(1e2, 1e6))
+    Y, T = synth.flame_1d(m, 4, dx=0.02)
+    prob = FlameProblem(m, (0.02,), (100.0,))
+    phi0 = relaxed_initial_state(prob, Y, T)
+    return prob, phi0
+
+
+@pytest.fixture(scope="module")
+def mild_collocation(mild_flame):
+    prob, phi0 = mild_flame
+    return collocation_solve(prob, phi0, 2e-5, 5)
+
+
+@pytest.mark.parametrize("scheme,nu", [("misdc", 1), ("misdcq", 1), ("cisdcq", 1), ("cisdcq", 3)])
+def test_sweeps_reach_collocation_fixed_point(mild_flame, mild_collocation, scheme, nu):
+    prob, phi0 = mild_flame
+    out, _ = sdc_step(prob, phi0, 2e-5, 5, 60, scheme, nu=nu)
+    scale = np.abs(mild_collocation[-1]).max(axis=1, keepdims=True)
+    assert (np.abs(out - mild_collocation[-1]) / scale).max() < 1e-11
+
+
+def test_collocation_residual_is_small(mild_flame, mild_collocation):
+    # independent check of the brute-force solve: plug it back in
+    from oracle.coefficients import sdc_tables
+    prob, phi0 = mild_flame
+    t = sdc_tables(5)
+    F = [prob.FA(x) + prob.FD(x) + prob.FR(x) for x in mild_collocation]
+    for p in range(1, 5):
+        rhs = phi0 + 2e-5 * sum(t["Q"][p - 1, j] * F[j] for j in range(5))
+        scale = np.abs(rhs).max(axis=1, keepdims=True)
+        assert (np.abs(mild_collocation[p] - rhs) / scale).max() < 1e-13
+
+
+def _nagumo_solution(scheme, nu, dt, sweeps, t_end=0.4):
+    prob = Nagumo(a=1.0, d=2.0, r=4.0, nx=200)
+    phi = prob.initial()
+    for _ in range(int(round(t_end / dt))):
+        phi, _ = sdc_step(prob, phi, dt, 5, sweeps, scheme, nu=nu)
+    return phi
+
+
+@pytest.fixture(scope="module")
+def nagumo_reference():
+    return _nagumo_solution("misdcq", 1, 0.1 / 32, 8)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("scheme,nu", [("misdcq", 1), ("cisdcq", 1)])
+@pytest.mark.parametrize("sweeps,order", [(2, 2), (4, 4)])
+def test_nagumo_temporal_order(nagumo_reference, scheme, nu, sweeps, order):
+    errs = []
+    dts = (0.1, 0.05, 0.025)
+    for dt in dts:
+        phi = _nagumo_solution(scheme, nu, dt, sweeps)
+        errs.append(np.mean(np.abs(phi - nagumo_reference)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] > order - 0.35, (errs, rates)
+
+
+@pytest.mark.parametrize("scheme,nu", [("misdc", 1), ("cisdcq", 2)])
+def test_flame_step_conservation(scheme, nu):
+    m = synth.make_mechanism(9, 21, 0)
+    Y, T = synth.flame_2d(m, 12, 10)
+    prob = FlameProblem(m, (0.01, 0.01), (100.0, 0.0))
+    phi0 = relaxed_initial_state(prob, Y, T)
+    out, _ = sdc_step(prob, phi0, 5e-5, 3, 3, scheme, nu=nu)
+    N = m["N"]
+    np.testing.assert_allclose(out[:N].sum(axis=0), 1.0, atol=1e-13)
+    el = lambda p: m["comp"] @ (p[:N] / m["W"][:, None, None]).reshape(N, -1)
+    np.testing.assert_allclose(el(out).sum(axis=1), el(phi0).sum(axis=1), rtol=1e-12, atol=1e-16)
+    np.testing.assert_allclose(out[N].sum(), phi0[N].sum(), rtol=1e-13)
+    assert np.all(np.isfinite(out))
+    assert all(np.all(it > 0) for it in prob.newton_iters)
