@@ -1,0 +1,276 @@
+/*
+ * misdc.h - C ABI of the MI355X multi-implicit spectral deferred correction
+ * library (Hamon, Day & Minion, "Concurrent implicit spectral deferred
+ * correction scheme for low-Mach number combustion with detailed chemistry",
+ * arXiv:1801.01201).
+ *
+ * One time step advances phi = (Y_1..Y_N, h) of a constant-density reacting
+ * flow, phi_t = FA(phi) + FD(phi) + FR(phi), on M+1 Gauss-Lobatto nodes with
+ * K correction sweeps (section 3.1).  Three sweep schemes are provided:
+ *   MISDC_SCHEME_MISDC   serial node-to-node MISDC
+ *                        (eqs. update_equation_misdc_discrete_form_D/R);
+ *   MISDC_SCHEME_MISDCQ  serial MISDCQ with LU-trick implicit weights
+ *                        (eqs. update_equation_misdcq_discrete_form_D/R);
+ *   MISDC_SCHEME_CISDCQ  the concurrent scheme CISDCQ-nu: the diffusion step
+ *                        at node m+1 runs on one HIP stream while the
+ *                        reaction step at node m runs on another
+ *                        (eqs. update_equation_amisdcq_discrete_form_D and
+ *                        _R_alt, lag initialisation initial_lagged_values_*,
+ *                        nu nested iterations, algorithm steps S1-S7).
+ *
+ * Conventions
+ *  - Every function returns an int status: MISDC_OK (0) or a negative code.
+ *    misdc_last_error() returns a thread-local message for the last failure.
+ *    No exception crosses the ABI.
+ *  - Fields are stored structure-of-arrays, field-major: element (f, i) of a
+ *    field array is at [f * n_cells + i]; in 2-D the cell index is
+ *    i = iy * nx + ix (x fastest).  A state holds N+1 fields: the N mass
+ *    fractions, then the enthalpy per unit mass h (erg/g).  Units are CGS.
+ *  - Pointers named dev_* are device pointers owned by the caller (for
+ *    example torch tensor storage); they must stay valid until the work
+ *    enqueued on the given/bound stream has completed.  Host pointers are
+ *    read during the call only.  Handles own their device workspace.
+ *  - Calls that take a stream (hipStream_t passed as void*, NULL = the
+ *    default stream) enqueue work and return without synchronising, except
+ *    where stated.  Argument errors are detected on the host before any
+ *    work is enqueued (these checks need no GPU).
+ *  - Only FP64 arithmetic is used unless a mixed-precision option says
+ *    otherwise.
+ */
+#ifndef MISDC_H
+#define MISDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MISDC_OK = 0,
+    MISDC_EINVAL = -1,      /* invalid argument (shape, range, null pointer) */
+    MISDC_ENOMEM = -2,      /* device or host allocation failed */
+    MISDC_EDEVICE = -3,     /* HIP runtime error */
+    MISDC_ENOTCONV = -4,    /* a solver did not converge (see the stats) */
+    MISDC_EUNSUPPORTED = -5 /* valid request outside what is built */
+};
+
+enum { MISDC_SCHEME_MISDC = 0, MISDC_SCHEME_MISDCQ = 1, MISDC_SCHEME_CISDCQ = 2 };
+enum { MISDC_QE_CUMULATIVE = 0, MISDC_QE_LITERAL = 1 };
+enum { MISDC_QI_LU = 0, MISDC_QI_BE = 1 };
+
+typedef struct misdc_mech_s* misdc_mech_t;
+typedef struct misdc_grid_s* misdc_grid_t;
+typedef struct misdc_integ_s* misdc_integ_t;
+
+/* ---------------------------------------------------------------------- */
+/* Library                                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Thread-local message describing the last non-zero status of this thread. */
+const char* misdc_last_error(void);
+
+/* Library version string. */
+const char* misdc_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* SDC coefficients (host only, no GPU needed)                             */
+/* ---------------------------------------------------------------------- */
+
+/* Section 3.1: n_nodes Gauss-Lobatto nodes on [0, 1] (M = n_nodes - 1),
+ * the integration matrix Q (M x (M+1), q_{m+1,j} = integral from 0 to
+ * tau_{m+1} of the Lagrange polynomial L_j), the implicit weights QI (M x M;
+ * qi_kind MISDC_QI_LU: transpose of the upper factor of the Doolittle LU
+ * decomposition of transpose(Q~), Q~ = Q without its first column;
+ * MISDC_QI_BE: cumulative backward Euler), the explicit weights QE (M x M;
+ * MISDC_QE_CUMULATIVE: forward Euler from every earlier node,
+ * MISDC_QE_LITERAL: only the (m+1, m) entry) and the node-to-node weights
+ * S (M x (M+1), s_{m+1,j} = integral over [tau_m, tau_{m+1}] of L_j).
+ * All weights are divided by dt.  Row-major host arrays of the stated
+ * sizes; any output pointer may be NULL.  2 <= n_nodes <= 9. */
+int misdc_sdc_tables(int n_nodes, int qi_kind, int qe_mode, double* tau,
+                     double* Q, double* QI, double* QE, double* S);
+
+/* ---------------------------------------------------------------------- */
+/* Mechanism                                                               */
+/* ---------------------------------------------------------------------- */
+
+/* Reversible mass-action mechanism (eq. species_equation source term).
+ * All arrays are host arrays, copied by misdc_mech_create.
+ *   react/prod: (R x 2) species index per slot or -1; a repeated index is a
+ *               stoichiometric coefficient of 2.  At most 2 + 2 slots.
+ *   A, beta, Ea: kf = A T^beta exp(-Ea / (R_c T)), Ea in cal/mol.
+ *   cp, hf, s0: constant molar heat capacity (erg/mol/K), enthalpy of
+ *               formation at 298.15 K (erg/mol), entropy at 298.15 K and
+ *               p_atm (erg/mol/K).  kr = kf / Kc with Kc from the Gibbs
+ *               energies (thermodynamic consistency).
+ *   D0: species diffusivities at 300 K (cm^2/s); alpha0: enthalpy
+ *       diffusivity at 300 K; both scale as (T/300)^1.7.
+ *   bath: the dominant species i0 whose diffusion flux closes the sum
+ *         (section 2); it must not react.
+ *   rho0: constant density (g/cm^3). */
+typedef struct {
+    int32_t n_species;
+    int32_t n_reactions;
+    int32_t bath;
+    const double* W;
+    const int32_t* react;
+    const int32_t* prod;
+    const double* A;
+    const double* beta;
+    const double* Ea;
+    const double* cp;
+    const double* hf;
+    const double* s0;
+    const double* D0;
+    double alpha0;
+    double rho0;
+    double p_atm;
+    double R_u;
+    double R_c;
+} misdc_mech_desc;
+
+/* Validates and copies the mechanism to the current HIP device.
+ * Supported species counts for the reaction solve: 9 (FP64, one thread per
+ * cell); other counts are accepted by the operator kernels only. */
+int misdc_mech_create(const misdc_mech_desc* desc, misdc_mech_t* out);
+int misdc_mech_destroy(misdc_mech_t mech);
+/* Species count of a mechanism (host, no GPU work). */
+int misdc_mech_species(misdc_mech_t mech, int32_t* n_species);
+
+/* h = sum_k Y_k h_k(T) / W_k for n cells.  dev_Y: N x n, dev_T, dev_h: n. */
+int misdc_enthalpy(misdc_mech_t mech, int64_t n, const double* dev_Y,
+                   const double* dev_T, double* dev_h, void* stream);
+/* Closed-form inverse: T from (Y, h). */
+int misdc_temperature(misdc_mech_t mech, int64_t n, const double* dev_Y,
+                      const double* dev_h, double* dev_T, void* stream);
+/* FR_k = W_k omega_k(Y, T(Y, h)) / rho0 for n cells; dev_FR: N x n. */
+int misdc_reaction_source(misdc_mech_t mech, int64_t n, const double* dev_Y,
+                          const double* dev_h, double* dev_FR, void* stream);
+
+/* Reaction step S5 (eq. reaction_step_numerical_methodology) for n
+ * independent cells: solve, at constant enthalpy h,
+ *     Y - c FR(Y, T) = bY,   sum_k Y_k h_k(T) / W_k = h
+ * for x = (Y, T) by Newton's method with the analytic Jacobian (LU with
+ * partial pivoting), globalised by pseudo-transient continuation:
+ *   start from (Y_guess, T(Y_guess, h)) with an infinite pseudo-step; a trial
+ *   x - delta that is not finite, has T <= 0 or some Y_k < min(bY_k, 0) -
+ *   neg_slack is rejected and the pseudo-step shrinks (1/dtau: 0 -> 1/dtau0,
+ *   else x4); accepted steps grow it by max(2, |G_old|/|G|) until it passes
+ *   dtau_max and becomes infinite again; converged when a plain Newton step
+ *   has max|delta_Y| <= tol and |delta_T| <= tol T.
+ * dev_bY, dev_Y (in: guess, out: solution): N x n; dev_h, dev_c: n.
+ * dev_T_out (n), dev_FR_out (N x n, FR at (Y, T(Y, h))) may be NULL.
+ * dev_iters_out (n int32): linear solves per cell, -1 if not converged.
+ * Parameters <= 0 take the defaults tol 1e-12, maxit 200, dtau0 1,
+ * dtau_max 1e10, neg_slack 1e-6. */
+typedef struct {
+    double tol;
+    int32_t maxit;
+    double dtau0;
+    double dtau_max;
+    double neg_slack;
+} misdc_newton_opts;
+
+int misdc_reaction_solve_batch(misdc_mech_t mech, int64_t n, const double* dev_bY,
+                               const double* dev_h, const double* dev_c,
+                               double* dev_Y, double* dev_T_out, double* dev_FR_out,
+                               int32_t* dev_iters_out, const misdc_newton_opts* opts,
+                               void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Grid and transport                                                      */
+/* ---------------------------------------------------------------------- */
+
+/* Uniform periodic grid, dim 1 or 2; n[d], dx[d], u[d] for d = x, y.
+ * u is the prescribed uniform velocity (cm/s). */
+int misdc_grid_create(int dim, const int64_t* n, const double* dx,
+                      const double* u, misdc_grid_t* out);
+/* Ensemble of n_flames independent periodic 1-D grids of lengths[f] cells,
+ * spacing dx[f] and velocity u[f]; cells are concatenated flame by flame. */
+int misdc_grid_create_ensemble(int n_flames, const int64_t* lengths,
+                               const double* dx, const double* u, misdc_grid_t* out);
+int misdc_grid_destroy(misdc_grid_t grid);
+int misdc_grid_cells(misdc_grid_t grid, int64_t* n_cells);
+
+/* Explicit operators at a state (N+1 fields): FA = -u . grad(phi) with the
+ * fourth-order face value (7(phi_i+phi_{i+1}) - (phi_{i-1}+phi_{i+2}))/12;
+ * FD = div(kappa_f(T) grad phi_f) in second-order flux form with face
+ * coefficient the mean of the cell values, kappa = D0_k or alpha0 times
+ * (T/300)^1.7, T = T(Y, h); the bath row is minus the sum of the other
+ * species rows.  dev_FA / dev_FD may be NULL. */
+int misdc_transport_operators(misdc_mech_t mech, misdc_grid_t grid,
+                              const double* dev_state, double* dev_FA,
+                              double* dev_FD, void* stream);
+
+/* Implicit diffusion (steps S3/S4): for every field except the bath solve
+ * (I - c kappa0_f L_theta) y_f = r_f, theta = (T_lag/300)^1.7, then
+ * y_bath = r_bath - sum_{k != bath} (y_k - r_k).  1-D grids: direct cyclic
+ * tridiagonal solve; 2-D grids: Jacobi-preconditioned conjugate gradients on
+ * all fields at once until |r_f|_2 <= rtol |b_f|_2 (rtol <= 0: 1e-13,
+ * maxit <= 0: 500).  dev_rhs, dev_y: N+1 fields; dev_T_lag: cells;
+ * dev_iters_out (int32, may be NULL) receives the iteration count.  The
+ * initial guess is dev_y's content if guess_in_y is non-zero, else rhs. */
+int misdc_diffusion_solve(misdc_mech_t mech, misdc_grid_t grid, double c,
+                          const double* dev_T_lag, const double* dev_rhs,
+                          double* dev_y, int guess_in_y, double rtol, int maxit,
+                          int32_t* dev_iters_out, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Integrator                                                              */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t n_nodes;     /* M + 1 Gauss-Lobatto nodes, 2..9 */
+    int32_t n_sweeps;    /* K correction sweeps per step */
+    int32_t nu;          /* nested iterations per sweep (CISDCQ) */
+    int32_t scheme;      /* MISDC_SCHEME_* */
+    int32_t qe_mode;     /* MISDC_QE_* */
+    int32_t serialize;   /* 1: run the two tasks on one stream (same DAG) */
+    misdc_newton_opts newton;
+    double cg_rtol;      /* 2-D diffusion CG tolerance (<= 0: 1e-13) */
+    int32_t cg_maxit;    /* (<= 0: 500) */
+} misdc_opts;
+
+/* Fills the defaults: 5 nodes, 6 sweeps, nu 1, CISDCQ, cumulative QE. */
+void misdc_opts_default(misdc_opts* opts);
+
+/* Creates an integrator for a mechanism and grid; allocates its device
+ * workspace and two streams (diffusion, reaction) of default priority. */
+int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* opts,
+                       misdc_integ_t* out);
+int misdc_integ_destroy(misdc_integ_t integ);
+
+/* One time step of size dt (dev_dt: NULL for a scalar dt; for an ensemble
+ * grid a device array of one dt per flame, in which case dt is ignored):
+ * I1-I2 spread the state to every node, I4 evaluates FA, FD, FR at it, K
+ * sweeps, and the state at node M is written back to dev_state in place.
+ * Ordered after prior work on ``stream`` and before later work on it. */
+int misdc_step(misdc_integ_t integ, double* dev_state, double dt,
+               const double* dev_dt, void* stream);
+
+/* Statistics of the last step (synchronises with the integrator's streams).
+ * sweep_increment[k] = max over fields of max_i |phi^{M,(k+1)} - phi^{M,(k)}|
+ * normalised by max_i |phi^{M,(k+1)}| of that field. */
+typedef struct {
+    int64_t newton_solves;      /* cell-node Newton solves */
+    int64_t newton_iters;       /* total linear solves */
+    int32_t newton_max;
+    int64_t newton_failed;
+    int64_t cg_solves;
+    int64_t cg_iters;           /* sum over 2-D diffusion solves */
+    int32_t cg_max;
+    int32_t cg_failed;
+    int32_t n_sweeps;
+    double sweep_increment[64];
+    double ms_diffusion;        /* device time of the diffusion task, last step */
+    double ms_reaction;         /* device time of the reaction task, last step */
+} misdc_stats;
+
+int misdc_get_stats(misdc_integ_t integ, misdc_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MISDC_H */

@@ -28,11 +28,18 @@ def lobatto_nodes_mp(n_nodes):
             raise ValueError("need at least two nodes")
         inner = []
         if M > 1:
-            # roots of P'_M on (-1, 1): refine Chebyshev-Gauss-Lobatto guesses
-            dP = lambda x: mp.diff(lambda y: mp.legendre(M, y), x)
-            for k in range(1, M):
-                x0 = -mp.cos(mp.pi * k / M)
-                inner.append(mp.findroot(dP, x0))
+            # roots of P'_M on (-1, 1); P_M by the three-term recurrence
+            # (coefficients, highest degree first), then its derivative
+            p0, p1 = [mp.mpf(1)], [mp.mpf(1), mp.mpf(0)]
+            for k in range(2, M + 1):
+                a = [(2 * k - 1) * c / mp.mpf(k) for c in p1] + [mp.mpf(0)]
+                b = [mp.mpf(0), mp.mpf(0)] + [(k - 1) * c / mp.mpf(k) for c in p0]
+                p0, p1 = p1, [x - y for x, y in zip(a, b)]
+            PM = p1 if M > 1 else p1
+            deg = len(PM) - 1
+            dPM = [c * (deg - i) for i, c in enumerate(PM[:-1])]
+            roots = mp.polyroots(dPM, maxsteps=200, extraprec=200)
+            inner = [mp.re(r) for r in roots]
         xs = [mp.mpf(-1)] + sorted(inner) + [mp.mpf(1)]
         return [(x + 1) / 2 for x in xs]
 

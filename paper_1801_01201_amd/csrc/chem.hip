@@ -1,0 +1,401 @@
+// Chemistry kernels: thermodynamics, mass-action rates and the per-cell
+// backward-Euler reaction solve of step S5 (eq.
+// reaction_step_numerical_methodology).
+//
+// Layout: structure of arrays, one thread per cell; field k of cell i is at
+// [k * ld + i], so every load and store of a wavefront is one coalesced
+// 512-byte transaction per field.  The mechanism tables are indexed with
+// wave-uniform indices (reaction j, species k), so they are fetched through
+// the scalar cache.  Per-thread arrays (state, residual, Jacobian) are only
+// ever indexed with compile-time indices so that they stay in registers;
+// runtime species indices taken from the mechanism are resolved with select
+// chains over the (template) species count NS.
+#include <cfloat>
+#include <cmath>
+
+#include "misdc_impl.h"
+
+namespace misdc {
+
+namespace {
+
+__device__ __forceinline__ double species_h(const MechDev& m, int k, double T) {
+    return m.hf[k] + m.cp[k] * (T - T_REF);
+}
+
+// T from (Y, h), closed form for constant heat capacities
+template <int NS>
+__device__ __forceinline__ double temperature_of(const MechDev& m, const double (&Y)[NS], double h) {
+    double hform = 0.0, cpm = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        hform += Y[k] * m.hf[k] * m.invW[k];
+        cpm += Y[k] * m.cp[k] * m.invW[k];
+    }
+    return T_REF + (h - hform) / cpm;
+}
+
+template <int NS>
+__device__ __forceinline__ double pick(const double (&v)[NS], int s) {
+    double r = 1.0;                 // empty slot: neutral factor
+#pragma unroll
+    for (int l = 0; l < NS; ++l) r = (l == s) ? v[l] : r;
+    return r;
+}
+
+// Rates and (optionally) Jacobian at (Y, T).
+//   FR[k]  = W_k omega_k / rho0
+//   J[k][l] = d FR_k / d Y_l,  JT[k] = d FR_k / d T
+template <int NS, bool JAC>
+__device__ __forceinline__ void reaction_terms(const MechDev& m, const double (&Y)[NS], double T,
+                                               double (&FR)[NS], double (&J)[NS][NS],
+                                               double (&JT)[NS]) {
+    double X[NS], gk[NS], hk[NS];
+    const double lnT = log(T);
+    const double invT = 1.0 / T;
+    const double lnTr = lnT - log(T_REF);
+    const double RuT = m.R_u * T;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        X[k] = m.rho0 * Y[k] * m.invW[k];
+        hk[k] = species_h(m, k, T);
+        gk[k] = hk[k] - T * (m.s0[k] + m.cp[k] * lnTr);
+        FR[k] = 0.0;
+        if (JAC) {
+            JT[k] = 0.0;
+#pragma unroll
+            for (int l = 0; l < NS; ++l) J[k][l] = 0.0;
+        }
+    }
+    const double ln_c0 = m.ln_patm_over_Ru - lnT;      // ln(p_atm / (R_u T))
+    for (int j = 0; j < m.R; ++j) {
+        const int r0 = m.slots[4 * j + 0], r1 = m.slots[4 * j + 1];
+        const int p0 = m.slots[4 * j + 2], p1 = m.slots[4 * j + 3];
+        // sum of nu g and nu h over the (at most four) slots
+        double sg = 0.0, sh = 0.0;
+#pragma unroll
+        for (int l = 0; l < NS; ++l) {
+            const double w = (double)((l == p0) + (l == p1) - (l == r0) - (l == r1));
+            sg += w * gk[l];
+            sh += w * hk[l];
+        }
+        const double dn = m.dn[j];
+        const double kf = m.A[j] * exp(m.beta[j] * lnT - m.Ta[j] * invT);
+        const double lnKc = -sg / RuT + dn * ln_c0;
+        const double kr = kf * exp(-lnKc);
+        const double xr0 = pick(X, r0), xr1 = pick(X, r1);
+        const double xp0 = pick(X, p0), xp1 = pick(X, p1);
+        const double pf = xr0 * xr1, pr = xp0 * xp1;
+        const double q = kf * pf - kr * pr;
+        double dqdT = 0.0;
+        double v[NS];
+        if (JAC) {
+            const double dlnkf = m.beta[j] * invT + m.Ta[j] * invT * invT;
+            const double dlnKc = sh / (RuT * T) - dn * invT;
+            dqdT = kf * dlnkf * pf - kr * (dlnkf - dlnKc) * pr;
+            const double dr0 = kf * xr1, dr1 = kf * xr0, dp0 = -kr * xp1, dp1 = -kr * xp0;
+#pragma unroll
+            for (int l = 0; l < NS; ++l) {
+                double d = 0.0;
+                d += (l == r0) ? dr0 : 0.0;
+                d += (l == r1) ? dr1 : 0.0;
+                d += (l == p0) ? dp0 : 0.0;
+                d += (l == p1) ? dp1 : 0.0;
+                v[l] = d * m.rho0 * m.invW[l];       // d q / d Y_l
+            }
+        }
+        const double* u = m.uW + (size_t)j * m.N;  // nu_kj W_k / rho0
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const double uk = u[k];
+            FR[k] += uk * q;
+            if (JAC) {
+                JT[k] += uk * dqdT;
+#pragma unroll
+                for (int l = 0; l < NS; ++l) J[k][l] += uk * v[l];
+            }
+        }
+    }
+}
+
+// Solve A x = b in place (A: n x n, b -> x) by LU with partial pivoting;
+// the pivot row is the first row holding the largest magnitude in the column.
+template <int n>
+__device__ __forceinline__ void lu_solve(double (&A)[n][n], double (&b)[n]) {
+#pragma unroll
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        double amax = fabs(A[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < n; ++r) {
+            const double a = fabs(A[r][c]);
+            const bool gt = a > amax;
+            amax = gt ? a : amax;
+            piv = gt ? r : piv;
+        }
+#pragma unroll
+        for (int r = c + 1; r < n; ++r) {
+            const bool sw = (r == piv);
+#pragma unroll
+            for (int l = c; l < n; ++l) {
+                const double t = A[c][l];
+                A[c][l] = sw ? A[r][l] : t;
+                A[r][l] = sw ? t : A[r][l];
+            }
+            const double t = b[c];
+            b[c] = sw ? b[r] : t;
+            b[r] = sw ? t : b[r];
+        }
+        const double inv = 1.0 / A[c][c];
+#pragma unroll
+        for (int r = c + 1; r < n; ++r) {
+            const double f = A[r][c] * inv;
+#pragma unroll
+            for (int l = c + 1; l < n; ++l) A[r][l] -= f * A[c][l];
+            b[r] -= f * b[c];
+        }
+    }
+#pragma unroll
+    for (int r = n - 1; r >= 0; --r) {
+        double s = b[r];
+#pragma unroll
+        for (int l = r + 1; l < n; ++l) s -= A[r][l] * b[l];
+        b[r] = s / A[r][r];
+    }
+}
+
+template <int NS>
+__global__ void __launch_bounds__(64) newton_kernel(MechDev m, NewtonArgs a) {
+    constexpr int NX = NS + 1;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const double c = a.c ? a.c[i] : a.c_scalar;
+    const double h = a.h[i];
+    double bY[NS], Y[NS], lo[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        bY[k] = a.bY[k * a.ldb + i];
+        Y[k] = a.guess[k * a.ldg + i];
+        lo[k] = fmin(bY[k], 0.0) - a.opt.neg_slack;
+    }
+    double T = temperature_of<NS>(m, Y, h);
+    const double inv_scale = 1.0 / m.newton_scale;
+    double inv_dtau = 0.0;          // 0: plain Newton step
+    double gnorm_old = -1.0;        // < 0: none yet
+    int it = 0;
+    bool conv = false;
+    while (!conv && it < a.opt.maxit) {
+        double FR[NS], J[NS][NS], JT[NS];
+        reaction_terms<NS, true>(m, Y, T, FR, J, JT);
+        double M[NX][NX], G[NX];
+        double hsum = 0.0, cpm = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const double hk = species_h(m, k, T) * m.invW[k];
+            hsum += Y[k] * hk;
+            cpm += Y[k] * m.cp[k] * m.invW[k];
+            G[k] = Y[k] - c * FR[k] - bY[k];
+#pragma unroll
+            for (int l = 0; l < NS; ++l) M[k][l] = ((k == l) ? 1.0 : 0.0) - c * J[k][l];
+            M[k][NS] = -c * JT[k];
+            M[NS][k] = hk * inv_scale;
+        }
+        G[NS] = (hsum - h) * inv_scale;
+        M[NS][NS] = cpm * inv_scale;
+        double gn2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+            gn2 += G[k] * G[k];
+            M[k][k] += inv_dtau;
+        }
+        lu_solve<NX>(M, G);          // G now holds delta
+        ++it;
+        bool ok = true;
+        double dmax = 0.0;
+        double Yt[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            Yt[k] = Y[k] - G[k];
+            ok = ok && isfinite(G[k]) && (Yt[k] >= lo[k]);
+            dmax = fmax(dmax, fabs(G[k]));
+        }
+        const double Tt = T - G[NS];
+        ok = ok && isfinite(G[NS]) && (Tt > 0.0);
+        if (!ok) {
+            inv_dtau = (inv_dtau == 0.0) ? 1.0 / a.opt.dtau0 : inv_dtau * 4.0;
+            continue;
+        }
+        const bool was_newton = (inv_dtau == 0.0);
+        const double gnorm = sqrt(gn2);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) Y[k] = Yt[k];
+        T = Tt;
+        if (!was_newton) {
+            double grow = 2.0;
+            if (gnorm_old >= 0.0 && gnorm > 0.0) grow = fmax(2.0, gnorm_old / gnorm);
+            inv_dtau = inv_dtau / grow;
+            if (inv_dtau < 1.0 / a.opt.dtau_max) inv_dtau = 0.0;
+        }
+        gnorm_old = gnorm;
+        conv = was_newton && (dmax <= a.opt.tol) && (fabs(G[NS]) <= a.opt.tol * fabs(Tt));
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) a.Y[k * a.ldy + i] = Y[k];
+    const double Tc = temperature_of<NS>(m, Y, h);
+    if (a.T) a.T[i] = Tc;
+    if (a.FR) {
+        double FR[NS], J[NS][NS], JT[NS];
+        reaction_terms<NS, false>(m, Y, Tc, FR, J, JT);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) a.FR[k * a.ldf + i] = FR[k];
+    }
+    const int code = conv ? it : -1;
+    if (a.iters) a.iters[i] = code;
+}
+
+// wave-aggregated statistics: [0] solves, [1] iterations, [2] failures, [3] max
+template <int NS>
+__global__ void __launch_bounds__(256) newton_stats_kernel(int64_t n, const int32_t* iters,
+                                                           unsigned long long* stats) {
+    __shared__ unsigned long long s_sum[4], s_bad[4], s_max[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = 0, b = 0, mx = 0;
+    if (i < n) {
+        const int32_t it = iters[i];
+        v = it > 0 ? (unsigned long long)it : 0ull;
+        b = it < 0 ? 1ull : 0ull;
+        mx = v;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        v += __shfl_xor(v, off);
+        b += __shfl_xor(b, off);
+        const unsigned long long o = __shfl_xor(mx, off);
+        mx = o > mx ? o : mx;
+    }
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0) { s_sum[wave] = v; s_bad[wave] = b; s_max[wave] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long S = 0, B = 0, X = 0;
+        const int nw = (blockDim.x + 63) / 64;
+        for (int w = 0; w < nw; ++w) {
+            S += s_sum[w];
+            B += s_bad[w];
+            X = s_max[w] > X ? s_max[w] : X;
+        }
+        const int64_t lo = (int64_t)blockIdx.x * blockDim.x;
+        const int64_t cnt = (n - lo) < (int64_t)blockDim.x ? (n - lo) : (int64_t)blockDim.x;
+        atomicAdd(&stats[0], (unsigned long long)cnt);
+        atomicAdd(&stats[1], S);
+        atomicAdd(&stats[2], B);
+        atomicMax(&stats[3], X);
+    }
+}
+
+__global__ void __launch_bounds__(256) enthalpy_kernel(MechDev m, int64_t n, const double* Yp,
+                                                       const double* Tp, double* hp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double T = Tp[i];
+    double h = 0.0;
+    for (int k = 0; k < m.N; ++k) h += Yp[k * n + i] * species_h(m, k, T) * m.invW[k];
+    hp[i] = h;
+}
+
+__global__ void __launch_bounds__(256) temperature_kernel(MechDev m, int64_t n, const double* Yp,
+                                                          int64_t ldy, const double* hp,
+                                                          double* Tp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double hform = 0.0, cpm = 0.0;
+    for (int k = 0; k < m.N; ++k) {
+        const double y = Yp[k * ldy + i];
+        hform += y * m.hf[k] * m.invW[k];
+        cpm += y * m.cp[k] * m.invW[k];
+    }
+    Tp[i] = T_REF + (hp[i] - hform) / cpm;
+}
+
+template <int NS>
+__global__ void __launch_bounds__(64) source_kernel(MechDev m, int64_t n, const double* Yp,
+                                                    int64_t ldy, const double* hp, double* FRp,
+                                                    int64_t ldf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double Y[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Y[k] = Yp[k * ldy + i];
+    const double T = temperature_of<NS>(m, Y, hp[i]);
+    double FR[NS], J[NS][NS], JT[NS];
+    reaction_terms<NS, false>(m, Y, T, FR, J, JT);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) FRp[k * ldf + i] = FR[k];
+}
+
+inline unsigned grid_for(int64_t n, int threads) {
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+}  // namespace
+
+int launch_enthalpy(const Mech& m, int64_t n, const double* Y, const double* T, double* h,
+                    hipStream_t s) {
+    if (n == 0) return MISDC_OK;
+    hipLaunchKernelGGL(enthalpy_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, n, Y,
+                       T, h);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+int launch_temperature(const Mech& m, int64_t n, const double* Y, const double* h, double* T,
+                       hipStream_t s) {
+    if (n == 0) return MISDC_OK;
+    hipLaunchKernelGGL(temperature_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, n, Y,
+                       n, h, T);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+int launch_state_temperature(const Mech& m, int64_t n, const double* state, double* T,
+                             hipStream_t s) {
+    if (n == 0) return MISDC_OK;
+    hipLaunchKernelGGL(temperature_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, n,
+                       state, n, state + (size_t)m.dev.N * n, T);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+int launch_reaction_source(const Mech& m, int64_t n, const double* Y, const double* h,
+                           double* FR, hipStream_t s) {
+    if (n == 0) return MISDC_OK;
+    switch (m.dev.N) {
+        case 9:
+            hipLaunchKernelGGL(source_kernel<9>, dim3(grid_for(n, 64)), dim3(64), 0, s, m.dev, n,
+                               Y, n, h, FR, n);
+            break;
+        default:
+            return fail(MISDC_EUNSUPPORTED, "reaction source: %d species not built", m.dev.N);
+    }
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s) {
+    if (a.n == 0) return MISDC_OK;
+    switch (m.dev.N) {
+        case 9:
+            hipLaunchKernelGGL(newton_kernel<9>, dim3(grid_for(a.n, 64)), dim3(64), 0, s, m.dev, a);
+            MISDC_HIP(hipGetLastError());
+            if (a.stats && a.iters) {
+                hipLaunchKernelGGL(newton_stats_kernel<9>, dim3(grid_for(a.n, 256)), dim3(256), 0,
+                                   s, a.n, a.iters, a.stats);
+                MISDC_HIP(hipGetLastError());
+            }
+            break;
+        default:
+            return fail(MISDC_EUNSUPPORTED, "reaction solve: %d species not built", m.dev.N);
+    }
+    return MISDC_OK;
+}
+
+}  // namespace misdc

@@ -1,0 +1,1009 @@
+// Integrator and C ABI.
+//
+// One time step (section 3.3, initialisation I1-I4 and sweeps S1-S7) is
+// issued as a DAG of stream-ordered kernels on two HIP streams: the
+// diffusion task (right-hand side, implicit diffusion, explicit operators at
+// the advection-diffusion state) and the reaction task (right-hand side,
+// per-cell Newton solve, explicit operators at the new state).  For the
+// concurrent scheme the diffusion step at node m+1 and the reaction step at
+// node m of the same nested iteration are independent (the decoupling of
+// section 3.2.1), so the host enqueues them stage by stage on the two streams
+// with events only where the update equations create a dependency:
+//   D_p^(l+1) needs R_{p-2}^(l+1) (values of iteration l+1 at nodes <= m-1)
+//             and, for l >= 1, R_p^(l) (lagged reaction term and lagged
+//             diffusion coefficients at node m+1; R_{p-1}^(l) precedes it on
+//             the reaction stream);
+//   R_p^(l+1) needs D_p^(l+1) (the advection-diffusion state);
+//   the next sweep's quadrature needs every reaction task of this sweep.
+// Every task writes buffers of its own (one buffer set per nested
+// iteration), so there is no write-after-read hazard and the result is
+// bitwise independent of the interleaving (option ``serialize`` runs the same
+// DAG on one stream).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "misdc_impl.h"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace misdc {
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+}  // namespace misdc
+
+using namespace misdc;
+
+struct misdc_mech_s {
+    Mech m;
+};
+
+struct misdc_grid_s {
+    Grid g;
+};
+
+namespace {
+
+struct NodeBuf {
+    double* phi = nullptr;   // N+1 fields
+    double* T = nullptr;     // 1 field
+    double* FA = nullptr;    // N+1 fields
+    double* FD = nullptr;    // N+1 fields
+    double* FR = nullptr;    // N fields
+};
+
+}  // namespace
+
+struct misdc_integ_s {
+    Mech* mech = nullptr;
+    Grid* grid = nullptr;
+    misdc_opts opt;
+    Tables tab;
+    int M = 0, N = 0, NF = 0, nu = 1, levels = 2;
+    int64_t n = 0;
+    hipStream_t sD = nullptr, sR = nullptr;
+    std::vector<std::vector<NodeBuf>> lev;        // [levels][M+1]
+    std::vector<double*> phiAD, TAD, hatA, hatD;  // [M+1]
+    std::vector<double*> C, CR;                   // [M+1] sweep constants (diffusion, reaction)
+    double* rD = nullptr;                         // diffusion right-hand side (N+1 fields)
+    double* bR = nullptr;                         // reaction right-hand side (N fields)
+    double* thD = nullptr;                        // theta work (diffusion stream)
+    double* thR = nullptr;                        // theta work (reaction stream)
+    int32_t* iters = nullptr;                     // Newton iterations (cells)
+    unsigned long long* nstats = nullptr;         // Newton statistics (4)
+    int32_t* cgstats = nullptr;                   // CG: [0] sum, [1] max, [2] failed, [3] solves, [4] timeouts
+    double* inc = nullptr;                        // sweep increments: 64 x NF x 2
+    double* inc_partial = nullptr;
+    int inc_blocks = 64;
+    DiffusionWork dw;
+    std::vector<void*> allocs;
+    std::vector<hipEvent_t> evD, evR;             // [(levels) x (M+1)]
+    hipEvent_t ev_in = nullptr, ev_outD = nullptr, ev_outR = nullptr;
+    int last_sweeps = 0;
+    double dt = 0.0;
+
+    hipEvent_t& D_ev(int l, int p) { return evD[(size_t)l * (M + 1) + p]; }
+    hipEvent_t& R_ev(int l, int p) { return evR[(size_t)l * (M + 1) + p]; }
+};
+
+namespace {
+
+bool valid_ptr(const void* p) { return p != nullptr; }
+
+int check_mech_desc(const misdc_mech_desc* d) {
+    if (!d) return fail(MISDC_EINVAL, "mechanism descriptor is NULL");
+    if (d->n_species < 2 || d->n_species > 256)
+        return fail(MISDC_EINVAL, "n_species must be in [2, 256], got %d", d->n_species);
+    if (d->n_reactions < 0 || d->n_reactions > 100000)
+        return fail(MISDC_EINVAL, "n_reactions out of range: %d", d->n_reactions);
+    if (d->bath < 0 || d->bath >= d->n_species)
+        return fail(MISDC_EINVAL, "bath index %d outside [0, %d)", d->bath, d->n_species);
+    const void* arrs[] = {d->W, d->A, d->beta, d->Ea, d->cp, d->hf, d->s0, d->D0};
+    for (const void* a : arrs)
+        if (!valid_ptr(a)) return fail(MISDC_EINVAL, "mechanism array is NULL");
+    if (d->n_reactions > 0 && (!d->react || !d->prod))
+        return fail(MISDC_EINVAL, "reaction slot arrays are NULL");
+    for (int k = 0; k < d->n_species; ++k) {
+        if (!(d->W[k] > 0) || !std::isfinite(d->W[k]))
+            return fail(MISDC_EINVAL, "W[%d] must be positive and finite", k);
+        if (!(d->cp[k] > 0) || !std::isfinite(d->cp[k]))
+            return fail(MISDC_EINVAL, "cp[%d] must be positive and finite", k);
+        if (!(d->D0[k] >= 0) || !std::isfinite(d->D0[k]))
+            return fail(MISDC_EINVAL, "D0[%d] must be non-negative and finite", k);
+        if (!std::isfinite(d->hf[k]) || !std::isfinite(d->s0[k]))
+            return fail(MISDC_EINVAL, "hf/s0[%d] not finite", k);
+    }
+    if (!(d->alpha0 >= 0) || !(d->rho0 > 0) || !(d->p_atm > 0) || !(d->R_u > 0) || !(d->R_c > 0))
+        return fail(MISDC_EINVAL, "alpha0 >= 0 and rho0, p_atm, R_u, R_c > 0 required");
+    for (int j = 0; j < d->n_reactions; ++j) {
+        for (int s = 0; s < 2; ++s) {
+            const int a = d->react[2 * j + s], b = d->prod[2 * j + s];
+            if (a < -1 || a >= d->n_species || b < -1 || b >= d->n_species)
+                return fail(MISDC_EINVAL, "reaction %d: species index out of range", j);
+            if (a == d->bath || b == d->bath)
+                return fail(MISDC_EINVAL, "reaction %d involves the bath species", j);
+        }
+        if (d->react[2 * j] < 0 && d->react[2 * j + 1] < 0)
+            return fail(MISDC_EINVAL, "reaction %d has no reactant", j);
+        if (d->prod[2 * j] < 0 && d->prod[2 * j + 1] < 0)
+            return fail(MISDC_EINVAL, "reaction %d has no product", j);
+        if (!(d->A[j] >= 0) || !std::isfinite(d->A[j]) || !std::isfinite(d->beta[j]) ||
+            !std::isfinite(d->Ea[j]))
+            return fail(MISDC_EINVAL, "reaction %d: invalid Arrhenius parameters", j);
+        // mass balance: sum of W over reactant slots equals that over product slots
+        double wr = 0, wp = 0;
+        for (int s = 0; s < 2; ++s) {
+            if (d->react[2 * j + s] >= 0) wr += d->W[d->react[2 * j + s]];
+            if (d->prod[2 * j + s] >= 0) wp += d->W[d->prod[2 * j + s]];
+        }
+        if (std::fabs(wr - wp) > 1e-9 * (wr + wp))
+            return fail(MISDC_EINVAL, "reaction %d is not mass balanced", j);
+    }
+    return MISDC_OK;
+}
+
+int check_opts(const misdc_opts* o) {
+    if (!o) return fail(MISDC_EINVAL, "options are NULL");
+    if (o->n_nodes < 2 || o->n_nodes > MAX_NODES)
+        return fail(MISDC_EINVAL, "n_nodes must be in [2, %d]", MAX_NODES);
+    if (o->n_sweeps < 1 || o->n_sweeps > 64)
+        return fail(MISDC_EINVAL, "n_sweeps must be in [1, 64]");
+    if (o->scheme < MISDC_SCHEME_MISDC || o->scheme > MISDC_SCHEME_CISDCQ)
+        return fail(MISDC_EINVAL, "unknown scheme %d", o->scheme);
+    if (o->nu < 1 || o->nu > 16) return fail(MISDC_EINVAL, "nu must be in [1, 16]");
+    if (o->scheme != MISDC_SCHEME_CISDCQ && o->nu != 1)
+        return fail(MISDC_EINVAL, "nu > 1 needs the concurrent scheme");
+    if (o->qe_mode != MISDC_QE_CUMULATIVE && o->qe_mode != MISDC_QE_LITERAL)
+        return fail(MISDC_EINVAL, "unknown qe_mode %d", o->qe_mode);
+    return MISDC_OK;
+}
+
+misdc_newton_opts newton_defaults(const misdc_newton_opts* in) {
+    misdc_newton_opts o;
+    o.tol = 1e-12;
+    o.maxit = 200;
+    o.dtau0 = 1.0;
+    o.dtau_max = 1e10;
+    o.neg_slack = 1e-6;
+    if (in) {
+        if (in->tol > 0) o.tol = in->tol;
+        if (in->maxit > 0) o.maxit = in->maxit;
+        if (in->dtau0 > 0) o.dtau0 = in->dtau0;
+        if (in->dtau_max > 0) o.dtau_max = in->dtau_max;
+        if (in->neg_slack > 0) o.neg_slack = in->neg_slack;
+    }
+    return o;
+}
+
+template <class T>
+int dalloc(misdc_integ_s* I, T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T) + 256);
+    if (e != hipSuccess) return fail(MISDC_ENOMEM, "hipMalloc of %zu bytes: %s", count * sizeof(T),
+                                     hipGetErrorString(e));
+    I->allocs.push_back(q);
+    *p = (T*)q;
+    return MISDC_OK;
+}
+
+// Linear combination builder.
+struct LC {
+    LinComb lc;
+    explicit LC(int nfields, int64_t n) {
+        std::memset(&lc, 0, sizeof(lc));
+        lc.nfields = nfields;
+        lc.ncells = n;
+    }
+    int out(double* p) {
+        lc.out[lc.nout] = p;
+        return lc.nout++;
+    }
+    // add weight w (to output o) of array X with nf fields; merges duplicates
+    void add(int o, double w, const double* X, int nf) {
+        if (w == 0.0 || !X) return;
+        for (int t = 0; t < lc.nterms; ++t)
+            if (lc.X[t] == X) {
+                lc.W[o][t] += w;
+                return;
+            }
+        const int t = lc.nterms++;
+        lc.X[t] = X;
+        lc.nf[t] = nf;
+        for (int q = 0; q < LC_MAX_OUT; ++q) lc.W[q][t] = 0.0;
+        lc.W[o][t] = w;
+    }
+};
+
+int eval_ops(misdc_integ_s* I, const NodeBuf& b, double* th, hipStream_t s, bool with_R) {
+    int rc = launch_transport(*I->mech, *I->grid, b.phi, b.T, b.FA, b.FD, th, s);
+    if (rc) return rc;
+    if (with_R) {
+        rc = launch_reaction_source(*I->mech, I->n, b.phi, b.phi + (size_t)I->N * I->n, b.FR, s);
+        if (rc) return rc;
+    }
+    return MISDC_OK;
+}
+
+int accum_cg(misdc_integ_s* I, hipStream_t s);
+
+// ---- diffusion task at node p of nested iteration ell (writes phiAD[p]) ----
+int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
+    const int M = I->M, N = I->N, NF = I->NF;
+    const int64_t n = I->n;
+    const Tables& t = I->tab;
+    const int m = p - 1;
+    auto& L0 = I->lev[0];
+    auto& Lc = I->lev[ell + 1];       // iteration ell+1 (serial schemes: the new sweep)
+    auto& Lp = I->lev[ell];           // iteration ell (lagged); ell = 0: sweep k
+    LC b(NF, n);
+    const int o = b.out(I->rD);
+    double c = 0.0;
+    const double* T_lag = nullptr;
+    if (I->opt.scheme == MISDC_SCHEME_MISDC) {
+        const double dtm = dt * (t.tau[p] - t.tau[p - 1]);
+        c = dtm;
+        // phi^{m,(k+1)} + dt^m FA(phi^{m,(k+1)}) + [constant part in C]
+        // (the advection bracket at node 0 vanishes: phi^0 is fixed)
+        b.add(o, 1.0, I->C[p], NF);
+        b.add(o, 1.0, (m == 0) ? L0[0].phi : Lc[m].phi, NF);
+        if (m >= 1) b.add(o, dtm, Lc[m].FA, NF);
+        T_lag = L0[p].T;
+    } else if (I->opt.scheme == MISDC_SCHEME_MISDCQ) {
+        c = dt * t.QI[p - 1][p - 1];
+        b.add(o, 1.0, I->C[p], NF);
+        for (int j = 1; j <= m; ++j) {
+            b.add(o, dt * t.QE[p - 1][j - 1], Lc[j].FA, NF);
+            b.add(o, dt * t.QI[p - 1][j - 1], Lc[j].FD, NF);
+        }
+        T_lag = L0[p].T;
+    } else {
+        c = dt * t.QI[p - 1][p - 1];
+        b.add(o, 1.0, I->C[p], NF);
+        for (int j = 1; j <= m - 1; ++j) {
+            b.add(o, dt * t.QE[p - 1][j - 1], Lc[j].FA, NF);
+            b.add(o, dt * t.QI[p - 1][j - 1], Lc[j].FD, NF);
+            b.add(o, dt * t.QI[p - 1][j - 1], Lc[j].FR, N);
+        }
+        if (m >= 1) {
+            const double* lagA = (ell == 0) ? I->hatA[m] : Lp[m].FA;
+            const double* lagD = (ell == 0) ? I->hatD[m] : Lp[m].FD;
+            b.add(o, dt * t.QE[p - 1][m - 1], lagA, NF);
+            b.add(o, dt * t.QI[p - 1][m - 1], lagD, NF);
+            b.add(o, dt * t.QI[p - 1][m - 1], Lp[m].FR, N);
+        }
+        b.add(o, c, Lp[p].FR, N);
+        T_lag = (ell == 0) ? L0[p].T : Lp[p].T;
+    }
+    int rc = launch_lincomb(b.lc, I->sD);
+    if (rc) return rc;
+    // initial guess of the iterative solve: the lagged state at this node
+    const double* guess = (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell > 0) ? Lp[p].phi : L0[p].phi;
+    MISDC_HIP(hipMemcpyAsync(I->phiAD[p], guess, sizeof(double) * NF * n, hipMemcpyDeviceToDevice,
+                             I->sD));
+    rc = launch_diffusion_solve(*I->mech, *I->grid, I->dw, c, nullptr, 0.0, T_lag, I->rD,
+                                I->phiAD[p], 1, I->opt.cg_rtol, I->opt.cg_maxit, I->sD);
+    if (rc) return rc;
+    if (I->grid->dim == 2 && I->grid->n_flames == 0) {
+        rc = accum_cg(I, I->sD);
+        if (rc) return rc;
+    }
+    rc = launch_state_temperature(*I->mech, n, I->phiAD[p], I->TAD[p], I->sD);
+    if (rc) return rc;
+    if (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell == 0) {
+        // lag initialisation (initial_lagged_values_A/D): FA, FD at phi_AD^{p,(k+1,1)}
+        rc = launch_transport(*I->mech, *I->grid, I->phiAD[p], I->TAD[p], I->hatA[p], I->hatD[p],
+                              I->thD, I->sD);
+        if (rc) return rc;
+    }
+    (void)M;
+    return MISDC_OK;
+}
+
+// ---- reaction task at node p of nested iteration ell (writes lev[ell+1][p]) ----
+int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
+    const int N = I->N, NF = I->NF;
+    const int64_t n = I->n;
+    const Tables& t = I->tab;
+    const int m = p - 1;
+    auto& L0 = I->lev[0];
+    auto& Lc = I->lev[ell + 1];
+    auto& Lp = I->lev[ell];
+    LC b(N, n);
+    const int o = b.out(I->bR);
+    double c = 0.0;
+    b.add(o, 1.0, I->phiAD[p], N);
+    if (I->opt.scheme == MISDC_SCHEME_MISDC) {
+        c = dt * (t.tau[p] - t.tau[p - 1]);
+        b.add(o, -c, L0[p].FR, N);
+    } else if (I->opt.scheme == MISDC_SCHEME_MISDCQ) {
+        c = dt * t.QI[p - 1][p - 1];
+        b.add(o, 1.0, I->CR[p], N);
+        for (int j = 1; j <= m; ++j) b.add(o, dt * t.QI[p - 1][j - 1], Lc[j].FR, N);
+    } else {
+        c = dt * t.QI[p - 1][p - 1];
+        if (m >= 1) {
+            b.add(o, dt * t.QI[p - 1][m - 1], Lc[m].FR, N);
+            b.add(o, -dt * t.QI[p - 1][m - 1], Lp[m].FR, N);
+        }
+        b.add(o, -c, Lp[p].FR, N);
+    }
+    int rc = launch_lincomb(b.lc, I->sR);
+    if (rc) return rc;
+    NodeBuf& out = Lc[p];
+    // enthalpy is not changed by the reaction step
+    MISDC_HIP(hipMemcpyAsync(out.phi + (size_t)N * n, I->phiAD[p] + (size_t)N * n,
+                             sizeof(double) * n, hipMemcpyDeviceToDevice, I->sR));
+    NewtonArgs a;
+    a.n = n;
+    a.bY = I->bR;
+    a.ldb = n;
+    a.h = I->phiAD[p] + (size_t)N * n;
+    a.c = nullptr;
+    a.c_scalar = c;
+    a.guess = Lp[p].phi;
+    a.ldg = n;
+    a.Y = out.phi;
+    a.ldy = n;
+    a.T = out.T;
+    a.FR = out.FR;
+    a.ldf = n;
+    a.iters = I->iters;
+    a.stats = I->nstats;
+    a.opt = I->opt.newton;
+    rc = launch_reaction_newton(*I->mech, a, I->sR);
+    if (rc) return rc;
+    rc = eval_ops(I, out, I->thR, I->sR, false);
+    (void)NF;
+    return rc;
+}
+
+__global__ void cg_accum_kernel(int32_t* info, int32_t* st) {
+    st[0] += info[0];
+    st[1] = info[0] > st[1] ? info[0] : st[1];
+    st[2] += info[1];
+    st[3] += 1;
+    st[4] += info[2];
+    info[2] = 0;
+}
+
+int accum_cg(misdc_integ_s* I, hipStream_t s) {
+    hipLaunchKernelGGL(cg_accum_kernel, dim3(1), dim3(1), 0, s, I->dw.info, I->cgstats);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+// sweep-start constants (all terms of sweep k)
+int sweep_constants(misdc_integ_s* I, double dt) {
+    const int M = I->M, N = I->N, NF = I->NF;
+    const int64_t n = I->n;
+    const Tables& t = I->tab;
+    auto& L0 = I->lev[0];
+    LC b(NF, n);
+    for (int p = 1; p <= M; ++p) {
+        const int o = b.out(I->C[p]);
+        if (I->opt.scheme == MISDC_SCHEME_MISDC) {
+            // dt S^{m:m+1} F^{(k)} - dt^m FA^{m,(k)} - dt^m FD^{p,(k)}
+            const double dtm = dt * (t.tau[p] - t.tau[p - 1]);
+            for (int j = 0; j <= M; ++j) {
+                b.add(o, dt * t.S[p - 1][j], L0[j].FA, NF);
+                b.add(o, dt * t.S[p - 1][j], L0[j].FD, NF);
+                b.add(o, dt * t.S[p - 1][j], L0[j].FR, N);
+            }
+            if (p - 1 >= 1) b.add(o, -dtm, L0[p - 1].FA, NF);
+            b.add(o, -dtm, L0[p].FD, NF);
+        } else {
+            b.add(o, 1.0, L0[0].phi, NF);
+            for (int j = 0; j <= M; ++j) {
+                b.add(o, dt * t.Q[p - 1][j], L0[j].FA, NF);
+                b.add(o, dt * t.Q[p - 1][j], L0[j].FD, NF);
+                b.add(o, dt * t.Q[p - 1][j], L0[j].FR, N);
+            }
+            for (int j = 1; j <= p - 1; ++j) b.add(o, -dt * t.QE[p - 1][j - 1], L0[j].FA, NF);
+            const bool with_R = (I->opt.scheme == MISDC_SCHEME_CISDCQ);
+            for (int j = 1; j <= p; ++j) {
+                b.add(o, -dt * t.QI[p - 1][j - 1], L0[j].FD, NF);
+                if (with_R) b.add(o, -dt * t.QI[p - 1][j - 1], L0[j].FR, N);
+            }
+        }
+    }
+    int rc = launch_lincomb(b.lc, I->sD);
+    if (rc) return rc;
+    if (I->opt.scheme == MISDC_SCHEME_MISDCQ) {
+        LC r(N, n);
+        for (int p = 1; p <= M; ++p) {
+            const int o = r.out(I->CR[p]);
+            for (int j = 1; j <= p; ++j) r.add(o, -dt * t.QI[p - 1][j - 1], L0[j].FR, N);
+        }
+        rc = launch_lincomb(r.lc, I->sD);
+        if (rc) return rc;
+    }
+    return MISDC_OK;
+}
+
+int run_sweep(misdc_integ_s* I, int k, double dt) {
+    const int M = I->M;
+    const int nu = (I->opt.scheme == MISDC_SCHEME_CISDCQ) ? I->nu : 1;
+    int rc;
+    // the constants read every reaction output of the previous sweep
+    MISDC_HIP(hipStreamWaitEvent(I->sD, I->R_ev(0, M), 0));
+    rc = sweep_constants(I, dt);
+    if (rc) return rc;
+    if (I->opt.scheme != MISDC_SCHEME_CISDCQ) {
+        for (int p = 1; p <= M; ++p) {
+            if (p > 1) MISDC_HIP(hipStreamWaitEvent(I->sD, I->R_ev(1, p - 1), 0));
+            rc = diffusion_task(I, 0, p, dt);
+            if (rc) return rc;
+            MISDC_HIP(hipEventRecord(I->D_ev(1, p), I->sD));
+            MISDC_HIP(hipStreamWaitEvent(I->sR, I->D_ev(1, p), 0));
+            rc = reaction_task(I, 0, p, dt);
+            if (rc) return rc;
+            MISDC_HIP(hipEventRecord(I->R_ev(1, p), I->sR));
+        }
+    } else {
+        for (int ell = 0; ell < nu; ++ell) {
+            for (int s = 0; s <= M; ++s) {
+                const int pd = s + 1;     // diffusion node
+                const int pr = s;         // reaction node
+                if (pd <= M) {
+                    if (pd >= 3) MISDC_HIP(hipStreamWaitEvent(I->sD, I->R_ev(ell + 1, pd - 2), 0));
+                    if (ell >= 1) MISDC_HIP(hipStreamWaitEvent(I->sD, I->R_ev(ell, pd), 0));
+                    rc = diffusion_task(I, ell, pd, dt);
+                    if (rc) return rc;
+                    MISDC_HIP(hipEventRecord(I->D_ev(ell + 1, pd), I->sD));
+                }
+                if (pr >= 1) {
+                    MISDC_HIP(hipStreamWaitEvent(I->sR, I->D_ev(ell + 1, pr), 0));
+                    rc = reaction_task(I, ell, pr, dt);
+                    if (rc) return rc;
+                    MISDC_HIP(hipEventRecord(I->R_ev(ell + 1, pr), I->sR));
+                }
+            }
+        }
+    }
+    // sweep increment at node M (reaction stream, after the last reaction task)
+    const int lv = nu;
+    rc = launch_field_diff_max(I->NF, I->n, I->lev[lv][M].phi, I->lev[0][M].phi, I->inc_partial,
+                               I->inc_blocks, I->inc + (size_t)k * I->NF * 2, I->sR);
+    if (rc) return rc;
+    // S7: the last nested iteration becomes sweep k+1 (swap buffer sets)
+    for (int p = 1; p <= M; ++p) std::swap(I->lev[0][p], I->lev[lv][p]);
+    MISDC_HIP(hipEventRecord(I->R_ev(0, M), I->sR));
+    return MISDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* misdc_last_error(void) { return g_err; }
+
+const char* misdc_version(void) { return "misdc-mi355x 0.1 (gfx950)"; }
+
+int misdc_mech_create(const misdc_mech_desc* d, misdc_mech_t* out) {
+    if (!out) return fail(MISDC_EINVAL, "output handle pointer is NULL");
+    *out = nullptr;
+    int rc = check_mech_desc(d);
+    if (rc) return rc;
+    const int N = d->n_species, R = d->n_reactions;
+    auto* h = new (std::nothrow) misdc_mech_s();
+    if (!h) return fail(MISDC_ENOMEM, "host allocation failed");
+    Mech& m = h->m;
+    // host-side table construction
+    std::vector<int> slots(4 * (size_t)R);
+    std::vector<double> Ta(R), dn(R), uW((size_t)R * N, 0.0), invW(N), kappa0(N + 1);
+    for (int j = 0; j < R; ++j) {
+        slots[4 * j + 0] = d->react[2 * j];
+        slots[4 * j + 1] = d->react[2 * j + 1];
+        slots[4 * j + 2] = d->prod[2 * j];
+        slots[4 * j + 3] = d->prod[2 * j + 1];
+        Ta[j] = d->Ea[j] / d->R_c;
+        double net = 0;
+        for (int s = 0; s < 2; ++s) {
+            if (d->react[2 * j + s] >= 0) {
+                uW[(size_t)j * N + d->react[2 * j + s]] -= d->W[d->react[2 * j + s]] / d->rho0;
+                net -= 1;
+            }
+            if (d->prod[2 * j + s] >= 0) {
+                uW[(size_t)j * N + d->prod[2 * j + s]] += d->W[d->prod[2 * j + s]] / d->rho0;
+                net += 1;
+            }
+        }
+        dn[j] = net;
+    }
+    double scale = 0;
+    for (int k = 0; k < N; ++k) {
+        invW[k] = 1.0 / d->W[k];
+        scale += d->cp[k] / d->W[k];
+        kappa0[k] = d->D0[k];
+    }
+    kappa0[N] = d->alpha0;
+    scale /= N;
+    // one device block: doubles then ints
+    const size_t nd = (size_t)R * 5 + (size_t)R * N + (size_t)N * 6 + (N + 1);
+    const size_t bytes = nd * sizeof(double) + slots.size() * sizeof(int) + 64;
+    hipError_t e = hipGetDevice(&m.device);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(MISDC_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    e = hipMalloc(&m.block, bytes);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(MISDC_ENOMEM, "hipMalloc(mechanism): %s", hipGetErrorString(e));
+    }
+    std::vector<char> host(bytes, 0);
+    double* dp = (double*)host.data();
+    size_t off = 0;
+    auto put = [&](const double* src, size_t cnt) {
+        const size_t at = off;
+        if (cnt) std::memcpy(dp + off, src, cnt * sizeof(double));
+        off += cnt;
+        return at;
+    };
+    const size_t oA = put(d->A, R), ob = put(d->beta, R), oT = put(Ta.data(), R),
+                 odn = put(dn.data(), R), ouW = put(uW.data(), uW.size()),
+                 oW = put(d->W, N), oiW = put(invW.data(), N), ocp = put(d->cp, N),
+                 ohf = put(d->hf, N), os0 = put(d->s0, N), ok0 = put(kappa0.data(), N + 1);
+    off += R;   // spare
+    int* ip = (int*)(dp + off);
+    if (!slots.empty()) std::memcpy(ip, slots.data(), slots.size() * sizeof(int));
+    e = hipMemcpy(m.block, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(m.block);
+        delete h;
+        return fail(MISDC_EDEVICE, "hipMemcpy(mechanism): %s", hipGetErrorString(e));
+    }
+    const double* base = (const double*)m.block;
+    MechDev& md = m.dev;
+    md.N = N;
+    md.R = R;
+    md.bath = d->bath;
+    md.rho0 = d->rho0;
+    md.p_atm = d->p_atm;
+    md.R_u = d->R_u;
+    md.R_c = d->R_c;
+    md.alpha0 = d->alpha0;
+    md.newton_scale = scale;
+    md.ln_patm_over_Ru = std::log(d->p_atm / d->R_u);
+    md.slots = (const int*)(base + off);
+    md.A = base + oA;
+    md.beta = base + ob;
+    md.Ta = base + oT;
+    md.dn = base + odn;
+    md.uW = base + ouW;
+    md.W = base + oW;
+    md.invW = base + oiW;
+    md.cp = base + ocp;
+    md.hf = base + ohf;
+    md.s0 = base + os0;
+    md.kappa0 = base + ok0;
+    m.W.assign(d->W, d->W + N);
+    m.cp.assign(d->cp, d->cp + N);
+    m.hf.assign(d->hf, d->hf + N);
+    m.kappa0 = kappa0;
+    *out = h;
+    return MISDC_OK;
+}
+
+int misdc_mech_destroy(misdc_mech_t mech) {
+    if (!mech) return MISDC_OK;
+    if (mech->m.block) (void)hipFree(mech->m.block);
+    delete mech;
+    return MISDC_OK;
+}
+
+int misdc_mech_species(misdc_mech_t mech, int32_t* n_species) {
+    if (!mech || !n_species) return fail(MISDC_EINVAL, "NULL argument");
+    *n_species = mech->m.dev.N;
+    return MISDC_OK;
+}
+
+int misdc_enthalpy(misdc_mech_t mech, int64_t n, const double* Y, const double* T, double* h,
+                   void* stream) {
+    if (!mech) return fail(MISDC_EINVAL, "mechanism is NULL");
+    if (n < 0) return fail(MISDC_EINVAL, "n < 0");
+    if (n > 0 && (!Y || !T || !h)) return fail(MISDC_EINVAL, "NULL array");
+    return launch_enthalpy(mech->m, n, Y, T, h, (hipStream_t)stream);
+}
+
+int misdc_temperature(misdc_mech_t mech, int64_t n, const double* Y, const double* h, double* T,
+                      void* stream) {
+    if (!mech) return fail(MISDC_EINVAL, "mechanism is NULL");
+    if (n < 0) return fail(MISDC_EINVAL, "n < 0");
+    if (n > 0 && (!Y || !T || !h)) return fail(MISDC_EINVAL, "NULL array");
+    return launch_temperature(mech->m, n, Y, h, T, (hipStream_t)stream);
+}
+
+int misdc_reaction_source(misdc_mech_t mech, int64_t n, const double* Y, const double* h,
+                          double* FR, void* stream) {
+    if (!mech) return fail(MISDC_EINVAL, "mechanism is NULL");
+    if (n < 0) return fail(MISDC_EINVAL, "n < 0");
+    if (n > 0 && (!Y || !FR || !h)) return fail(MISDC_EINVAL, "NULL array");
+    return launch_reaction_source(mech->m, n, Y, h, FR, (hipStream_t)stream);
+}
+
+int misdc_reaction_solve_batch(misdc_mech_t mech, int64_t n, const double* bY, const double* h,
+                               const double* c, double* Y, double* T_out, double* FR_out,
+                               int32_t* iters_out, const misdc_newton_opts* opts, void* stream) {
+    if (!mech) return fail(MISDC_EINVAL, "mechanism is NULL");
+    if (n < 0) return fail(MISDC_EINVAL, "n < 0");
+    if (n == 0) return MISDC_OK;
+    if (!bY || !h || !c || !Y || !iters_out) return fail(MISDC_EINVAL, "NULL array");
+    if (mech->m.dev.N != 9)
+        return fail(MISDC_EUNSUPPORTED, "reaction solve built for 9 species, mechanism has %d",
+                    mech->m.dev.N);
+    NewtonArgs a;
+    a.n = n;
+    a.bY = bY;
+    a.ldb = n;
+    a.h = h;
+    a.c = c;
+    a.c_scalar = 0;
+    a.guess = Y;
+    a.ldg = n;
+    a.Y = Y;
+    a.ldy = n;
+    a.T = T_out;
+    a.FR = FR_out;
+    a.ldf = n;
+    a.iters = iters_out;
+    a.stats = nullptr;
+    a.opt = newton_defaults(opts);
+    return launch_reaction_newton(mech->m, a, (hipStream_t)stream);
+}
+
+int misdc_grid_create(int dim, const int64_t* n, const double* dx, const double* u,
+                      misdc_grid_t* out) {
+    if (!out) return fail(MISDC_EINVAL, "output handle pointer is NULL");
+    *out = nullptr;
+    if (dim != 1 && dim != 2) return fail(MISDC_EINVAL, "dim must be 1 or 2, got %d", dim);
+    if (!n || !dx || !u) return fail(MISDC_EINVAL, "NULL array");
+    for (int d = 0; d < dim; ++d) {
+        if (n[d] < 4 || n[d] > (int64_t)1 << 30)
+            return fail(MISDC_EINVAL, "n[%d] must be in [4, 2^30], got %lld", d, (long long)n[d]);
+        if (!(dx[d] > 0) || !std::isfinite(dx[d]) || !std::isfinite(u[d]))
+            return fail(MISDC_EINVAL, "dx[%d] must be positive and u finite", d);
+    }
+    auto* h = new (std::nothrow) misdc_grid_s();
+    if (!h) return fail(MISDC_ENOMEM, "host allocation failed");
+    Grid& g = h->g;
+    g.dim = dim;
+    g.nx = n[0];
+    g.ny = dim == 2 ? n[1] : 1;
+    g.dx = dx[0];
+    g.dy = dim == 2 ? dx[1] : 0.0;
+    g.ux = u[0];
+    g.uy = dim == 2 ? u[1] : 0.0;
+    if (g.nx * g.ny > ((int64_t)1 << 31)) {
+        delete h;
+        return fail(MISDC_EINVAL, "grid too large");
+    }
+    *out = h;
+    return MISDC_OK;
+}
+
+int misdc_grid_create_ensemble(int n_flames, const int64_t* lengths, const double* dx,
+                               const double* u, misdc_grid_t* out) {
+    if (!out) return fail(MISDC_EINVAL, "output handle pointer is NULL");
+    *out = nullptr;
+    if (n_flames < 1 || n_flames > 65536) return fail(MISDC_EINVAL, "n_flames out of range");
+    if (!lengths || !dx || !u) return fail(MISDC_EINVAL, "NULL array");
+    auto* h = new (std::nothrow) misdc_grid_s();
+    if (!h) return fail(MISDC_ENOMEM, "host allocation failed");
+    Grid& g = h->g;
+    g.dim = 1;
+    g.n_flames = n_flames;
+    g.off.assign(n_flames + 1, 0);
+    for (int f = 0; f < n_flames; ++f) {
+        if (lengths[f] < 4 || !(dx[f] > 0) || !std::isfinite(u[f])) {
+            delete h;
+            return fail(MISDC_EINVAL, "flame %d: length >= 4, dx > 0 required", f);
+        }
+        g.off[f + 1] = g.off[f] + lengths[f];
+    }
+    g.len.assign(lengths, lengths + n_flames);
+    g.fdx.assign(dx, dx + n_flames);
+    g.fu.assign(u, u + n_flames);
+    g.nx = g.off.back();
+    g.ny = 1;
+    hipError_t e = hipMalloc(&g.d_off, sizeof(int64_t) * (n_flames + 1));
+    if (e == hipSuccess) e = hipMalloc(&g.d_dx, sizeof(double) * n_flames);
+    if (e == hipSuccess) e = hipMalloc(&g.d_u, sizeof(double) * n_flames);
+    if (e == hipSuccess)
+        e = hipMemcpy(g.d_off, g.off.data(), sizeof(int64_t) * (n_flames + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g.d_dx, dx, sizeof(double) * n_flames, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g.d_u, u, sizeof(double) * n_flames, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        misdc_grid_destroy(h);
+        return fail(MISDC_EDEVICE, "ensemble grid: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return MISDC_OK;
+}
+
+int misdc_grid_destroy(misdc_grid_t grid) {
+    if (!grid) return MISDC_OK;
+    if (grid->g.d_off) (void)hipFree(grid->g.d_off);
+    if (grid->g.d_dx) (void)hipFree(grid->g.d_dx);
+    if (grid->g.d_u) (void)hipFree(grid->g.d_u);
+    delete grid;
+    return MISDC_OK;
+}
+
+int misdc_grid_cells(misdc_grid_t grid, int64_t* n_cells) {
+    if (!grid || !n_cells) return fail(MISDC_EINVAL, "NULL argument");
+    *n_cells = grid->g.cells();
+    return MISDC_OK;
+}
+
+int misdc_transport_operators(misdc_mech_t mech, misdc_grid_t grid, const double* state,
+                              double* FA, double* FD, void* stream) {
+    if (!mech || !grid) return fail(MISDC_EINVAL, "NULL handle");
+    if (!state) return fail(MISDC_EINVAL, "state is NULL");
+    const int64_t n = grid->g.cells();
+    hipStream_t s = (hipStream_t)stream;
+    double* T = nullptr;
+    double* th = nullptr;
+    MISDC_HIP(hipMallocAsync((void**)&T, sizeof(double) * n, s));
+    MISDC_HIP(hipMallocAsync((void**)&th, sizeof(double) * n, s));
+    int rc = launch_state_temperature(mech->m, n, state, T, s);
+    if (!rc) rc = launch_transport(mech->m, grid->g, state, T, FA, FD, th, s);
+    (void)hipFreeAsync(T, s);
+    (void)hipFreeAsync(th, s);
+    return rc;
+}
+
+int misdc_diffusion_solve(misdc_mech_t mech, misdc_grid_t grid, double c, const double* T_lag,
+                          const double* rhs, double* y, int guess_in_y, double rtol, int maxit,
+                          int32_t* iters_out, void* stream) {
+    if (!mech || !grid) return fail(MISDC_EINVAL, "NULL handle");
+    if (!T_lag || !rhs || !y) return fail(MISDC_EINVAL, "NULL array");
+    if (rhs == y) return fail(MISDC_EINVAL, "rhs and y must not alias");
+    if (!(c >= 0) || !std::isfinite(c)) return fail(MISDC_EINVAL, "c must be >= 0 and finite");
+    hipStream_t s = (hipStream_t)stream;
+    DiffusionWork w;
+    int rc = diffusion_work_alloc(w, mech->m, grid->g);
+    if (rc) {
+        diffusion_work_free(w);
+        return rc;
+    }
+    rc = launch_diffusion_solve(mech->m, grid->g, w, c, nullptr, 0.0, T_lag, rhs, y, guess_in_y,
+                                rtol, maxit, s);
+    if (!rc && iters_out) {
+        hipError_t e = hipMemcpyAsync(iters_out, w.info, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) rc = fail(MISDC_EDEVICE, "copy iterations: %s", hipGetErrorString(e));
+    }
+    // the work buffers must outlive the kernels: wait before freeing
+    hipError_t e = hipStreamSynchronize(s);
+    diffusion_work_free(w);
+    if (!rc && e != hipSuccess) rc = fail(MISDC_EDEVICE, "synchronise: %s", hipGetErrorString(e));
+    return rc;
+}
+
+void misdc_opts_default(misdc_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->n_nodes = 5;
+    o->n_sweeps = 6;
+    o->nu = 1;
+    o->scheme = MISDC_SCHEME_CISDCQ;
+    o->qe_mode = MISDC_QE_CUMULATIVE;
+    o->serialize = 0;
+    o->newton = newton_defaults(nullptr);
+    o->cg_rtol = 1e-13;
+    o->cg_maxit = 500;
+}
+
+int misdc_integ_destroy(misdc_integ_t I);
+
+int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* opts,
+                       misdc_integ_t* out) {
+    if (!out) return fail(MISDC_EINVAL, "output handle pointer is NULL");
+    *out = nullptr;
+    if (!mech || !grid) return fail(MISDC_EINVAL, "NULL handle");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (mech->m.dev.N != 9)
+        return fail(MISDC_EUNSUPPORTED, "integrator built for 9 species, mechanism has %d",
+                    mech->m.dev.N);
+    auto* I = new (std::nothrow) misdc_integ_s();
+    if (!I) return fail(MISDC_ENOMEM, "host allocation failed");
+    I->mech = &mech->m;
+    I->grid = &grid->g;
+    I->opt = *opts;
+    I->opt.newton = newton_defaults(&opts->newton);
+    if (!(I->opt.cg_rtol > 0)) I->opt.cg_rtol = 1e-13;
+    if (I->opt.cg_maxit <= 0) I->opt.cg_maxit = 500;
+    rc = make_tables(opts->n_nodes, opts->scheme == MISDC_SCHEME_MISDC ? MISDC_QI_BE : MISDC_QI_LU,
+                     opts->qe_mode, I->tab);
+    if (rc) {
+        delete I;
+        return rc;
+    }
+    I->M = opts->n_nodes - 1;
+    I->N = mech->m.dev.N;
+    I->NF = I->N + 1;
+    I->n = grid->g.cells();
+    I->nu = opts->scheme == MISDC_SCHEME_CISDCQ ? opts->nu : 1;
+    I->levels = I->nu + 1;
+    const int M = I->M, N = I->N, NF = I->NF;
+    const int64_t n = I->n;
+    auto bail = [&](int code) {
+        misdc_integ_destroy(I);
+        return code;
+    };
+    I->lev.assign(I->levels, std::vector<NodeBuf>(M + 1));
+    for (int l = 0; l < I->levels; ++l)
+        for (int p = 0; p <= M; ++p) {
+            NodeBuf& b = I->lev[l][p];
+            if ((rc = dalloc(I, &b.phi, (size_t)NF * n))) return bail(rc);
+            if ((rc = dalloc(I, &b.T, (size_t)n))) return bail(rc);
+            if ((rc = dalloc(I, &b.FA, (size_t)NF * n))) return bail(rc);
+            if ((rc = dalloc(I, &b.FD, (size_t)NF * n))) return bail(rc);
+            if ((rc = dalloc(I, &b.FR, (size_t)N * n))) return bail(rc);
+        }
+    I->phiAD.assign(M + 1, nullptr);
+    I->TAD.assign(M + 1, nullptr);
+    I->hatA.assign(M + 1, nullptr);
+    I->hatD.assign(M + 1, nullptr);
+    I->C.assign(M + 1, nullptr);
+    I->CR.assign(M + 1, nullptr);
+    for (int p = 1; p <= M; ++p) {
+        if ((rc = dalloc(I, &I->phiAD[p], (size_t)NF * n))) return bail(rc);
+        if ((rc = dalloc(I, &I->TAD[p], (size_t)n))) return bail(rc);
+        if ((rc = dalloc(I, &I->hatA[p], (size_t)NF * n))) return bail(rc);
+        if ((rc = dalloc(I, &I->hatD[p], (size_t)NF * n))) return bail(rc);
+        if ((rc = dalloc(I, &I->C[p], (size_t)NF * n))) return bail(rc);
+        if ((rc = dalloc(I, &I->CR[p], (size_t)N * n))) return bail(rc);
+    }
+    if ((rc = dalloc(I, &I->rD, (size_t)NF * n))) return bail(rc);
+    if ((rc = dalloc(I, &I->bR, (size_t)N * n))) return bail(rc);
+    if ((rc = dalloc(I, &I->thD, (size_t)n))) return bail(rc);
+    if ((rc = dalloc(I, &I->thR, (size_t)n))) return bail(rc);
+    if ((rc = dalloc(I, &I->iters, (size_t)n))) return bail(rc);
+    if ((rc = dalloc(I, &I->nstats, 4))) return bail(rc);
+    if ((rc = dalloc(I, &I->cgstats, 8))) return bail(rc);
+    if ((rc = dalloc(I, &I->inc, (size_t)64 * NF * 2))) return bail(rc);
+    if ((rc = dalloc(I, &I->inc_partial, (size_t)I->inc_blocks * NF * 2))) return bail(rc);
+    if ((rc = diffusion_work_alloc(I->dw, mech->m, grid->g))) return bail(rc);
+    hipError_t e = hipStreamCreateWithFlags(&I->sD, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        if (opts->serialize)
+            I->sR = I->sD;
+        else
+            e = hipStreamCreateWithFlags(&I->sR, hipStreamNonBlocking);
+    }
+    if (e != hipSuccess) return bail(fail(MISDC_EDEVICE, "stream: %s", hipGetErrorString(e)));
+    const size_t nev = (size_t)I->levels * (M + 1);
+    I->evD.assign(nev, nullptr);
+    I->evR.assign(nev, nullptr);
+    for (size_t k = 0; k < nev && e == hipSuccess; ++k) {
+        e = hipEventCreateWithFlags(&I->evD[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->evR[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_outD, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_outR, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(fail(MISDC_EDEVICE, "events: %s", hipGetErrorString(e)));
+    *out = I;
+    return MISDC_OK;
+}
+
+int misdc_integ_destroy(misdc_integ_t I) {
+    if (!I) return MISDC_OK;
+    if (I->sD) (void)hipStreamSynchronize(I->sD);
+    if (I->sR && I->sR != I->sD) (void)hipStreamSynchronize(I->sR);
+    for (hipEvent_t ev : I->evD)
+        if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : I->evR)
+        if (ev) (void)hipEventDestroy(ev);
+    if (I->ev_in) (void)hipEventDestroy(I->ev_in);
+    if (I->ev_outD) (void)hipEventDestroy(I->ev_outD);
+    if (I->ev_outR) (void)hipEventDestroy(I->ev_outR);
+    if (I->sR && I->sR != I->sD) (void)hipStreamDestroy(I->sR);
+    if (I->sD) (void)hipStreamDestroy(I->sD);
+    diffusion_work_free(I->dw);
+    for (void* p : I->allocs) (void)hipFree(p);
+    delete I;
+    return MISDC_OK;
+}
+
+int misdc_step(misdc_integ_t I, double* state, double dt, const double* dev_dt, void* stream) {
+    if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
+    if (!state) return fail(MISDC_EINVAL, "state is NULL");
+    if (dev_dt) return fail(MISDC_EUNSUPPORTED, "per-flame step sizes are not built yet");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(MISDC_EINVAL, "dt must be positive");
+    hipStream_t cs = (hipStream_t)stream;
+    const int M = I->M, N = I->N, NF = I->NF;
+    const int64_t n = I->n;
+    const size_t fb = sizeof(double) * (size_t)NF * n;
+    int rc;
+    // order after the caller's stream
+    MISDC_HIP(hipEventRecord(I->ev_in, cs));
+    MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_in, 0));
+    if (I->sR != I->sD) MISDC_HIP(hipStreamWaitEvent(I->sR, I->ev_in, 0));
+    MISDC_HIP(hipMemsetAsync(I->nstats, 0, 4 * sizeof(unsigned long long), I->sD));
+    MISDC_HIP(hipMemsetAsync(I->cgstats, 0, 8 * sizeof(int32_t), I->sD));
+    // I1, I2, I4: every node of sweep 0 holds phi^n and F(phi^n)
+    NodeBuf& b0 = I->lev[0][0];
+    MISDC_HIP(hipMemcpyAsync(b0.phi, state, fb, hipMemcpyDeviceToDevice, I->sD));
+    if ((rc = launch_state_temperature(*I->mech, n, b0.phi, b0.T, I->sD))) return rc;
+    if ((rc = eval_ops(I, b0, I->thD, I->sD, true))) return rc;
+    for (int p = 1; p <= M; ++p) {
+        NodeBuf& b = I->lev[0][p];
+        MISDC_HIP(hipMemcpyAsync(b.phi, b0.phi, fb, hipMemcpyDeviceToDevice, I->sD));
+        MISDC_HIP(hipMemcpyAsync(b.T, b0.T, sizeof(double) * n, hipMemcpyDeviceToDevice, I->sD));
+        MISDC_HIP(hipMemcpyAsync(b.FA, b0.FA, fb, hipMemcpyDeviceToDevice, I->sD));
+        MISDC_HIP(hipMemcpyAsync(b.FD, b0.FD, fb, hipMemcpyDeviceToDevice, I->sD));
+        MISDC_HIP(hipMemcpyAsync(b.FR, b0.FR, sizeof(double) * (size_t)N * n,
+                                 hipMemcpyDeviceToDevice, I->sD));
+    }
+    // node 0 is shared by every nested-iteration level
+    for (int l = 1; l < I->levels; ++l) I->lev[l][0] = b0;
+    // "previous sweep finished" marker for the first sweep's constants
+    MISDC_HIP(hipEventRecord(I->R_ev(0, M), I->sD));
+    for (int k = 0; k < I->opt.n_sweeps; ++k)
+        if ((rc = run_sweep(I, k, dt))) return rc;
+    MISDC_HIP(hipMemcpyAsync(state, I->lev[0][M].phi, fb, hipMemcpyDeviceToDevice, I->sR));
+    MISDC_HIP(hipEventRecord(I->ev_outD, I->sD));
+    MISDC_HIP(hipEventRecord(I->ev_outR, I->sR));
+    MISDC_HIP(hipStreamWaitEvent(cs, I->ev_outD, 0));
+    MISDC_HIP(hipStreamWaitEvent(cs, I->ev_outR, 0));
+    I->last_sweeps = I->opt.n_sweeps;
+    I->dt = dt;
+    return MISDC_OK;
+}
+
+int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
+    if (!I || !st) return fail(MISDC_EINVAL, "NULL argument");
+    MISDC_HIP(hipStreamSynchronize(I->sD));
+    MISDC_HIP(hipStreamSynchronize(I->sR));
+    std::memset(st, 0, sizeof(*st));
+    unsigned long long ns[4];
+    int32_t cg[8];
+    MISDC_HIP(hipMemcpy(ns, I->nstats, sizeof(ns), hipMemcpyDeviceToHost));
+    MISDC_HIP(hipMemcpy(cg, I->cgstats, sizeof(cg), hipMemcpyDeviceToHost));
+    st->newton_solves = (int64_t)ns[0];
+    st->newton_iters = (int64_t)ns[1];
+    st->newton_failed = (int64_t)ns[2];
+    st->newton_max = (int32_t)ns[3];
+    st->cg_iters = cg[0];
+    st->cg_max = cg[1];
+    st->cg_failed = cg[2] + cg[4];
+    st->cg_solves = cg[3];
+    const int K = I->last_sweeps;
+    st->n_sweeps = K;
+    if (K > 0) {
+        std::vector<double> inc((size_t)K * I->NF * 2);
+        MISDC_HIP(hipMemcpy(inc.data(), I->inc, sizeof(double) * inc.size(), hipMemcpyDeviceToHost));
+        for (int k = 0; k < K && k < 64; ++k) {
+            double worst = 0.0;
+            for (int f = 0; f < I->NF; ++f) {
+                const double d = inc[((size_t)k * I->NF + f) * 2], a = inc[((size_t)k * I->NF + f) * 2 + 1];
+                const double rel = a > 0 ? d / a : d;
+                worst = rel > worst ? rel : worst;
+            }
+            st->sweep_increment[k] = worst;
+        }
+    }
+    return MISDC_OK;
+}
+
+}  // extern "C"

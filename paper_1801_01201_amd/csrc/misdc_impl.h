@@ -1,0 +1,158 @@
+// Internal declarations of the MI355X MISDC library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "misdc.h"
+
+namespace misdc {
+
+// ---- error handling -------------------------------------------------------
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+
+#define MISDC_HIP(call)                                                          \
+    do {                                                                         \
+        hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess)                                                    \
+            return ::misdc::fail(MISDC_EDEVICE, "%s failed: %s (%s:%d)", #call,  \
+                                 hipGetErrorString(e_), __FILE__, __LINE__);     \
+    } while (0)
+
+// ---- constants -------------------------------------------------------------
+constexpr double T_REF = 298.15;        // thermodynamic reference temperature
+constexpr double T_DIFF_REF = 300.0;    // reference of the (T/300)^1.7 law
+constexpr double THETA_EXP = 1.7;
+constexpr int MAX_NODES = 9;
+
+// ---- device mechanism tables (passed to kernels by value) ------------------
+struct MechDev {
+    int N, R, bath;
+    double rho0, p_atm, R_u, R_c, alpha0;
+    double newton_scale;          // mean of cp_k / W_k: enthalpy residual -> K
+    double ln_patm_over_Ru;       // ln(p_atm / R_u)
+    const int* slots;             // R x 4: reactant 0, reactant 1, product 0, product 1 (or -1)
+    const double* A;              // R
+    const double* beta;           // R
+    const double* Ta;             // R: Ea / R_c (K)
+    const double* dn;             // R: sum of net stoichiometric coefficients
+    const double* uW;             // R x N: nu_kj W_k / rho0 (dense net stoichiometry)
+    const double* W;              // N
+    const double* invW;           // N
+    const double* cp;             // N (molar)
+    const double* hf;             // N
+    const double* s0;             // N
+    const double* kappa0;         // N+1: D0_k, then alpha0
+};
+
+struct Mech {
+    MechDev dev;
+    int device = 0;
+    void* block = nullptr;        // one device allocation holding every table
+    std::vector<double> W, cp, hf, kappa0;   // host copies (for host-side checks)
+};
+
+// ---- grid ------------------------------------------------------------------
+struct Grid {
+    int dim = 1;                  // 1 or 2
+    int64_t nx = 0, ny = 1;       // single grid
+    double dx = 0, dy = 0, ux = 0, uy = 0;
+    int n_flames = 0;             // > 0: ensemble of 1-D flames
+    std::vector<int64_t> len, off;
+    std::vector<double> fdx, fu;
+    int64_t* d_off = nullptr;     // device copies for the ensemble (n_flames + 1)
+    double* d_dx = nullptr;
+    double* d_u = nullptr;
+    int64_t cells() const {
+        if (n_flames > 0) return off.back();
+        return nx * ny;
+    }
+};
+
+// ---- kernel launchers (stream-ordered, no synchronisation) -----------------
+int launch_enthalpy(const Mech& m, int64_t n, const double* Y, const double* T, double* h,
+                    hipStream_t s);
+int launch_temperature(const Mech& m, int64_t n, const double* Y, const double* h, double* T,
+                       hipStream_t s);
+int launch_reaction_source(const Mech& m, int64_t n, const double* Y, const double* h,
+                           double* FR, hipStream_t s);
+// state: N+1 fields (Y, h) with stride n; bY: N fields stride ldb;
+// c: per-cell array or nullptr with c_scalar.
+struct NewtonArgs {
+    int64_t n;
+    const double* bY; int64_t ldb;          // N fields
+    const double* h;                        // n
+    const double* c; double c_scalar;
+    const double* guess; int64_t ldg;       // N fields
+    double* Y; int64_t ldy;                 // N fields out
+    double* T;                              // n out (closed form of (Y, h)), may be null
+    double* FR; int64_t ldf;                // N fields out, may be null
+    int32_t* iters;                         // n out, may be null
+    unsigned long long* stats;              // [0] solves, [1] iters, [2] failed, [3] max; may be null
+    misdc_newton_opts opt;
+};
+int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s);
+
+// out[p] = sum_t W[p][t] X_t, field-wise; X_t has nf_t fields (missing fields are zero)
+constexpr int LC_MAX_TERMS = 32;
+constexpr int LC_MAX_OUT = 8;
+struct LinComb {
+    int nterms = 0, nout = 0, nfields = 0;
+    int64_t ncells = 0;
+    const double* X[LC_MAX_TERMS];
+    int nf[LC_MAX_TERMS];
+    double* out[LC_MAX_OUT];
+    double W[LC_MAX_OUT][LC_MAX_TERMS];
+};
+int launch_lincomb(const LinComb& lc, hipStream_t s);
+
+// T (cells) from a state with N+1 fields
+int launch_state_temperature(const Mech& m, int64_t n, const double* state, double* T, hipStream_t s);
+// FA and FD (N+1 fields) at a state whose temperature is T; either output may be null
+int launch_transport(const Mech& m, const Grid& g, const double* state, const double* T,
+                     double* FA, double* FD, double* work_theta, hipStream_t s);
+
+struct DiffusionWork {
+    double* theta = nullptr;      // cells
+    double* Kx = nullptr;         // cells: east-face coefficient / dx^2
+    double* Ky = nullptr;         // cells: north-face coefficient / dy^2
+    double* x = nullptr;          // N+1 fields (CG vectors, 2-D only)
+    double* r = nullptr;
+    double* z = nullptr;
+    double* p = nullptr;
+    double* q = nullptr;
+    double* partial = nullptr;    // blocks x fields x 4
+    unsigned* barrier = nullptr;  // 4 words
+    int32_t* info = nullptr;      // [0] iterations, [1] failed, [2] barrier timeout
+    int blocks = 0;
+    int threads = 0;
+    int fields_cap = 0;
+};
+int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g);
+void diffusion_work_free(DiffusionWork& w);
+// Solves all N+1 fields (bath by closure); y may hold the guess (guess_in_y)
+int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, double c,
+                           const double* dt_flame, double c_factor,
+                           const double* T_lag, const double* rhs, double* y, int guess_in_y,
+                           double rtol, int maxit, hipStream_t s);
+
+// max_i |a - b| and max_i |a| per field into out[2*f], out[2*f+1] (device)
+int launch_field_diff_max(int nfields, int64_t n, const double* a, const double* b,
+                          double* partial, int partial_blocks, double* out, hipStream_t s);
+
+// ---- host SDC tables -------------------------------------------------------
+struct Tables {
+    int M = 0;
+    double tau[MAX_NODES];
+    double Q[MAX_NODES][MAX_NODES + 1];
+    double QI[MAX_NODES][MAX_NODES];
+    double QE[MAX_NODES][MAX_NODES];
+    double S[MAX_NODES][MAX_NODES + 1];
+};
+int make_tables(int n_nodes, int qi_kind, int qe_mode, Tables& t);
+
+}  // namespace misdc

@@ -1,0 +1,691 @@
+// Transport kernels: explicit advection/diffusion operators, the linear
+// combinations that assemble the SDC right-hand sides, and the implicit
+// diffusion solves of steps S3/S4.
+//
+// All field arrays are structure of arrays (field-major, cells contiguous,
+// x fastest), so every kernel below reads and writes whole 512-byte
+// wavefront segments.  The 2-D implicit diffusion is a persistent
+// Jacobi-preconditioned conjugate-gradient kernel that solves all diffused
+// fields of one node at once and iterates on the device until every field
+// has converged: one launch per solve, two grid-wide barriers per
+// iteration, deterministic fixed-order reductions (so the result does not
+// depend on scheduling), and a grid sized to be fully co-resident.
+#include <cmath>
+
+#include "misdc_impl.h"
+
+namespace misdc {
+
+namespace {
+
+inline unsigned grid_for(int64_t n, int threads) {
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+// ---------------------------------------------------------------------------
+// linear combinations
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) lincomb_kernel(LinComb lc) {
+    const int64_t total = (int64_t)lc.nfields * lc.ncells;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int f = (int)(e / lc.ncells);
+        double acc[LC_MAX_OUT];
+#pragma unroll
+        for (int p = 0; p < LC_MAX_OUT; ++p) acc[p] = 0.0;
+        for (int t = 0; t < lc.nterms; ++t) {
+            if (f >= lc.nf[t]) continue;
+            const double v = lc.X[t][e];
+#pragma unroll
+            for (int p = 0; p < LC_MAX_OUT; ++p)
+                if (p < lc.nout) acc[p] += lc.W[p][t] * v;
+        }
+#pragma unroll
+        for (int p = 0; p < LC_MAX_OUT; ++p)
+            if (p < lc.nout) lc.out[p][e] = acc[p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// explicit operators
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) theta_kernel(int64_t n, const double* T, double* th) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) th[i] = pow(T[i] / T_DIFF_REF, THETA_EXP);
+}
+
+struct GridDev {
+    int dim;
+    int64_t nx, ny;
+    double dx, dy, ux, uy;
+    int n_flames;
+    const int64_t* off;     // ensemble: flame offsets (n_flames + 1)
+    const double* fdx;
+    const double* fu;
+};
+
+// neighbour index along x with periodic wrap inside the row (or the flame)
+struct Row {
+    int64_t base, len, pos;
+    double dx, u;
+};
+
+__device__ __forceinline__ int64_t wrap(int64_t k, int64_t len) {
+    k %= len;
+    return k < 0 ? k + len : k;
+}
+
+__device__ __forceinline__ Row row_of(const GridDev& g, int64_t i) {
+    Row r;
+    if (g.n_flames > 0) {
+        int lo = 0, hi = g.n_flames;           // find f with off[f] <= i < off[f+1]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (g.off[mid] <= i) lo = mid; else hi = mid;
+        }
+        r.base = g.off[lo];
+        r.len = g.off[lo + 1] - g.off[lo];
+        r.pos = i - r.base;
+        r.dx = g.fdx[lo];
+        r.u = g.fu[lo];
+    } else {
+        r.len = g.nx;
+        r.pos = i % g.nx;
+        r.base = i - r.pos;
+        r.dx = g.dx;
+        r.u = g.ux;
+    }
+    return r;
+}
+
+// FA and FD for every field of one cell.  FD of the bath species is minus the
+// sum of the other species' FD.
+__global__ void __launch_bounds__(256) transport_kernel(GridDev g, MechDev m, int64_t n,
+                                                        const double* st, const double* th,
+                                                        double* FA, double* FD) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Row r = row_of(g, i);
+    const int64_t xm2 = r.base + wrap(r.pos - 2, r.len), xm1 = r.base + wrap(r.pos - 1, r.len);
+    const int64_t xp1 = r.base + wrap(r.pos + 1, r.len), xp2 = r.base + wrap(r.pos + 2, r.len);
+    int64_t ym2 = 0, ym1 = 0, yp1 = 0, yp2 = 0;
+    const bool two_d = (g.dim == 2 && g.n_flames == 0);
+    if (two_d) {
+        const int64_t iy = i / g.nx, ix = i - iy * g.nx;
+        ym2 = wrap(iy - 2, g.ny) * g.nx + ix;
+        ym1 = wrap(iy - 1, g.ny) * g.nx + ix;
+        yp1 = wrap(iy + 1, g.ny) * g.nx + ix;
+        yp2 = wrap(iy + 2, g.ny) * g.nx + ix;
+    }
+    const double t0 = th[i];
+    const double idx2 = 1.0 / (r.dx * r.dx);
+    const double kxe = 0.5 * (t0 + th[xp1]) * idx2, kxw = 0.5 * (t0 + th[xm1]) * idx2;
+    double kyn = 0.0, kys = 0.0;
+    if (two_d) {
+        const double idy2 = 1.0 / (g.dy * g.dy);
+        kyn = 0.5 * (t0 + th[yp1]) * idy2;
+        kys = 0.5 * (t0 + th[ym1]) * idy2;
+    }
+    const double ax = r.u / r.dx;
+    const double ay = two_d ? g.uy / g.dy : 0.0;
+    double fd_sum = 0.0;
+    const int NF = m.N + 1;
+    for (int f = 0; f < NF; ++f) {
+        const double* p = st + (size_t)f * n;
+        const double c0 = p[i], w1 = p[xm1], w2 = p[xm2], e1 = p[xp1], e2 = p[xp2];
+        // fourth-order face values at i+1/2 and i-1/2
+        const double fe = (7.0 * (c0 + e1) - (w1 + e2)) / 12.0;
+        const double fw = (7.0 * (w1 + c0) - (w2 + e1)) / 12.0;
+        double fa = -ax * (fe - fw);
+        double lap = kxe * (e1 - c0) - kxw * (c0 - w1);
+        if (two_d) {
+            const double s1 = p[ym1], s2 = p[ym2], n1 = p[yp1], n2 = p[yp2];
+            const double fn = (7.0 * (c0 + n1) - (s1 + n2)) / 12.0;
+            const double fs = (7.0 * (s1 + c0) - (s2 + n1)) / 12.0;
+            if (ay != 0.0) fa -= ay * (fn - fs);
+            lap += kyn * (n1 - c0) - kys * (c0 - s1);
+        }
+        if (FA) FA[(size_t)f * n + i] = fa;
+        if (FD && f != m.bath) {
+            const double fd = m.kappa0[f] * lap;
+            FD[(size_t)f * n + i] = fd;
+            if (f < m.N) fd_sum += fd;
+        }
+    }
+    if (FD) FD[(size_t)m.bath * n + i] = -fd_sum;
+}
+
+// ---------------------------------------------------------------------------
+// implicit diffusion
+// ---------------------------------------------------------------------------
+
+// face coefficients of the lagged operator: Kx[i] = east face / dx^2, Ky[i] =
+// north face / dy^2, both from theta = (T_lag/300)^1.7.
+__global__ void __launch_bounds__(256) faces_kernel(GridDev g, int64_t n, const double* T,
+                                                    double* th, double* Kx, double* Ky) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Row r = row_of(g, i);
+    const int64_t xp1 = r.base + wrap(r.pos + 1, r.len);
+    const double t0 = pow(T[i] / T_DIFF_REF, THETA_EXP);
+    const double t1 = pow(T[xp1] / T_DIFF_REF, THETA_EXP);
+    th[i] = t0;
+    Kx[i] = 0.5 * (t0 + t1) / (r.dx * r.dx);
+    if (g.dim == 2 && g.n_flames == 0) {
+        const int64_t iy = i / g.nx, ix = i - iy * g.nx;
+        const int64_t yp1 = wrap(iy + 1, g.ny) * g.nx + ix;
+        const double t2 = pow(T[yp1] / T_DIFF_REF, THETA_EXP);
+        Ky[i] = 0.5 * (t0 + t2) / (g.dy * g.dy);
+    }
+}
+
+// Cyclic tridiagonal solve of (I - cf L) y = r on one periodic 1-D system per
+// thread: Thomas' algorithm on the tridiagonal part plus a Sherman-Morrison
+// correction for the two corner entries.  Work arrays w1, w2 (same layout as
+// y) hold the modified super-diagonal and the correction vector.
+__global__ void __launch_bounds__(64) cyclic_kernel(GridDev g, MechDev m, int64_t n, double c,
+                                                    const double* dtf, double cfac,
+                                                    const double* Kx, const double* rhs,
+                                                    double* y, double* w1, double* w2) {
+    const int nsys_f = g.n_flames > 0 ? g.n_flames : 1;
+    const int fields = m.N + 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsys_f * fields) return;
+    const int f = t / nsys_f, fl = t % nsys_f;
+    if (f == m.bath) return;
+    const int64_t base = g.n_flames > 0 ? g.off[fl] : 0;
+    const int64_t len = g.n_flames > 0 ? g.off[fl + 1] - g.off[fl] : n;
+    const double cc = (dtf ? dtf[fl] * cfac : c) * m.kappa0[f];
+    const double* b = rhs + (size_t)f * n + base;
+    double* x = y + (size_t)f * n + base;
+    double* cp = w1 + (size_t)f * n + base;
+    double* u = w2 + (size_t)f * n + base;
+    const double* K = Kx + base;
+    // row i: -cc Kw y_{i-1} + (1 + cc (Kw + Ke)) y_i - cc Ke y_{i+1}
+    auto sub = [&](int64_t i) { return -cc * K[(i - 1 + len) % len]; };   // a_i
+    auto sup = [&](int64_t i) { return -cc * K[i]; };                     // c_i
+    auto dia = [&](int64_t i) { return 1.0 + cc * (K[(i - 1 + len) % len] + K[i]); };
+    if (len == 1) { x[0] = b[0]; return; }
+    const double a0 = sub(0), cN = sup(len - 1);
+    const double gam = -dia(0);
+    // modified diagonal: d0 - gam, d_{n-1} - a0 cN / gam
+    // forward sweep for two right-hand sides: b and the vector (gam, 0, .., cN)
+    double dprev = dia(0) - gam;
+    double cprev = sup(0) / dprev;
+    cp[0] = cprev;
+    x[0] = b[0] / dprev;
+    u[0] = gam / dprev;
+    for (int64_t i = 1; i < len; ++i) {
+        double d = dia(i);
+        if (i == len - 1) d -= a0 * cN / gam;
+        const double ai = sub(i);
+        const double den = d - ai * cprev;
+        const double rb = b[i];
+        const double ru = (i == len - 1) ? cN : 0.0;
+        x[i] = (rb - ai * x[i - 1]) / den;
+        u[i] = (ru - ai * u[i - 1]) / den;
+        cprev = (i < len - 1) ? sup(i) / den : 0.0;
+        cp[i] = cprev;
+    }
+    for (int64_t i = len - 2; i >= 0; --i) {
+        x[i] -= cp[i] * x[i + 1];
+        u[i] -= cp[i] * u[i + 1];
+    }
+    // v = (1, 0, ..., 0, a0 / gam)
+    const double vy = x[0] + a0 / gam * x[len - 1];
+    const double vu = u[0] + a0 / gam * u[len - 1];
+    const double fct = vy / (1.0 + vu);
+    for (int64_t i = 0; i < len; ++i) x[i] -= fct * u[i];
+}
+
+// bath closure y_i0 = r_i0 - sum_{k != i0, k < N} (y_k - r_k)
+__global__ void __launch_bounds__(256) closure_kernel(MechDev m, int64_t n, const double* rhs,
+                                                      double* y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < m.N; ++k)
+        if (k != m.bath) s += y[(size_t)k * n + i] - rhs[(size_t)k * n + i];
+    y[(size_t)m.bath * n + i] = rhs[(size_t)m.bath * n + i] - s;
+}
+
+// ---- grid-wide barrier for the persistent CG kernel -------------------------
+// bar[0]: arrival counter, bar[1]: generation.  Every thread publishes its
+// stores with an agent-scope release fence before the workgroup barrier; the
+// last workgroup to arrive resets the counter and bumps the generation; the
+// others wait (bounded spin: after the limit the kernel records a timeout in
+// info[2] and proceeds, so every wave always terminates).
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, int32_t* info) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1u << 26)) {
+                    __hip_atomic_store(&info[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+constexpr int CG_THREADS = 256;
+constexpr int CG_MAX_FIELDS = 64;
+
+struct CGArgs {
+    int64_t n;              // cells
+    int nx, ny;
+    int nf;                 // diffused fields (all but the bath)
+    int fmap[CG_MAX_FIELDS];// field index of diffused field d
+    double cf[CG_MAX_FIELDS];// c * kappa0_f
+    const double* Kx;
+    const double* Ky;
+    const double* b;        // rhs (N+1 fields)
+    double* x;              // solution (N+1 fields, bath untouched)
+    double* r;
+    double* z;
+    double* p;
+    double* q;
+    double* partial;        // blocks x nf x 4
+    unsigned* bar;
+    int32_t* info;          // [0] iterations, [1] failed, [2] barrier timeout
+    double rtol2;
+    int maxit;
+    int guess_in_x;
+};
+
+// A_f v at cell i: v_i - cf (Ke (v_E - v_i) - Kw (v_i - v_W) + Kn (...) - Ks (...))
+__device__ __forceinline__ void stencil_at(const CGArgs& a, int64_t i, int64_t& e, int64_t& w,
+                                           int64_t& nn, int64_t& s, double& ke, double& kw,
+                                           double& kn, double& ks) {
+    const int64_t iy = i / a.nx, ix = i - iy * a.nx;
+    e = iy * a.nx + (ix + 1 == a.nx ? 0 : ix + 1);
+    w = iy * a.nx + (ix == 0 ? a.nx - 1 : ix - 1);
+    nn = (iy + 1 == a.ny ? 0 : iy + 1) * a.nx + ix;
+    s = (iy == 0 ? a.ny - 1 : iy - 1) * a.nx + ix;
+    ke = a.Kx[i];
+    kw = a.Kx[w];
+    kn = a.Ky[i];
+    ks = a.Ky[s];
+}
+
+// Wave-level sum, lane 0 stores the wave's value into red[slot * nw + wave].
+__device__ __forceinline__ void wave_store(double v, double* red, int slot) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) red[slot * (CG_THREADS / 64) + (threadIdx.x >> 6)] = v;
+}
+
+// After __syncthreads: sum the wave values of every slot in a fixed order and
+// write this block's partials to global memory.
+__device__ __forceinline__ void block_publish(const double* red, int nslots, double* partial) {
+    for (int t = threadIdx.x; t < nslots; t += CG_THREADS) {
+        double s = 0.0;
+        for (int k = 0; k < CG_THREADS / 64; ++k) s += red[t * (CG_THREADS / 64) + k];
+        partial[(size_t)blockIdx.x * (CG_MAX_FIELDS * 4) + t] = s;
+    }
+}
+
+// Sum of the partials of every block for slots [0, nslots): each wave handles
+// a subset of slots, its lanes stride over the blocks, fixed order -> every
+// block obtains bitwise the same totals.
+__device__ __forceinline__ void grid_totals(const double* partial, int nslots, double* tot) {
+    const int nb = gridDim.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = wave; t < nslots; t += CG_THREADS / 64) {
+        double s = 0.0;
+        for (int b = lane; b < nb; b += 64) s += partial[(size_t)b * (CG_MAX_FIELDS * 4) + t];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) tot[t] = s;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(CG_THREADS) cg_kernel(CGArgs a) {
+    // slot layout: slot = field * 4 + value
+    __shared__ double red[CG_MAX_FIELDS * 4 * (CG_THREADS / 64)];
+    __shared__ double tot[CG_MAX_FIELDS * 4];
+    __shared__ double s_rz[CG_MAX_FIELDS], s_bb[CG_MAX_FIELDS], s_alpha[CG_MAX_FIELDS],
+        s_beta[CG_MAX_FIELDS];
+    __shared__ int s_active[CG_MAX_FIELDS];
+    __shared__ int s_any;
+    const unsigned nb = gridDim.x;
+    const int64_t stride = (int64_t)gridDim.x * CG_THREADS;
+    const int64_t i0 = (int64_t)blockIdx.x * CG_THREADS + threadIdx.x;
+    const int nf = a.nf;
+
+    // ---- r = b - A x0, z = D^{-1} r; partials rz, rr, bb ----
+    for (int d = 0; d < nf; ++d) {
+        const size_t o = (size_t)a.fmap[d] * a.n;
+        const double* X = a.guess_in_x ? a.x + o : a.b + o;
+        const double cf = a.cf[d];
+        double rz = 0.0, rr = 0.0, bb = 0.0;
+        for (int64_t i = i0; i < a.n; i += stride) {
+            int64_t e, w, nn, s;
+            double ke, kw, kn, ks;
+            stencil_at(a, i, e, w, nn, s, ke, kw, kn, ks);
+            const double xi = X[i];
+            const double Ax = xi - cf * (ke * (X[e] - xi) - kw * (xi - X[w]) + kn * (X[nn] - xi) -
+                                         ks * (xi - X[s]));
+            const double bi = a.b[o + i];
+            const double ri = bi - Ax;
+            const double zi = ri / (1.0 + cf * (ke + kw + kn + ks));
+            a.r[o + i] = ri;
+            a.z[o + i] = zi;
+            if (!a.guess_in_x) a.x[o + i] = xi;
+            rz += ri * zi;
+            rr += ri * ri;
+            bb += bi * bi;
+        }
+        wave_store(rz, red, d * 4 + 0);
+        wave_store(rr, red, d * 4 + 1);
+        wave_store(bb, red, d * 4 + 2);
+    }
+    __syncthreads();
+    block_publish(red, nf * 4, a.partial);
+    grid_barrier(a.bar, nb, a.info);
+    grid_totals(a.partial, nf * 4, tot);
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < nf; ++d) {
+            s_rz[d] = tot[d * 4 + 0];
+            s_bb[d] = tot[d * 4 + 2];
+            s_active[d] = tot[d * 4 + 1] > a.rtol2 * s_bb[d];
+            s_beta[d] = 0.0;
+        }
+    }
+    __syncthreads();
+    int it = 0;
+    for (; it < a.maxit; ++it) {
+        if (threadIdx.x == 0) {
+            int any = 0;
+            for (int d = 0; d < nf; ++d) any |= s_active[d];
+            s_any = any;
+        }
+        __syncthreads();
+        if (!s_any) break;
+        // ---- p = z + beta p ; q = A z + beta q  (so q = A p) ; partial pq ----
+        for (int d = 0; d < nf; ++d) {
+            double pq = 0.0;
+            if (s_active[d]) {
+                const size_t o = (size_t)a.fmap[d] * a.n;
+                const double* Z = a.z + o;
+                const double cf = a.cf[d];
+                const double be = s_beta[d];
+                for (int64_t i = i0; i < a.n; i += stride) {
+                    int64_t e, w, nn, s;
+                    double ke, kw, kn, ks;
+                    stencil_at(a, i, e, w, nn, s, ke, kw, kn, ks);
+                    const double zi = Z[i];
+                    const double Az = zi - cf * (ke * (Z[e] - zi) - kw * (zi - Z[w]) +
+                                                 kn * (Z[nn] - zi) - ks * (zi - Z[s]));
+                    const double pi = (it == 0) ? zi : zi + be * a.p[o + i];
+                    const double qi = (it == 0) ? Az : Az + be * a.q[o + i];
+                    a.p[o + i] = pi;
+                    a.q[o + i] = qi;
+                    pq += pi * qi;
+                }
+            }
+            wave_store(pq, red, d * 4 + 0);
+        }
+        __syncthreads();
+        block_publish(red, nf * 4, a.partial);
+        grid_barrier(a.bar, nb, a.info);
+        grid_totals(a.partial, nf * 4, tot);
+        if (threadIdx.x == 0)
+            for (int d = 0; d < nf; ++d) s_alpha[d] = s_active[d] ? s_rz[d] / tot[d * 4 + 0] : 0.0;
+        __syncthreads();
+        // ---- x += alpha p ; r -= alpha q ; z = D^{-1} r ; partials rz, rr ----
+        for (int d = 0; d < nf; ++d) {
+            double rz = 0.0, rr = 0.0;
+            if (s_active[d]) {
+                const size_t o = (size_t)a.fmap[d] * a.n;
+                const double al = s_alpha[d];
+                const double cf = a.cf[d];
+                for (int64_t i = i0; i < a.n; i += stride) {
+                    const int64_t iy = i / a.nx, ix = i - iy * a.nx;
+                    const int64_t w = iy * a.nx + (ix == 0 ? a.nx - 1 : ix - 1);
+                    const int64_t s = (iy == 0 ? a.ny - 1 : iy - 1) * a.nx + ix;
+                    const double ksum = a.Kx[i] + a.Kx[w] + a.Ky[i] + a.Ky[s];
+                    a.x[o + i] += al * a.p[o + i];
+                    const double ri = a.r[o + i] - al * a.q[o + i];
+                    const double zi = ri / (1.0 + cf * ksum);
+                    a.r[o + i] = ri;
+                    a.z[o + i] = zi;
+                    rz += ri * zi;
+                    rr += ri * ri;
+                }
+            }
+            wave_store(rz, red, d * 4 + 0);
+            wave_store(rr, red, d * 4 + 1);
+        }
+        __syncthreads();
+        block_publish(red, nf * 4, a.partial);
+        grid_barrier(a.bar, nb, a.info);
+        grid_totals(a.partial, nf * 4, tot);
+        if (threadIdx.x == 0)
+            for (int d = 0; d < nf; ++d) {
+                if (!s_active[d]) continue;
+                const double rz_new = tot[d * 4 + 0];
+                s_beta[d] = rz_new / s_rz[d];
+                s_rz[d] = rz_new;
+                s_active[d] = tot[d * 4 + 1] > a.rtol2 * s_bb[d];
+            }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.info[0] = it;
+        int any = 0;
+        for (int d = 0; d < nf; ++d) any |= s_active[d];
+        a.info[1] = any;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) diffmax_kernel(int nfields, int64_t n, const double* a,
+                                                      const double* b, double* partial) {
+    __shared__ double sd[4], sa[4];
+    const int f = blockIdx.y;
+    double md = 0.0, ma = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double va = a[(size_t)f * n + i];
+        md = fmax(md, fabs(va - b[(size_t)f * n + i]));
+        ma = fmax(ma, fabs(va));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        md = fmax(md, __shfl_xor(md, off));
+        ma = fmax(ma, __shfl_xor(ma, off));
+    }
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    if (lane == 0) { sd[wave] = md; sa[wave] = ma; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        md = 0.0;
+        ma = 0.0;
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) {
+            md = fmax(md, sd[w]);
+            ma = fmax(ma, sa[w]);
+        }
+        partial[((size_t)f * gridDim.x + blockIdx.x) * 2 + 0] = md;
+        partial[((size_t)f * gridDim.x + blockIdx.x) * 2 + 1] = ma;
+    }
+}
+
+__global__ void diffmax_final(int nfields, int nblocks, const double* partial, double* out) {
+    const int f = threadIdx.x;
+    if (f >= nfields) return;
+    double md = 0.0, ma = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        md = fmax(md, partial[((size_t)f * nblocks + b) * 2 + 0]);
+        ma = fmax(ma, partial[((size_t)f * nblocks + b) * 2 + 1]);
+    }
+    out[2 * f] = md;
+    out[2 * f + 1] = ma;
+}
+
+GridDev grid_dev(const Grid& g) {
+    GridDev d;
+    d.dim = g.dim;
+    d.nx = g.n_flames > 0 ? g.cells() : g.nx;
+    d.ny = g.n_flames > 0 ? 1 : g.ny;
+    d.dx = g.dx;
+    d.dy = g.dy;
+    d.ux = g.ux;
+    d.uy = g.uy;
+    d.n_flames = g.n_flames;
+    d.off = g.d_off;
+    d.fdx = g.d_dx;
+    d.fu = g.d_u;
+    return d;
+}
+
+}  // namespace
+
+int launch_lincomb(const LinComb& lc, hipStream_t s) {
+    const int64_t total = (int64_t)lc.nfields * lc.ncells;
+    if (total == 0) return MISDC_OK;
+    if (lc.nterms > LC_MAX_TERMS || lc.nout > LC_MAX_OUT || lc.nout < 1)
+        return fail(MISDC_EINVAL, "linear combination too large (%d terms, %d outputs)", lc.nterms,
+                    lc.nout);
+    unsigned blocks = grid_for(total, 256);
+    if (blocks > 65536u) blocks = 65536u;
+    hipLaunchKernelGGL(lincomb_kernel, dim3(blocks), dim3(256), 0, s, lc);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+int launch_transport(const Mech& m, const Grid& g, const double* state, const double* T,
+                     double* FA, double* FD, double* work_theta, hipStream_t s) {
+    const int64_t n = g.cells();
+    if (n == 0) return MISDC_OK;
+    hipLaunchKernelGGL(theta_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, n, T, work_theta);
+    MISDC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(transport_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, grid_dev(g),
+                       m.dev, n, state, work_theta, FA, FD);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
+    const int64_t n = g.cells();
+    const int NF = m.dev.N + 1;
+    if (NF - 1 > CG_MAX_FIELDS)
+        return fail(MISDC_EUNSUPPORTED, "at most %d diffused fields, got %d", CG_MAX_FIELDS, NF - 1);
+    size_t cells_bytes = (size_t)n * sizeof(double);
+    MISDC_HIP(hipMalloc(&w.theta, cells_bytes));
+    MISDC_HIP(hipMalloc(&w.Kx, cells_bytes));
+    MISDC_HIP(hipMalloc(&w.Ky, cells_bytes));
+    MISDC_HIP(hipMemset(w.Ky, 0, cells_bytes));
+    MISDC_HIP(hipMalloc(&w.x, cells_bytes * NF));
+    MISDC_HIP(hipMalloc(&w.r, cells_bytes * NF));
+    MISDC_HIP(hipMalloc(&w.z, cells_bytes * NF));
+    MISDC_HIP(hipMalloc(&w.p, cells_bytes * NF));
+    MISDC_HIP(hipMalloc(&w.q, cells_bytes * NF));
+    int dev = 0, cus = 0, per = 0;
+    MISDC_HIP(hipGetDevice(&dev));
+    MISDC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cg_kernel, CG_THREADS, 0));
+    if (per < 1)
+        return fail(MISDC_EDEVICE, "CG kernel cannot be resident (occupancy %d)", per);
+    // one resident block per CU: co-residency of the whole grid is guaranteed
+    // even while other kernels occupy part of each CU
+    int blocks = cus;
+    const int64_t need = (n + CG_THREADS - 1) / CG_THREADS;
+    if (blocks > need) blocks = (int)need;
+    if (blocks < 1) blocks = 1;
+    w.blocks = blocks;
+    w.threads = CG_THREADS;
+    MISDC_HIP(hipMalloc(&w.partial, sizeof(double) * (size_t)blocks * CG_MAX_FIELDS * 4));
+    MISDC_HIP(hipMalloc(&w.barrier, sizeof(unsigned) * 4));
+    MISDC_HIP(hipMemset(w.barrier, 0, sizeof(unsigned) * 4));
+    MISDC_HIP(hipMalloc(&w.info, sizeof(int32_t) * 4));
+    MISDC_HIP(hipMemset(w.info, 0, sizeof(int32_t) * 4));
+    w.fields_cap = NF;
+    return MISDC_OK;
+}
+
+void diffusion_work_free(DiffusionWork& w) {
+    double* ptrs[] = {w.theta, w.Kx, w.Ky, w.x, w.r, w.z, w.p, w.q, w.partial};
+    for (double* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (w.barrier) (void)hipFree(w.barrier);
+    if (w.info) (void)hipFree(w.info);
+    w = DiffusionWork();
+}
+
+int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, double c,
+                           const double* dt_flame, double c_factor, const double* T_lag,
+                           const double* rhs, double* y, int guess_in_y, double rtol, int maxit,
+                           hipStream_t s) {
+    const int64_t n = g.cells();
+    if (n == 0) return MISDC_OK;
+    const GridDev gd = grid_dev(g);
+    hipLaunchKernelGGL(faces_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, gd, n, T_lag,
+                       w.theta, w.Kx, w.Ky);
+    MISDC_HIP(hipGetLastError());
+    const int NF = m.dev.N + 1;
+    if (g.dim == 1 || g.n_flames > 0) {
+        const int nsys = (g.n_flames > 0 ? g.n_flames : 1) * NF;
+        hipLaunchKernelGGL(cyclic_kernel, dim3(grid_for(nsys, 64)), dim3(64), 0, s, gd, m.dev, n,
+                           c, dt_flame, c_factor, w.Kx, rhs, y, w.r, w.z);
+        MISDC_HIP(hipGetLastError());
+    } else {
+        CGArgs a;
+        a.n = n;
+        a.nx = (int)g.nx;
+        a.ny = (int)g.ny;
+        a.nf = 0;
+        for (int f = 0; f < NF; ++f) {
+            if (f == m.dev.bath) continue;
+            a.fmap[a.nf] = f;
+            a.cf[a.nf] = c * m.kappa0[f];
+            ++a.nf;
+        }
+        a.Kx = w.Kx;
+        a.Ky = w.Ky;
+        a.b = rhs;
+        a.x = y;
+        a.r = w.r;
+        a.z = w.z;
+        a.p = w.p;
+        a.q = w.q;
+        a.partial = w.partial;
+        a.bar = w.barrier;
+        a.info = w.info;
+        const double rt = rtol > 0 ? rtol : 1e-13;
+        a.rtol2 = rt * rt;
+        a.maxit = maxit > 0 ? maxit : 500;
+        a.guess_in_x = guess_in_y;
+        hipLaunchKernelGGL(cg_kernel, dim3(w.blocks), dim3(CG_THREADS), 0, s, a);
+        MISDC_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(closure_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, n, rhs, y);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+int launch_field_diff_max(int nfields, int64_t n, const double* a, const double* b,
+                          double* partial, int partial_blocks, double* out, hipStream_t s) {
+    if (n == 0) return MISDC_OK;
+    hipLaunchKernelGGL(diffmax_kernel, dim3(partial_blocks, nfields), dim3(256), 0, s, nfields, n,
+                       a, b, partial);
+    MISDC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(diffmax_final, dim3(1), dim3(64), 0, s, nfields, partial_blocks, partial,
+                       out);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+}  // namespace misdc

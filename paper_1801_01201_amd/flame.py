@@ -1,0 +1,94 @@
+"""Flame workloads on the GPU: handles for a mechanism and a grid, the
+initial state, and the integrator.  Thin wrappers over the C ABI; all
+arithmetic runs in the library's kernels.
+"""
+import numpy as np
+
+from . import native as nat
+
+# Length of the backward-Euler reaction solve that relaxes the synthetic
+# initial composition onto the fast chemical manifold (s).
+RELAX_TIME = 1.0
+
+
+class Mechanism:
+    def __init__(self, mech):
+        self.desc = mech
+        self.N = int(mech["N"])
+        self.handle = nat.misdc_mech_create(mech)
+
+    def close(self):
+        if self.handle:
+            nat.misdc_mech_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Grid:
+    def __init__(self, dim=None, n=None, dx=None, u=None, ensemble=None):
+        if ensemble is not None:
+            lengths, dxs, us = ensemble
+            self.handle = nat.misdc_grid_create_ensemble(lengths, dxs, us)
+            self.cells = int(np.sum(lengths))
+        else:
+            self.handle = nat.misdc_grid_create(dim, n, dx, u)
+            self.cells = int(np.prod(n))
+
+    def close(self):
+        if self.handle:
+            nat.misdc_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def initial_state(mech, Y, T, relax_time=RELAX_TIME, stream=None):
+    """State (N+1, cells) on the device from synthetic (Y, T) device tensors:
+    h = enthalpy(Y, T), then one constant-enthalpy backward-Euler reaction
+    solve of length ``relax_time`` started from Y.  Returns (state, iters)."""
+    import torch
+    N = mech.N
+    n = T.numel()
+    Yc = Y.reshape(N, n).contiguous()
+    state = torch.empty((N + 1, n), dtype=torch.float64, device=Y.device)
+    nat.misdc_enthalpy(mech.handle, n, Yc, T.reshape(n).contiguous(), state[N], stream)
+    state[:N].copy_(Yc)
+    c = torch.full((n,), float(relax_time), dtype=torch.float64, device=Y.device)
+    iters = torch.empty(n, dtype=torch.int32, device=Y.device)
+    bY = Yc.clone()
+    nat.misdc_reaction_solve_batch(mech.handle, n, bY, state[N], c, state[:N], None, None, iters,
+                                   stream=stream)
+    return state, iters
+
+
+class Integrator:
+    def __init__(self, mech, grid, **opts):
+        self.mech, self.grid = mech, grid
+        self.opts = nat.make_opts(**opts)
+        self.handle = nat.misdc_integ_create(mech.handle, grid.handle, self.opts)
+
+    def step(self, state, dt, stream=None):
+        nat.misdc_step(self.handle, state, dt, None, stream)
+
+    def stats(self):
+        return nat.misdc_get_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            nat.misdc_integ_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

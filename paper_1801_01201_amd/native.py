@@ -1,0 +1,293 @@
+"""ctypes binding of libmisdc.so (argument marshalling only).
+
+Every function of the C ABI (include/misdc.h) is exposed under the same name;
+torch tensors are passed as device pointers and torch streams as hipStream_t.
+No arithmetic of the method happens here: every step runs in the library's
+HIP kernels.  Importing this module raises if the library has not been
+built; nothing falls back to another implementation.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmisdc.so")
+
+MISDC_OK = 0
+MISDC_EINVAL = -1
+MISDC_ENOMEM = -2
+MISDC_EDEVICE = -3
+MISDC_ENOTCONV = -4
+MISDC_EUNSUPPORTED = -5
+SCHEME = {"misdc": 0, "misdcq": 1, "cisdcq": 2}
+QE = {"cumulative": 0, "literal": 1}
+QI = {"lu": 0, "be": 1}
+
+EXPORTED = [
+    "misdc_last_error", "misdc_version", "misdc_sdc_tables", "misdc_mech_create",
+    "misdc_mech_destroy", "misdc_mech_species", "misdc_enthalpy", "misdc_temperature",
+    "misdc_reaction_source", "misdc_reaction_solve_batch", "misdc_grid_create",
+    "misdc_grid_create_ensemble", "misdc_grid_destroy", "misdc_grid_cells",
+    "misdc_transport_operators", "misdc_diffusion_solve", "misdc_opts_default",
+    "misdc_integ_create", "misdc_integ_destroy", "misdc_step", "misdc_get_stats",
+]
+
+
+class MisdcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"misdc error {code}: {msg}")
+        self.code = code
+
+
+class misdc_mech_desc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32), ("bath", C.c_int32),
+                ("W", C.c_void_p), ("react", C.c_void_p), ("prod", C.c_void_p),
+                ("A", C.c_void_p), ("beta", C.c_void_p), ("Ea", C.c_void_p),
+                ("cp", C.c_void_p), ("hf", C.c_void_p), ("s0", C.c_void_p), ("D0", C.c_void_p),
+                ("alpha0", C.c_double), ("rho0", C.c_double), ("p_atm", C.c_double),
+                ("R_u", C.c_double), ("R_c", C.c_double)]
+
+
+class misdc_newton_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("dtau0", C.c_double),
+                ("dtau_max", C.c_double), ("neg_slack", C.c_double)]
+
+
+class misdc_opts(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_sweeps", C.c_int32), ("nu", C.c_int32),
+                ("scheme", C.c_int32), ("qe_mode", C.c_int32), ("serialize", C.c_int32),
+                ("newton", misdc_newton_opts), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32)]
+
+
+class misdc_stats(C.Structure):
+    _fields_ = [("newton_solves", C.c_int64), ("newton_iters", C.c_int64),
+                ("newton_max", C.c_int32), ("newton_failed", C.c_int64),
+                ("cg_solves", C.c_int64), ("cg_iters", C.c_int64), ("cg_max", C.c_int32),
+                ("cg_failed", C.c_int32), ("n_sweeps", C.c_int32),
+                ("sweep_increment", C.c_double * 64), ("ms_diffusion", C.c_double),
+                ("ms_reaction", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "sweep_increment"}
+        d["sweep_increment"] = list(self.sweep_increment[:self.n_sweeps])
+        return d
+
+
+def load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run paper_1801_01201_amd.build.build()")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "misdc_last_error": (C.c_char_p, []),
+        "misdc_version": (C.c_char_p, []),
+        "misdc_sdc_tables": (C.c_int, [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp]),
+        "misdc_mech_create": (C.c_int, [C.POINTER(misdc_mech_desc), C.POINTER(vp)]),
+        "misdc_mech_destroy": (C.c_int, [vp]),
+        "misdc_mech_species": (C.c_int, [vp, C.POINTER(i32)]),
+        "misdc_enthalpy": (C.c_int, [vp, i64, vp, vp, vp, vp]),
+        "misdc_temperature": (C.c_int, [vp, i64, vp, vp, vp, vp]),
+        "misdc_reaction_source": (C.c_int, [vp, i64, vp, vp, vp, vp]),
+        "misdc_reaction_solve_batch": (C.c_int, [vp, i64, vp, vp, vp, vp, vp, vp, vp,
+                                                 C.POINTER(misdc_newton_opts), vp]),
+        "misdc_grid_create": (C.c_int, [C.c_int, vp, vp, vp, C.POINTER(vp)]),
+        "misdc_grid_create_ensemble": (C.c_int, [C.c_int, vp, vp, vp, C.POINTER(vp)]),
+        "misdc_grid_destroy": (C.c_int, [vp]),
+        "misdc_grid_cells": (C.c_int, [vp, C.POINTER(i64)]),
+        "misdc_transport_operators": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "misdc_diffusion_solve": (C.c_int, [vp, vp, dbl, vp, vp, vp, C.c_int, dbl, C.c_int,
+                                            vp, vp]),
+        "misdc_opts_default": (None, [C.POINTER(misdc_opts)]),
+        "misdc_integ_create": (C.c_int, [vp, vp, C.POINTER(misdc_opts), C.POINTER(vp)]),
+        "misdc_integ_destroy": (C.c_int, [vp]),
+        "misdc_step": (C.c_int, [vp, vp, dbl, vp, vp]),
+        "misdc_get_stats": (C.c_int, [vp, C.POINTER(misdc_stats)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB
+
+
+def check(code):
+    if code != MISDC_OK:
+        raise MisdcError(code, lib().misdc_last_error().decode())
+    return code
+
+
+def _ptr(t):
+    """Device (or host numpy) pointer of a tensor/array; None stays NULL."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# C ABI, same names
+# ---------------------------------------------------------------------------
+def misdc_version():
+    return lib().misdc_version().decode()
+
+
+def misdc_sdc_tables(n_nodes, qi="lu", qe="cumulative"):
+    M = n_nodes - 1
+    out = dict(tau=np.zeros(M + 1), Q=np.zeros((M, M + 1)), QI=np.zeros((M, M)),
+               QE=np.zeros((M, M)), S=np.zeros((M, M + 1)))
+    check(lib().misdc_sdc_tables(n_nodes, QI[qi], QE[qe], _ptr(out["tau"]), _ptr(out["Q"]),
+                                 _ptr(out["QI"]), _ptr(out["QE"]), _ptr(out["S"])))
+    return out
+
+
+def misdc_mech_create(mech):
+    """mech: dict in the generator's format (host arrays)."""
+    keep = {}
+
+    def arr(key, dtype):
+        a = np.ascontiguousarray(np.asarray(mech[key], dtype=dtype))
+        keep[key] = a
+        return a.ctypes.data
+
+    d = misdc_mech_desc()
+    d.n_species = int(mech["N"])
+    d.n_reactions = int(mech["R"])
+    d.bath = int(mech["bath"])
+    d.W = arr("W", np.float64)
+    d.react = arr("react", np.int32)
+    d.prod = arr("prod", np.int32)
+    for k in ("A", "beta", "Ea", "cp", "hf", "s0", "D0"):
+        setattr(d, k, arr(k, np.float64))
+    d.alpha0 = float(mech["alpha0"])
+    d.rho0 = float(mech["rho0"])
+    d.p_atm = float(mech["p_atm"])
+    d.R_u = float(mech["R_u"])
+    d.R_c = float(mech["R_c"])
+    h = C.c_void_p()
+    check(lib().misdc_mech_create(C.byref(d), C.byref(h)))
+    return h.value
+
+
+def misdc_mech_destroy(h):
+    check(lib().misdc_mech_destroy(h))
+
+
+def misdc_enthalpy(mech, n, Y, T, h, stream=None):
+    check(lib().misdc_enthalpy(mech, n, _ptr(Y), _ptr(T), _ptr(h), _stream(stream)))
+
+
+def misdc_temperature(mech, n, Y, h, T, stream=None):
+    check(lib().misdc_temperature(mech, n, _ptr(Y), _ptr(h), _ptr(T), _stream(stream)))
+
+
+def misdc_reaction_source(mech, n, Y, h, FR, stream=None):
+    check(lib().misdc_reaction_source(mech, n, _ptr(Y), _ptr(h), _ptr(FR), _stream(stream)))
+
+
+def newton_opts(tol=0.0, maxit=0, dtau0=0.0, dtau_max=0.0, neg_slack=0.0):
+    return misdc_newton_opts(tol, maxit, dtau0, dtau_max, neg_slack)
+
+
+def misdc_reaction_solve_batch(mech, n, bY, h, c, Y, T_out=None, FR_out=None, iters=None,
+                               opts=None, stream=None):
+    o = opts if opts is not None else newton_opts()
+    check(lib().misdc_reaction_solve_batch(mech, n, _ptr(bY), _ptr(h), _ptr(c), _ptr(Y),
+                                           _ptr(T_out), _ptr(FR_out), _ptr(iters), C.byref(o),
+                                           _stream(stream)))
+
+
+def misdc_grid_create(dim, n, dx, u):
+    nn = np.asarray(n, dtype=np.int64)
+    dd = np.asarray(dx, dtype=np.float64)
+    uu = np.asarray(u, dtype=np.float64)
+    h = C.c_void_p()
+    check(lib().misdc_grid_create(dim, _ptr(nn), _ptr(dd), _ptr(uu), C.byref(h)))
+    return h.value
+
+
+def misdc_grid_create_ensemble(lengths, dx, u):
+    ll = np.ascontiguousarray(lengths, dtype=np.int64)
+    dd = np.ascontiguousarray(dx, dtype=np.float64)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    h = C.c_void_p()
+    check(lib().misdc_grid_create_ensemble(len(ll), _ptr(ll), _ptr(dd), _ptr(uu), C.byref(h)))
+    return h.value
+
+
+def misdc_grid_destroy(h):
+    check(lib().misdc_grid_destroy(h))
+
+
+def misdc_transport_operators(mech, grid, state, FA, FD, stream=None):
+    check(lib().misdc_transport_operators(mech, grid, _ptr(state), _ptr(FA), _ptr(FD),
+                                          _stream(stream)))
+
+
+def misdc_diffusion_solve(mech, grid, c, T_lag, rhs, y, guess_in_y=False, rtol=0.0, maxit=0,
+                          iters=None, stream=None):
+    check(lib().misdc_diffusion_solve(mech, grid, float(c), _ptr(T_lag), _ptr(rhs), _ptr(y),
+                                      int(bool(guess_in_y)), float(rtol), int(maxit),
+                                      _ptr(iters), _stream(stream)))
+
+
+def misdc_opts_default():
+    o = misdc_opts()
+    lib().misdc_opts_default(C.byref(o))
+    return o
+
+
+def misdc_integ_create(mech, grid, opts):
+    h = C.c_void_p()
+    check(lib().misdc_integ_create(mech, grid, C.byref(opts), C.byref(h)))
+    return h.value
+
+
+def misdc_integ_destroy(h):
+    check(lib().misdc_integ_destroy(h))
+
+
+def misdc_step(integ, state, dt, dt_per_flame=None, stream=None):
+    check(lib().misdc_step(integ, _ptr(state), float(dt), _ptr(dt_per_flame), _stream(stream)))
+
+
+def misdc_get_stats(integ):
+    s = misdc_stats()
+    check(lib().misdc_get_stats(integ, C.byref(s)))
+    return s.as_dict()
+
+
+def make_opts(n_nodes=5, sweeps=6, nu=1, scheme="cisdcq", qe="cumulative", serialize=False,
+              cg_rtol=1e-13, cg_maxit=500, newton=None):
+    o = misdc_opts_default()
+    o.n_nodes = n_nodes
+    o.n_sweeps = sweeps
+    o.nu = nu
+    o.scheme = SCHEME[scheme]
+    o.qe_mode = QE[qe]
+    o.serialize = int(bool(serialize))
+    o.cg_rtol = cg_rtol
+    o.cg_maxit = cg_maxit
+    if newton is not None:
+        o.newton = newton
+    return o

@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI library: it loads, exports every declared
+symbol, computes the SDC tables on the host, and rejects bad arguments
+before touching the GPU (none of these tests needs a device)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.coefficients import sdc_tables
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "misdc.h")
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_1801_01201_amd import native
+    native.lib()
+    return native
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(misdc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(nat):
+    lib = C.CDLL(nat.LIB_PATH)
+    declared = _declared_functions()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(nat.EXPORTED) == declared
+
+
+@pytest.mark.parametrize("n_nodes", range(2, 10))
+@pytest.mark.parametrize("qi", ["lu", "be"])
+@pytest.mark.parametrize("qe", ["cumulative", "literal"])
+def test_host_tables_match_oracle(nat, n_nodes, qi, qe):
+    a = nat.misdc_sdc_tables(n_nodes, qi, qe)
+    b = sdc_tables(n_nodes, qi, qe)
+    for k in ("tau", "Q", "QI", "QE"):
+        ulps = np.abs(a[k] - b[k]) / np.spacing(np.maximum(np.abs(b[k]), 1e-300))
+        assert np.all(ulps <= 2), (k, ulps.max())
+
+
+def test_node_to_node_weights_are_differences_of_Q(nat):
+    for n_nodes in (3, 5, 7):
+        a = nat.misdc_sdc_tables(n_nodes)
+        Q, S = a["Q"], a["S"]
+        np.testing.assert_allclose(S[0], Q[0], atol=1e-16)
+        np.testing.assert_allclose(S[1:], Q[1:] - Q[:-1], atol=2e-16)
+
+
+def test_table_arguments_rejected(nat):
+    with pytest.raises(nat.MisdcError) as e:
+        nat.misdc_sdc_tables(1)
+    assert e.value.code == nat.MISDC_EINVAL
+    with pytest.raises(nat.MisdcError):
+        nat.misdc_sdc_tables(10)
+    rc = nat.lib().misdc_sdc_tables(5, 7, 0, None, None, None, None, None)
+    assert rc == nat.MISDC_EINVAL
+
+
+def test_grid_arguments_rejected(nat):
+    for dim, n, dx, u in [(3, [8, 8], [0.1, 0.1], [0, 0]), (1, [2], [0.1], [0.0]),
+                          (2, [8, 8], [0.1, -1.0], [0, 0]), (1, [8], [0.1], [np.inf])]:
+        with pytest.raises(nat.MisdcError) as e:
+            nat.misdc_grid_create(dim, n, dx, u)
+        assert e.value.code == nat.MISDC_EINVAL
+    with pytest.raises(nat.MisdcError):
+        nat.misdc_grid_create_ensemble([64, 3], [0.1, 0.1], [1.0, 1.0])
+
+
+def test_mechanism_validation_before_device(nat):
+    m = synth.make_mechanism(9, 21, 0)
+    bad = dict(m)
+    bad["W"] = m["W"].copy()
+    bad["W"][2] = -1.0
+    with pytest.raises(nat.MisdcError) as e:
+        nat.misdc_mech_create(bad)
+    assert e.value.code == nat.MISDC_EINVAL
+    bad = dict(m)
+    bad["react"] = m["react"].copy()
+    bad["react"][0, 0] = m["bath"]            # the bath may not react
+    with pytest.raises(nat.MisdcError):
+        nat.misdc_mech_create(bad)
+    bad = dict(m)
+    bad["prod"] = m["prod"].copy()
+    bad["prod"][0] = [-1, -1]                 # no product
+    with pytest.raises(nat.MisdcError):
+        nat.misdc_mech_create(bad)
+    bad = dict(m)
+    bad["W"] = m["W"].copy()
+    bad["W"][int(m["react"][0, 0])] *= 1.5    # unbalanced reaction
+    with pytest.raises(nat.MisdcError) as e:
+        nat.misdc_mech_create(bad)
+    assert "balanced" in str(e.value)
+
+
+def test_null_handles_rejected(nat):
+    lib = nat.lib()
+    assert lib.misdc_step(None, None, 1.0, None, None) == nat.MISDC_EINVAL
+    assert lib.misdc_integ_create(None, None, None, C.byref(C.c_void_p())) == nat.MISDC_EINVAL
+    assert lib.misdc_reaction_solve_batch(None, 1, None, None, None, None, None, None, None,
+                                          None, None) == nat.MISDC_EINVAL
+    assert lib.misdc_get_stats(None, None) == nat.MISDC_EINVAL
+    o = nat.misdc_opts_default()
+    assert (o.n_nodes, o.n_sweeps, o.nu, o.scheme) == (5, 6, 1, 2)
