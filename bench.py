@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of the concurrent multi-implicit SDC step on one MI355X.
+
+Workload (the 2-D flame of 256 x 256 cells): seeded 9-species / 21-reaction
+Arrhenius mechanism, periodic tanh flame 300 -> 2000 K, uniform velocity
+1 m/s, dx = 0.01 cm, dt = 5e-5 s, CISDCQ with nu = 1, 5 Gauss-Lobatto nodes,
+6 sweeps per step.  A bench step is one full time step (every sweep, every
+node: implicit diffusion on one stream, per-cell Newton reaction solves on the
+other).  Inputs are resident in device memory before timing starts.
+
+metric: cell-node updates per second per concurrent sweep
+        = cells * M * nu * sweeps * steps / timed seconds.
+Also reported: Newton iterations per cell-node solve, the roofline of the
+dominant kernel (live HIP-event timing inside the library, on the stream the
+kernel runs on), the FP64 oracle timed on the host for one sweep of the same
+workload, and an accuracy gate (GPU vs oracle on a 48 x 40 step, <= 1e-8).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-node updates/s per concurrent-MISDC sweep at 1e-8 rel err; Newton iters/cell"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+# algorithmic traffic of one preconditioned CG iteration per unknown, fused:
+# read p, q(=Ap), x, r, z/diag and write x, r, z -> 7 doubles
+CG_BYTES_PER_UNKNOWN_ITER = 56.0
+# algorithmic FP64 work of one Newton iteration for 9 species / 21 reactions
+NEWTON_FLOP_PER_ITER_9 = 3.4e3
+NEWTON_BYTES_PER_SOLVE_9 = 316.0
+
+
+def workload():
+    import synth
+    c = synth.config("flame2d_256")
+    return c
+
+
+def cpu_baseline_leg(cfg):
+    """The FP64 oracle, as it stands, on one sweep of the same workload."""
+    import numpy as np
+    import synth
+    from oracle.adr import FlameProblem, relaxed_initial_state
+    from oracle.sdc import sdc_step
+    mech = synth.make_mechanism(**cfg["mech"])
+    # bounded sample: the same flame, mechanism, step and scheme on a
+    # 128 x 128 grid (a quarter of the cells), three sweeps
+    nx, ny = 128, 128
+    Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
+    prob = FlameProblem(mech, cfg["dx"], cfg["u"])
+    phi = relaxed_initial_state(prob, Y, T)
+    w0, c0 = time.perf_counter(), time.process_time()
+    sweeps = 3
+    sdc_step(prob, phi, cfg["dt"], cfg["n_nodes"], sweeps, cfg["scheme"], nu=cfg["nu"])
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0
+    M = cfg["n_nodes"] - 1
+    updates = nx * ny * M * cfg["nu"] * sweeps
+    return {"value": updates / wall, "unit": "cell-node updates/s",
+            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+            "sample": f"{sweeps} CISDCQ-{cfg['nu']} sweeps ({M} nodes) of the same flame workload on "
+                      f"{nx}x{ny} cells (one quarter of the cells), wall {wall:.1f} s; "
+                      f"the metric is per cell-node update",
+            "seconds": wall}
+
+
+def accuracy_gate(cfg, mech, mh):
+    """GPU step vs oracle step on a 48 x 40 version of the workload."""
+    import numpy as np
+    import torch
+    import synth
+    from oracle.adr import FlameProblem, relaxed_initial_state
+    from oracle.sdc import sdc_step
+    from paper_1801_01201_amd.flame import Grid, Integrator, initial_state
+    nx, ny = 48, 40
+    Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
+    prob = FlameProblem(mech, cfg["dx"], cfg["u"])
+    ref, _ = sdc_step(prob, relaxed_initial_state(prob, Y, T), cfg["dt"], cfg["n_nodes"],
+                      cfg["sweeps"], cfg["scheme"], nu=cfg["nu"])
+    st, _ = initial_state(mh, torch.tensor(Y.reshape(9, -1), device="cuda"),
+                          torch.tensor(T.ravel(), device="cuda"))
+    g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
+    integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
+                       scheme=cfg["scheme"])
+    integ.step(st, cfg["dt"])
+    out = st.cpu().numpy()
+    integ.close()
+    g.close()
+    ref = ref.reshape(10, -1)
+    err = float((np.abs(out - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
+    return {"err": err, "tol": 1e-8, "passed": bool(err <= 1e-8), "grid": f"{nx}x{ny}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gate", action="store_true")
+    ap.add_argument("--nu", type=int, default=None)
+    ap.add_argument("--serialize", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              f"design is described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+    cfg = workload()
+    if args.nu:
+        cfg["nu"] = args.nu
+    # the CPU leg runs first, before anything touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline_leg(cfg)
+    if cpu:
+        print(f"[bench] cpu baseline: {cpu['value']:.4g} {cpu['unit']} ({cpu['sample']})",
+              file=sys.stderr, flush=True)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_1801_01201_amd import native
+    from paper_1801_01201_amd.flame import Mechanism, Grid, Integrator, initial_state
+    native.lib()
+    mech = synth.make_mechanism(**cfg["mech"])
+    nx, ny = cfg["n"]
+    n = nx * ny
+    M = cfg["n_nodes"] - 1
+    mh = Mechanism(mech)
+    g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
+    Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
+    state, _ = initial_state(mh, torch.tensor(Y.reshape(9, -1), device="cuda"),
+                             torch.tensor(T.ravel(), device="cuda"))
+    integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
+                       scheme=cfg["scheme"], serialize=args.serialize, profile=True)
+    for _ in range(args.warmup):
+        integ.step(state, cfg["dt"])
+    torch.cuda.synchronize()
+    native.misdc_reset_profile(integ.handle)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        integ.step(state, cfg["dt"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = integ.stats()          # last step's counters + timings over all timed steps
+    elapsed = t1 - t0
+    updates = n * M * cfg["nu"] * cfg["sweeps"] * args.steps
+    value = updates / elapsed
+    newton_per_cell = stats["newton_iters"] / max(1, stats["newton_solves"])
+    cg_per_solve = stats["cg_iters"] / max(1, stats["cg_solves"])
+
+    # roofline of the dominant kernel
+    d_ms, d_n = stats["diffusion_kernel_ms"], stats["diffusion_kernel_launches"]
+    r_ms, r_n = stats["newton_kernel_ms"], stats["newton_kernel_launches"]
+    if d_ms >= r_ms:
+        avg_s = d_ms / max(1, d_n) * 1e-3
+        unknowns = 8 * n + n            # 8 diffused species + enthalpy
+        traffic = CG_BYTES_PER_UNKNOWN_ITER * unknowns * cg_per_solve
+        achieved = traffic / avg_s / 1e9
+        roof = {"kernel": "cg_kernel (batched Jacobi-PCG, implicit diffusion)",
+                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "avg_launch_ms": avg_s * 1e3, "launches": d_n,
+                "algorithmic_bytes_per_launch": traffic,
+                "cg_iterations_per_launch": cg_per_solve}
+    else:
+        avg_s = r_ms / max(1, r_n) * 1e-3
+        flops = NEWTON_FLOP_PER_ITER_9 * n * newton_per_cell
+        achieved = flops / avg_s / 1e12
+        roof = {"kernel": "newton_kernel<9> (per-cell reaction solve)", "bound": "alu",
+                "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "avg_launch_ms": avg_s * 1e3, "launches": r_n}
+    other = {"diffusion_solve_ms_per_launch": d_ms / max(1, d_n),
+             "newton_ms_per_launch": r_ms / max(1, r_n),
+             "diffusion_solve_share_of_step": d_ms / (elapsed * 1e3),
+             "newton_share_of_step": r_ms / (elapsed * 1e3)}
+    gate = None if args.no_gate else accuracy_gate(cfg, mech, mh)
+    integ.close()
+    g.close()
+    line = {
+        "metric": METRIC, "value": value, "unit": "cell-node updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"flame2d_256: 2-D periodic {nx}x{ny} flame, 9 species / 21 "
+                               f"reactions, CISDCQ-{cfg['nu']}, {cfg['n_nodes']} Gauss-Lobatto "
+                               f"nodes, {cfg['sweeps']} sweeps, dt {cfg['dt']} s",
+                   "cells": n, "nodes": cfg["n_nodes"], "sweeps": cfg["sweeps"],
+                   "nu": cfg["nu"], "scheme": cfg["scheme"], "serialize": args.serialize},
+        "newton_iters_per_cell": newton_per_cell,
+        "cg_iters_per_solve": cg_per_solve,
+        "cell_node_updates_per_step_incl_node0": n * (M + 1) * cfg["nu"] * cfg["sweeps"],
+        "roofline": roof,
+        "kernel_split": other,
+        "cpu_baseline": cpu,
+        "accuracy_gate": gate,
+        "newton_failed": stats["newton_failed"], "cg_failed": stats["cg_failed"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

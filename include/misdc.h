@@ -230,6 +230,8 @@ typedef struct {
     misdc_newton_opts newton;
     double cg_rtol;      /* 2-D diffusion CG tolerance (<= 0: 1e-13) */
     int32_t cg_maxit;    /* (<= 0: 500) */
+    int32_t profile;     /* 1: time every diffusion-solve and Newton kernel with
+                            HIP events on the stream it runs on (see stats) */
 } misdc_opts;
 
 /* Fills the defaults: 5 nodes, 6 sweeps, nu 1, CISDCQ, cumulative QE. */
@@ -263,9 +265,17 @@ typedef struct {
     int32_t cg_failed;
     int32_t n_sweeps;
     double sweep_increment[64];
-    double ms_diffusion;        /* device time of the diffusion task, last step */
-    double ms_reaction;         /* device time of the reaction task, last step */
+    /* with opts.profile: summed device durations (ms) and launch counts of
+     * the implicit-diffusion solve kernels and of the Newton kernels since
+     * the integrator was created or the last misdc_reset_profile() */
+    double diffusion_kernel_ms;
+    int64_t diffusion_kernel_launches;
+    double newton_kernel_ms;
+    int64_t newton_kernel_launches;
 } misdc_stats;
+
+/* Clears the accumulated kernel timings of opts.profile. */
+int misdc_reset_profile(misdc_integ_t integ);
 
 int misdc_get_stats(misdc_integ_t integ, misdc_stats* stats);
 

@@ -98,6 +98,12 @@ struct misdc_integ_s {
     hipEvent_t ev_in = nullptr, ev_outD = nullptr, ev_outR = nullptr;
     int last_sweeps = 0;
     double dt = 0.0;
+    // kernel timing (opts.profile): event pairs recorded around launches
+    struct Timed { hipEvent_t a, b; int kind; };
+    std::vector<Timed> timed;                     // pending pairs (not yet summed)
+    std::vector<hipEvent_t> ev_pool;
+    double t_ms[2] = {0.0, 0.0};                  // [0] diffusion solve, [1] Newton
+    int64_t t_cnt[2] = {0, 0};
 
     hipEvent_t& D_ev(int l, int p) { return evD[(size_t)l * (M + 1) + p]; }
     hipEvent_t& R_ev(int l, int p) { return evR[(size_t)l * (M + 1) + p]; }
@@ -243,6 +249,46 @@ int eval_ops(misdc_integ_s* I, const NodeBuf& b, double* th, hipStream_t s, bool
 
 int accum_cg(misdc_integ_s* I, hipStream_t s);
 
+hipEvent_t pool_event(misdc_integ_s* I) {
+    if (!I->ev_pool.empty()) {
+        hipEvent_t e = I->ev_pool.back();
+        I->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Sums the durations of completed timing pairs (the streams are synchronised).
+int drain_timing(misdc_integ_s* I) {
+    for (auto& t : I->timed) {
+        float ms = 0.f;
+        MISDC_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+        I->t_ms[t.kind] += ms;
+        I->t_cnt[t.kind] += 1;
+        I->ev_pool.push_back(t.a);
+        I->ev_pool.push_back(t.b);
+    }
+    I->timed.clear();
+    return MISDC_OK;
+}
+
+// Records a start event when profiling; returns it (or null).
+hipEvent_t timing_begin(misdc_integ_s* I, hipStream_t s) {
+    if (!I->opt.profile) return nullptr;
+    hipEvent_t e = pool_event(I);
+    if (e && hipEventRecord(e, s) != hipSuccess) return nullptr;
+    return e;
+}
+
+void timing_end(misdc_integ_s* I, hipEvent_t start, hipStream_t s, int kind) {
+    if (!start) return;
+    hipEvent_t e = pool_event(I);
+    if (!e || hipEventRecord(e, s) != hipSuccess) return;
+    I->timed.push_back({start, e, kind});
+}
+
 // ---- diffusion task at node p of nested iteration ell (writes phiAD[p]) ----
 int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     const int M = I->M, N = I->N, NF = I->NF;
@@ -297,9 +343,13 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     const double* guess = (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell > 0) ? Lp[p].phi : L0[p].phi;
     MISDC_HIP(hipMemcpyAsync(I->phiAD[p], guess, sizeof(double) * NF * n, hipMemcpyDeviceToDevice,
                              I->sD));
+    // with profiling, the events bracket the solve kernel itself (CG or cyclic)
+    hipEvent_t t0 = I->opt.profile ? pool_event(I) : nullptr;
+    hipEvent_t t1 = I->opt.profile ? pool_event(I) : nullptr;
     rc = launch_diffusion_solve(*I->mech, *I->grid, I->dw, c, nullptr, 0.0, T_lag, I->rD,
-                                I->phiAD[p], 1, I->opt.cg_rtol, I->opt.cg_maxit, I->sD);
+                                I->phiAD[p], 1, I->opt.cg_rtol, I->opt.cg_maxit, I->sD, t0, t1);
     if (rc) return rc;
+    if (t0 && t1) I->timed.push_back({t0, t1, 0});
     if (I->grid->dim == 2 && I->grid->n_flames == 0) {
         rc = accum_cg(I, I->sD);
         if (rc) return rc;
@@ -367,8 +417,10 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     a.iters = I->iters;
     a.stats = I->nstats;
     a.opt = I->opt.newton;
+    hipEvent_t t0 = timing_begin(I, I->sR);
     rc = launch_reaction_newton(*I->mech, a, I->sR);
     if (rc) return rc;
+    timing_end(I, t0, I->sR, 1);
     rc = eval_ops(I, out, I->thR, I->sR, false);
     (void)NF;
     return rc;
@@ -809,6 +861,7 @@ void misdc_opts_default(misdc_opts* o) {
     o->newton = newton_defaults(nullptr);
     o->cg_rtol = 1e-13;
     o->cg_maxit = 500;
+    o->profile = 0;
 }
 
 int misdc_integ_destroy(misdc_integ_t I);
@@ -914,6 +967,11 @@ int misdc_integ_destroy(misdc_integ_t I) {
         if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : I->evR)
         if (ev) (void)hipEventDestroy(ev);
+    for (auto& t : I->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (hipEvent_t ev : I->ev_pool) (void)hipEventDestroy(ev);
     if (I->ev_in) (void)hipEventDestroy(I->ev_in);
     if (I->ev_outD) (void)hipEventDestroy(I->ev_outD);
     if (I->ev_outR) (void)hipEventDestroy(I->ev_outR);
@@ -990,6 +1048,12 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
     st->cg_solves = cg[3];
     const int K = I->last_sweeps;
     st->n_sweeps = K;
+    int rc = drain_timing(I);
+    if (rc) return rc;
+    st->diffusion_kernel_ms = I->t_ms[0];
+    st->diffusion_kernel_launches = I->t_cnt[0];
+    st->newton_kernel_ms = I->t_ms[1];
+    st->newton_kernel_launches = I->t_cnt[1];
     if (K > 0) {
         std::vector<double> inc((size_t)K * I->NF * 2);
         MISDC_HIP(hipMemcpy(inc.data(), I->inc, sizeof(double) * inc.size(), hipMemcpyDeviceToHost));
@@ -1003,6 +1067,17 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
             st->sweep_increment[k] = worst;
         }
     }
+    return MISDC_OK;
+}
+
+int misdc_reset_profile(misdc_integ_t I) {
+    if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
+    MISDC_HIP(hipStreamSynchronize(I->sD));
+    MISDC_HIP(hipStreamSynchronize(I->sR));
+    int rc = drain_timing(I);
+    if (rc) return rc;
+    I->t_ms[0] = I->t_ms[1] = 0.0;
+    I->t_cnt[0] = I->t_cnt[1] = 0;
     return MISDC_OK;
 }
 

@@ -138,7 +138,8 @@ void diffusion_work_free(DiffusionWork& w);
 int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, double c,
                            const double* dt_flame, double c_factor,
                            const double* T_lag, const double* rhs, double* y, int guess_in_y,
-                           double rtol, int maxit, hipStream_t s);
+                           double rtol, int maxit, hipStream_t s,
+                           hipEvent_t core_begin = nullptr, hipEvent_t core_end = nullptr);
 
 // max_i |a - b| and max_i |a| per field into out[2*f], out[2*f+1] (device)
 int launch_field_diff_max(int nfields, int64_t n, const double* a, const double* b,

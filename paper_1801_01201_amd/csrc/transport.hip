@@ -628,13 +628,14 @@ void diffusion_work_free(DiffusionWork& w) {
 int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, double c,
                            const double* dt_flame, double c_factor, const double* T_lag,
                            const double* rhs, double* y, int guess_in_y, double rtol, int maxit,
-                           hipStream_t s) {
+                           hipStream_t s, hipEvent_t core_begin, hipEvent_t core_end) {
     const int64_t n = g.cells();
     if (n == 0) return MISDC_OK;
     const GridDev gd = grid_dev(g);
     hipLaunchKernelGGL(faces_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, gd, n, T_lag,
                        w.theta, w.Kx, w.Ky);
     MISDC_HIP(hipGetLastError());
+    if (core_begin) MISDC_HIP(hipEventRecord(core_begin, s));
     const int NF = m.dev.N + 1;
     if (g.dim == 1 || g.n_flames > 0) {
         const int nsys = (g.n_flames > 0 ? g.n_flames : 1) * NF;
@@ -671,6 +672,7 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
         hipLaunchKernelGGL(cg_kernel, dim3(w.blocks), dim3(CG_THREADS), 0, s, a);
         MISDC_HIP(hipGetLastError());
     }
+    if (core_end) MISDC_HIP(hipEventRecord(core_end, s));
     hipLaunchKernelGGL(closure_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, n, rhs, y);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;

@@ -31,6 +31,7 @@ EXPORTED = [
     "misdc_grid_create_ensemble", "misdc_grid_destroy", "misdc_grid_cells",
     "misdc_transport_operators", "misdc_diffusion_solve", "misdc_opts_default",
     "misdc_integ_create", "misdc_integ_destroy", "misdc_step", "misdc_get_stats",
+    "misdc_reset_profile",
 ]
 
 
@@ -57,7 +58,8 @@ class misdc_newton_opts(C.Structure):
 class misdc_opts(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("n_sweeps", C.c_int32), ("nu", C.c_int32),
                 ("scheme", C.c_int32), ("qe_mode", C.c_int32), ("serialize", C.c_int32),
-                ("newton", misdc_newton_opts), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32)]
+                ("newton", misdc_newton_opts), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
+                ("profile", C.c_int32)]
 
 
 class misdc_stats(C.Structure):
@@ -65,8 +67,9 @@ class misdc_stats(C.Structure):
                 ("newton_max", C.c_int32), ("newton_failed", C.c_int64),
                 ("cg_solves", C.c_int64), ("cg_iters", C.c_int64), ("cg_max", C.c_int32),
                 ("cg_failed", C.c_int32), ("n_sweeps", C.c_int32),
-                ("sweep_increment", C.c_double * 64), ("ms_diffusion", C.c_double),
-                ("ms_reaction", C.c_double)]
+                ("sweep_increment", C.c_double * 64), ("diffusion_kernel_ms", C.c_double),
+                ("diffusion_kernel_launches", C.c_int64), ("newton_kernel_ms", C.c_double),
+                ("newton_kernel_launches", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "sweep_increment"}
@@ -103,6 +106,7 @@ def load(path=LIB_PATH):
         "misdc_integ_destroy": (C.c_int, [vp]),
         "misdc_step": (C.c_int, [vp, vp, dbl, vp, vp]),
         "misdc_get_stats": (C.c_int, [vp, C.POINTER(misdc_stats)]),
+        "misdc_reset_profile": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -277,8 +281,12 @@ def misdc_get_stats(integ):
     return s.as_dict()
 
 
+def misdc_reset_profile(integ):
+    check(lib().misdc_reset_profile(integ))
+
+
 def make_opts(n_nodes=5, sweeps=6, nu=1, scheme="cisdcq", qe="cumulative", serialize=False,
-              cg_rtol=1e-13, cg_maxit=500, newton=None):
+              cg_rtol=1e-13, cg_maxit=500, newton=None, profile=False):
     o = misdc_opts_default()
     o.n_nodes = n_nodes
     o.n_sweeps = sweeps
@@ -288,6 +296,7 @@ def make_opts(n_nodes=5, sweeps=6, nu=1, scheme="cisdcq", qe="cumulative", seria
     o.serialize = int(bool(serialize))
     o.cg_rtol = cg_rtol
     o.cg_maxit = cg_maxit
+    o.profile = int(bool(profile))
     if newton is not None:
         o.newton = newton
     return o
