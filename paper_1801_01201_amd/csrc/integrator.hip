@@ -97,6 +97,7 @@ struct misdc_integ_s {
     std::vector<hipEvent_t> evD, evR;             // [(levels) x (M+1)]
     hipEvent_t ev_in = nullptr, ev_outD = nullptr, ev_outR = nullptr;
     int last_sweeps = 0;
+    int sweep_index = 0;                          // sweep being issued within the step
     double dt = 0.0;
     // kernel timing (opts.profile): event pairs recorded around launches
     struct Timed { hipEvent_t a, b; int kind; };
@@ -1017,8 +1018,10 @@ int misdc_step(misdc_integ_t I, double* state, double dt, const double* dev_dt, 
     for (int l = 1; l < I->levels; ++l) I->lev[l][0] = b0;
     // "previous sweep finished" marker for the first sweep's constants
     MISDC_HIP(hipEventRecord(I->R_ev(0, M), I->sD));
-    for (int k = 0; k < I->opt.n_sweeps; ++k)
+    for (int k = 0; k < I->opt.n_sweeps; ++k) {
+        I->sweep_index = k;
         if ((rc = run_sweep(I, k, dt))) return rc;
+    }
     MISDC_HIP(hipMemcpyAsync(state, I->lev[0][M].phi, fb, hipMemcpyDeviceToDevice, I->sR));
     MISDC_HIP(hipEventRecord(I->ev_outD, I->sD));
     MISDC_HIP(hipEventRecord(I->ev_outR, I->sR));

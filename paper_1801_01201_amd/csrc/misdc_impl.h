@@ -126,11 +126,13 @@ struct DiffusionWork {
     double* p = nullptr;
     double* q = nullptr;
     double* partial = nullptr;    // blocks x fields x 4
+    double* totals = nullptr;     // fields x 4
     unsigned* barrier = nullptr;  // 4 words
     int32_t* info = nullptr;      // [0] iterations, [1] failed, [2] barrier timeout
     int blocks = 0;
     int threads = 0;
     int fields_cap = 0;
+    int variant = 0;              // 0: vectors in global memory; 1, 2, 4: cells per thread in registers
 };
 int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g);
 void diffusion_work_free(DiffusionWork& w);

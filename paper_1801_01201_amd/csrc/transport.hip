@@ -11,6 +11,7 @@
 // iteration, deterministic fixed-order reductions (so the result does not
 // depend on scheduling), and a grid sized to be fully co-resident.
 #include <cmath>
+#include <cstdlib>
 
 #include "misdc_impl.h"
 
@@ -162,8 +163,12 @@ __global__ void __launch_bounds__(256) transport_kernel(GridDev g, MechDev m, in
 // face coefficients of the lagged operator: Kx[i] = east face / dx^2, Ky[i] =
 // north face / dy^2, both from theta = (T_lag/300)^1.7.
 __global__ void __launch_bounds__(256) faces_kernel(GridDev g, int64_t n, const double* T,
-                                                    double* th, double* Kx, double* Ky) {
+                                                    double* th, double* Kx, double* Ky,
+                                                    unsigned* bar) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the persistent CG kernel that follows on this stream counts its grid
+    // barriers from zero
+    if (i == 0 && bar) { bar[0] = 0u; bar[1] = 0u; }
     if (i >= n) return;
     const Row r = row_of(g, i);
     const int64_t xp1 = r.base + wrap(r.pos + 1, r.len);
@@ -249,39 +254,48 @@ __global__ void __launch_bounds__(256) closure_kernel(MechDev m, int64_t n, cons
     y[(size_t)m.bath * n + i] = rhs[(size_t)m.bath * n + i] - s;
 }
 
-// ---- grid-wide barrier for the persistent CG kernel -------------------------
-// bar[0]: arrival counter, bar[1]: generation.  Every thread publishes its
-// stores with an agent-scope release fence before the workgroup barrier; the
-// last workgroup to arrive resets the counter and bumps the generation; the
-// others wait (bounded spin: after the limit the kernel records a timeout in
-// info[2] and proceeds, so every wave always terminates).
+constexpr int CG_THREADS = 256;
+// block size of the register-resident CG: 512 threads with one cell each
+// (2 waves per SIMD), 256 threads when each thread owns 2 or 4 cells
+constexpr int cg_regs_block(int cpt) { return cpt == 1 ? 512 : 256; }
+constexpr int CG_MAX_FIELDS = 64;
+constexpr int CG_MAX_BLOCKS = 256;
+
+// ---- grid-wide barrier for the persistent CG kernels -------------------------
+// bar[0]: arrival counter, bar[1]: generation.  The workgroup barrier makes
+// every wave's stores complete; one agent-scope release fence per workgroup
+// then publishes them to the other XCDs (L2 write-back); the last workgroup to
+// arrive resets the counter and bumps the generation; the others poll the
+// generation with relaxed agent-scope loads (bounded: after the limit the
+// kernel records a timeout in info[2] and proceeds, so every wave always
+// terminates); one acquire fence per workgroup makes the other workgroups'
+// data visible before the workgroup barrier releases its waves.
 __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, int32_t* info) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned arrived =
-            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == nblocks - 1) {
             __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             unsigned spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > (1u << 26)) {
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1u << 27)) {
                     __hip_atomic_store(&info[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
-constexpr int CG_THREADS = 256;
-constexpr int CG_MAX_FIELDS = 64;
+
 
 struct CGArgs {
     int64_t n;              // cells
@@ -298,6 +312,7 @@ struct CGArgs {
     double* p;
     double* q;
     double* partial;        // blocks x nf x 4
+    double* totals;         // nf x 4 (written by the last block of a fused reduction)
     unsigned* bar;
     int32_t* info;          // [0] iterations, [1] failed, [2] barrier timeout
     double rtol2;
@@ -490,6 +505,237 @@ __global__ void __launch_bounds__(CG_THREADS) cg_kernel(CGArgs a) {
     }
 }
 
+// Grid barrier number k (0-based) of the current launch, with a monotonic
+// arrival counter that the preceding faces_kernel zeroed: every workgroup
+// publishes its stores with one agent-scope release fence and one relaxed
+// increment, then waits until all workgroups have arrived k+1 times (the
+// increments form one release sequence, so the acquire fence after the wait
+// makes every workgroup's stores visible).  Bounded wait: after the limit the
+// kernel records a timeout in info[2] and proceeds, so every wave terminates.
+__device__ __forceinline__ void grid_sync(unsigned* counter, unsigned nb, unsigned k,
+                                          int32_t* info) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = (k + 1u) * nb;
+        unsigned spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1u << 27)) {
+                __hip_atomic_store(&info[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// All-reduce of nslots values fused with grid barrier k.  red holds one value
+// per (slot, wave) of this workgroup.  The partials go to buffer k % 2 (so a
+// workgroup that is one barrier ahead cannot overwrite values another one is
+// still reading); after the barrier every workgroup loads all partials at
+// once into LDS and sums them in block order: bitwise identical totals in
+// every workgroup, whatever the scheduling.
+template <int BS>
+__device__ __forceinline__ void grid_allreduce(const CGArgs& a, unsigned k, int nslots,
+                                               const double* red, double* stage, double* tot) {
+    constexpr int NW = BS / 64;
+    const unsigned nb = gridDim.x;
+    double* part = a.partial + (size_t)(k & 1u) * CG_MAX_BLOCKS * (CG_MAX_FIELDS * 4);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nslots; t += BS) {
+        double v = 0.0;
+        for (int w = 0; w < NW; ++w) v += red[t * NW + w];
+        part[(size_t)blockIdx.x * (CG_MAX_FIELDS * 4) + t] = v;
+    }
+    grid_sync(a.bar, nb, k, a.info);
+    const int total = (int)nb * nslots;
+    for (int e = threadIdx.x; e < total; e += BS) {
+        const int b = e / nslots, t = e - b * nslots;
+        stage[e] = part[(size_t)b * (CG_MAX_FIELDS * 4) + t];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = wave; t < nslots; t += NW) {
+        double v = 0.0;
+        for (unsigned b = lane; b < nb; b += 64) v += stage[b * nslots + t];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) tot[t] = v;
+    }
+    __syncthreads();
+}
+
+template <int BS>
+__device__ __forceinline__ void wave_put(double v, double* red, int slot) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) red[slot * (BS / 64) + (threadIdx.x >> 6)] = v;
+}
+
+// Register-resident pipelined preconditioned CG (the single-reduction
+// recurrences of Ghysels & Vanroose).  Every thread owns CPT cells for the
+// whole solve and keeps all vectors of the NFD fields in registers; the only
+// vector exchanged through memory is m = D^{-1} w, whose stencil product is
+// taken after the barrier that also reduces (r,u), (w,u) and (r,r) -- one
+// grid barrier per iteration.  m is double-buffered in a.z / a.q.  Fields stop
+// (their updates are masked) once |r|_2 <= rtol |b|_2.
+template <int NFD, int CPT, int BS>
+__global__ void __launch_bounds__(BS) cg_regs_kernel(CGArgs a) {
+    constexpr int NS = 3 * NFD;               // slots: gamma, delta, rr per field
+    __shared__ double stage[CG_MAX_BLOCKS * NS];
+    __shared__ double red[NS * (BS / 64)];
+    __shared__ double tot[NS];
+    __shared__ double s_bb[NFD], s_gprev[NFD], s_aprev[NFD], s_alpha[NFD], s_beta[NFD];
+    __shared__ int s_active[NFD], s_any;
+    const unsigned nb = gridDim.x;
+    const int64_t T = (int64_t)gridDim.x * BS;
+    const int64_t t0 = (int64_t)blockIdx.x * BS + threadIdx.x;
+    int64_t cell[CPT], ie[CPT], iw[CPT], in_[CPT], is_[CPT];
+    double ke[CPT], kw[CPT], kn[CPT], ks[CPT];
+    bool own[CPT];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        cell[k] = t0 + k * T;
+        own[k] = cell[k] < a.n;
+        const int64_t i = own[k] ? cell[k] : 0;
+        stencil_at(a, i, ie[k], iw[k], in_[k], is_[k], ke[k], kw[k], kn[k], ks[k]);
+    }
+    double x[NFD][CPT], r[NFD][CPT], u[NFD][CPT], w[NFD][CPT];
+    double zz[NFD][CPT], qq[NFD][CPT], ss[NFD][CPT], pp[NFD][CPT];
+    unsigned kb = 0;                          // grid barriers done in this launch
+    // ---- r = b - A x0, u = D^{-1} r (published), partial (b, b) ----
+#pragma unroll
+    for (int d = 0; d < NFD; ++d) {
+        const size_t o = (size_t)a.fmap[d] * a.n;
+        const double* X = a.guess_in_x ? a.x + o : a.b + o;
+        const double cf = a.cf[d];
+        double bb = 0.0;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            x[d][k] = r[d][k] = u[d][k] = w[d][k] = 0.0;
+            zz[d][k] = qq[d][k] = ss[d][k] = pp[d][k] = 0.0;
+            if (!own[k]) continue;
+            const int64_t i = cell[k];
+            const double xi = X[i];
+            const double Ax = xi - cf * (ke[k] * (X[ie[k]] - xi) - kw[k] * (xi - X[iw[k]]) +
+                                         kn[k] * (X[in_[k]] - xi) - ks[k] * (xi - X[is_[k]]));
+            const double bi = a.b[o + i];
+            x[d][k] = xi;
+            r[d][k] = bi - Ax;
+            u[d][k] = r[d][k] / (1.0 + cf * (ke[k] + kw[k] + kn[k] + ks[k]));
+            a.r[o + i] = u[d][k];             // exchange buffer of u
+            bb += bi * bi;
+        }
+        wave_put<BS>(bb, red, d);
+    }
+    grid_allreduce<BS>(a, kb++, NFD, red, stage, tot);
+    if (threadIdx.x < NFD) s_bb[threadIdx.x] = tot[threadIdx.x];
+    // ---- w = A u ----
+#pragma unroll
+    for (int d = 0; d < NFD; ++d) {
+        const size_t o = (size_t)a.fmap[d] * a.n;
+        const double* U = a.r + o;
+        const double cf = a.cf[d];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            if (!own[k]) continue;
+            const double ui = u[d][k];
+            w[d][k] = ui - cf * (ke[k] * (U[ie[k]] - ui) - kw[k] * (ui - U[iw[k]]) +
+                                 kn[k] * (U[in_[k]] - ui) - ks[k] * (ui - U[is_[k]]));
+        }
+    }
+    int it = 0;
+    for (; it < a.maxit; ++it) {
+        // ---- m = D^{-1} w (published), partials gamma = (r,u), delta = (w,u), rr ----
+        double* Mbuf = (it & 1) ? a.q : a.z;
+#pragma unroll
+        for (int d = 0; d < NFD; ++d) {
+            const size_t o = (size_t)a.fmap[d] * a.n;
+            const double cf = a.cf[d];
+            double g = 0.0, de = 0.0, rr = 0.0;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                if (!own[k]) continue;
+                Mbuf[o + cell[k]] = w[d][k] / (1.0 + cf * (ke[k] + kw[k] + kn[k] + ks[k]));
+                g += r[d][k] * u[d][k];
+                de += w[d][k] * u[d][k];
+                rr += r[d][k] * r[d][k];
+            }
+            wave_put<BS>(g, red, 3 * d + 0);
+            wave_put<BS>(de, red, 3 * d + 1);
+            wave_put<BS>(rr, red, 3 * d + 2);
+        }
+        grid_allreduce<BS>(a, kb++, NS, red, stage, tot);
+        if (threadIdx.x == 0) {
+            int any = 0;
+            for (int d = 0; d < NFD; ++d) {
+                const double g = tot[3 * d], de = tot[3 * d + 1], rr = tot[3 * d + 2];
+                const int act = rr > a.rtol2 * s_bb[d];
+                double al = 0.0, be = 0.0;
+                if (act) {
+                    if (it == 0) {
+                        al = g / de;
+                    } else {
+                        be = g / s_gprev[d];
+                        al = g / (de - be * g / s_aprev[d]);
+                    }
+                    s_gprev[d] = g;
+                    s_aprev[d] = al;
+                }
+                s_active[d] = act;
+                s_alpha[d] = al;
+                s_beta[d] = be;
+                any |= act;
+            }
+            s_any = any;
+        }
+        __syncthreads();
+        if (!s_any) break;
+        // ---- n = A m ; recurrences ----
+#pragma unroll
+        for (int d = 0; d < NFD; ++d) {
+            const size_t o = (size_t)a.fmap[d] * a.n;
+            const double* Mv = Mbuf + o;
+            const double cf = a.cf[d];
+            const bool act = s_active[d];
+            const double al = s_alpha[d], be = s_beta[d];
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                if (!own[k]) continue;
+                const double mi = Mv[cell[k]];
+                const double ni = mi - cf * (ke[k] * (Mv[ie[k]] - mi) - kw[k] * (mi - Mv[iw[k]]) +
+                                             kn[k] * (Mv[in_[k]] - mi) - ks[k] * (mi - Mv[is_[k]]));
+                const double z1 = ni + be * zz[d][k];
+                const double q1 = mi + be * qq[d][k];
+                const double s1 = w[d][k] + be * ss[d][k];
+                const double p1 = u[d][k] + be * pp[d][k];
+                zz[d][k] = act ? z1 : zz[d][k];
+                qq[d][k] = act ? q1 : qq[d][k];
+                ss[d][k] = act ? s1 : ss[d][k];
+                pp[d][k] = act ? p1 : pp[d][k];
+                x[d][k] = act ? x[d][k] + al * p1 : x[d][k];
+                r[d][k] = act ? r[d][k] - al * s1 : r[d][k];
+                u[d][k] = act ? u[d][k] - al * q1 : u[d][k];
+                w[d][k] = act ? w[d][k] - al * z1 : w[d][k];
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < NFD; ++d) {
+        const size_t o = (size_t)a.fmap[d] * a.n;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+            if (own[k]) a.x[o + cell[k]] = x[d][k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.info[0] = it;
+        int any = 0;
+        for (int d = 0; d < NFD; ++d) any |= s_active[d];
+        a.info[1] = (it == a.maxit) ? any : 0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
@@ -596,18 +842,53 @@ int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
     int dev = 0, cus = 0, per = 0;
     MISDC_HIP(hipGetDevice(&dev));
     MISDC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cg_kernel, CG_THREADS, 0));
-    if (per < 1)
-        return fail(MISDC_EDEVICE, "CG kernel cannot be resident (occupancy %d)", per);
-    // one resident block per CU: co-residency of the whole grid is guaranteed
-    // even while other kernels occupy part of each CU
-    int blocks = cus;
-    const int64_t need = (n + CG_THREADS - 1) / CG_THREADS;
-    if (blocks > need) blocks = (int)need;
-    if (blocks < 1) blocks = 1;
-    w.blocks = blocks;
+    // At most one block per CU: the whole grid is co-resident even while
+    // other kernels occupy part of every CU, so the grid barrier always
+    // completes.  The register-resident kernel is used when every cell fits
+    // in CPT <= 4 registers slots per thread of such a grid.
+    w.variant = 0;
+    const char* force = std::getenv("MISDC_FORCE_CG_GLOBAL");   // test switch
+    const bool allow_regs = !(force && force[0] == '1');
+    if (allow_regs && NF - 1 == 9 && g.dim == 2 && g.n_flames == 0) {
+        // blocks of CG_REGS_BS threads; grid barriers cost less with fewer
+        // blocks, so take the fewest cells per thread that keeps the grid at
+        // most half the CUs, else at most all of them
+        const int cpts[3] = {1, 2, 4};
+        for (int pass = 0; pass < 2 && w.variant == 0; ++pass) {
+            int64_t cap = pass == 0 ? cus / 2 : cus;
+            if (cap > CG_MAX_BLOCKS) cap = CG_MAX_BLOCKS;
+            for (int c : cpts) {
+                const int bs = cg_regs_block(c);
+                const int64_t blocks = (n + (int64_t)bs * c - 1) / ((int64_t)bs * c);
+                if (blocks > cap) continue;
+                int occ = 0;
+                if (c == 1)
+                    MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 1, 512>, bs, 0));
+                else if (c == 2)
+                    MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 2, 256>, bs, 0));
+                else
+                    MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 4, 256>, bs, 0));
+                if (occ >= 1) {
+                    w.variant = c;
+                    w.blocks = (int)blocks;
+                }
+                break;
+            }
+        }
+    }
+    if (w.variant == 0) {
+        MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cg_kernel, CG_THREADS, 0));
+        if (per < 1)
+            return fail(MISDC_EDEVICE, "CG kernel cannot be resident (occupancy %d)", per);
+        int blocks = cus;
+        const int64_t need = (n + CG_THREADS - 1) / CG_THREADS;
+        if (blocks > need) blocks = (int)need;
+        if (blocks < 1) blocks = 1;
+        w.blocks = blocks;
+    }
     w.threads = CG_THREADS;
-    MISDC_HIP(hipMalloc(&w.partial, sizeof(double) * (size_t)blocks * CG_MAX_FIELDS * 4));
+    MISDC_HIP(hipMalloc(&w.partial, sizeof(double) * 2 * (size_t)CG_MAX_BLOCKS * CG_MAX_FIELDS * 4));
+    MISDC_HIP(hipMalloc(&w.totals, sizeof(double) * CG_MAX_FIELDS * 4));
     MISDC_HIP(hipMalloc(&w.barrier, sizeof(unsigned) * 4));
     MISDC_HIP(hipMemset(w.barrier, 0, sizeof(unsigned) * 4));
     MISDC_HIP(hipMalloc(&w.info, sizeof(int32_t) * 4));
@@ -617,7 +898,7 @@ int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
 }
 
 void diffusion_work_free(DiffusionWork& w) {
-    double* ptrs[] = {w.theta, w.Kx, w.Ky, w.x, w.r, w.z, w.p, w.q, w.partial};
+    double* ptrs[] = {w.theta, w.Kx, w.Ky, w.x, w.r, w.z, w.p, w.q, w.partial, w.totals};
     for (double* p : ptrs)
         if (p) (void)hipFree(p);
     if (w.barrier) (void)hipFree(w.barrier);
@@ -633,7 +914,7 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
     if (n == 0) return MISDC_OK;
     const GridDev gd = grid_dev(g);
     hipLaunchKernelGGL(faces_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, gd, n, T_lag,
-                       w.theta, w.Kx, w.Ky);
+                       w.theta, w.Kx, w.Ky, w.barrier);
     MISDC_HIP(hipGetLastError());
     if (core_begin) MISDC_HIP(hipEventRecord(core_begin, s));
     const int NF = m.dev.N + 1;
@@ -663,13 +944,19 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
         a.p = w.p;
         a.q = w.q;
         a.partial = w.partial;
+        a.totals = w.totals;
         a.bar = w.barrier;
         a.info = w.info;
         const double rt = rtol > 0 ? rtol : 1e-13;
         a.rtol2 = rt * rt;
         a.maxit = maxit > 0 ? maxit : 500;
         a.guess_in_x = guess_in_y;
-        hipLaunchKernelGGL(cg_kernel, dim3(w.blocks), dim3(CG_THREADS), 0, s, a);
+        switch (w.variant) {
+            case 1: hipLaunchKernelGGL((cg_regs_kernel<9, 1, 512>), dim3(w.blocks), dim3(512), 0, s, a); break;
+            case 2: hipLaunchKernelGGL((cg_regs_kernel<9, 2, 256>), dim3(w.blocks), dim3(256), 0, s, a); break;
+            case 4: hipLaunchKernelGGL((cg_regs_kernel<9, 4, 256>), dim3(w.blocks), dim3(256), 0, s, a); break;
+            default: hipLaunchKernelGGL(cg_kernel, dim3(w.blocks), dim3(CG_THREADS), 0, s, a); break;
+        }
         MISDC_HIP(hipGetLastError());
     }
     if (core_end) MISDC_HIP(hipEventRecord(core_end, s));

@@ -253,6 +253,13 @@ def test_step_parity(nat, mech9, mh, case):
     assert err <= TOL, err
 
 
+def test_step_parity_global_memory_cg(nat, mech9, mh, monkeypatch):
+    """The CG variant that keeps its vectors in global memory (used when the
+    register-resident one does not fit) gives the same step."""
+    monkeypatch.setenv("MISDC_FORCE_CG_GLOBAL", "1")
+    test_step_parity(nat, mech9, mh, STEP_CASES[3])
+
+
 def test_concurrent_equals_serialized_bitwise(nat, mech9, mh):
     Y, T = synth.flame_2d(mech9, 40, 32)
     outs = []
