@@ -14,6 +14,7 @@
 #include <cstdlib>
 
 #include "misdc_impl.h"
+#include "wave.h"
 
 namespace misdc {
 
@@ -561,7 +562,7 @@ __device__ __forceinline__ void grid_allreduce(const CGArgs& a, unsigned k, int 
     for (int t = wave; t < nslots; t += NW) {
         double v = 0.0;
         for (unsigned b = lane; b < nb; b += 64) v += stage[b * nslots + t];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        v = wave_sum(v);
         if (lane == 0) tot[t] = v;
     }
     __syncthreads();
@@ -569,7 +570,7 @@ __device__ __forceinline__ void grid_allreduce(const CGArgs& a, unsigned k, int 
 
 template <int BS>
 __device__ __forceinline__ void wave_put(double v, double* red, int slot) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) red[slot * (BS / 64) + (threadIdx.x >> 6)] = v;
 }
 
@@ -587,7 +588,7 @@ __global__ void __launch_bounds__(BS) cg_regs_kernel(CGArgs a) {
     __shared__ double red[NS * (BS / 64)];
     __shared__ double tot[NS];
     __shared__ double s_bb[NFD], s_gprev[NFD], s_aprev[NFD], s_alpha[NFD], s_beta[NFD];
-    __shared__ int s_active[NFD], s_any;
+    __shared__ int s_active[NFD];
     const unsigned nb = gridDim.x;
     const int64_t T = (int64_t)gridDim.x * BS;
     const int64_t t0 = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -667,31 +668,31 @@ __global__ void __launch_bounds__(BS) cg_regs_kernel(CGArgs a) {
             wave_put<BS>(rr, red, 3 * d + 2);
         }
         grid_allreduce<BS>(a, kb++, NS, red, stage, tot);
-        if (threadIdx.x == 0) {
-            int any = 0;
-            for (int d = 0; d < NFD; ++d) {
-                const double g = tot[3 * d], de = tot[3 * d + 1], rr = tot[3 * d + 2];
-                const int act = rr > a.rtol2 * s_bb[d];
-                double al = 0.0, be = 0.0;
-                if (act) {
-                    if (it == 0) {
-                        al = g / de;
-                    } else {
-                        be = g / s_gprev[d];
-                        al = g / (de - be * g / s_aprev[d]);
-                    }
-                    s_gprev[d] = g;
-                    s_aprev[d] = al;
+        // recurrence coefficients, one thread per field
+        if (threadIdx.x < NFD) {
+            const int d = threadIdx.x;
+            const double g = tot[3 * d], de = tot[3 * d + 1], rr = tot[3 * d + 2];
+            const int act = rr > a.rtol2 * s_bb[d];
+            double al = 0.0, be = 0.0;
+            if (act) {
+                if (it == 0) {
+                    al = g / de;
+                } else {
+                    be = g / s_gprev[d];
+                    al = g / (de - be * g / s_aprev[d]);
                 }
-                s_active[d] = act;
-                s_alpha[d] = al;
-                s_beta[d] = be;
-                any |= act;
+                s_gprev[d] = g;
+                s_aprev[d] = al;
             }
-            s_any = any;
+            s_active[d] = act;
+            s_alpha[d] = al;
+            s_beta[d] = be;
         }
         __syncthreads();
-        if (!s_any) break;
+        int any = 0;
+#pragma unroll
+        for (int d = 0; d < NFD; ++d) any |= s_active[d];
+        if (!any) break;
         // ---- n = A m ; recurrences ----
 #pragma unroll
         for (int d = 0; d < NFD; ++d) {
