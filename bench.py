@@ -37,6 +37,22 @@ NEWTON_FLOP_PER_ITER_9 = 3.4e3
 NEWTON_BYTES_PER_SOLVE_9 = 316.0
 
 
+def measured_traffic(profile_name, source_rel):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", profile_name)
+    try:
+        text = open(path).read()
+        sha = re.search(r"source_sha1: ([0-9a-f]+)", text).group(1)
+        val = float(re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text).group(1))
+        cur = hashlib.sha1(open(os.path.join(ROOT, source_rel), "rb").read()).hexdigest()
+    except (OSError, AttributeError, ValueError):
+        return None
+    return val if cur == sha else None
+
+
 def workload():
     import synth
     c = synth.config("flame2d_256")
@@ -107,7 +123,19 @@ def main():
     ap.add_argument("--no-gate", action="store_true")
     ap.add_argument("--nu", type=int, default=None)
     ap.add_argument("--serialize", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device-to-device 4 times (calibrates the HBM "
+                         "byte counters of rocprofv3 --pmc) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": src.numel() * 8, "copies": 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               f"design is described in DESIGN.md and not built", file=sys.stderr)
@@ -163,9 +191,12 @@ def main():
         unknowns = 8 * n + n            # 8 diffused species + enthalpy
         traffic = CG_BYTES_PER_UNKNOWN_ITER * unknowns * cg_per_solve
         achieved = traffic / avg_s / 1e9
-        roof = {"kernel": "cg_kernel (batched Jacobi-PCG, implicit diffusion)",
+        roof = {"kernel": "cg_regs_kernel<9,1,512> (batched pipelined Jacobi-PCG, implicit "
+                          "diffusion of 9 fields)",
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic("pmc_cg_kernel_flame2d_256.md",
+                                            "paper_1801_01201_amd/csrc/transport.hip"),
                 "avg_launch_ms": avg_s * 1e3, "launches": d_n,
                 "algorithmic_bytes_per_launch": traffic,
                 "cg_iterations_per_launch": cg_per_solve}
