@@ -231,7 +231,12 @@ typedef struct {
     double cg_rtol;      /* 2-D diffusion CG tolerance (<= 0: 1e-13) */
     int32_t cg_maxit;    /* (<= 0: 500) */
     int32_t profile;     /* 1: time every diffusion-solve and Newton kernel with
-                            HIP events on the stream it runs on (see stats) */
+                            HIP events on the stream it runs on (see stats);
+                            ignored while use_graph is set */
+    int32_t use_graph;   /* 1: capture a whole step (both streams and their
+                            event dependencies) into one HIP graph on its first
+                            call and replay it while dev_state, dt and dev_dt
+                            are unchanged; a change re-captures */
 } misdc_opts;
 
 /* Fills the defaults: 5 nodes, 6 sweeps, nu 1, CISDCQ, cumulative QE. */
@@ -247,9 +252,43 @@ int misdc_integ_destroy(misdc_integ_t integ);
  * grid a device array of one dt per flame, in which case dt is ignored):
  * I1-I2 spread the state to every node, I4 evaluates FA, FD, FR at it, K
  * sweeps, and the state at node M is written back to dev_state in place.
- * Ordered after prior work on ``stream`` and before later work on it. */
+ * With per-flame step sizes every term of the sweep that carries dt (the
+ * quadrature and correction terms, the implicit factors of the diffusion and
+ * reaction solves) takes the dt of the cell's flame, so each flame advances
+ * exactly as it would alone.  dev_dt is read by the device during the step
+ * and must stay valid until the step has completed on ``stream``.
+ * Ordered after prior work on ``stream`` and before later work on it.
+ * Errors: MISDC_EINVAL (NULL state, dt <= 0 without dev_dt, dev_dt on a grid
+ * that is not an ensemble). */
 int misdc_step(misdc_integ_t integ, double* dev_state, double dt,
                const double* dev_dt, void* stream);
+
+/* Launch configuration of an integrator, chosen by misdc_autotune or set by
+ * the caller.  Results agree to the solvers' tolerances across choices;
+ * the choice only changes speed. */
+typedef struct {
+    int32_t cg_variant;   /* 2-D diffusion: 0 vectors in global memory, 1/2/4
+                             cells per thread held in registers */
+    int32_t cg_blocks;    /* workgroups of the 2-D diffusion solve (<= CUs) */
+    int32_t cyclic;       /* 1-D diffusion: 0 one thread per periodic system,
+                             1 one wavefront per system (partition method) */
+    int32_t serialize;    /* 1: both tasks on one stream */
+    double step_ms;       /* measured by misdc_autotune: mean time of one step */
+} misdc_tune;
+
+/* Times candidate launch configurations on the caller's workload (reps steps
+ * each, after one warm-up step, on a private copy of dev_state, which is not
+ * modified), keeps the fastest one in the integrator and returns it in
+ * *best.  Candidates: for 2-D grids every register-resident CG variant that
+ * fits with 1/4, 1/2 and all of the CUs, and the global-memory variant; for
+ * 1-D grids and ensembles both cyclic solvers; each with one and two
+ * streams.  Synchronises; allocates a state copy.  Errors as misdc_step. */
+int misdc_autotune(misdc_integ_t integ, const double* dev_state, double dt,
+                   const double* dev_dt, int reps, misdc_tune* best, void* stream);
+/* Reads / sets the launch configuration (set: MISDC_EINVAL if the CG
+ * variant cannot hold the grid or the block count exceeds the CUs). */
+int misdc_get_tune(misdc_integ_t integ, misdc_tune* tune);
+int misdc_set_tune(misdc_integ_t integ, const misdc_tune* tune);
 
 /* Statistics of the last step (synchronises with the integrator's streams).
  * sweep_increment[k] = max over fields of max_i |phi^{M,(k+1)} - phi^{M,(k)}|

@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(64) newton_kernel(MechDev m, NewtonArgs a) {
     constexpr int NX = NS + 1;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-    const double c = a.c ? a.c[i] : a.c_scalar;
+    const double c = a.c ? a.c[i] * a.c_scalar : a.c_scalar;
     const double h = a.h[i];
     double bY[NS], Y[NS], lo[NS];
 #pragma unroll

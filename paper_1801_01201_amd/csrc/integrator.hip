@@ -78,7 +78,8 @@ struct misdc_integ_s {
     Tables tab;
     int M = 0, N = 0, NF = 0, nu = 1, levels = 2;
     int64_t n = 0;
-    hipStream_t sD = nullptr, sR = nullptr;
+    hipStream_t sD = nullptr, sR = nullptr;       // sR is sR2, or sD when serialised
+    hipStream_t sR2 = nullptr;
     std::vector<std::vector<NodeBuf>> lev;        // [levels][M+1]
     std::vector<double*> phiAD, TAD, hatA, hatD;  // [M+1]
     std::vector<double*> C, CR;                   // [M+1] sweep constants (diffusion, reaction)
@@ -105,6 +106,19 @@ struct misdc_integ_s {
     std::vector<hipEvent_t> ev_pool;
     double t_ms[2] = {0.0, 0.0};                  // [0] diffusion solve, [1] Newton
     int64_t t_cnt[2] = {0, 0};
+    // per-flame step sizes of an ensemble: dtf (flames, caller's array) and
+    // its per-cell expansion dtc; both null for a scalar step
+    const double* dtf = nullptr;
+    const double* dtc = nullptr;
+    double* dt_cell = nullptr;
+    double tuned_ms = 0.0;                        // step time measured by the autotuner
+    // graph of one whole step, replayed while (state, dt, dev_dt) are unchanged
+    bool capturing = false;
+    hipGraphExec_t gexec = nullptr;
+    const double* g_state = nullptr;
+    double g_dt = 0.0;
+    const double* g_dtf = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     hipEvent_t& D_ev(int l, int p) { return evD[(size_t)l * (M + 1) + p]; }
     hipEvent_t& R_ev(int l, int p) { return evR[(size_t)l * (M + 1) + p]; }
@@ -210,32 +224,49 @@ int dalloc(misdc_integ_s* I, T** p, size_t count) {
     return MISDC_OK;
 }
 
-// Linear combination builder.
+// Linear combination builder.  Terms added with addS carry a factor of the
+// step size: with a scalar step it is folded into the weight (dts * w), with
+// per-cell step sizes (ensembles) the kernel multiplies by dtc[cell].
 struct LC {
     LinComb lc;
-    explicit LC(int nfields, int64_t n) {
+    double dts = 1.0;
+    const double* dtc = nullptr;
+    LC(int nfields, int64_t n, double dt_scalar, const double* dt_cell) {
         std::memset(&lc, 0, sizeof(lc));
         lc.nfields = nfields;
         lc.ncells = n;
+        dts = dt_cell ? 1.0 : dt_scalar;
+        dtc = dt_cell;
+        lc.scale = dt_cell;
     }
     int out(double* p) {
         lc.out[lc.nout] = p;
         return lc.nout++;
     }
     // add weight w (to output o) of array X with nf fields; merges duplicates
-    void add(int o, double w, const double* X, int nf) {
+    bool sc[LC_MAX_TERMS] = {};
+    void put(int o, double w, const double* X, int nf, bool scaled) {
         if (w == 0.0 || !X) return;
         for (int t = 0; t < lc.nterms; ++t)
-            if (lc.X[t] == X) {
+            if (lc.X[t] == X && sc[t] == scaled) {
                 lc.W[o][t] += w;
                 return;
             }
+        // more terms than the kernel takes: launch_lincomb reports it
+        if (lc.nterms >= LC_MAX_TERMS) {
+            lc.nterms = LC_MAX_TERMS + 1;
+            return;
+        }
         const int t = lc.nterms++;
         lc.X[t] = X;
         lc.nf[t] = nf;
+        sc[t] = scaled;
         for (int q = 0; q < LC_MAX_OUT; ++q) lc.W[q][t] = 0.0;
         lc.W[o][t] = w;
+        if (scaled && dtc) lc.smask |= 1u << t;
     }
+    void add(int o, double w, const double* X, int nf) { put(o, w, X, nf, false); }
+    void addS(int o, double w, const double* X, int nf) { put(o, dts * w, X, nf, true); }
 };
 
 int eval_ops(misdc_integ_s* I, const NodeBuf& b, double* th, hipStream_t s, bool with_R) {
@@ -277,7 +308,7 @@ int drain_timing(misdc_integ_s* I) {
 
 // Records a start event when profiling; returns it (or null).
 hipEvent_t timing_begin(misdc_integ_s* I, hipStream_t s) {
-    if (!I->opt.profile) return nullptr;
+    if (!I->opt.profile || I->capturing) return nullptr;
     hipEvent_t e = pool_event(I);
     if (e && hipEventRecord(e, s) != hipSuccess) return nullptr;
     return e;
@@ -299,55 +330,55 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     auto& L0 = I->lev[0];
     auto& Lc = I->lev[ell + 1];       // iteration ell+1 (serial schemes: the new sweep)
     auto& Lp = I->lev[ell];           // iteration ell (lagged); ell = 0: sweep k
-    LC b(NF, n);
+    LC b(NF, n, dt, I->dtc);
     const int o = b.out(I->rD);
-    double c = 0.0;
+    double cf = 0.0;                  // implicit factor c = dt * cf
     const double* T_lag = nullptr;
     if (I->opt.scheme == MISDC_SCHEME_MISDC) {
-        const double dtm = dt * (t.tau[p] - t.tau[p - 1]);
-        c = dtm;
+        cf = t.tau[p] - t.tau[p - 1];
         // phi^{m,(k+1)} + dt^m FA(phi^{m,(k+1)}) + [constant part in C]
         // (the advection bracket at node 0 vanishes: phi^0 is fixed)
         b.add(o, 1.0, I->C[p], NF);
         b.add(o, 1.0, (m == 0) ? L0[0].phi : Lc[m].phi, NF);
-        if (m >= 1) b.add(o, dtm, Lc[m].FA, NF);
+        if (m >= 1) b.addS(o, cf, Lc[m].FA, NF);
         T_lag = L0[p].T;
     } else if (I->opt.scheme == MISDC_SCHEME_MISDCQ) {
-        c = dt * t.QI[p - 1][p - 1];
+        cf = t.QI[p - 1][p - 1];
         b.add(o, 1.0, I->C[p], NF);
         for (int j = 1; j <= m; ++j) {
-            b.add(o, dt * t.QE[p - 1][j - 1], Lc[j].FA, NF);
-            b.add(o, dt * t.QI[p - 1][j - 1], Lc[j].FD, NF);
+            b.addS(o, t.QE[p - 1][j - 1], Lc[j].FA, NF);
+            b.addS(o, t.QI[p - 1][j - 1], Lc[j].FD, NF);
         }
         T_lag = L0[p].T;
     } else {
-        c = dt * t.QI[p - 1][p - 1];
+        cf = t.QI[p - 1][p - 1];
         b.add(o, 1.0, I->C[p], NF);
         for (int j = 1; j <= m - 1; ++j) {
-            b.add(o, dt * t.QE[p - 1][j - 1], Lc[j].FA, NF);
-            b.add(o, dt * t.QI[p - 1][j - 1], Lc[j].FD, NF);
-            b.add(o, dt * t.QI[p - 1][j - 1], Lc[j].FR, N);
+            b.addS(o, t.QE[p - 1][j - 1], Lc[j].FA, NF);
+            b.addS(o, t.QI[p - 1][j - 1], Lc[j].FD, NF);
+            b.addS(o, t.QI[p - 1][j - 1], Lc[j].FR, N);
         }
         if (m >= 1) {
             const double* lagA = (ell == 0) ? I->hatA[m] : Lp[m].FA;
             const double* lagD = (ell == 0) ? I->hatD[m] : Lp[m].FD;
-            b.add(o, dt * t.QE[p - 1][m - 1], lagA, NF);
-            b.add(o, dt * t.QI[p - 1][m - 1], lagD, NF);
-            b.add(o, dt * t.QI[p - 1][m - 1], Lp[m].FR, N);
+            b.addS(o, t.QE[p - 1][m - 1], lagA, NF);
+            b.addS(o, t.QI[p - 1][m - 1], lagD, NF);
+            b.addS(o, t.QI[p - 1][m - 1], Lp[m].FR, N);
         }
-        b.add(o, c, Lp[p].FR, N);
+        b.addS(o, cf, Lp[p].FR, N);
         T_lag = (ell == 0) ? L0[p].T : Lp[p].T;
     }
     int rc = launch_lincomb(b.lc, I->sD);
     if (rc) return rc;
     // initial guess of the iterative solve: the lagged state at this node
     const double* guess = (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell > 0) ? Lp[p].phi : L0[p].phi;
-    MISDC_HIP(hipMemcpyAsync(I->phiAD[p], guess, sizeof(double) * NF * n, hipMemcpyDeviceToDevice,
-                             I->sD));
+    rc = launch_copy(I->phiAD[p], guess, (int64_t)NF * n, I->sD);
+    if (rc) return rc;
     // with profiling, the events bracket the solve kernel itself (CG or cyclic)
-    hipEvent_t t0 = I->opt.profile ? pool_event(I) : nullptr;
-    hipEvent_t t1 = I->opt.profile ? pool_event(I) : nullptr;
-    rc = launch_diffusion_solve(*I->mech, *I->grid, I->dw, c, nullptr, 0.0, T_lag, I->rD,
+    const bool timed = I->opt.profile && !I->capturing;
+    hipEvent_t t0 = timed ? pool_event(I) : nullptr;
+    hipEvent_t t1 = timed ? pool_event(I) : nullptr;
+    rc = launch_diffusion_solve(*I->mech, *I->grid, I->dw, dt * cf, I->dtf, cf, T_lag, I->rD,
                                 I->phiAD[p], 1, I->opt.cg_rtol, I->opt.cg_maxit, I->sD, t0, t1);
     if (rc) return rc;
     if (t0 && t1) I->timed.push_back({t0, t1, 0});
@@ -376,38 +407,39 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     auto& L0 = I->lev[0];
     auto& Lc = I->lev[ell + 1];
     auto& Lp = I->lev[ell];
-    LC b(N, n);
+    LC b(N, n, dt, I->dtc);
     const int o = b.out(I->bR);
-    double c = 0.0;
+    double cf = 0.0;                  // implicit factor c = dt * cf
     b.add(o, 1.0, I->phiAD[p], N);
     if (I->opt.scheme == MISDC_SCHEME_MISDC) {
-        c = dt * (t.tau[p] - t.tau[p - 1]);
-        b.add(o, -c, L0[p].FR, N);
+        cf = t.tau[p] - t.tau[p - 1];
+        b.addS(o, -cf, L0[p].FR, N);
     } else if (I->opt.scheme == MISDC_SCHEME_MISDCQ) {
-        c = dt * t.QI[p - 1][p - 1];
+        cf = t.QI[p - 1][p - 1];
         b.add(o, 1.0, I->CR[p], N);
-        for (int j = 1; j <= m; ++j) b.add(o, dt * t.QI[p - 1][j - 1], Lc[j].FR, N);
+        for (int j = 1; j <= m; ++j) b.addS(o, t.QI[p - 1][j - 1], Lc[j].FR, N);
     } else {
-        c = dt * t.QI[p - 1][p - 1];
+        cf = t.QI[p - 1][p - 1];
         if (m >= 1) {
-            b.add(o, dt * t.QI[p - 1][m - 1], Lc[m].FR, N);
-            b.add(o, -dt * t.QI[p - 1][m - 1], Lp[m].FR, N);
+            b.addS(o, t.QI[p - 1][m - 1], Lc[m].FR, N);
+            b.addS(o, -t.QI[p - 1][m - 1], Lp[m].FR, N);
         }
-        b.add(o, -c, Lp[p].FR, N);
+        b.addS(o, -cf, Lp[p].FR, N);
     }
     int rc = launch_lincomb(b.lc, I->sR);
     if (rc) return rc;
     NodeBuf& out = Lc[p];
     // enthalpy is not changed by the reaction step
-    MISDC_HIP(hipMemcpyAsync(out.phi + (size_t)N * n, I->phiAD[p] + (size_t)N * n,
-                             sizeof(double) * n, hipMemcpyDeviceToDevice, I->sR));
+    rc = launch_copy(out.phi + (size_t)N * n, I->phiAD[p] + (size_t)N * n, n, I->sR);
+    if (rc) return rc;
     NewtonArgs a;
     a.n = n;
     a.bY = I->bR;
     a.ldb = n;
     a.h = I->phiAD[p] + (size_t)N * n;
-    a.c = nullptr;
-    a.c_scalar = c;
+    // c = dt * cf: per cell for ensembles with per-flame step sizes
+    a.c = I->dtc;
+    a.c_scalar = I->dtc ? cf : dt * cf;
     a.guess = Lp[p].phi;
     a.ldg = n;
     a.Y = out.phi;
@@ -448,41 +480,41 @@ int sweep_constants(misdc_integ_s* I, double dt) {
     const int64_t n = I->n;
     const Tables& t = I->tab;
     auto& L0 = I->lev[0];
-    LC b(NF, n);
+    LC b(NF, n, dt, I->dtc);
     for (int p = 1; p <= M; ++p) {
         const int o = b.out(I->C[p]);
         if (I->opt.scheme == MISDC_SCHEME_MISDC) {
             // dt S^{m:m+1} F^{(k)} - dt^m FA^{m,(k)} - dt^m FD^{p,(k)}
-            const double dtm = dt * (t.tau[p] - t.tau[p - 1]);
+            const double cm = t.tau[p] - t.tau[p - 1];
             for (int j = 0; j <= M; ++j) {
-                b.add(o, dt * t.S[p - 1][j], L0[j].FA, NF);
-                b.add(o, dt * t.S[p - 1][j], L0[j].FD, NF);
-                b.add(o, dt * t.S[p - 1][j], L0[j].FR, N);
+                b.addS(o, t.S[p - 1][j], L0[j].FA, NF);
+                b.addS(o, t.S[p - 1][j], L0[j].FD, NF);
+                b.addS(o, t.S[p - 1][j], L0[j].FR, N);
             }
-            if (p - 1 >= 1) b.add(o, -dtm, L0[p - 1].FA, NF);
-            b.add(o, -dtm, L0[p].FD, NF);
+            if (p - 1 >= 1) b.addS(o, -cm, L0[p - 1].FA, NF);
+            b.addS(o, -cm, L0[p].FD, NF);
         } else {
             b.add(o, 1.0, L0[0].phi, NF);
             for (int j = 0; j <= M; ++j) {
-                b.add(o, dt * t.Q[p - 1][j], L0[j].FA, NF);
-                b.add(o, dt * t.Q[p - 1][j], L0[j].FD, NF);
-                b.add(o, dt * t.Q[p - 1][j], L0[j].FR, N);
+                b.addS(o, t.Q[p - 1][j], L0[j].FA, NF);
+                b.addS(o, t.Q[p - 1][j], L0[j].FD, NF);
+                b.addS(o, t.Q[p - 1][j], L0[j].FR, N);
             }
-            for (int j = 1; j <= p - 1; ++j) b.add(o, -dt * t.QE[p - 1][j - 1], L0[j].FA, NF);
+            for (int j = 1; j <= p - 1; ++j) b.addS(o, -t.QE[p - 1][j - 1], L0[j].FA, NF);
             const bool with_R = (I->opt.scheme == MISDC_SCHEME_CISDCQ);
             for (int j = 1; j <= p; ++j) {
-                b.add(o, -dt * t.QI[p - 1][j - 1], L0[j].FD, NF);
-                if (with_R) b.add(o, -dt * t.QI[p - 1][j - 1], L0[j].FR, N);
+                b.addS(o, -t.QI[p - 1][j - 1], L0[j].FD, NF);
+                if (with_R) b.addS(o, -t.QI[p - 1][j - 1], L0[j].FR, N);
             }
         }
     }
     int rc = launch_lincomb(b.lc, I->sD);
     if (rc) return rc;
     if (I->opt.scheme == MISDC_SCHEME_MISDCQ) {
-        LC r(N, n);
+        LC r(N, n, dt, I->dtc);
         for (int p = 1; p <= M; ++p) {
             const int o = r.out(I->CR[p]);
-            for (int j = 1; j <= p; ++j) r.add(o, -dt * t.QI[p - 1][j - 1], L0[j].FR, N);
+            for (int j = 1; j <= p; ++j) r.addS(o, -t.QI[p - 1][j - 1], L0[j].FR, N);
         }
         rc = launch_lincomb(r.lc, I->sD);
         if (rc) return rc;
@@ -538,6 +570,77 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
     // S7: the last nested iteration becomes sweep k+1 (swap buffer sets)
     for (int p = 1; p <= M; ++p) std::swap(I->lev[0][p], I->lev[lv][p]);
     MISDC_HIP(hipEventRecord(I->R_ev(0, M), I->sR));
+    return MISDC_OK;
+}
+
+// Validates the arguments of a step (also used by the autotuner).
+int check_step_args(misdc_integ_s* I, const double* state, double dt, const double* dev_dt) {
+    if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
+    if (!state) return fail(MISDC_EINVAL, "state is NULL");
+    if (dev_dt) {
+        if (I->grid->n_flames == 0)
+            return fail(MISDC_EINVAL, "per-flame step sizes need an ensemble grid");
+    } else if (!(dt > 0) || !std::isfinite(dt)) {
+        return fail(MISDC_EINVAL, "dt must be positive and finite");
+    }
+    return MISDC_OK;
+}
+
+void drop_graph(misdc_integ_s* I) {
+    if (I->gexec) (void)hipGraphExecDestroy(I->gexec);
+    I->gexec = nullptr;
+    I->g_state = nullptr;
+    I->g_dtf = nullptr;
+    I->g_dt = 0.0;
+}
+
+// Issues one step on the integrator's streams.  sD is the origin: the
+// reaction stream forks from it at the start and joins it at the end, so the
+// whole step can be captured from sD into one graph.  Only kernels, event
+// records and event waits are issued (no memset or memcpy nodes).
+int issue_step(misdc_integ_s* I, double* state, double dt, const double* dtf) {
+    const int M = I->M, N = I->N, NF = I->NF;
+    const int64_t n = I->n;
+    int rc;
+    if (I->sR != I->sD) {
+        MISDC_HIP(hipEventRecord(I->ev_fork, I->sD));
+        MISDC_HIP(hipStreamWaitEvent(I->sR, I->ev_fork, 0));
+    }
+    I->dtf = dtf;
+    I->dtc = nullptr;
+    if (dtf) {
+        if ((rc = launch_expand_flames(*I->grid, dtf, I->dt_cell, I->sD))) return rc;
+        I->dtc = I->dt_cell;
+        dt = 1.0;      // every dt-carrying term takes dtc[cell] (or dtf[flame])
+    }
+    if ((rc = launch_zero(I->nstats, 4 * sizeof(unsigned long long), I->sD))) return rc;
+    if ((rc = launch_zero(I->cgstats, 8 * sizeof(int32_t), I->sD))) return rc;
+    // I1, I2, I4: every node of sweep 0 holds phi^n and F(phi^n)
+    NodeBuf& b0 = I->lev[0][0];
+    if ((rc = launch_copy(b0.phi, state, (int64_t)NF * n, I->sD))) return rc;
+    if ((rc = launch_state_temperature(*I->mech, n, b0.phi, b0.T, I->sD))) return rc;
+    if ((rc = eval_ops(I, b0, I->thD, I->sD, true))) return rc;
+    for (int p = 1; p <= M; ++p) {
+        NodeBuf& b = I->lev[0][p];
+        if ((rc = launch_copy(b.phi, b0.phi, (int64_t)NF * n, I->sD))) return rc;
+        if ((rc = launch_copy(b.T, b0.T, n, I->sD))) return rc;
+        if ((rc = launch_copy(b.FA, b0.FA, (int64_t)NF * n, I->sD))) return rc;
+        if ((rc = launch_copy(b.FD, b0.FD, (int64_t)NF * n, I->sD))) return rc;
+        if ((rc = launch_copy(b.FR, b0.FR, (int64_t)N * n, I->sD))) return rc;
+    }
+    // node 0 is shared by every nested-iteration level
+    for (int l = 1; l < I->levels; ++l) I->lev[l][0] = b0;
+    // "previous sweep finished" marker for the first sweep's constants
+    MISDC_HIP(hipEventRecord(I->R_ev(0, M), I->sD));
+    for (int k = 0; k < I->opt.n_sweeps; ++k) {
+        I->sweep_index = k;
+        if ((rc = run_sweep(I, k, dt))) return rc;
+    }
+    if ((rc = launch_copy(state, I->lev[0][M].phi, (int64_t)NF * n, I->sR))) return rc;
+    if (I->sR != I->sD) {
+        MISDC_HIP(hipEventRecord(I->ev_join, I->sR));
+        MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_join, 0));
+    }
     return MISDC_OK;
 }
 
@@ -708,7 +811,7 @@ int misdc_reaction_solve_batch(misdc_mech_t mech, int64_t n, const double* bY, c
     a.ldb = n;
     a.h = h;
     a.c = c;
-    a.c_scalar = 0;
+    a.c_scalar = 1.0;
     a.guess = Y;
     a.ldg = n;
     a.Y = Y;
@@ -863,6 +966,7 @@ void misdc_opts_default(misdc_opts* o) {
     o->cg_rtol = 1e-13;
     o->cg_maxit = 500;
     o->profile = 0;
+    o->use_graph = 0;
 }
 
 int misdc_integ_destroy(misdc_integ_t I);
@@ -937,14 +1041,11 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if ((rc = dalloc(I, &I->inc, (size_t)64 * NF * 2))) return bail(rc);
     if ((rc = dalloc(I, &I->inc_partial, (size_t)I->inc_blocks * NF * 2))) return bail(rc);
     if ((rc = diffusion_work_alloc(I->dw, mech->m, grid->g))) return bail(rc);
+    if (grid->g.n_flames > 0 && (rc = dalloc(I, &I->dt_cell, (size_t)n))) return bail(rc);
     hipError_t e = hipStreamCreateWithFlags(&I->sD, hipStreamNonBlocking);
-    if (e == hipSuccess) {
-        if (opts->serialize)
-            I->sR = I->sD;
-        else
-            e = hipStreamCreateWithFlags(&I->sR, hipStreamNonBlocking);
-    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->sR2, hipStreamNonBlocking);
     if (e != hipSuccess) return bail(fail(MISDC_EDEVICE, "stream: %s", hipGetErrorString(e)));
+    I->sR = opts->serialize ? I->sD : I->sR2;
     const size_t nev = (size_t)I->levels * (M + 1);
     I->evD.assign(nev, nullptr);
     I->evR.assign(nev, nullptr);
@@ -955,6 +1056,8 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_outD, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_outR, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) return bail(fail(MISDC_EDEVICE, "events: %s", hipGetErrorString(e)));
     *out = I;
     return MISDC_OK;
@@ -963,7 +1066,8 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
 int misdc_integ_destroy(misdc_integ_t I) {
     if (!I) return MISDC_OK;
     if (I->sD) (void)hipStreamSynchronize(I->sD);
-    if (I->sR && I->sR != I->sD) (void)hipStreamSynchronize(I->sR);
+    if (I->sR2) (void)hipStreamSynchronize(I->sR2);
+    if (I->gexec) (void)hipGraphExecDestroy(I->gexec);
     for (hipEvent_t ev : I->evD)
         if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : I->evR)
@@ -976,7 +1080,9 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (I->ev_in) (void)hipEventDestroy(I->ev_in);
     if (I->ev_outD) (void)hipEventDestroy(I->ev_outD);
     if (I->ev_outR) (void)hipEventDestroy(I->ev_outR);
-    if (I->sR && I->sR != I->sD) (void)hipStreamDestroy(I->sR);
+    if (I->ev_fork) (void)hipEventDestroy(I->ev_fork);
+    if (I->ev_join) (void)hipEventDestroy(I->ev_join);
+    if (I->sR2) (void)hipStreamDestroy(I->sR2);
     if (I->sD) (void)hipStreamDestroy(I->sD);
     diffusion_work_free(I->dw);
     for (void* p : I->allocs) (void)hipFree(p);
@@ -985,57 +1091,162 @@ int misdc_integ_destroy(misdc_integ_t I) {
 }
 
 int misdc_step(misdc_integ_t I, double* state, double dt, const double* dev_dt, void* stream) {
-    if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
-    if (!state) return fail(MISDC_EINVAL, "state is NULL");
-    if (dev_dt) return fail(MISDC_EUNSUPPORTED, "per-flame step sizes are not built yet");
-    if (!(dt > 0) || !std::isfinite(dt)) return fail(MISDC_EINVAL, "dt must be positive");
+    int rc = check_step_args(I, state, dt, dev_dt);
+    if (rc) return rc;
     hipStream_t cs = (hipStream_t)stream;
-    const int M = I->M, N = I->N, NF = I->NF;
-    const int64_t n = I->n;
-    const size_t fb = sizeof(double) * (size_t)NF * n;
-    int rc;
     // order after the caller's stream
     MISDC_HIP(hipEventRecord(I->ev_in, cs));
     MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_in, 0));
-    if (I->sR != I->sD) MISDC_HIP(hipStreamWaitEvent(I->sR, I->ev_in, 0));
-    MISDC_HIP(hipMemsetAsync(I->nstats, 0, 4 * sizeof(unsigned long long), I->sD));
-    MISDC_HIP(hipMemsetAsync(I->cgstats, 0, 8 * sizeof(int32_t), I->sD));
-    // I1, I2, I4: every node of sweep 0 holds phi^n and F(phi^n)
-    NodeBuf& b0 = I->lev[0][0];
-    MISDC_HIP(hipMemcpyAsync(b0.phi, state, fb, hipMemcpyDeviceToDevice, I->sD));
-    if ((rc = launch_state_temperature(*I->mech, n, b0.phi, b0.T, I->sD))) return rc;
-    if ((rc = eval_ops(I, b0, I->thD, I->sD, true))) return rc;
-    for (int p = 1; p <= M; ++p) {
-        NodeBuf& b = I->lev[0][p];
-        MISDC_HIP(hipMemcpyAsync(b.phi, b0.phi, fb, hipMemcpyDeviceToDevice, I->sD));
-        MISDC_HIP(hipMemcpyAsync(b.T, b0.T, sizeof(double) * n, hipMemcpyDeviceToDevice, I->sD));
-        MISDC_HIP(hipMemcpyAsync(b.FA, b0.FA, fb, hipMemcpyDeviceToDevice, I->sD));
-        MISDC_HIP(hipMemcpyAsync(b.FD, b0.FD, fb, hipMemcpyDeviceToDevice, I->sD));
-        MISDC_HIP(hipMemcpyAsync(b.FR, b0.FR, sizeof(double) * (size_t)N * n,
-                                 hipMemcpyDeviceToDevice, I->sD));
+    if (I->opt.use_graph) {
+        if (!I->gexec || I->g_state != state || I->g_dt != dt || I->g_dtf != dev_dt) {
+            drop_graph(I);
+            hipGraph_t graph = nullptr;
+            MISDC_HIP(hipStreamBeginCapture(I->sD, hipStreamCaptureModeThreadLocal));
+            I->capturing = true;
+            rc = issue_step(I, state, dt, dev_dt);
+            I->capturing = false;
+            hipError_t e = hipStreamEndCapture(I->sD, &graph);
+            if (rc || e != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc ? rc : fail(MISDC_EDEVICE, "step capture: %s", hipGetErrorString(e));
+            }
+            e = hipGraphInstantiate(&I->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                I->gexec = nullptr;
+                return fail(MISDC_EDEVICE, "graph instantiation: %s", hipGetErrorString(e));
+            }
+            I->g_state = state;
+            I->g_dt = dt;
+            I->g_dtf = dev_dt;
+        }
+        MISDC_HIP(hipGraphLaunch(I->gexec, I->sD));
+    } else {
+        rc = issue_step(I, state, dt, dev_dt);
+        if (rc) return rc;
     }
-    // node 0 is shared by every nested-iteration level
-    for (int l = 1; l < I->levels; ++l) I->lev[l][0] = b0;
-    // "previous sweep finished" marker for the first sweep's constants
-    MISDC_HIP(hipEventRecord(I->R_ev(0, M), I->sD));
-    for (int k = 0; k < I->opt.n_sweeps; ++k) {
-        I->sweep_index = k;
-        if ((rc = run_sweep(I, k, dt))) return rc;
-    }
-    MISDC_HIP(hipMemcpyAsync(state, I->lev[0][M].phi, fb, hipMemcpyDeviceToDevice, I->sR));
     MISDC_HIP(hipEventRecord(I->ev_outD, I->sD));
-    MISDC_HIP(hipEventRecord(I->ev_outR, I->sR));
     MISDC_HIP(hipStreamWaitEvent(cs, I->ev_outD, 0));
-    MISDC_HIP(hipStreamWaitEvent(cs, I->ev_outR, 0));
     I->last_sweeps = I->opt.n_sweeps;
     I->dt = dt;
+    return MISDC_OK;
+}
+
+int misdc_get_tune(misdc_integ_t I, misdc_tune* t) {
+    if (!I || !t) return fail(MISDC_EINVAL, "NULL argument");
+    t->cg_variant = I->dw.variant;
+    t->cg_blocks = I->dw.blocks;
+    t->cyclic = I->dw.cyclic;
+    t->serialize = I->sR == I->sD ? 1 : 0;
+    t->step_ms = I->tuned_ms;
+    return MISDC_OK;
+}
+
+int misdc_set_tune(misdc_integ_t I, const misdc_tune* t) {
+    if (!I || !t) return fail(MISDC_EINVAL, "NULL argument");
+    if (t->cyclic != 0 && t->cyclic != 1) return fail(MISDC_EINVAL, "cyclic must be 0 or 1");
+    if (t->serialize != 0 && t->serialize != 1) return fail(MISDC_EINVAL, "serialize must be 0 or 1");
+    const Grid& g = *I->grid;
+    MISDC_HIP(hipStreamSynchronize(I->sD));
+    MISDC_HIP(hipStreamSynchronize(I->sR2));
+    if (g.dim == 2 && g.n_flames == 0) {
+        DiffusionWork probe = I->dw;
+        int rc = diffusion_work_set(probe, *I->mech, g, t->cg_variant, t->cg_blocks);
+        if (rc) return rc;
+        I->dw.variant = probe.variant;
+        I->dw.blocks = probe.blocks;
+    }
+    I->dw.cyclic = t->cyclic;
+    I->sR = t->serialize ? I->sD : I->sR2;
+    drop_graph(I);
+    return MISDC_OK;
+}
+
+int misdc_autotune(misdc_integ_t I, const double* state, double dt, const double* dev_dt, int reps,
+                   misdc_tune* best, void* stream) {
+    int rc = check_step_args(I, state, dt, dev_dt);
+    if (rc) return rc;
+    if (reps < 1 || reps > 100) return fail(MISDC_EINVAL, "reps must be in [1, 100]");
+    hipStream_t cs = (hipStream_t)stream;
+    const Grid& g = *I->grid;
+    int cus = 0;
+    if ((rc = device_cus(cus))) return rc;
+    std::vector<misdc_tune> cand;
+    misdc_tune base;
+    misdc_get_tune(I, &base);
+    for (int ser = 0; ser <= 1; ++ser) {
+        misdc_tune t = base;
+        t.serialize = ser;
+        if (g.dim == 2 && g.n_flames == 0) {
+            const int cap = cus < 256 ? cus : 256;
+            if (I->N == 9)
+                for (int c : {1, 2, 4}) {
+                    const int64_t b = cg_regs_min_blocks(I->n, c);
+                    if (b <= cap) {
+                        t.cg_variant = c;
+                        t.cg_blocks = (int)b;
+                        cand.push_back(t);
+                    }
+                }
+            for (int div : {4, 2, 1}) {
+                t.cg_variant = 0;
+                t.cg_blocks = cap / div > 0 ? cap / div : 1;
+                cand.push_back(t);
+            }
+        } else {
+            for (int cy : {0, 1}) {
+                t.cyclic = cy;
+                cand.push_back(t);
+            }
+        }
+    }
+    const size_t bytes = sizeof(double) * (size_t)I->NF * I->n;
+    double* work = nullptr;
+    MISDC_HIP(hipMalloc(&work, bytes));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    const int saved_graph = I->opt.use_graph;
+    I->opt.use_graph = 0;
+    double best_ms = -1.0;
+    misdc_tune pick = base;
+    for (size_t k = 0; k < cand.size() && he == hipSuccess && !rc; ++k) {
+        if (misdc_set_tune(I, &cand[k]) != MISDC_OK) continue;   // does not fit: skip
+        he = hipMemcpyAsync(work, state, bytes, hipMemcpyDeviceToDevice, cs);
+        if (he != hipSuccess) break;
+        if ((rc = misdc_step(I, work, dt, dev_dt, stream))) break;
+        if ((he = hipEventRecord(e0, cs)) != hipSuccess) break;
+        for (int r = 0; r < reps && !rc; ++r) rc = misdc_step(I, work, dt, dev_dt, stream);
+        if (rc) break;
+        if ((he = hipEventRecord(e1, cs)) != hipSuccess) break;
+        if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        const double per = ms / reps;
+        if (best_ms < 0 || per < best_ms) {
+            best_ms = per;
+            pick = cand[k];
+            pick.step_ms = per;
+        }
+    }
+    I->opt.use_graph = saved_graph;
+    (void)hipStreamSynchronize(cs);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(work);
+    if (rc) return rc;
+    if (he != hipSuccess) return fail(MISDC_EDEVICE, "autotune: %s", hipGetErrorString(he));
+    if (best_ms < 0) return fail(MISDC_EDEVICE, "autotune: no configuration ran");
+    if ((rc = misdc_set_tune(I, &pick))) return rc;
+    I->tuned_ms = best_ms;
+    if (best) *best = pick;
     return MISDC_OK;
 }
 
 int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
     if (!I || !st) return fail(MISDC_EINVAL, "NULL argument");
     MISDC_HIP(hipStreamSynchronize(I->sD));
-    MISDC_HIP(hipStreamSynchronize(I->sR));
+    MISDC_HIP(hipStreamSynchronize(I->sR2));
     std::memset(st, 0, sizeof(*st));
     unsigned long long ns[4];
     int32_t cg[8];
@@ -1076,7 +1287,7 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
 int misdc_reset_profile(misdc_integ_t I) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
     MISDC_HIP(hipStreamSynchronize(I->sD));
-    MISDC_HIP(hipStreamSynchronize(I->sR));
+    MISDC_HIP(hipStreamSynchronize(I->sR2));
     int rc = drain_timing(I);
     if (rc) return rc;
     I->t_ms[0] = I->t_ms[1] = 0.0;

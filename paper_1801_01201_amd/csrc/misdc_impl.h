@@ -86,7 +86,7 @@ struct NewtonArgs {
     int64_t n;
     const double* bY; int64_t ldb;          // N fields
     const double* h;                        // n
-    const double* c; double c_scalar;
+    const double* c; double c_scalar;      // c = c[i] * c_scalar, or c_scalar
     const double* guess; int64_t ldg;       // N fields
     double* Y; int64_t ldy;                 // N fields out
     double* T;                              // n out (closed form of (Y, h)), may be null
@@ -97,7 +97,9 @@ struct NewtonArgs {
 };
 int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s);
 
-// out[p] = sum_t W[p][t] X_t, field-wise; X_t has nf_t fields (missing fields are zero)
+// out[p] = sum_t W[p][t] s_t X_t, field-wise; X_t has nf_t fields (missing
+// fields are zero); s_t = scale[cell] for the terms in smask (per-cell step
+// sizes of an ensemble), else 1
 constexpr int LC_MAX_TERMS = 32;
 constexpr int LC_MAX_OUT = 8;
 struct LinComb {
@@ -107,8 +109,15 @@ struct LinComb {
     int nf[LC_MAX_TERMS];
     double* out[LC_MAX_OUT];
     double W[LC_MAX_OUT][LC_MAX_TERMS];
+    const double* scale;
+    unsigned smask;
 };
 int launch_lincomb(const LinComb& lc, hipStream_t s);
+// device-side copy and fill (stream-ordered kernels, safe under graph capture)
+int launch_copy(double* dst, const double* src, int64_t count, hipStream_t s);
+int launch_zero(void* dst, int64_t bytes, hipStream_t s);
+// per-cell value of a per-flame array: out[i] = v[flame of cell i]
+int launch_expand_flames(const Grid& g, const double* v, double* out, hipStream_t s);
 
 // T (cells) from a state with N+1 fields
 int launch_state_temperature(const Mech& m, int64_t n, const double* state, double* T, hipStream_t s);
@@ -133,8 +142,14 @@ struct DiffusionWork {
     int threads = 0;
     int fields_cap = 0;
     int variant = 0;              // 0: vectors in global memory; 1, 2, 4: cells per thread in registers
+    int cyclic = 1;               // 1-D systems: 0 one thread per system, 1 one wavefront per system
 };
 int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g);
+// selects the 2-D CG variant (0 global memory, 1/2/4 cells per thread in
+// registers) and its block count, after checking that it fits
+int diffusion_work_set(DiffusionWork& w, const Mech& m, const Grid& g, int variant, int blocks);
+int64_t cg_regs_min_blocks(int64_t n, int cpt);
+int device_cus(int& cus);
 void diffusion_work_free(DiffusionWork& w);
 // Solves all N+1 fields (bath by closure); y may hold the guess (guess_in_y)
 int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, double c,

@@ -35,9 +35,11 @@ __global__ void __launch_bounds__(256) lincomb_kernel(LinComb lc) {
         double acc[LC_MAX_OUT];
 #pragma unroll
         for (int p = 0; p < LC_MAX_OUT; ++p) acc[p] = 0.0;
+        const double sc = lc.smask ? lc.scale[e - (int64_t)f * lc.ncells] : 1.0;
         for (int t = 0; t < lc.nterms; ++t) {
             if (f >= lc.nf[t]) continue;
-            const double v = lc.X[t][e];
+            double v = lc.X[t][e];
+            if ((lc.smask >> t) & 1u) v *= sc;
 #pragma unroll
             for (int p = 0; p < LC_MAX_OUT; ++p)
                 if (p < lc.nout) acc[p] += lc.W[p][t] * v;
@@ -46,6 +48,29 @@ __global__ void __launch_bounds__(256) lincomb_kernel(LinComb lc) {
         for (int p = 0; p < LC_MAX_OUT; ++p)
             if (p < lc.nout) lc.out[p][e] = acc[p];
     }
+}
+
+__global__ void __launch_bounds__(256) copy_kernel(double* dst, const double* src, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(256) zero_kernel(unsigned* dst, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = 0u;
+}
+
+__global__ void __launch_bounds__(256) expand_kernel(int n_flames, const int64_t* off,
+                                                     const double* v, double* out) {
+    const int f = blockIdx.y;
+    if (f >= n_flames) return;
+    const int64_t b = off[f], e = off[f + 1];
+    const double x = v[f];
+    for (int64_t i = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < e;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = x;
 }
 
 // ---------------------------------------------------------------------------
@@ -242,6 +267,141 @@ __global__ void __launch_bounds__(64) cyclic_kernel(GridDev g, MechDev m, int64_
     const double vu = u[0] + a0 / gam * u[len - 1];
     const double fct = vy / (1.0 + vu);
     for (int64_t i = 0; i < len; ++i) x[i] -= fct * u[i];
+}
+
+// Periodic tridiagonal solve with one wavefront per system (partition
+// method).  The system of length L is cut into P = min(64, L) chunks of
+// consecutive rows; the last row of every chunk is a separator.  Lane p
+// eliminates the interior rows of its chunk with Thomas' algorithm for three
+// right-hand sides (the load and the couplings to the separators on either
+// side), so that each interior unknown is u - v G_{p-1} - w G_p in terms of
+// the separator unknowns G.  Substituting into the separator rows leaves a
+// periodic tridiagonal system of P unknowns (diagonally dominant, as a Schur
+// complement of a diagonally dominant matrix), which lane 0 solves; every
+// lane then recovers its interior rows.  The serial depth is about
+// 2 L / 64 + 2 P instead of 3 L.  Scratch arrays sc, su, sv, sw hold the
+// interior rows of lane p at position k P + p of the system's range.
+__global__ void __launch_bounds__(64) cyclic_wave_kernel(GridDev g, MechDev m, int64_t n, double c,
+                                                         const double* dtf, double cfac,
+                                                         const double* Kx, const double* rhs,
+                                                         double* y, double* sc, double* su,
+                                                         double* sv, double* sw) {
+    __shared__ double ra[64], rb[64], rcs[64], rr[64];   // reduced system
+    __shared__ double fu[64], fv[64], fw[64];            // first interior row of each chunk
+    __shared__ double G[64], wc[64], wu[64];
+    const int nsys_f = g.n_flames > 0 ? g.n_flames : 1;
+    const int f = blockIdx.x / nsys_f, fl = blockIdx.x % nsys_f;
+    if (f == m.bath || f > m.N) return;     // uniform over the block
+    const int64_t base = g.n_flames > 0 ? g.off[fl] : 0;
+    const int64_t len = g.n_flames > 0 ? g.off[fl + 1] - g.off[fl] : n;
+    const double cc = (dtf ? dtf[fl] * cfac : c) * m.kappa0[f];
+    const double* b = rhs + (size_t)f * n + base;
+    double* x = y + (size_t)f * n + base;
+    double* Sc = sc + (size_t)f * n + base;
+    double* Su = su + (size_t)f * n + base;
+    double* Sv = sv + (size_t)f * n + base;
+    double* Sw = sw + (size_t)f * n + base;
+    const double* K = Kx + base;
+    const int lane = threadIdx.x;
+    const int P = len < 64 ? (int)len : 64;
+    const int64_t s0 = len / P, rem = len % P;
+    int64_t r0 = 0, mi = 0;
+    double ul = 0.0, vl = -1.0, wl = 0.0;       // last interior row (none: the left separator)
+    if (lane < P) {
+        r0 = lane * s0 + (lane < rem ? lane : rem);
+        mi = s0 + (lane < rem ? 1 : 0) - 1;
+        double cprev = 0.0, uprev = 0.0, vprev = 0.0, wprev = 0.0;
+        for (int64_t k = 0; k < mi; ++k) {
+            const int64_t i = r0 + k;
+            const double Km = K[i == 0 ? len - 1 : i - 1], K0 = K[i];
+            const double a = -cc * Km, d = 1.0 + cc * (Km + K0), cu = -cc * K0;
+            const double aa = (k == 0) ? 0.0 : a;
+            const double den = d - aa * cprev;
+            const double cn = (k == mi - 1) ? 0.0 : cu / den;
+            const double u = (b[i] - aa * uprev) / den;
+            const double v = ((k == 0 ? a : 0.0) - aa * vprev) / den;
+            const double w = ((k == mi - 1 ? cu : 0.0) - aa * wprev) / den;
+            const int64_t q = k * P + lane;
+            Sc[q] = cn;
+            Su[q] = u;
+            Sv[q] = v;
+            Sw[q] = w;
+            cprev = cn;
+            uprev = u;
+            vprev = v;
+            wprev = w;
+        }
+        if (mi > 0) {
+            ul = uprev;
+            vl = vprev;
+            wl = wprev;
+        }
+        double un = ul, vn = vl, wn = wl;
+        for (int64_t k = mi - 2; k >= 0; --k) {
+            const int64_t q = k * P + lane;
+            const double cn = Sc[q];
+            un = Su[q] - cn * un;
+            vn = Sv[q] - cn * vn;
+            wn = Sw[q] - cn * wn;
+            Su[q] = un;
+            Sv[q] = vn;
+            Sw[q] = wn;
+        }
+        // first interior row (none: the right separator itself)
+        fu[lane] = mi > 0 ? un : 0.0;
+        fv[lane] = mi > 0 ? vn : 0.0;
+        fw[lane] = mi > 0 ? wn : -1.0;
+    }
+    __syncthreads();
+    if (lane < P) {
+        const int64_t i = r0 + mi;                  // separator row
+        const int nx = lane + 1 == P ? 0 : lane + 1;
+        const double Km = K[i == 0 ? len - 1 : i - 1], K0 = K[i];
+        const double a = -cc * Km, d = 1.0 + cc * (Km + K0), cu = -cc * K0;
+        ra[lane] = -a * vl;
+        rb[lane] = d - a * wl - cu * fv[nx];
+        rcs[lane] = -cu * fw[nx];
+        rr[lane] = b[i] - a * ul - cu * fu[nx];
+    }
+    __syncthreads();
+    if (lane == 0) {
+        // periodic system of P separators: Thomas + Sherman-Morrison
+        const double a0 = ra[0], cN = rcs[P - 1];
+        const double gam = -rb[0];
+        double dprev = rb[0] - gam;
+        double cprev = rcs[0] / dprev;
+        wc[0] = cprev;
+        G[0] = rr[0] / dprev;
+        wu[0] = gam / dprev;
+        for (int i = 1; i < P; ++i) {
+            double d = rb[i];
+            if (i == P - 1) d -= a0 * cN / gam;
+            const double ai = ra[i];
+            const double den = d - ai * cprev;
+            const double ru = (i == P - 1) ? cN : 0.0;
+            G[i] = (rr[i] - ai * G[i - 1]) / den;
+            wu[i] = (ru - ai * wu[i - 1]) / den;
+            cprev = (i < P - 1) ? rcs[i] / den : 0.0;
+            wc[i] = cprev;
+        }
+        for (int i = P - 2; i >= 0; --i) {
+            G[i] -= wc[i] * G[i + 1];
+            wu[i] -= wc[i] * wu[i + 1];
+        }
+        const double vy = G[0] + a0 / gam * G[P - 1];
+        const double vu = wu[0] + a0 / gam * wu[P - 1];
+        const double fct = vy / (1.0 + vu);
+        for (int i = 0; i < P; ++i) G[i] -= fct * wu[i];
+    }
+    __syncthreads();
+    if (lane < P) {
+        const double gl = G[lane == 0 ? P - 1 : lane - 1], gr = G[lane];
+        for (int64_t k = 0; k < mi; ++k) {
+            const int64_t q = k * P + lane;
+            x[r0 + k] = Su[q] - Sv[q] * gl - Sw[q] * gr;
+        }
+        x[r0 + mi] = gr;
+    }
 }
 
 // bath closure y_i0 = r_i0 - sum_{k != i0, k < N} (y_k - r_k)
@@ -800,12 +960,93 @@ GridDev grid_dev(const Grid& g) {
 
 }  // namespace
 
+int64_t cg_regs_min_blocks(int64_t n, int cpt) {
+    const int64_t per = (int64_t)cg_regs_block(cpt) * cpt;
+    return (n + per - 1) / per;
+}
+
+int device_cus(int& cus) {
+    int dev = 0;
+    MISDC_HIP(hipGetDevice(&dev));
+    MISDC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return MISDC_OK;
+}
+
+int diffusion_work_set(DiffusionWork& w, const Mech& m, const Grid& g, int variant, int blocks) {
+    const int64_t n = g.cells();
+    const int NF = m.dev.N + 1;
+    int cus = 0;
+    int rc = device_cus(cus);
+    if (rc) return rc;
+    const int cap = cus < CG_MAX_BLOCKS ? cus : CG_MAX_BLOCKS;
+    if (blocks < 1 || blocks > cap)
+        return fail(MISDC_EINVAL, "CG blocks must be in [1, %d], got %d", cap, blocks);
+    int occ = 0;
+    switch (variant) {
+        case 0:
+            MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_kernel, CG_THREADS, 0));
+            break;
+        case 1:
+        case 2:
+        case 4:
+            if (!(NF - 1 == 9 && g.dim == 2 && g.n_flames == 0))
+                return fail(MISDC_EINVAL, "register CG variants need a 2-D grid and 9 diffused fields");
+            if (blocks < cg_regs_min_blocks(n, variant))
+                return fail(MISDC_EINVAL, "CG variant %d needs at least %lld blocks", variant,
+                            (long long)cg_regs_min_blocks(n, variant));
+            if (variant == 1)
+                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 1, 512>, 512, 0));
+            else if (variant == 2)
+                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 2, 256>, 256, 0));
+            else
+                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 4, 256>, 256, 0));
+            break;
+        default:
+            return fail(MISDC_EINVAL, "unknown CG variant %d", variant);
+    }
+    if (occ < 1) return fail(MISDC_EDEVICE, "CG variant %d cannot be resident", variant);
+    w.variant = variant;
+    w.blocks = blocks;
+    return MISDC_OK;
+}
+
+int launch_copy(double* dst, const double* src, int64_t count, hipStream_t s) {
+    if (count <= 0) return MISDC_OK;
+    unsigned blocks = grid_for(count, 256);
+    if (blocks > 8192u) blocks = 8192u;
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, s, dst, src, count);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+int launch_zero(void* dst, int64_t bytes, hipStream_t s) {
+    if (bytes <= 0) return MISDC_OK;
+    if (bytes % 4) return fail(MISDC_EINVAL, "zero fill of %lld bytes: not whole words", (long long)bytes);
+    const int64_t words = bytes / 4;
+    unsigned blocks = grid_for(words, 256);
+    if (blocks > 8192u) blocks = 8192u;
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, s, (unsigned*)dst, words);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+int launch_expand_flames(const Grid& g, const double* v, double* out, hipStream_t s) {
+    if (g.n_flames <= 0) return fail(MISDC_EINVAL, "per-flame values need an ensemble grid");
+    int64_t longest = 0;
+    for (int64_t L : g.len) longest = L > longest ? L : longest;
+    hipLaunchKernelGGL(expand_kernel, dim3(grid_for(longest, 256), g.n_flames), dim3(256), 0, s,
+                       g.n_flames, g.d_off, v, out);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
 int launch_lincomb(const LinComb& lc, hipStream_t s) {
     const int64_t total = (int64_t)lc.nfields * lc.ncells;
     if (total == 0) return MISDC_OK;
     if (lc.nterms > LC_MAX_TERMS || lc.nout > LC_MAX_OUT || lc.nout < 1)
         return fail(MISDC_EINVAL, "linear combination too large (%d terms, %d outputs)", lc.nterms,
                     lc.nout);
+    if (lc.smask && !lc.scale) return fail(MISDC_EINVAL, "scaled terms without a scale array");
     unsigned blocks = grid_for(total, 256);
     if (blocks > 65536u) blocks = 65536u;
     hipLaunchKernelGGL(lincomb_kernel, dim3(blocks), dim3(256), 0, s, lc);
@@ -840,52 +1081,37 @@ int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
     MISDC_HIP(hipMalloc(&w.z, cells_bytes * NF));
     MISDC_HIP(hipMalloc(&w.p, cells_bytes * NF));
     MISDC_HIP(hipMalloc(&w.q, cells_bytes * NF));
-    int dev = 0, cus = 0, per = 0;
-    MISDC_HIP(hipGetDevice(&dev));
-    MISDC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int cus = 0;
+    int rc = device_cus(cus);
+    if (rc) return rc;
     // At most one block per CU: the whole grid is co-resident even while
     // other kernels occupy part of every CU, so the grid barrier always
     // completes.  The register-resident kernel is used when every cell fits
     // in CPT <= 4 registers slots per thread of such a grid.
-    w.variant = 0;
+    w.variant = -1;
     const char* force = std::getenv("MISDC_FORCE_CG_GLOBAL");   // test switch
     const bool allow_regs = !(force && force[0] == '1');
     if (allow_regs && NF - 1 == 9 && g.dim == 2 && g.n_flames == 0) {
-        // blocks of CG_REGS_BS threads; grid barriers cost less with fewer
-        // blocks, so take the fewest cells per thread that keeps the grid at
-        // most half the CUs, else at most all of them
+        // grid barriers cost less with fewer blocks, so take the fewest cells
+        // per thread that keeps the grid at most half the CUs, else at most
+        // all of them
         const int cpts[3] = {1, 2, 4};
-        for (int pass = 0; pass < 2 && w.variant == 0; ++pass) {
-            int64_t cap = pass == 0 ? cus / 2 : cus;
-            if (cap > CG_MAX_BLOCKS) cap = CG_MAX_BLOCKS;
+        for (int pass = 0; pass < 2 && w.variant < 0; ++pass) {
+            const int64_t cap = pass == 0 ? cus / 2 : cus;
             for (int c : cpts) {
-                const int bs = cg_regs_block(c);
-                const int64_t blocks = (n + (int64_t)bs * c - 1) / ((int64_t)bs * c);
+                const int64_t blocks = cg_regs_min_blocks(n, c);
                 if (blocks > cap) continue;
-                int occ = 0;
-                if (c == 1)
-                    MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 1, 512>, bs, 0));
-                else if (c == 2)
-                    MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 2, 256>, bs, 0));
-                else
-                    MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 4, 256>, bs, 0));
-                if (occ >= 1) {
-                    w.variant = c;
-                    w.blocks = (int)blocks;
-                }
-                break;
+                if (diffusion_work_set(w, m, g, c, (int)blocks) == MISDC_OK) break;
             }
         }
     }
-    if (w.variant == 0) {
-        MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cg_kernel, CG_THREADS, 0));
-        if (per < 1)
-            return fail(MISDC_EDEVICE, "CG kernel cannot be resident (occupancy %d)", per);
-        int blocks = cus;
-        const int64_t need = (n + CG_THREADS - 1) / CG_THREADS;
-        if (blocks > need) blocks = (int)need;
+    if (w.variant < 0) {
+        int64_t blocks = (n + CG_THREADS - 1) / CG_THREADS;
+        if (blocks > cus) blocks = cus;
+        if (blocks > CG_MAX_BLOCKS) blocks = CG_MAX_BLOCKS;
         if (blocks < 1) blocks = 1;
-        w.blocks = blocks;
+        rc = diffusion_work_set(w, m, g, 0, (int)blocks);
+        if (rc) return rc;
     }
     w.threads = CG_THREADS;
     MISDC_HIP(hipMalloc(&w.partial, sizeof(double) * 2 * (size_t)CG_MAX_BLOCKS * CG_MAX_FIELDS * 4));
@@ -921,8 +1147,12 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
     const int NF = m.dev.N + 1;
     if (g.dim == 1 || g.n_flames > 0) {
         const int nsys = (g.n_flames > 0 ? g.n_flames : 1) * NF;
-        hipLaunchKernelGGL(cyclic_kernel, dim3(grid_for(nsys, 64)), dim3(64), 0, s, gd, m.dev, n,
-                           c, dt_flame, c_factor, w.Kx, rhs, y, w.r, w.z);
+        if (w.cyclic == 1)
+            hipLaunchKernelGGL(cyclic_wave_kernel, dim3(nsys), dim3(64), 0, s, gd, m.dev, n, c,
+                               dt_flame, c_factor, w.Kx, rhs, y, w.r, w.z, w.p, w.q);
+        else
+            hipLaunchKernelGGL(cyclic_kernel, dim3(grid_for(nsys, 64)), dim3(64), 0, s, gd, m.dev,
+                               n, c, dt_flame, c_factor, w.Kx, rhs, y, w.r, w.z);
         MISDC_HIP(hipGetLastError());
     } else {
         CGArgs a;

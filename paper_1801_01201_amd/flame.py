@@ -76,8 +76,19 @@ class Integrator:
         self.opts = nat.make_opts(**opts)
         self.handle = nat.misdc_integ_create(mech.handle, grid.handle, self.opts)
 
-    def step(self, state, dt, stream=None):
-        nat.misdc_step(self.handle, state, dt, None, stream)
+    def step(self, state, dt, dt_per_flame=None, stream=None):
+        """One step; ``dt_per_flame`` (device tensor, one dt per flame of an
+        ensemble grid) replaces the scalar ``dt``."""
+        nat.misdc_step(self.handle, state, dt, dt_per_flame, stream)
+
+    def autotune(self, state, dt, dt_per_flame=None, reps=3, stream=None):
+        return nat.misdc_autotune(self.handle, state, dt, dt_per_flame, reps, stream)
+
+    def tune(self):
+        return nat.misdc_get_tune(self.handle)
+
+    def set_tune(self, cg_variant, cg_blocks, cyclic, serialize):
+        nat.misdc_set_tune(self.handle, cg_variant, cg_blocks, cyclic, serialize)
 
     def stats(self):
         return nat.misdc_get_stats(self.handle)

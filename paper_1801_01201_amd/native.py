@@ -31,7 +31,7 @@ EXPORTED = [
     "misdc_grid_create_ensemble", "misdc_grid_destroy", "misdc_grid_cells",
     "misdc_transport_operators", "misdc_diffusion_solve", "misdc_opts_default",
     "misdc_integ_create", "misdc_integ_destroy", "misdc_step", "misdc_get_stats",
-    "misdc_reset_profile",
+    "misdc_reset_profile", "misdc_autotune", "misdc_get_tune", "misdc_set_tune",
 ]
 
 
@@ -59,7 +59,15 @@ class misdc_opts(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("n_sweeps", C.c_int32), ("nu", C.c_int32),
                 ("scheme", C.c_int32), ("qe_mode", C.c_int32), ("serialize", C.c_int32),
                 ("newton", misdc_newton_opts), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
-                ("profile", C.c_int32)]
+                ("profile", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class misdc_tune(C.Structure):
+    _fields_ = [("cg_variant", C.c_int32), ("cg_blocks", C.c_int32), ("cyclic", C.c_int32),
+                ("serialize", C.c_int32), ("step_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class misdc_stats(C.Structure):
@@ -107,6 +115,9 @@ def load(path=LIB_PATH):
         "misdc_step": (C.c_int, [vp, vp, dbl, vp, vp]),
         "misdc_get_stats": (C.c_int, [vp, C.POINTER(misdc_stats)]),
         "misdc_reset_profile": (C.c_int, [vp]),
+        "misdc_autotune": (C.c_int, [vp, vp, dbl, vp, C.c_int, C.POINTER(misdc_tune), vp]),
+        "misdc_get_tune": (C.c_int, [vp, C.POINTER(misdc_tune)]),
+        "misdc_set_tune": (C.c_int, [vp, C.POINTER(misdc_tune)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -285,8 +296,26 @@ def misdc_reset_profile(integ):
     check(lib().misdc_reset_profile(integ))
 
 
+def misdc_autotune(integ, state, dt, dt_per_flame=None, reps=3, stream=None):
+    t = misdc_tune()
+    check(lib().misdc_autotune(integ, _ptr(state), float(dt), _ptr(dt_per_flame), int(reps),
+                               C.byref(t), _stream(stream)))
+    return t.as_dict()
+
+
+def misdc_get_tune(integ):
+    t = misdc_tune()
+    check(lib().misdc_get_tune(integ, C.byref(t)))
+    return t.as_dict()
+
+
+def misdc_set_tune(integ, cg_variant, cg_blocks, cyclic, serialize):
+    t = misdc_tune(int(cg_variant), int(cg_blocks), int(cyclic), int(serialize), 0.0)
+    check(lib().misdc_set_tune(integ, C.byref(t)))
+
+
 def make_opts(n_nodes=5, sweeps=6, nu=1, scheme="cisdcq", qe="cumulative", serialize=False,
-              cg_rtol=1e-13, cg_maxit=500, newton=None, profile=False):
+              cg_rtol=1e-13, cg_maxit=500, newton=None, profile=False, use_graph=False):
     o = misdc_opts_default()
     o.n_nodes = n_nodes
     o.n_sweeps = sweeps
@@ -297,6 +326,7 @@ def make_opts(n_nodes=5, sweeps=6, nu=1, scheme="cisdcq", qe="cumulative", seria
     o.cg_rtol = cg_rtol
     o.cg_maxit = cg_maxit
     o.profile = int(bool(profile))
+    o.use_graph = int(bool(use_graph))
     if newton is not None:
         o.newton = newton
     return o

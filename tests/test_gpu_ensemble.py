@@ -1,0 +1,306 @@
+"""GPU parity for the ensemble workload (independent periodic 1-D flames of
+uneven length, each with its own step size), the wavefront-per-system cyclic
+diffusion solver, whole-step graph replay and the autotuner.
+
+The oracle of an ensemble step is the definition: every flame advanced alone
+by the oracle's step with its own dx, u and dt.  Tolerance 1e-10 in the
+field-max-normalised norm per flame.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import transport as tr
+from oracle.adr import FlameProblem, relaxed_initial_state
+from oracle.sdc import sdc_step
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_1801_01201_amd import native
+    native.lib()
+    return native
+
+
+@pytest.fixture(scope="module")
+def mech9():
+    return synth.make_mechanism(9, 21, 0)
+
+
+@pytest.fixture(scope="module")
+def mh(nat, mech9):
+    from paper_1801_01201_amd.flame import Mechanism
+    m = Mechanism(mech9)
+    yield m
+    m.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def field_err(a, b):
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    scale = np.maximum(np.abs(b).max(axis=1), 1e-300)
+    return float((np.abs(a - b).max(axis=1) / scale).max())
+
+
+def _gpu_initial(mh, Y, T):
+    from paper_1801_01201_amd.flame import initial_state
+    st, it = initial_state(mh, dev(Y.reshape(9, -1)), dev(T.ravel()))
+    assert np.all(host(it) > 0)
+    return st
+
+
+# ---------------------------------------------------------------------------
+# 1-D implicit diffusion: wavefront-per-system partition solver
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [4, 5, 63, 64, 65, 127, 130, 1000, 4096])
+def test_cyclic_wave_solver(nat, mech9, mh, n):
+    """Lengths below, at and above one chunk per lane, and ragged tails."""
+    g = nat.misdc_grid_create(1, [n], [0.01], [100.0])
+    T, rhs = synth.random_helmholtz_problem((n,), 10, seed=40 + n % 7)
+    c = 2.0e-5
+    y_ref = tr.diffusion_solve(mech9, c, rhs, T, (0.01,))
+    y = torch.empty((10, n), dtype=torch.float64, device="cuda")
+    nat.misdc_diffusion_solve(mh.handle, g, c, dev(T.ravel()), dev(rhs.reshape(10, -1)), y)
+    assert field_err(host(y), y_ref.reshape(10, -1)) <= TOL
+    nat.misdc_grid_destroy(g)
+
+
+def test_ensemble_diffusion_solve(nat, mech9, mh):
+    lengths = [4, 17, 64, 65, 200, 1031]
+    dxs = [0.01, 0.02, 0.005, 0.01, 0.015, 0.01]
+    g = nat.misdc_grid_create_ensemble(lengths, dxs, [100.0] * len(lengths))
+    parts_T, parts_r, refs = [], [], []
+    c = 1.5e-5
+    for k, (n, dx) in enumerate(zip(lengths, dxs)):
+        T, rhs = synth.random_helmholtz_problem((n,), 10, seed=60 + k)
+        parts_T.append(T)
+        parts_r.append(rhs.reshape(10, -1))
+        refs.append(tr.diffusion_solve(mech9, c, rhs, T, (dx,)).reshape(10, -1))
+    T = np.concatenate(parts_T)
+    rhs = np.concatenate(parts_r, axis=1)
+    y = torch.empty((10, T.size), dtype=torch.float64, device="cuda")
+    nat.misdc_diffusion_solve(mh.handle, g, c, dev(T), dev(rhs), y)
+    out = host(y)
+    off = np.concatenate([[0], np.cumsum(lengths)])
+    for k in range(len(lengths)):
+        assert field_err(out[:, off[k]:off[k + 1]], refs[k]) <= TOL, k
+    nat.misdc_grid_destroy(g)
+
+
+# ---------------------------------------------------------------------------
+# ensemble steps with per-flame step sizes
+# ---------------------------------------------------------------------------
+def _oracle_ensemble(mech9, flames, dxs, us, dts, n_nodes, sweeps, scheme, nu, steps=1):
+    outs = []
+    for (Y, T), dx, u, dt in zip(flames, dxs, us, dts):
+        prob = FlameProblem(mech9, (dx,), (u,))
+        phi = relaxed_initial_state(prob, Y, T)
+        for _ in range(steps):
+            phi, _ = sdc_step(prob, phi, dt, n_nodes, sweeps, scheme, nu=nu)
+        outs.append(phi.reshape(10, -1))
+    return outs
+
+
+def _gpu_ensemble(nat, mh, flames, lengths, dxs, us, dts, steps=1, **opts):
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    Y = np.concatenate([f[0] for f in flames], axis=1)
+    T = np.concatenate([f[1] for f in flames])
+    st = _gpu_initial(mh, Y, T)
+    g = Grid(ensemble=(lengths, dxs, us))
+    integ = Integrator(mh, g, **opts)
+    d_dt = dev(np.asarray(dts, dtype=np.float64))
+    for _ in range(steps):
+        integ.step(st, 0.0, dt_per_flame=d_dt)
+    stats = integ.stats()
+    out = host(st)
+    integ.close()
+    g.close()
+    return out, stats
+
+
+ENSEMBLE_CASES = [
+    # (name, scheme, n_nodes, sweeps, nu, steps)
+    ("cisdcq1_3nodes", "cisdcq", 3, 4, 1, 1),
+    ("cisdcq2_3nodes", "cisdcq", 3, 3, 2, 1),
+    ("misdc_3nodes_2steps", "misdc", 3, 4, 1, 2),
+    ("misdcq_5nodes", "misdcq", 5, 4, 1, 1),
+]
+
+
+@pytest.mark.parametrize("case", ENSEMBLE_CASES, ids=[c[0] for c in ENSEMBLE_CASES])
+def test_ensemble_step_parity(nat, mech9, mh, case):
+    name, scheme, n_nodes, sweeps, nu, steps = case
+    lengths = [4, 23, 64, 65, 130]
+    dxs = [0.01, 0.02, 0.01, 0.005, 0.01]
+    us = [100.0, -50.0, 100.0, 0.0, 80.0]
+    dts = [5e-6, 5e-5, 1.7e-5, 8e-6, 3.1e-5]
+    flames = [synth.flame_1d(mech9, n, dx) for n, dx in zip(lengths, dxs)]
+    refs = _oracle_ensemble(mech9, flames, dxs, us, dts, n_nodes, sweeps, scheme, nu, steps)
+    out, stats = _gpu_ensemble(nat, mh, flames, lengths, dxs, us, dts, steps=steps,
+                               n_nodes=n_nodes, sweeps=sweeps, nu=nu, scheme=scheme)
+    assert stats["newton_failed"] == 0
+    off = np.concatenate([[0], np.cumsum(lengths)])
+    for k in range(len(lengths)):
+        err = field_err(out[:, off[k]:off[k + 1]], refs[k])
+        assert err <= TOL, (k, err)
+
+
+def test_ensemble_uniform_dt_matches_scalar(nat, mech9, mh):
+    """Per-flame step sizes that are all equal give the scalar-dt step.  The
+    two forms differ only in where dt multiplies (dt folded into the weight,
+    or applied per cell), a rounding-level difference that the Newton and
+    diffusion solves of four sweeps carry to about 1e-13."""
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    lengths = [40, 70, 33]
+    flames = [synth.flame_1d(mech9, n, 0.01) for n in lengths]
+    Y = np.concatenate([f[0] for f in flames], axis=1)
+    T = np.concatenate([f[1] for f in flames])
+    g = Grid(ensemble=(lengths, [0.01] * 3, [100.0] * 3))
+    outs = []
+    for per_flame in (False, True):
+        st = _gpu_initial(mh, Y, T)
+        integ = Integrator(mh, g, n_nodes=3, sweeps=4, scheme="cisdcq")
+        if per_flame:
+            integ.step(st, 0.0, dt_per_flame=dev(np.full(3, 2e-5)))
+        else:
+            integ.step(st, 2e-5)
+        outs.append(host(st))
+        integ.close()
+    g.close()
+    assert field_err(outs[1], outs[0]) <= 1e-12
+
+
+def test_ensemble64_sampled_flames(nat, mech9, mh):
+    """The full 64-flame workload (lengths 128..4096, 10x dt spread, 3 nodes,
+    4 sweeps, CISDCQ-1) in the launch configuration the benchmark uses
+    (graph replay after autotuning); three flames (shortest, longest, one
+    in between) are recomputed alone by the oracle."""
+    cfg = synth.config("ensemble64")
+    lengths, dts, flames = synth.ensemble_flames(mech9, cfg["n_flames"], cfg["len_range"],
+                                                 cfg["dt"], cfg["dt_spread"], cfg["dx"][0],
+                                                 cfg["ens_seed"])
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    Y = np.concatenate([f[0] for f in flames], axis=1)
+    T = np.concatenate([f[1] for f in flames])
+    st = _gpu_initial(mh, Y, T)
+    nf = len(lengths)
+    g = Grid(ensemble=(lengths, [cfg["dx"][0]] * nf, [cfg["u"][0]] * nf))
+    integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
+                       scheme=cfg["scheme"], use_graph=True)
+    d_dt = dev(dts)
+    tune = integ.autotune(st, 0.0, dt_per_flame=d_dt, reps=1)
+    assert tune["cyclic"] in (0, 1) and tune["step_ms"] > 0
+    integ.step(st, 0.0, dt_per_flame=d_dt)
+    stats = integ.stats()
+    out = host(st)
+    integ.close()
+    g.close()
+    assert stats["newton_failed"] == 0
+    assert np.all(np.isfinite(out))
+    off = np.concatenate([[0], np.cumsum(lengths)])
+    picks = [int(np.argmin(lengths)), int(np.argmax(lengths)), 7]
+    for k in picks:
+        ref = _oracle_ensemble(mech9, [flames[k]], [cfg["dx"][0]], [cfg["u"][0]], [dts[k]],
+                               cfg["n_nodes"], cfg["sweeps"], cfg["scheme"], cfg["nu"])[0]
+        err = field_err(out[:, off[k]:off[k + 1]], ref)
+        assert err <= TOL, (k, int(lengths[k]), err)
+
+
+# ---------------------------------------------------------------------------
+# graph replay and autotuning
+# ---------------------------------------------------------------------------
+def test_graph_replay_matches_eager(nat, mech9, mh):
+    """A captured step replayed several times, with eager torch work and
+    synchronisations between the replays, equals the eagerly issued steps
+    bit for bit (same kernels, same arguments, deterministic reductions)."""
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    Y, T = synth.flame_2d(mech9, 40, 32)
+    g = Grid(2, [40, 32], [0.01, 0.01], [100.0, 0.0])
+    seqs = []
+    for use_graph in (False, True):
+        st = _gpu_initial(mh, Y, T)
+        integ = Integrator(mh, g, n_nodes=5, sweeps=3, nu=2, scheme="cisdcq",
+                           use_graph=use_graph)
+        seq = []
+        for k in range(3):
+            integ.step(st, 5e-5)
+            scratch = torch.randn(1000, device="cuda").sum()     # eager work between replays
+            torch.cuda.synchronize()
+            seq.append(host(st))
+            assert np.isfinite(float(scratch))
+            s = integ.stats()
+            assert s["newton_failed"] == 0 and s["cg_failed"] == 0
+            assert s["newton_solves"] == 3 * 2 * 4 * 40 * 32
+        integ.close()
+        seqs.append(seq)
+    g.close()
+    for a, b in zip(*seqs):
+        assert np.array_equal(a, b)
+
+
+def test_graph_ensemble_dt_change_without_recapture(nat, mech9, mh):
+    """With per-flame step sizes the graph reads dev_dt at replay time: new
+    values in the same array take effect without a new capture."""
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    lengths = [30, 90]
+    flames = [synth.flame_1d(mech9, n, 0.01) for n in lengths]
+    Y = np.concatenate([f[0] for f in flames], axis=1)
+    T = np.concatenate([f[1] for f in flames])
+    g = Grid(ensemble=(lengths, [0.01, 0.01], [100.0, 100.0]))
+    results = {}
+    for use_graph in (False, True):
+        st = _gpu_initial(mh, Y, T)
+        integ = Integrator(mh, g, n_nodes=3, sweeps=4, scheme="cisdcq", use_graph=use_graph)
+        d_dt = dev(np.array([1e-5, 3e-5]))
+        seq = []
+        for vals in ([1e-5, 3e-5], [2e-5, 7e-6], [4e-5, 4e-5]):
+            d_dt.copy_(torch.tensor(vals, dtype=torch.float64))
+            integ.step(st, 0.0, dt_per_flame=d_dt)
+            seq.append(host(st))
+        integ.close()
+        results[use_graph] = seq
+    g.close()
+    for a, b in zip(results[False], results[True]):
+        assert np.array_equal(a, b)
+
+
+def test_autotune_and_set_tune(nat, mech9, mh):
+    """The autotuner leaves the state alone, keeps a valid configuration,
+    and every configuration gives the same step to the solver tolerance."""
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    Y, T = synth.flame_2d(mech9, 64, 48)
+    g = Grid(2, [64, 48], [0.01, 0.01], [100.0, 0.0])
+    st0 = _gpu_initial(mh, Y, T)
+    ref_in = host(st0)
+    integ = Integrator(mh, g, n_nodes=5, sweeps=4, scheme="cisdcq")
+    tune = integ.autotune(st0, 5e-5, reps=1)
+    assert np.array_equal(host(st0), ref_in)
+    assert tune["cg_variant"] in (0, 1, 2, 4) and tune["cg_blocks"] >= 1
+    assert integ.tune()["cg_variant"] == tune["cg_variant"]
+    outs = []
+    for cfg in ((tune["cg_variant"], tune["cg_blocks"], 1, tune["serialize"]), (0, 32, 1, 1),
+                (1, 8, 1, 0)):
+        integ.set_tune(*cfg)
+        st = st0.clone()
+        integ.step(st, 5e-5)
+        outs.append(host(st))
+    with pytest.raises(nat.MisdcError):
+        integ.set_tune(1, 1, 1, 0)          # 1 block cannot hold 3072 cells in registers
+    integ.close()
+    g.close()
+    for o in outs[1:]:
+        assert field_err(o, outs[0]) <= 1e-12
