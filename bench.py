@@ -114,6 +114,125 @@ def accuracy_gate(cfg, mech, mh):
     return {"err": err, "tol": 1e-8, "passed": bool(err <= 1e-8), "grid": f"{nx}x{ny}"}
 
 
+def graph_leg(integ, mh, g, cfg, state, args, tune):
+    """The same steps replayed as one captured HIP graph per step (a second
+    integrator with the tuned launch configuration); kernel timing events
+    are not recorded in graphs, so the roofline comes from the eager steps."""
+    import torch
+    from paper_1801_01201_amd.flame import Integrator
+    gi = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
+                    scheme=cfg["scheme"], use_graph=True)
+    if tune:
+        gi.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"])
+    st = state.clone()
+    for _ in range(max(1, args.warmup)):
+        gi.step(st, cfg["dt"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gi.step(st, cfg["dt"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s = gi.stats()
+    gi.close()
+    nx, ny = cfg["n"]
+    upd = nx * ny * (cfg["n_nodes"] - 1) * cfg["nu"] * cfg["sweeps"] * args.steps
+    return {"value": upd / el, "ms_per_step": el / args.steps * 1e3,
+            "newton_failed": s["newton_failed"], "cg_failed": s["cg_failed"]}
+
+
+def ensemble_main(args):
+    """64 independent periodic 1-D flames of 128..4096 cells with a 10x
+    spread of step sizes (3 Gauss-Lobatto nodes, 4 sweeps, CISDCQ-1); every
+    step of every flame in one call, per-flame dt, autotuned, replayed as a
+    HIP graph for the throughput and run eagerly with kernel timing for the
+    roofline of the dominant kernel."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1801_01201_amd import native
+    from paper_1801_01201_amd.flame import Mechanism, Grid, Integrator, initial_state
+    native.lib()
+    cfg = synth.config("ensemble64")
+    mech = synth.make_mechanism(**cfg["mech"])
+    lengths, dts, flames = synth.ensemble_flames(mech, cfg["n_flames"], cfg["len_range"], cfg["dt"],
+                                                 cfg["dt_spread"], cfg["dx"][0], cfg["ens_seed"])
+    nf = len(lengths)
+    n = int(np.sum(lengths))
+    M = cfg["n_nodes"] - 1
+    mh = Mechanism(mech)
+    g = Grid(ensemble=(lengths, [cfg["dx"][0]] * nf, [cfg["u"][0]] * nf))
+    Y = np.concatenate([f[0] for f in flames], axis=1)
+    T = np.concatenate([f[1] for f in flames])
+    state, _ = initial_state(mh, torch.tensor(Y, device="cuda"), torch.tensor(T, device="cuda"))
+    d_dt = torch.tensor(dts, dtype=torch.float64, device="cuda")
+    kw = dict(n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"], scheme=cfg["scheme"])
+    res = {}
+    tune = None
+    for mode in ("graph", "profile"):
+        integ = Integrator(mh, g, use_graph=(mode == "graph"), profile=(mode == "profile"), **kw)
+        if tune is None and not args.no_autotune:
+            tune = integ.autotune(state, 0.0, dt_per_flame=d_dt, reps=3)
+        elif tune is not None:
+            integ.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"])
+        st = state.clone()
+        for _ in range(max(1, args.warmup)):
+            integ.step(st, 0.0, dt_per_flame=d_dt)
+        torch.cuda.synchronize()
+        native.misdc_reset_profile(integ.handle)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            integ.step(st, 0.0, dt_per_flame=d_dt)
+        torch.cuda.synchronize()
+        res[mode] = (time.perf_counter() - t0, integ.stats())
+        integ.close()
+    el, stats = res["graph"]
+    elp, sp = res["profile"]
+    updates = n * M * cfg["nu"] * cfg["sweeps"] * args.steps
+    d_ms, d_n = sp["diffusion_kernel_ms"], sp["diffusion_kernel_launches"]
+    r_ms, r_n = sp["newton_kernel_ms"], sp["newton_kernel_launches"]
+    newton_per_cell = sp["newton_iters"] / max(1, sp["newton_solves"])
+    if d_ms >= r_ms:
+        avg_s = d_ms / max(1, d_n) * 1e-3
+        # one solve reads rhs and writes y for 9 fields, reads the face
+        # coefficients once: 2 * 9 * 8 + 8 bytes per cell
+        byts = (2 * 9 * 8 + 8) * n
+        roof = {"kernel": "cyclic_wave_kernel (one wavefront per periodic tridiagonal system)",
+                "bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                "avg_launch_ms": avg_s * 1e3, "launches": d_n,
+                "algorithmic_bytes_per_launch": byts}
+    else:
+        avg_s = r_ms / max(1, r_n) * 1e-3
+        flops = NEWTON_FLOP_PER_ITER_9 * n * newton_per_cell
+        roof = {"kernel": "newton_kernel<9> (per-cell reaction solve)", "bound": "alu",
+                "achieved": flops / avg_s / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": None, "avg_launch_ms": avg_s * 1e3, "launches": r_n}
+    line = {
+        "metric": METRIC, "value": updates / el, "unit": "cell-node updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"ensemble64: {nf} periodic 1-D flames of "
+                               f"{int(lengths.min())}..{int(lengths.max())} cells ({n} cells), "
+                               f"per-flame dt {dts.min():.3g}..{dts.max():.3g} s, "
+                               f"CISDCQ-{cfg['nu']}, {cfg['n_nodes']} nodes, {cfg['sweeps']} sweeps",
+                   "cells": n, "flames": nf},
+        "newton_iters_per_cell": newton_per_cell,
+        "eager_profiled_ms_per_step": elp / args.steps * 1e3,
+        "roofline": roof,
+        "kernel_split": {"diffusion_solve_ms_per_launch": d_ms / max(1, d_n),
+                         "newton_ms_per_launch": r_ms / max(1, r_n),
+                         "diffusion_solve_share_of_step": d_ms / (elp * 1e3),
+                         "newton_share_of_step": r_ms / (elp * 1e3)},
+        "autotune": tune,
+        "newton_failed": stats["newton_failed"],
+    }
+    mh.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +242,10 @@ def main():
     ap.add_argument("--no-gate", action="store_true")
     ap.add_argument("--nu", type=int, default=None)
     ap.add_argument("--serialize", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the extra timing of the same steps replayed as one HIP graph")
+    ap.add_argument("--workload", default="flame2d_256", choices=["flame2d_256", "ensemble64"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device-to-device 4 times (calibrates the HBM "
                          "byte counters of rocprofv3 --pmc) and exit")
@@ -140,6 +263,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               f"design is described in DESIGN.md and not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "ensemble64":
+        return ensemble_main(args)
     cfg = workload()
     if args.nu:
         cfg["nu"] = args.nu
@@ -166,6 +291,14 @@ def main():
                              torch.tensor(T.ravel(), device="cuda"))
     integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
                        scheme=cfg["scheme"], serialize=args.serialize, profile=True)
+    tune = None
+    if not args.no_autotune:
+        # untimed: pick the launch configuration on this workload (the state
+        # is not modified)
+        tune = integ.autotune(state, cfg["dt"], reps=2)
+        if args.serialize:
+            integ.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], 1)
+        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         integ.step(state, cfg["dt"])
     torch.cuda.synchronize()
@@ -182,6 +315,7 @@ def main():
     value = updates / elapsed
     newton_per_cell = stats["newton_iters"] / max(1, stats["newton_solves"])
     cg_per_solve = stats["cg_iters"] / max(1, stats["cg_solves"])
+    graph = None if args.no_graph else graph_leg(integ, mh, g, cfg, state, args, tune)
 
     # roofline of the dominant kernel
     d_ms, d_n = stats["diffusion_kernel_ms"], stats["diffusion_kernel_launches"]
@@ -230,6 +364,8 @@ def main():
         "cell_node_updates_per_step_incl_node0": n * (M + 1) * cfg["nu"] * cfg["sweeps"],
         "roofline": roof,
         "kernel_split": other,
+        "autotune": tune,
+        "graph_replay": graph,
         "cpu_baseline": cpu,
         "accuracy_gate": gate,
         "newton_failed": stats["newton_failed"], "cg_failed": stats["cg_failed"],
