@@ -148,6 +148,16 @@ int misdc_temperature(misdc_mech_t mech, int64_t n, const double* dev_Y,
 int misdc_reaction_source(misdc_mech_t mech, int64_t n, const double* dev_Y,
                           const double* dev_h, double* dev_FR, void* stream);
 
+enum {
+    MISDC_NEWTON_AUTO = 0,
+    MISDC_NEWTON_THREAD = 1,     /* one thread per cell (9 species only) */
+    MISDC_NEWTON_WAVE = 2        /* one 64-lane wavefront per cell (<= 63 species) */
+};
+enum {
+    MISDC_LU_FP64 = 0,           /* LU with partial pivoting in FP64 */
+    MISDC_LU_FP32_MFMA = 1       /* FP32 LU (matrix cores) refined in FP64 */
+};
+
 /* Reaction step S5 (eq. reaction_step_numerical_methodology) for n
  * independent cells: solve, at constant enthalpy h,
  *     Y - c FR(Y, T) = bY,   sum_k Y_k h_k(T) / W_k = h
@@ -170,6 +180,10 @@ typedef struct {
     double dtau0;
     double dtau_max;
     double neg_slack;
+    int32_t kernel;      /* MISDC_NEWTON_*: 0 auto (one thread per cell for 9
+                            species, else one wavefront per cell) */
+    int32_t lu;          /* MISDC_LU_*: precision of the Newton linear solves
+                            (wavefront kernel only) */
 } misdc_newton_opts;
 
 int misdc_reaction_solve_batch(misdc_mech_t mech, int64_t n, const double* dev_bY,

@@ -368,32 +368,28 @@ int launch_state_temperature(const Mech& m, int64_t n, const double* state, doub
 int launch_reaction_source(const Mech& m, int64_t n, const double* Y, const double* h,
                            double* FR, hipStream_t s) {
     if (n == 0) return MISDC_OK;
-    switch (m.dev.N) {
-        case 9:
-            hipLaunchKernelGGL(source_kernel<9>, dim3(grid_for(n, 64)), dim3(64), 0, s, m.dev, n,
-                               Y, n, h, FR, n);
-            break;
-        default:
-            return fail(MISDC_EUNSUPPORTED, "reaction source: %d species not built", m.dev.N);
-    }
+    if (m.dev.N != 9) return launch_reaction_source_wave(m, n, Y, n, h, FR, n, s);
+    hipLaunchKernelGGL(source_kernel<9>, dim3(grid_for(n, 64)), dim3(64), 0, s, m.dev, n, Y, n,
+                       h, FR, n);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;
 }
 
 int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s) {
     if (a.n == 0) return MISDC_OK;
-    switch (m.dev.N) {
-        case 9:
-            hipLaunchKernelGGL(newton_kernel<9>, dim3(grid_for(a.n, 64)), dim3(64), 0, s, m.dev, a);
-            MISDC_HIP(hipGetLastError());
-            if (a.stats && a.iters) {
-                hipLaunchKernelGGL(newton_stats_kernel<9>, dim3(grid_for(a.n, 256)), dim3(256), 0,
-                                   s, a.n, a.iters, a.stats);
-                MISDC_HIP(hipGetLastError());
-            }
-            break;
-        default:
-            return fail(MISDC_EUNSUPPORTED, "reaction solve: %d species not built", m.dev.N);
+    const int kind = a.opt.kernel;
+    const bool thread = (kind == MISDC_NEWTON_THREAD) || (kind == MISDC_NEWTON_AUTO && m.dev.N == 9);
+    if (thread && a.opt.lu != MISDC_LU_FP64)
+        return fail(MISDC_EINVAL, "the per-thread reaction solve computes its LU in FP64 only");
+    if (!thread) return launch_reaction_newton_wave(m, a, a.opt.lu, s);
+    if (m.dev.N != 9)
+        return fail(MISDC_EUNSUPPORTED, "per-thread reaction solve: %d species not built", m.dev.N);
+    hipLaunchKernelGGL(newton_kernel<9>, dim3(grid_for(a.n, 64)), dim3(64), 0, s, m.dev, a);
+    MISDC_HIP(hipGetLastError());
+    if (a.stats && a.iters) {
+        hipLaunchKernelGGL(newton_stats_kernel<9>, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a.n,
+                           a.iters, a.stats);
+        MISDC_HIP(hipGetLastError());
     }
     return MISDC_OK;
 }

@@ -203,7 +203,11 @@ misdc_newton_opts newton_defaults(const misdc_newton_opts* in) {
     o.dtau0 = 1.0;
     o.dtau_max = 1e10;
     o.neg_slack = 1e-6;
+    o.kernel = MISDC_NEWTON_AUTO;
+    o.lu = MISDC_LU_FP64;
     if (in) {
+        o.kernel = in->kernel;
+        o.lu = in->lu;
         if (in->tol > 0) o.tol = in->tol;
         if (in->maxit > 0) o.maxit = in->maxit;
         if (in->dtau0 > 0) o.dtau0 = in->dtau0;
@@ -691,9 +695,23 @@ int misdc_mech_create(const misdc_mech_desc* d, misdc_mech_t* out) {
     }
     kappa0[N] = d->alpha0;
     scale /= N;
+    // per-species reaction lists for the wavefront-per-cell kernels
+    std::vector<int> rowp(N + 1, 0), rowj;
+    std::vector<double> rowu;
+    for (int k = 0; k < N; ++k) {
+        for (int j = 0; j < R; ++j) {
+            const double u = uW[(size_t)j * N + k];
+            if (u != 0.0) {
+                rowj.push_back(j);
+                rowu.push_back(u);
+            }
+        }
+        rowp[k + 1] = (int)rowj.size();
+    }
+    const size_t nnz = rowj.size();
     // one device block: doubles then ints
-    const size_t nd = (size_t)R * 5 + (size_t)R * N + (size_t)N * 6 + (N + 1);
-    const size_t bytes = nd * sizeof(double) + slots.size() * sizeof(int) + 64;
+    const size_t nd = (size_t)R * 5 + (size_t)R * N + (size_t)N * 6 + (N + 1) + nnz;
+    const size_t bytes = nd * sizeof(double) + (slots.size() + rowp.size() + nnz) * sizeof(int) + 64;
     hipError_t e = hipGetDevice(&m.device);
     if (e != hipSuccess) {
         delete h;
@@ -716,10 +734,13 @@ int misdc_mech_create(const misdc_mech_desc* d, misdc_mech_t* out) {
     const size_t oA = put(d->A, R), ob = put(d->beta, R), oT = put(Ta.data(), R),
                  odn = put(dn.data(), R), ouW = put(uW.data(), uW.size()),
                  oW = put(d->W, N), oiW = put(invW.data(), N), ocp = put(d->cp, N),
-                 ohf = put(d->hf, N), os0 = put(d->s0, N), ok0 = put(kappa0.data(), N + 1);
+                 ohf = put(d->hf, N), os0 = put(d->s0, N), ok0 = put(kappa0.data(), N + 1),
+                 oru = put(rowu.data(), nnz);
     off += R;   // spare
     int* ip = (int*)(dp + off);
     if (!slots.empty()) std::memcpy(ip, slots.data(), slots.size() * sizeof(int));
+    std::memcpy(ip + slots.size(), rowp.data(), rowp.size() * sizeof(int));
+    if (nnz) std::memcpy(ip + slots.size() + rowp.size(), rowj.data(), nnz * sizeof(int));
     e = hipMemcpy(m.block, host.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(m.block);
@@ -750,6 +771,9 @@ int misdc_mech_create(const misdc_mech_desc* d, misdc_mech_t* out) {
     md.hf = base + ohf;
     md.s0 = base + os0;
     md.kappa0 = base + ok0;
+    md.rowu = base + oru;
+    md.rowp = md.slots + slots.size();
+    md.rowj = md.rowp + rowp.size();
     m.W.assign(d->W, d->W + N);
     m.cp.assign(d->cp, d->cp + N);
     m.hf.assign(d->hf, d->hf + N);
@@ -802,9 +826,6 @@ int misdc_reaction_solve_batch(misdc_mech_t mech, int64_t n, const double* bY, c
     if (n < 0) return fail(MISDC_EINVAL, "n < 0");
     if (n == 0) return MISDC_OK;
     if (!bY || !h || !c || !Y || !iters_out) return fail(MISDC_EINVAL, "NULL array");
-    if (mech->m.dev.N != 9)
-        return fail(MISDC_EUNSUPPORTED, "reaction solve built for 9 species, mechanism has %d",
-                    mech->m.dev.N);
     NewtonArgs a;
     a.n = n;
     a.bY = bY;
@@ -978,8 +999,8 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if (!mech || !grid) return fail(MISDC_EINVAL, "NULL handle");
     int rc = check_opts(opts);
     if (rc) return rc;
-    if (mech->m.dev.N != 9)
-        return fail(MISDC_EUNSUPPORTED, "integrator built for 9 species, mechanism has %d",
+    if (mech->m.dev.N > 63)
+        return fail(MISDC_EUNSUPPORTED, "integrator built for at most 63 species, mechanism has %d",
                     mech->m.dev.N);
     auto* I = new (std::nothrow) misdc_integ_s();
     if (!I) return fail(MISDC_ENOMEM, "host allocation failed");

@@ -47,6 +47,12 @@ struct MechDev {
     const double* hf;             // N
     const double* s0;             // N
     const double* kappa0;         // N+1: D0_k, then alpha0
+    // per-species reaction lists (CSR over species k, reactions ascending):
+    // rowj[rowp[k] .. rowp[k+1]) are the reactions with nu_kj != 0 and
+    // rowu the matching nu_kj W_k / rho0
+    const int* rowp;              // N+1
+    const int* rowj;              // nnz
+    const double* rowu;           // nnz
 };
 
 struct Mech {
@@ -96,6 +102,12 @@ struct NewtonArgs {
     misdc_newton_opts opt;
 };
 int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s);
+// one wavefront per cell (any species count up to 63): FP64 LU, or an FP32
+// LU on the matrix cores refined against the FP64 matrix
+enum { NEWTON_LU_FP64 = 0, NEWTON_LU_FP32_MFMA = 1 };
+int launch_reaction_newton_wave(const Mech& m, const NewtonArgs& a, int lu, hipStream_t s);
+int launch_reaction_source_wave(const Mech& m, int64_t n, const double* Y, int64_t ldy,
+                                const double* h, double* FR, int64_t ldf, hipStream_t s);
 
 // out[p] = sum_t W[p][t] s_t X_t, field-wise; X_t has nf_t fields (missing
 // fields are zero); s_t = scale[cell] for the terms in smask (per-cell step

@@ -52,7 +52,8 @@ class misdc_mech_desc(C.Structure):
 
 class misdc_newton_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("dtau0", C.c_double),
-                ("dtau_max", C.c_double), ("neg_slack", C.c_double)]
+                ("dtau_max", C.c_double), ("neg_slack", C.c_double), ("kernel", C.c_int32),
+                ("lu", C.c_int32)]
 
 
 class misdc_opts(C.Structure):
@@ -220,8 +221,14 @@ def misdc_reaction_source(mech, n, Y, h, FR, stream=None):
     check(lib().misdc_reaction_source(mech, n, _ptr(Y), _ptr(h), _ptr(FR), _stream(stream)))
 
 
-def newton_opts(tol=0.0, maxit=0, dtau0=0.0, dtau_max=0.0, neg_slack=0.0):
-    return misdc_newton_opts(tol, maxit, dtau0, dtau_max, neg_slack)
+NEWTON_KERNEL = {"auto": 0, "thread": 1, "wave": 2}
+LU = {"fp64": 0, "fp32_mfma": 1}
+
+
+def newton_opts(tol=0.0, maxit=0, dtau0=0.0, dtau_max=0.0, neg_slack=0.0, kernel="auto",
+                lu="fp64"):
+    return misdc_newton_opts(tol, maxit, dtau0, dtau_max, neg_slack, NEWTON_KERNEL[kernel],
+                             LU[lu])
 
 
 def misdc_reaction_solve_batch(mech, n, bY, h, c, Y, T_out=None, FR_out=None, iters=None,

@@ -1,0 +1,172 @@
+"""GPU parity for the wavefront-per-cell reaction kernels (any species count
+up to 63) and for whole steps with the 53-species / 325-reaction mechanism,
+against the FP64 oracle.
+
+Tolerances: converged Newton states within 1e-11 (absolute, mass fractions);
+steps within 1e-10 in the field-max-normalised norm.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import chemistry as ch
+from oracle.adr import FlameProblem, relaxed_initial_state
+from oracle.sdc import sdc_step
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_1801_01201_amd import native
+    native.lib()
+    return native
+
+
+@pytest.fixture(scope="module")
+def mech9():
+    return synth.make_mechanism(9, 21, 0)
+
+
+@pytest.fixture(scope="module")
+def mech53():
+    return synth.make_mechanism(**synth.config("flame2d_512_n53")["mech"])
+
+
+@pytest.fixture(scope="module")
+def mh9(nat, mech9):
+    from paper_1801_01201_amd.flame import Mechanism
+    m = Mechanism(mech9)
+    yield m
+    m.close()
+
+
+@pytest.fixture(scope="module")
+def mh53(nat, mech53):
+    from paper_1801_01201_amd.flame import Mechanism
+    m = Mechanism(mech53)
+    yield m
+    m.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def field_err(a, b):
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    scale = np.maximum(np.abs(b).max(axis=1), 1e-300)
+    return float((np.abs(a - b).max(axis=1) / scale).max())
+
+
+def _iteration_counts_agree(it, itr):
+    """Same criterion as for the per-thread kernel: iteration counts are FP64
+    decisions on both sides, but the pseudo-step growth takes |G| ratios at
+    the rounding floor, so a few cold-start cells may follow another valid
+    path; >= 90 % identical and means within 2 %."""
+    assert np.mean(it == itr) >= 0.90
+    assert abs(it.mean() - itr.mean()) <= 0.02 * itr.mean()
+
+
+def _solve(nat, mh, N, Yb, h, c, Yg, **opts):
+    n = h.size
+    Y = dev(Yg)
+    T = torch.empty(n, dtype=torch.float64, device="cuda")
+    FR = torch.empty((N, n), dtype=torch.float64, device="cuda")
+    it = torch.empty(n, dtype=torch.int32, device="cuda")
+    nat.misdc_reaction_solve_batch(mh.handle, n, dev(Yb), dev(h), dev(c), Y, T, FR, it,
+                                   opts=nat.newton_opts(**opts))
+    return host(Y), host(T), host(FR), host(it)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 3), (130, 4)])
+def test_wave_kernel_9_species(nat, mech9, mh9, n, seed):
+    """The wavefront kernel on the 9-species mechanism: same roots as the
+    oracle and as the per-thread kernel."""
+    Yb, Tb, c, Yg = synth.random_cell_batch(mech9, n, seed=seed)
+    h = ch.enthalpy(mech9, Yb, Tb)
+    Y, T, FR, it = _solve(nat, mh9, 9, Yb, h, c, Yg, kernel="wave")
+    Yr, Tr, itr = ch.reaction_solve(mech9, c, Yb, h, Yg)
+    assert np.all(it > 0)
+    assert np.abs(Y - Yr).max() <= 1e-11
+    np.testing.assert_allclose(T, ch.temperature(mech9, Yr, h), rtol=1e-11)
+    if n > 100:
+        _iteration_counts_agree(it, itr)
+    Y2, _, FR2, it2 = _solve(nat, mh9, 9, Yb, h, c, Yg, kernel="thread")
+    assert np.abs(Y - Y2).max() <= 1e-11
+    FRr = ch.reaction_source(mech9, Yr, Tr)
+    assert np.all(np.abs(FR - FRr) <= 1e-10 * (1.0 + np.abs(FRr).max(axis=0)))
+
+
+@pytest.mark.parametrize("n,seed", [(1, 7), (67, 8), (300, 9)])
+def test_reaction_solve_53(nat, mech53, mh53, n, seed):
+    Yb, Tb, c, Yg = synth.random_cell_batch(mech53, n, seed=seed)
+    h = ch.enthalpy(mech53, Yb, Tb)
+    Y, T, FR, it = _solve(nat, mh53, 53, Yb, h, c, Yg)
+    Yr, Tr, itr = ch.reaction_solve(mech53, c, Yb, h, Yg)
+    assert np.all(it > 0) and np.all(itr > 0)
+    assert np.abs(Y - Yr).max() <= 1e-11
+    np.testing.assert_allclose(T, ch.temperature(mech53, Yr, h), rtol=1e-11)
+    if n > 100:
+        _iteration_counts_agree(it, itr)
+    np.testing.assert_allclose(Y.sum(axis=0), Yb.sum(axis=0), atol=1e-13)
+    comp, W = mech53["comp"], mech53["W"][:, None]
+    np.testing.assert_allclose(comp @ (Y / W), comp @ (Yb / W), rtol=1e-12, atol=1e-16)
+
+
+def test_source_53(nat, mech53, mh53):
+    n = 257
+    Yb, Tb, c, Yg = synth.random_cell_batch(mech53, n, seed=12)
+    h = ch.enthalpy(mech53, Yb, Tb)
+    FR = torch.empty((53, n), dtype=torch.float64, device="cuda")
+    nat.misdc_reaction_source(mh53.handle, n, dev(Yb), dev(h), FR)
+    FRr = ch.reaction_source(mech53, Yb, ch.temperature(mech53, Yb, h))
+    err = np.abs(host(FR) - FRr)
+    assert np.all(err <= 1e-11 * (1.0 + np.abs(FRr).max(axis=0)))
+
+
+def _gpu_initial(mh, N, Y, T):
+    from paper_1801_01201_amd.flame import initial_state
+    st, it = initial_state(mh, dev(Y.reshape(N, -1)), dev(T.ravel()))
+    assert np.all(host(it) > 0)
+    return st
+
+
+def test_initial_state_53(nat, mech53, mh53):
+    Y, T = synth.flame_2d(mech53, 9, 7, 0.005, 0.005)
+    prob = FlameProblem(mech53, (0.005, 0.005), (100.0, 0.0))
+    ref = relaxed_initial_state(prob, Y, T).reshape(54, -1)
+    st = host(_gpu_initial(mh53, 53, Y, T))
+    assert field_err(st, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("scheme,nu,sweeps", [("cisdcq", 1, 3), ("misdcq", 1, 2)])
+def test_step_53(nat, mech53, mh53, scheme, nu, sweeps):
+    """A 53-species step on a 12 x 10 grid (2-D diffusion by the CG kernel
+    with vectors in global memory, 53 diffused fields)."""
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    nx, ny, dx, dt = 12, 10, 0.005, 2.5e-5
+    Y, T = synth.flame_2d(mech53, nx, ny, dx, dx)
+    prob = FlameProblem(mech53, (dx, dx), (100.0, 0.0))
+    phi = relaxed_initial_state(prob, Y, T)
+    ref, _ = sdc_step(prob, phi, dt, 5, sweeps, scheme, nu=nu)
+    st = _gpu_initial(mh53, 53, Y, T)
+    g = Grid(2, [nx, ny], [dx, dx], [100.0, 0.0])
+    integ = Integrator(mh53, g, n_nodes=5, sweeps=sweeps, nu=nu, scheme=scheme)
+    integ.step(st, dt)
+    stats = integ.stats()
+    out = host(st)
+    integ.close()
+    g.close()
+    assert stats["newton_failed"] == 0 and stats["cg_failed"] == 0
+    err = field_err(out, ref.reshape(54, -1))
+    assert err <= TOL, err
