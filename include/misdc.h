@@ -325,6 +325,11 @@ typedef struct {
     int64_t diffusion_kernel_launches;
     double newton_kernel_ms;
     int64_t newton_kernel_launches;
+    /* with newton.lu = MISDC_LU_FP32_MFMA (last step): FP32 solves done by
+     * the refinement, and Newton iterations that fell back to the FP64 LU
+     * because the refinement did not contract */
+    int64_t newton_lu_solves;
+    int64_t newton_lu_fallbacks;
 } misdc_stats;
 
 /* Clears the accumulated kernel timings of opts.profile. */

@@ -24,7 +24,9 @@
 // With the FP32 variant the LU factors are computed in single precision on
 // the matrix cores (panel of 16 columns on the vector units, trailing update
 // with 16x16x4 FP32 MFMA) and the Newton correction is refined against the
-// FP64 matrix (residual in FP64) until the correction stops shrinking.
+// FP64 matrix (residual in FP64) until its backward error is at the FP64
+// rounding level; if the residual stops contracting (cond(M) 2^-24 near 1)
+// that Newton iteration uses the FP64 LU instead.
 #include <cfloat>
 #include <cmath>
 
@@ -69,6 +71,16 @@ __device__ __forceinline__ int first_lane(unsigned long long mask) {
     return mask ? __ffsll((long long)mask) - 1 : -1;
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int LDA32 = 65;
+
+struct Lds32 {
+    float* A;        // 64 x LDA32
+    float* piv;      // 17: pivot row (16 panel entries) and 1/pivot
+    int* pos;        // 64: pivot position of each row (64: not chosen yet)
+    double* vec;     // 64: broadcast vector (FP64)
+};
+
 // LDS layout of one cell (doubles): matrix rows (stride ld), species
 // buffers, the reaction chunk, the pivot row and the pivot lanes.
 struct Lds {
@@ -81,6 +93,7 @@ struct Lds {
     double* D;       // 4 x 64: d q / d Y of the slot species
     double* piv;     // NXP + 2: pivot row, its right-hand side, 1/pivot
     int* plane;      // NXP: pivot lane of each column
+    Lds32 s32;       // FP32 LU (LU variant only)
 };
 
 template <int NXP>
@@ -95,12 +108,18 @@ __device__ __forceinline__ Lds lds_layout(double* base, int n, int ld) {
     L.D = L.qT + WV;
     L.piv = L.D + 4 * WV;
     L.plane = (int*)(L.piv + NXP + 2);
+    double* tail = L.piv + NXP + 2 + (NXP + 1) / 2;
+    L.s32.vec = tail;
+    L.s32.A = (float*)(tail + WV);
+    L.s32.piv = L.s32.A + 64 * LDA32;
+    L.s32.pos = (int*)(L.s32.piv + 18);
     return L;
 }
 
-template <int NXP>
+template <int NXP, bool FP32>
 constexpr size_t lds_doubles(int n, int ld) {
-    return (size_t)n * ld + 10 * WV + NXP + 2 + (NXP + 1) / 2;
+    return (size_t)n * ld + 10 * WV + NXP + 2 + (NXP + 1) / 2 +
+           (FP32 ? WV + (64 * LDA32 + 18 + 64 + 1) / 2 : 0);
 }
 
 // temperature from (Y, h): closed form for constant heat capacities
@@ -247,9 +266,136 @@ __device__ __forceinline__ double lu_solve_lanes(double (&a)[NXP], double g, con
 }
 
 // ---------------------------------------------------------------------------
+// FP32 LU on the matrix cores.  The 64 x 64 (padded) matrix lives in LDS,
+// row r at A[r * LDA32]; rows stay in place and plane[c] is the row chosen as
+// pivot of column c.  Blocked right-looking factorisation with panels of 16
+// columns: the panel is factorised on the vector units (row per lane,
+// partial pivoting over every row not yet chosen), the 16 pivot rows'
+// trailing part is transformed by the panel's unit lower triangle
+// (U12 = L11^-1 A12, column per lane), and the remaining rows get the rank-16
+// update A22 -= L21 U12 as 16 x 16 tiles of 16x16x4 FP32 MFMA.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_maxf(float v) {
+    return (float)wave_max((double)v);
+}
+
+__device__ __forceinline__ float lane_readf(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
+// Factorises A in place; returns this lane's pivot position and 1/pivot.
+__device__ __forceinline__ void lu32_factor(const Lds32& S, int* plane, int& mypos, float& myinv) {
+    const int lane = threadIdx.x;
+    bool done = false;
+    mypos = 64;
+    myinv = 0.f;
+    S.pos[lane] = 64;
+    __syncthreads();
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) {
+        const int k0 = 16 * pb;
+        float pan[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) pan[t] = S.A[lane * LDA32 + k0 + t];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const float cand = done ? -1.f : fabsf(pan[t]);
+            const float mx = wave_maxf(cand);
+            int p = first_lane(__ballot(!done && cand == mx));
+            if (p < 0) p = first_lane(__ballot(!done));
+            p = __builtin_amdgcn_readfirstlane(p);
+            if (lane == p) {
+#pragma unroll
+                for (int u = t; u < 16; ++u) S.piv[u] = pan[u];
+                myinv = 1.f / pan[t];
+                S.piv[16] = myinv;
+                plane[k0 + t] = p;
+                S.pos[lane] = k0 + t;
+                mypos = k0 + t;
+                done = true;
+            }
+            __syncthreads();
+            if (!done) {
+                const float f = pan[t] * S.piv[16];
+                pan[t] = f;
+#pragma unroll
+                for (int u = t + 1; u < 16; ++u) pan[u] -= f * S.piv[u];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) S.A[lane * LDA32 + k0 + t] = pan[t];
+        __syncthreads();
+        if (pb == 3) break;
+        // U12 = L11^-1 A12 on the 16 pivot rows of the panel, column per lane
+        if (lane >= k0 + 16) {
+            float ut[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int pt = plane[k0 + t];
+                float u = S.A[pt * LDA32 + lane];
+#pragma unroll
+                for (int s = 0; s < t; ++s) u -= S.A[pt * LDA32 + k0 + s] * ut[s];
+                ut[t] = u;
+                S.A[pt * LDA32 + lane] = u;
+            }
+        }
+        __syncthreads();
+        // A22 -= L21 U12 for the rows not chosen yet (chosen rows: zero L)
+        const int li = lane % 16, lk = lane / 16;
+#pragma unroll
+        for (int R = 0; R < 4; ++R) {
+            const int arow = 16 * R + li;
+            const bool live = S.pos[arow] >= k0 + 16;
+#pragma unroll
+            for (int C = pb + 1; C < 4; ++C) {
+                v4f acc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = S.A[(16 * R + 4 * lk + r) * LDA32 + 16 * C + li];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const float av = live ? -S.A[arow * LDA32 + k0 + 4 * kk + lk] : 0.f;
+                    const float bv = S.A[plane[k0 + 4 * kk + lk] * LDA32 + 16 * C + li];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) S.A[(16 * R + 4 * lk + r) * LDA32 + 16 * C + li] = acc[r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Solves with the FP32 factors: b is this lane's entry of the right-hand
+// side (row order), the result is this lane's entry of the solution
+// (column order).
+__device__ __forceinline__ float lu32_solve(const Lds32& S, const int* plane, int mypos, float myinv,
+                                            float b) {
+    const int lane = threadIdx.x;
+#pragma unroll 8
+    for (int c = 0; c < 64; ++c) {
+        const int p = __builtin_amdgcn_readfirstlane(plane[c]);
+        const float yc = lane_readf(b, p);
+        if (mypos > c) b -= S.A[lane * LDA32 + c] * yc;
+    }
+    float x = 0.f;
+#pragma unroll 8
+    for (int c = 63; c >= 0; --c) {
+        const int p = __builtin_amdgcn_readfirstlane(plane[c]);
+        const float xc = lane_readf(b * myinv, p);
+        if (lane == c) x = xc;
+        if (mypos < c) b -= S.A[lane * LDA32 + c] * xc;
+    }
+    return x;
+}
+
+// ---------------------------------------------------------------------------
 // Newton solve, one wavefront per cell.
 // ---------------------------------------------------------------------------
-template <int NXP>
+// FP32 refinement: at most this many FP32 solves per Newton iteration
+constexpr int MAX_REFINE = 10;
+
+template <int NXP, int LUK>
 __global__ void __launch_bounds__(64) newton_wave_kernel(MechDev m, NewtonArgs a) {
     extern __shared__ double lds_base[];
     const int N = m.N, n = N + 1, ld = n + 1;
@@ -270,13 +416,13 @@ __global__ void __launch_bounds__(64) newton_wave_kernel(MechDev m, NewtonArgs a
     const double inv_scale = 1.0 / m.newton_scale;
     double inv_dtau = 0.0;
     double gnorm_old = -1.0;
-    int it = 0;
+    int it = 0, nref = 0, nfb = 0;
     bool conv = false;
     while (!conv && it < a.opt.maxit) {
         const double lnT = log(T);
         species_state(m, L, Y, T, lnT);
-        // identity part of the rows (and the enthalpy row, written by
-        // column: lane k writes M[N][k])
+        // identity part of the rows (the enthalpy row is written by column:
+        // lane k writes M[N][k])
         if (lane < n) {
             double* row = L.M + (size_t)lane * ld;
             for (int l = 0; l < n; ++l) row[l] = (l == lane) ? 1.0 : 0.0;
@@ -297,20 +443,74 @@ __global__ void __launch_bounds__(64) newton_wave_kernel(MechDev m, NewtonArgs a
             L.M[(size_t)N * ld + N] = cpm * inv_scale;
         }
         const double gn2 = wave_sum(G * G);
+        if (lane < n) L.M[(size_t)lane * ld + lane] += inv_dtau;
         __syncthreads();
-        double row[NXP];
-#pragma unroll
-        for (int l = 0; l < NXP; ++l) {
-            double v = (l == lane) ? 1.0 : 0.0;       // padding rows: identity
-            if (lane < n && l < n) v = L.M[(size_t)lane * ld + l];
-            row[l] = v;
+        double d = 0.0;
+        bool fp64 = (LUK == 0);
+        if (LUK == 1) {
+            // FP32 factors of the (padded) matrix, then refinement of the
+            // correction against the FP64 matrix
+            const Lds32& S = L.s32;
+            for (int l = 0; l < 64; ++l) {
+                float v = (l == lane) ? 1.f : 0.f;
+                if (lane < n && l < n) v = (float)L.M[(size_t)lane * ld + l];
+                S.A[lane * LDA32 + l] = v;
+            }
+            __syncthreads();
+            int mypos = 64;
+            float myinv = 0.f;
+            lu32_factor(S, L.plane, mypos, myinv);
+            // refinement: d += M32^-1 (G - M d) with the residual in FP64,
+            // until the backward error is at the FP64 rounding level
+            // |G - M d| <= 4 eps (|M| |d| + |G|) (infinity norms); if the
+            // residual stops shrinking by half per step first, this Newton
+            // iteration takes the FP64 LU instead
+            double rowsum = 0.0;
+            if (lane < n)
+                for (int l = 0; l < n; ++l) rowsum += fabs(L.M[(size_t)lane * ld + l]);
+            const double mnorm = wave_max(rowsum);
+            const double gnorm_inf = wave_max(lane < n ? fabs(G) : 0.0);
+            double rhs = G, rprev = gnorm_inf;
+            bool ok32 = false;
+            for (int r = 0; r < MAX_REFINE; ++r) {
+                const double corr = (double)lu32_solve(S, L.plane, mypos, myinv, (float)rhs);
+                ++nref;
+                d += (lane < n) ? corr : 0.0;
+                S.vec[lane] = d;
+                __syncthreads();
+                double md = 0.0;
+                if (lane < n) {
+                    const double* row = L.M + (size_t)lane * ld;
+                    for (int l = 0; l < n; ++l) md += row[l] * S.vec[l];
+                }
+                rhs = (lane < n) ? G - md : 0.0;
+                __syncthreads();
+                const double rn = wave_max(fabs(rhs));
+                const double dn = wave_max(lane < n ? fabs(d) : 0.0);
+                if (!isfinite(rn) || !isfinite(dn)) break;
+                const double floor64 = DBL_EPSILON * (mnorm * dn + gnorm_inf);
+                if (rn <= 4.0 * floor64) {
+                    ok32 = true;
+                    break;
+                }
+                if (!(rn <= 0.5 * rprev)) break;      // stalled: FP64 LU
+                rprev = rn;
+            }
+            if (!ok32) {
+                ++nfb;
+                fp64 = true;
+            }
         }
-        if (lane < n) {
+        if (fp64) {
+            double row[NXP];
 #pragma unroll
-            for (int l = 0; l < NXP; ++l)
-                if (l == lane) row[l] += inv_dtau;
+            for (int l = 0; l < NXP; ++l) {
+                double v = (l == lane) ? 1.0 : 0.0;       // padding rows: identity
+                if (lane < n && l < n) v = L.M[(size_t)lane * ld + l];
+                row[l] = v;
+            }
+            d = lu_solve_lanes<NXP>(row, lane < n ? G : 0.0, L);
         }
-        const double d = lu_solve_lanes<NXP>(row, lane < n ? G : 0.0, L);
         ++it;
         // acceptance of the trial x - delta
         const double dT = lane_read(d, N);
@@ -346,6 +546,7 @@ __global__ void __launch_bounds__(64) newton_wave_kernel(MechDev m, NewtonArgs a
         if (sp) a.FR[(size_t)lane * a.ldf + i] = fr;
     }
     if (a.iters && lane == 0) a.iters[i] = conv ? it : -1;
+    if (a.lu_info && lane == 0) a.lu_info[i] = (nref < 0xffff ? nref : 0xffff) | (nfb << 16);
 }
 
 // F_R at (Y, T(Y, h)), one wavefront per cell
@@ -371,31 +572,42 @@ inline unsigned grid_for(int64_t n, int threads) {
     return (unsigned)((n + threads - 1) / threads);
 }
 
+// [0] solves, [1] iterations, [2] failures, [3] max iterations,
+// [4] FP32 refinement solves, [5] FP64 fallbacks (with lu_info)
 __global__ void __launch_bounds__(256) wave_stats_kernel(int64_t n, const int32_t* iters,
+                                                         const int32_t* lu_info,
                                                          unsigned long long* stats) {
-    __shared__ unsigned long long s_sum[4], s_bad[4], s_max[4];
+    __shared__ unsigned long long s_sum[4], s_bad[4], s_max[4], s_ref[4], s_fb[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long v = 0, b = 0, mx = 0;
+    unsigned long long v = 0, b = 0, mx = 0, rf = 0, fb = 0;
     if (i < n) {
         const int32_t itc = iters[i];
         v = itc > 0 ? (unsigned long long)itc : 0ull;
         b = itc < 0 ? 1ull : 0ull;
         mx = v;
+        if (lu_info) {
+            rf = (unsigned long long)(lu_info[i] & 0xffff);
+            fb = (unsigned long long)((unsigned)lu_info[i] >> 16);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         v += __shfl_xor(v, off);
         b += __shfl_xor(b, off);
+        rf += __shfl_xor(rf, off);
+        fb += __shfl_xor(fb, off);
         const unsigned long long o = __shfl_xor(mx, off);
         mx = o > mx ? o : mx;
     }
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    if (lane == 0) { s_sum[wave] = v; s_bad[wave] = b; s_max[wave] = mx; }
+    if (lane == 0) { s_sum[wave] = v; s_bad[wave] = b; s_max[wave] = mx; s_ref[wave] = rf; s_fb[wave] = fb; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long S = 0, B = 0, X = 0;
+        unsigned long long S = 0, B = 0, X = 0, RF = 0, FB = 0;
         for (int w = 0; w < 4; ++w) {
             S += s_sum[w];
             B += s_bad[w];
+            RF += s_ref[w];
+            FB += s_fb[w];
             X = s_max[w] > X ? s_max[w] : X;
         }
         const int64_t lo = (int64_t)blockIdx.x * blockDim.x;
@@ -404,6 +616,10 @@ __global__ void __launch_bounds__(256) wave_stats_kernel(int64_t n, const int32_
         atomicAdd(&stats[1], S);
         atomicAdd(&stats[2], B);
         atomicMax(&stats[3], X);
+        if (lu_info) {
+            atomicAdd(&stats[4], RF);
+            atomicAdd(&stats[5], FB);
+        }
     }
 }
 
@@ -413,24 +629,27 @@ int launch_reaction_newton_wave(const Mech& m, const NewtonArgs& a, int lu, hipS
     if (a.n == 0) return MISDC_OK;
     const int N = m.dev.N, n = N + 1, ld = n + 1;
     if (N > 63) return fail(MISDC_EUNSUPPORTED, "wavefront reaction solve: at most 63 species");
-    if (lu != NEWTON_LU_FP64)
-        return fail(MISDC_EUNSUPPORTED, "wavefront reaction solve: LU variant %d not built", lu);
+    if (lu != NEWTON_LU_FP64 && lu != NEWTON_LU_FP32_MFMA)
+        return fail(MISDC_EINVAL, "unknown LU variant %d", lu);
     if (a.n > 0x7fffffffll) return fail(MISDC_EINVAL, "too many cells for one launch");
     const dim3 grid((unsigned)a.n), block(64);
-    if (n <= 16) {
-        const size_t lds = lds_doubles<16>(n, ld) * sizeof(double);
-        hipLaunchKernelGGL(newton_wave_kernel<16>, grid, block, lds, s, m.dev, a);
+    if (lu == NEWTON_LU_FP32_MFMA) {
+        const size_t lds = lds_doubles<64, true>(n, ld) * sizeof(double);
+        hipLaunchKernelGGL((newton_wave_kernel<64, 1>), grid, block, lds, s, m.dev, a);
+    } else if (n <= 16) {
+        const size_t lds = lds_doubles<16, false>(n, ld) * sizeof(double);
+        hipLaunchKernelGGL((newton_wave_kernel<16, 0>), grid, block, lds, s, m.dev, a);
     } else if (n <= 32) {
-        const size_t lds = lds_doubles<32>(n, ld) * sizeof(double);
-        hipLaunchKernelGGL(newton_wave_kernel<32>, grid, block, lds, s, m.dev, a);
+        const size_t lds = lds_doubles<32, false>(n, ld) * sizeof(double);
+        hipLaunchKernelGGL((newton_wave_kernel<32, 0>), grid, block, lds, s, m.dev, a);
     } else {
-        const size_t lds = lds_doubles<64>(n, ld) * sizeof(double);
-        hipLaunchKernelGGL(newton_wave_kernel<64>, grid, block, lds, s, m.dev, a);
+        const size_t lds = lds_doubles<64, false>(n, ld) * sizeof(double);
+        hipLaunchKernelGGL((newton_wave_kernel<64, 0>), grid, block, lds, s, m.dev, a);
     }
     MISDC_HIP(hipGetLastError());
     if (a.stats && a.iters) {
         hipLaunchKernelGGL(wave_stats_kernel, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a.n,
-                           a.iters, a.stats);
+                           a.iters, a.lu_info, a.stats);
         MISDC_HIP(hipGetLastError());
     }
     return MISDC_OK;
@@ -441,7 +660,7 @@ int launch_reaction_source_wave(const Mech& m, int64_t n, const double* Y, int64
     if (n == 0) return MISDC_OK;
     if (m.dev.N > 63) return fail(MISDC_EUNSUPPORTED, "wavefront source: at most 63 species");
     if (n > 0x7fffffffll) return fail(MISDC_EINVAL, "too many cells for one launch");
-    const size_t lds = lds_doubles<64>(0, m.dev.N + 2) * sizeof(double);
+    const size_t lds = lds_doubles<64, false>(0, m.dev.N + 2) * sizeof(double);
     hipLaunchKernelGGL(source_wave_kernel, dim3((unsigned)n), dim3(64), lds, s, m.dev, n, Y, ldy,
                        h, FR, ldf);
     MISDC_HIP(hipGetLastError());

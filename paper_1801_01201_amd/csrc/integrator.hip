@@ -88,7 +88,8 @@ struct misdc_integ_s {
     double* thD = nullptr;                        // theta work (diffusion stream)
     double* thR = nullptr;                        // theta work (reaction stream)
     int32_t* iters = nullptr;                     // Newton iterations (cells)
-    unsigned long long* nstats = nullptr;         // Newton statistics (4)
+    unsigned long long* nstats = nullptr;         // Newton statistics (8)
+    int32_t* lu_info = nullptr;                   // FP32 LU refinement record (cells)
     int32_t* cgstats = nullptr;                   // CG: [0] sum, [1] max, [2] failed, [3] solves, [4] timeouts
     double* inc = nullptr;                        // sweep increments: 64 x NF x 2
     double* inc_partial = nullptr;
@@ -452,6 +453,7 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     a.FR = out.FR;
     a.ldf = n;
     a.iters = I->iters;
+    a.lu_info = (I->opt.newton.lu == MISDC_LU_FP32_MFMA) ? I->lu_info : nullptr;
     a.stats = I->nstats;
     a.opt = I->opt.newton;
     hipEvent_t t0 = timing_begin(I, I->sR);
@@ -617,7 +619,7 @@ int issue_step(misdc_integ_s* I, double* state, double dt, const double* dtf) {
         I->dtc = I->dt_cell;
         dt = 1.0;      // every dt-carrying term takes dtc[cell] (or dtf[flame])
     }
-    if ((rc = launch_zero(I->nstats, 4 * sizeof(unsigned long long), I->sD))) return rc;
+    if ((rc = launch_zero(I->nstats, 8 * sizeof(unsigned long long), I->sD))) return rc;
     if ((rc = launch_zero(I->cgstats, 8 * sizeof(int32_t), I->sD))) return rc;
     // I1, I2, I4: every node of sweep 0 holds phi^n and F(phi^n)
     NodeBuf& b0 = I->lev[0][0];
@@ -1057,7 +1059,8 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if ((rc = dalloc(I, &I->thD, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->thR, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->iters, (size_t)n))) return bail(rc);
-    if ((rc = dalloc(I, &I->nstats, 4))) return bail(rc);
+    if ((rc = dalloc(I, &I->nstats, 8))) return bail(rc);
+    if ((rc = dalloc(I, &I->lu_info, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->cgstats, 8))) return bail(rc);
     if ((rc = dalloc(I, &I->inc, (size_t)64 * NF * 2))) return bail(rc);
     if ((rc = dalloc(I, &I->inc_partial, (size_t)I->inc_blocks * NF * 2))) return bail(rc);
@@ -1269,7 +1272,7 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
     MISDC_HIP(hipStreamSynchronize(I->sD));
     MISDC_HIP(hipStreamSynchronize(I->sR2));
     std::memset(st, 0, sizeof(*st));
-    unsigned long long ns[4];
+    unsigned long long ns[8];
     int32_t cg[8];
     MISDC_HIP(hipMemcpy(ns, I->nstats, sizeof(ns), hipMemcpyDeviceToHost));
     MISDC_HIP(hipMemcpy(cg, I->cgstats, sizeof(cg), hipMemcpyDeviceToHost));
@@ -1277,6 +1280,8 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
     st->newton_iters = (int64_t)ns[1];
     st->newton_failed = (int64_t)ns[2];
     st->newton_max = (int32_t)ns[3];
+    st->newton_lu_solves = (int64_t)ns[4];
+    st->newton_lu_fallbacks = (int64_t)ns[5];
     st->cg_iters = cg[0];
     st->cg_max = cg[1];
     st->cg_failed = cg[2] + cg[4];

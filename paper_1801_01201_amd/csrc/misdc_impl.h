@@ -98,7 +98,9 @@ struct NewtonArgs {
     double* T;                              // n out (closed form of (Y, h)), may be null
     double* FR; int64_t ldf;                // N fields out, may be null
     int32_t* iters;                         // n out, may be null
-    unsigned long long* stats;              // [0] solves, [1] iters, [2] failed, [3] max; may be null
+    int32_t* lu_info = nullptr;             // n out, may be null: FP32 solves | FP64 fallbacks << 16
+    unsigned long long* stats;              // [0] solves, [1] iters, [2] failed, [3] max,
+                                            // [4] FP32 solves, [5] fallbacks; may be null
     misdc_newton_opts opt;
 };
 int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s);

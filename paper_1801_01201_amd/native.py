@@ -78,7 +78,8 @@ class misdc_stats(C.Structure):
                 ("cg_failed", C.c_int32), ("n_sweeps", C.c_int32),
                 ("sweep_increment", C.c_double * 64), ("diffusion_kernel_ms", C.c_double),
                 ("diffusion_kernel_launches", C.c_int64), ("newton_kernel_ms", C.c_double),
-                ("newton_kernel_launches", C.c_int64)]
+                ("newton_kernel_launches", C.c_int64), ("newton_lu_solves", C.c_int64),
+                ("newton_lu_fallbacks", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "sweep_increment"}
