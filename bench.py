@@ -35,6 +35,8 @@ CG_BYTES_PER_UNKNOWN_ITER = 56.0
 # algorithmic FP64 work of one Newton iteration for 9 species / 21 reactions
 NEWTON_FLOP_PER_ITER_9 = 3.4e3
 NEWTON_BYTES_PER_SOLVE_9 = 316.0
+# 53 species / 325 reactions: rates ~24k, Jacobian ~13k, LU ~105k, solves ~6k
+NEWTON_FLOP_PER_ITER_53 = 1.49e5
 
 
 def measured_traffic(profile_name, source_rel):
@@ -233,6 +235,107 @@ def ensemble_main(args):
     print(json.dumps(line), flush=True)
 
 
+def n53_main(args):
+    """The 53-species / 325-reaction flame on 512 x 512 cells (CISDCQ-1,
+    5 nodes, 6 sweeps, dt 2.5e-5 s): the reaction solve runs one wavefront
+    per cell, the implicit diffusion of 53 fields runs the CG kernel with
+    vectors in global memory.  Both Newton LU variants are timed (FP64 LU;
+    FP32 LU on the matrix cores refined in FP64); ``value`` is the one named
+    by --lu.  Eager steps with kernel timing (roofline of the dominant
+    kernel)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1801_01201_amd import native
+    from paper_1801_01201_amd.flame import Mechanism, Grid, Integrator, initial_state
+    native.lib()
+    cfg = synth.config("flame2d_512_n53")
+    mech = synth.make_mechanism(**cfg["mech"])
+    N = mech["N"]
+    nx, ny = cfg["n"]
+    n = nx * ny
+    M = cfg["n_nodes"] - 1
+    mh = Mechanism(mech)
+    g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
+    Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
+    state, _ = initial_state(mh, torch.tensor(Y.reshape(N, -1), device="cuda"),
+                             torch.tensor(T.ravel(), device="cuda"))
+    torch.cuda.synchronize()
+    print("[bench] n53: initial state ready", file=sys.stderr, flush=True)
+    runs = {}
+    for lu in ("fp64", "fp32_mfma"):
+        integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
+                           scheme=cfg["scheme"], profile=True,
+                           newton=native.newton_opts(lu=lu))
+        st = state.clone()
+        for _ in range(args.warmup):
+            integ.step(st, cfg["dt"])
+        torch.cuda.synchronize()
+        native.misdc_reset_profile(integ.handle)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            integ.step(st, cfg["dt"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        stats = integ.stats()
+        integ.close()
+        runs[lu] = (el, stats, st)
+        print(f"[bench] n53 {lu}: {el / args.steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    el, stats, st = runs[args.lu]
+    a64, a32 = runs["fp64"][2], runs["fp32_mfma"][2]
+    agree = float(((a64 - a32).abs().amax(dim=1) / a64.abs().amax(dim=1).clamp_min(1e-300)).max())
+    updates = n * M * cfg["nu"] * cfg["sweeps"] * args.steps
+    d_ms, d_n = stats["diffusion_kernel_ms"], stats["diffusion_kernel_launches"]
+    r_ms, r_n = stats["newton_kernel_ms"], stats["newton_kernel_launches"]
+    newton_per_cell = stats["newton_iters"] / max(1, stats["newton_solves"])
+    cg_per_solve = stats["cg_iters"] / max(1, stats["cg_solves"])
+    if d_ms >= r_ms:
+        avg_s = d_ms / max(1, d_n) * 1e-3
+        byts = CG_BYTES_PER_UNKNOWN_ITER * N * n * cg_per_solve
+        roof = {"kernel": "cg_kernel (Jacobi-PCG, vectors in global memory, 53 fields)",
+                "bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                "avg_launch_ms": avg_s * 1e3, "launches": d_n,
+                "algorithmic_bytes_per_launch": byts, "cg_iterations_per_launch": cg_per_solve}
+    else:
+        avg_s = r_ms / max(1, r_n) * 1e-3
+        flops = NEWTON_FLOP_PER_ITER_53 * n * newton_per_cell
+        roof = {"kernel": f"newton_wave_kernel (one wavefront per cell, LU {args.lu})",
+                "bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": None, "avg_launch_ms": avg_s * 1e3, "launches": r_n}
+    variants = {}
+    for lu, (e, s2, _) in runs.items():
+        variants[lu] = {"ms_per_step": e / args.steps * 1e3,
+                        "newton_ms_per_launch": s2["newton_kernel_ms"] / max(1, s2["newton_kernel_launches"]),
+                        "newton_iters_per_cell": s2["newton_iters"] / max(1, s2["newton_solves"]),
+                        "fp32_solves": s2["newton_lu_solves"],
+                        "fp64_fallbacks": s2["newton_lu_fallbacks"],
+                        "newton_failed": s2["newton_failed"]}
+    line = {
+        "metric": METRIC, "value": updates / el, "unit": "cell-node updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"flame2d_512_n53: 2-D periodic {nx}x{ny} flame, {N} species / "
+                               f"{mech['R']} reactions, CISDCQ-{cfg['nu']}, {cfg['n_nodes']} nodes, "
+                               f"{cfg['sweeps']} sweeps, dt {cfg['dt']} s, Newton LU {args.lu}",
+                   "cells": n},
+        "newton_iters_per_cell": newton_per_cell,
+        "cg_iters_per_solve": cg_per_solve,
+        "roofline": roof,
+        "kernel_split": {"diffusion_solve_ms_per_launch": d_ms / max(1, d_n),
+                         "newton_ms_per_launch": r_ms / max(1, r_n),
+                         "diffusion_solve_share_of_step": d_ms / (el * 1e3),
+                         "newton_share_of_step": r_ms / (el * 1e3)},
+        "lu_variants": variants,
+        "fp32_vs_fp64_state_difference": agree,
+        "newton_failed": stats["newton_failed"], "cg_failed": stats["cg_failed"],
+    }
+    mh.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,7 +348,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the extra timing of the same steps replayed as one HIP graph")
-    ap.add_argument("--workload", default="flame2d_256", choices=["flame2d_256", "ensemble64"])
+    ap.add_argument("--workload", default="flame2d_256",
+                    choices=["flame2d_256", "ensemble64", "flame2d_512_n53"])
+    ap.add_argument("--lu", default="fp64", choices=["fp64", "fp32_mfma"],
+                    help="flame2d_512_n53: precision of the Newton LU of the timed run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device-to-device 4 times (calibrates the HBM "
                          "byte counters of rocprofv3 --pmc) and exit")
@@ -265,6 +371,8 @@ def main():
         sys.exit(2)
     if args.workload == "ensemble64":
         return ensemble_main(args)
+    if args.workload == "flame2d_512_n53":
+        return n53_main(args)
     cfg = workload()
     if args.nu:
         cfg["nu"] = args.nu
