@@ -24,4 +24,6 @@ adr           The advection-diffusion-reaction flame problem that ties the
 collocation   Brute-force solution of the collocation system (the fixed point
               of every sweep).
 nagumo        The paper's 1-D nonlinear test problem.
+mlp           The dense network of the learned Newton guess: forward pass,
+              mean-squared-error gradients, Adam, bfloat16 rounding.
 """

@@ -193,3 +193,16 @@ def make_mechanism(n_species=9, n_reactions=21, seed=0, rate_spread=None,
         rho0=float(rho0), p_atm=P_ATM, R_u=R_U, R_c=R_CAL,
         Y_cold=Y_cold, Y_hot=Y_hot, seed=int(seed),
     )
+
+
+def mlp_init(sizes, seed=7):
+    """Initial weights of a dense network with layer widths ``sizes``:
+    uniform in +-sqrt(6 / fan_in) (He), zero biases, float32 values.  Data
+    only: list of (W (fan_in, fan_out), b)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        lim = np.sqrt(6.0 / a)
+        W = rng.uniform(-lim, lim, (a, b)).astype(np.float32).astype(np.float64)
+        params.append((W, np.zeros(b)))
+    return params
