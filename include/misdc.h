@@ -330,12 +330,86 @@ typedef struct {
      * because the refinement did not contract */
     int64_t newton_lu_solves;
     int64_t newton_lu_fallbacks;
+    /* with a learned guess (misdc_integ_set_guess, last step): cell-node
+     * solves that started from the network's guess */
+    int64_t newton_guess_learned;
 } misdc_stats;
 
 /* Clears the accumulated kernel timings of opts.profile. */
 int misdc_reset_profile(misdc_integ_t integ);
 
 int misdc_get_stats(misdc_integ_t integ, misdc_stats* stats);
+
+/* ---------------------------------------------------------------------- */
+/* Learned Newton initial guess                                            */
+/* ---------------------------------------------------------------------- */
+/* An extension of the reaction step S5 (eq. reaction_step_numerical_
+ * methodology), where the paper starts Newton from the previous iterate: a
+ * dense network n_in -> n_hidden -> n_hidden -> n_out with ReLU hidden
+ * layers, n_in = N + 2 inputs (b_Y, T_b = T(b_Y, h), ln c, each normalised
+ * as (v - mu) / sd) and n_out = N + 1 outputs (Y* - b_Y, T* - T_b, each
+ * divided by its sd).  Products on the matrix cores with BF16 operands and
+ * FP32 accumulation (MISDC_MLP_BF16), or FP32 operands (MISDC_MLP_FP32).
+ * Parameters are FP32, packed as W1 (n_in x n_hidden, row-major), b1, W2,
+ * b2, W3, b3.  Device arrays of features and targets are FP32, row-major
+ * (batch x n_in, batch x n_out).  A network handle holds work buffers sized
+ * for the largest batch seen; calls on one handle must not overlap. */
+typedef struct misdc_mlp_s* misdc_mlp_t;
+enum { MISDC_MLP_BF16 = 0, MISDC_MLP_FP32 = 1 };
+
+/* Creates a network with zero parameters and identity normalisation
+ * (widths in [1, 512]; MISDC_EINVAL otherwise). */
+int misdc_mlp_create(int n_in, int n_hidden, int n_out, int precision, misdc_mlp_t* out);
+int misdc_mlp_destroy(misdc_mlp_t mlp);
+int misdc_mlp_param_count(misdc_mlp_t mlp, int64_t* count);
+/* Host FP32 arrays of param_count values; setting resets the Adam state. */
+int misdc_mlp_set_params(misdc_mlp_t mlp, const float* host_params);
+int misdc_mlp_get_params(misdc_mlp_t mlp, float* host_params);
+/* Host arrays: in_mu, in_sd (n_in), out_sd (n_out); scales must be > 0. */
+int misdc_mlp_set_normalization(misdc_mlp_t mlp, const float* in_mu, const float* in_sd,
+                                const float* out_sd);
+/* y = network(x) for batch rows. */
+int misdc_mlp_forward(misdc_mlp_t mlp, int64_t batch, const float* dev_x, float* dev_y,
+                      void* stream);
+/* Gradient (packed like the parameters) of the loss mean((y - t)^2) over
+ * the batch rows and the outputs; dev_loss (1 float, may be NULL) gets the
+ * loss.  Deterministic (fixed-order reductions, no atomics). */
+int misdc_mlp_gradients(misdc_mlp_t mlp, int64_t batch, const float* dev_x, const float* dev_t,
+                        float* dev_grad, float* dev_loss, void* stream);
+/* One Adam step (bias-corrected moments) with the given gradient. */
+int misdc_mlp_adam_step(misdc_mlp_t mlp, const float* dev_grad, float lr, float beta1,
+                        float beta2, float eps, void* stream);
+/* epochs passes over floor(n / batch) consecutive minibatches of the
+ * training set (the caller shuffles it), each forward + gradient + Adam
+ * (0.9, 0.999, 1e-8); dev_loss (epochs floats, may be NULL) gets the loss
+ * of each epoch's last minibatch. */
+int misdc_mlp_train(misdc_mlp_t mlp, int64_t n, const float* dev_x, const float* dev_t,
+                    int64_t batch, int epochs, float lr, float* dev_loss, void* stream);
+/* Normalised features of n reaction problems (dev_bY: N x n, dev_h, dev_c:
+ * n) and normalised targets from their solutions dev_Y (N x n). */
+int misdc_mlp_features(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, const double* dev_bY,
+                       const double* dev_h, const double* dev_c, float* dev_x, void* stream);
+int misdc_mlp_targets(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, const double* dev_bY,
+                      const double* dev_h, const double* dev_Y, float* dev_t, void* stream);
+/* Initial guess of misdc_reaction_solve_batch: dev_Y (N x n) holds the plain
+ * guess on entry; each cell takes the network's guess (b_Y + predicted
+ * increment, negative entries of non-negative b_Y clipped to 0) instead if
+ * its residual |Y - c FR(Y, T(Y, h)) - b_Y|_2 is smaller.  dev_choice (n
+ * int32, may be NULL) records 1 where the learned guess was taken. */
+int misdc_reaction_guess_mlp(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, const double* dev_bY,
+                             const double* dev_h, const double* dev_c, double* dev_Y,
+                             int32_t* dev_choice, void* stream);
+/* Every reaction task of later steps starts from the learned guess where it
+ * has the smaller residual (NULL: the plain guess, the previous iterate).
+ * Allocates the network's buffers for the grid; the network must outlive
+ * its use.  Synchronises. */
+int misdc_integ_set_guess(misdc_integ_t integ, misdc_mlp_t mlp);
+/* Records the reaction problems of later steps: task t (in issue order, up
+ * to max_tasks) writes (b_Y: N x n, h: n, c: n, Y: N x n) doubles at
+ * dev_buf + t (2N + 2) n.  max_tasks = 0 stops recording.  Steps are not
+ * replayed as graphs while recording.  Synchronises. */
+int misdc_integ_record(misdc_integ_t integ, double* dev_buf, int64_t max_tasks);
+int misdc_integ_recorded(misdc_integ_t integ, int64_t* tasks);
 
 #ifdef __cplusplus
 }

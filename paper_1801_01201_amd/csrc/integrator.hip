@@ -51,14 +51,6 @@ int fail(int code, const char* fmt, ...) {
 
 using namespace misdc;
 
-struct misdc_mech_s {
-    Mech m;
-};
-
-struct misdc_grid_s {
-    Grid g;
-};
-
 namespace {
 
 struct NodeBuf {
@@ -113,6 +105,12 @@ struct misdc_integ_s {
     const double* dtc = nullptr;
     double* dt_cell = nullptr;
     double tuned_ms = 0.0;                        // step time measured by the autotuner
+    // learned Newton guess (optional) and recording of reaction problems
+    MlpImpl* mlp = nullptr;
+    int32_t* choice = nullptr;                    // cells: learned guess taken
+    double* cbuf = nullptr;                       // cells: implicit factor c of the task
+    double* rec_buf = nullptr;                    // caller's buffer of recorded problems
+    int64_t rec_cap = 0, rec_count = 0;
     // graph of one whole step, replayed while (state, dt, dev_dt) are unchanged
     bool capturing = false;
     hipGraphExec_t gexec = nullptr;
@@ -437,6 +435,18 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     // enthalpy is not changed by the reaction step
     rc = launch_copy(out.phi + (size_t)N * n, I->phiAD[p] + (size_t)N * n, n, I->sR);
     if (rc) return rc;
+    const double c_scalar = I->dtc ? cf : dt * cf;
+    const double* guess = Lp[p].phi;
+    if (I->mlp) {
+        // the plain guess, replaced cell by cell by the learned one where
+        // that has the smaller residual
+        if ((rc = launch_copy(out.phi, Lp[p].phi, (int64_t)N * n, I->sR))) return rc;
+        if ((rc = mlp_guess(*I->mech, I->mlp, n, I->bR, I->phiAD[p] + (size_t)N * n, I->dtc,
+                            c_scalar, out.phi, n, I->choice, I->sR)))
+            return rc;
+        if ((rc = launch_count_flags(I->choice, n, I->nstats + 6, I->sR))) return rc;
+        guess = out.phi;
+    }
     NewtonArgs a;
     a.n = n;
     a.bY = I->bR;
@@ -444,8 +454,8 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     a.h = I->phiAD[p] + (size_t)N * n;
     // c = dt * cf: per cell for ensembles with per-flame step sizes
     a.c = I->dtc;
-    a.c_scalar = I->dtc ? cf : dt * cf;
-    a.guess = Lp[p].phi;
+    a.c_scalar = c_scalar;
+    a.guess = guess;
     a.ldg = n;
     a.Y = out.phi;
     a.ldy = n;
@@ -460,6 +470,15 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     rc = launch_reaction_newton(*I->mech, a, I->sR);
     if (rc) return rc;
     timing_end(I, t0, I->sR, 1);
+    if (I->rec_buf && I->rec_count < I->rec_cap) {
+        // record (b_Y, h, c, Y) of this reaction task
+        double* slot = I->rec_buf + (size_t)I->rec_count * (2 * N + 2) * n;
+        if ((rc = launch_copy(slot, I->bR, (int64_t)N * n, I->sR))) return rc;
+        if ((rc = launch_copy(slot + (size_t)N * n, I->phiAD[p] + (size_t)N * n, n, I->sR))) return rc;
+        if ((rc = launch_fill_c(n, I->dtc, c_scalar, slot + (size_t)(N + 1) * n, I->sR))) return rc;
+        if ((rc = launch_copy(slot + (size_t)(N + 2) * n, out.phi, (int64_t)N * n, I->sR))) return rc;
+        ++I->rec_count;
+    }
     rc = eval_ops(I, out, I->thR, I->sR, false);
     (void)NF;
     return rc;
@@ -1061,6 +1080,8 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if ((rc = dalloc(I, &I->iters, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->nstats, 8))) return bail(rc);
     if ((rc = dalloc(I, &I->lu_info, (size_t)n))) return bail(rc);
+    if ((rc = dalloc(I, &I->choice, (size_t)n))) return bail(rc);
+    if ((rc = dalloc(I, &I->cbuf, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->cgstats, 8))) return bail(rc);
     if ((rc = dalloc(I, &I->inc, (size_t)64 * NF * 2))) return bail(rc);
     if ((rc = dalloc(I, &I->inc_partial, (size_t)I->inc_blocks * NF * 2))) return bail(rc);
@@ -1121,7 +1142,7 @@ int misdc_step(misdc_integ_t I, double* state, double dt, const double* dev_dt, 
     // order after the caller's stream
     MISDC_HIP(hipEventRecord(I->ev_in, cs));
     MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_in, 0));
-    if (I->opt.use_graph) {
+    if (I->opt.use_graph && !I->rec_buf) {
         if (!I->gexec || I->g_state != state || I->g_dt != dt || I->g_dtf != dev_dt) {
             drop_graph(I);
             hipGraph_t graph = nullptr;
@@ -1153,6 +1174,40 @@ int misdc_step(misdc_integ_t I, double* state, double dt, const double* dev_dt, 
     MISDC_HIP(hipStreamWaitEvent(cs, I->ev_outD, 0));
     I->last_sweeps = I->opt.n_sweeps;
     I->dt = dt;
+    return MISDC_OK;
+}
+
+int misdc_integ_set_guess(misdc_integ_t I, misdc_mlp_t mlp) {
+    if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
+    MISDC_HIP(hipStreamSynchronize(I->sD));
+    MISDC_HIP(hipStreamSynchronize(I->sR2));
+    if (mlp) {
+        if (mlp_dims(mlp->p, 0) != I->N + 2 || mlp_dims(mlp->p, 3) != I->N + 1)
+            return fail(MISDC_EINVAL, "network widths do not match %d species", I->N);
+        // every buffer a step needs is allocated now (none during a step)
+        int rc = mlp_reserve(mlp->p, I->n);
+        if (rc) return rc;
+    }
+    I->mlp = mlp ? mlp->p : nullptr;
+    drop_graph(I);
+    return MISDC_OK;
+}
+
+int misdc_integ_record(misdc_integ_t I, double* dev_buf, int64_t max_tasks) {
+    if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
+    if (max_tasks < 0 || (max_tasks > 0 && !dev_buf)) return fail(MISDC_EINVAL, "invalid buffer");
+    MISDC_HIP(hipStreamSynchronize(I->sD));
+    MISDC_HIP(hipStreamSynchronize(I->sR2));
+    I->rec_buf = max_tasks > 0 ? dev_buf : nullptr;
+    I->rec_cap = max_tasks;
+    I->rec_count = 0;
+    drop_graph(I);
+    return MISDC_OK;
+}
+
+int misdc_integ_recorded(misdc_integ_t I, int64_t* tasks) {
+    if (!I || !tasks) return fail(MISDC_EINVAL, "NULL argument");
+    *tasks = I->rec_count;
     return MISDC_OK;
 }
 
@@ -1282,6 +1337,7 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
     st->newton_max = (int32_t)ns[3];
     st->newton_lu_solves = (int64_t)ns[4];
     st->newton_lu_fallbacks = (int64_t)ns[5];
+    st->newton_guess_learned = (int64_t)ns[6];
     st->cg_iters = cg[0];
     st->cg_max = cg[1];
     st->cg_failed = cg[2] + cg[4];

@@ -176,6 +176,34 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
 int launch_field_diff_max(int nfields, int64_t n, const double* a, const double* b,
                           double* partial, int partial_blocks, double* out, hipStream_t s);
 
+// ---- learned Newton guess (dense network on the matrix cores) ----------------
+struct MlpImpl;
+int mlp_create(int n_in, int n_hidden, int n_out, int prec, MlpImpl** out);
+void mlp_destroy(MlpImpl* p);
+int64_t mlp_param_count(const MlpImpl* p);
+int mlp_dims(const MlpImpl* p, int l);
+int mlp_set_params(MlpImpl* p, const float* host);
+int mlp_get_params(MlpImpl* p, float* host);
+int mlp_set_norm(MlpImpl* p, const float* in_mu, const float* in_sd, const float* out_sd);
+int mlp_reserve(MlpImpl* p, int64_t cells);
+int mlp_forward(MlpImpl* p, int64_t B, const float* x, float* y, hipStream_t s);
+int mlp_gradients(MlpImpl* p, int64_t B, const float* x, const float* t, float* grad, float* loss,
+                  hipStream_t s);
+int mlp_adam(MlpImpl* p, const float* grad, float lr, float b1, float b2, float eps, hipStream_t s);
+int mlp_train(MlpImpl* p, int64_t n, const float* x, const float* t, int64_t batch, int epochs,
+              float lr, float* loss_hist, hipStream_t s);
+int mlp_features(const Mech& m, MlpImpl* p, int64_t n, const double* bY, const double* h,
+                 const double* c, double c_scalar, float* x, hipStream_t s);
+int mlp_targets(const Mech& m, MlpImpl* p, int64_t n, const double* bY, const double* h,
+                const double* Ys, float* t, hipStream_t s);
+int mlp_guess(const Mech& m, MlpImpl* p, int64_t n, const double* bY, const double* h,
+              const double* c, double c_scalar, double* Y, int64_t ldy, int32_t* choice,
+              hipStream_t s);
+// sums int32 flags into *out (stream-ordered, one atomic per block)
+int launch_count_flags(const int32_t* flags, int64_t n, unsigned long long* out, hipStream_t s);
+// out[i] = c_scalar * (c ? c[i] : 1)
+int launch_fill_c(int64_t n, const double* c, double c_scalar, double* out, hipStream_t s);
+
 // ---- host SDC tables -------------------------------------------------------
 struct Tables {
     int M = 0;
@@ -188,3 +216,16 @@ struct Tables {
 int make_tables(int n_nodes, int qi_kind, int qe_mode, Tables& t);
 
 }  // namespace misdc
+
+// handles of the C ABI
+struct misdc_mech_s {
+    misdc::Mech m;
+};
+
+struct misdc_grid_s {
+    misdc::Grid g;
+};
+
+struct misdc_mlp_s {
+    misdc::MlpImpl* p = nullptr;
+};

@@ -84,6 +84,19 @@ class Integrator:
     def autotune(self, state, dt, dt_per_flame=None, reps=3, stream=None):
         return nat.misdc_autotune(self.handle, state, dt, dt_per_flame, reps, stream)
 
+    def set_guess(self, net):
+        """Start every reaction solve from the learned guess where it has the
+        smaller residual (``net``: a ``GuessNet``, or None)."""
+        nat.misdc_integ_set_guess(self.handle, net.handle if net is not None else None)
+
+    def record(self, buf, max_tasks):
+        """Record the reaction problems of later steps into ``buf`` (device,
+        float64, max_tasks * (2N + 2) * cells); max_tasks 0 stops."""
+        nat.misdc_integ_record(self.handle, buf, max_tasks)
+
+    def recorded(self):
+        return nat.misdc_integ_recorded(self.handle)
+
     def tune(self):
         return nat.misdc_get_tune(self.handle)
 
@@ -96,6 +109,40 @@ class Integrator:
     def close(self):
         if self.handle:
             nat.misdc_integ_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GuessNet:
+    """Dense network of the learned Newton guess, (N+2) -> H -> H -> (N+1),
+    held by the library (parameters, Adam state and work buffers on the
+    device)."""
+
+    def __init__(self, n_species, hidden=256, precision="bf16"):
+        self.N = int(n_species)
+        self.sizes = [self.N + 2, hidden, hidden, self.N + 1]
+        self.handle = nat.misdc_mlp_create(self.N + 2, hidden, self.N + 1, precision)
+
+    def param_count(self):
+        return nat.misdc_mlp_param_count(self.handle)
+
+    def set_params(self, flat):
+        nat.misdc_mlp_set_params(self.handle, flat)
+
+    def params(self):
+        return nat.misdc_mlp_get_params(self.handle)
+
+    def set_normalization(self, in_mu, in_sd, out_sd):
+        nat.misdc_mlp_set_normalization(self.handle, in_mu, in_sd, out_sd)
+
+    def close(self):
+        if self.handle:
+            nat.misdc_mlp_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

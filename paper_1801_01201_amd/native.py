@@ -32,7 +32,13 @@ EXPORTED = [
     "misdc_transport_operators", "misdc_diffusion_solve", "misdc_opts_default",
     "misdc_integ_create", "misdc_integ_destroy", "misdc_step", "misdc_get_stats",
     "misdc_reset_profile", "misdc_autotune", "misdc_get_tune", "misdc_set_tune",
+    "misdc_mlp_create", "misdc_mlp_destroy", "misdc_mlp_param_count", "misdc_mlp_set_params",
+    "misdc_mlp_get_params", "misdc_mlp_set_normalization", "misdc_mlp_forward",
+    "misdc_mlp_gradients", "misdc_mlp_adam_step", "misdc_mlp_train", "misdc_mlp_features",
+    "misdc_mlp_targets", "misdc_reaction_guess_mlp", "misdc_integ_set_guess",
+    "misdc_integ_record", "misdc_integ_recorded",
 ]
+MLP_PRECISION = {"bf16": 0, "fp32": 1}
 
 
 class MisdcError(RuntimeError):
@@ -79,7 +85,7 @@ class misdc_stats(C.Structure):
                 ("sweep_increment", C.c_double * 64), ("diffusion_kernel_ms", C.c_double),
                 ("diffusion_kernel_launches", C.c_int64), ("newton_kernel_ms", C.c_double),
                 ("newton_kernel_launches", C.c_int64), ("newton_lu_solves", C.c_int64),
-                ("newton_lu_fallbacks", C.c_int64)]
+                ("newton_lu_fallbacks", C.c_int64), ("newton_guess_learned", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "sweep_increment"}
@@ -120,6 +126,22 @@ def load(path=LIB_PATH):
         "misdc_autotune": (C.c_int, [vp, vp, dbl, vp, C.c_int, C.POINTER(misdc_tune), vp]),
         "misdc_get_tune": (C.c_int, [vp, C.POINTER(misdc_tune)]),
         "misdc_set_tune": (C.c_int, [vp, C.POINTER(misdc_tune)]),
+        "misdc_mlp_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp)]),
+        "misdc_mlp_destroy": (C.c_int, [vp]),
+        "misdc_mlp_param_count": (C.c_int, [vp, C.POINTER(i64)]),
+        "misdc_mlp_set_params": (C.c_int, [vp, vp]),
+        "misdc_mlp_get_params": (C.c_int, [vp, vp]),
+        "misdc_mlp_set_normalization": (C.c_int, [vp, vp, vp, vp]),
+        "misdc_mlp_forward": (C.c_int, [vp, i64, vp, vp, vp]),
+        "misdc_mlp_gradients": (C.c_int, [vp, i64, vp, vp, vp, vp, vp]),
+        "misdc_mlp_adam_step": (C.c_int, [vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
+        "misdc_mlp_train": (C.c_int, [vp, i64, vp, vp, i64, C.c_int, C.c_float, vp, vp]),
+        "misdc_mlp_features": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, vp]),
+        "misdc_mlp_targets": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, vp]),
+        "misdc_reaction_guess_mlp": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, vp, vp]),
+        "misdc_integ_set_guess": (C.c_int, [vp, vp]),
+        "misdc_integ_record": (C.c_int, [vp, vp, i64]),
+        "misdc_integ_recorded": (C.c_int, [vp, C.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -320,6 +342,86 @@ def misdc_get_tune(integ):
 def misdc_set_tune(integ, cg_variant, cg_blocks, cyclic, serialize):
     t = misdc_tune(int(cg_variant), int(cg_blocks), int(cyclic), int(serialize), 0.0)
     check(lib().misdc_set_tune(integ, C.byref(t)))
+
+
+def misdc_mlp_create(n_in, n_hidden, n_out, precision="bf16"):
+    h = C.c_void_p()
+    check(lib().misdc_mlp_create(int(n_in), int(n_hidden), int(n_out),
+                                 MLP_PRECISION[precision], C.byref(h)))
+    return h.value
+
+
+def misdc_mlp_destroy(h):
+    check(lib().misdc_mlp_destroy(h))
+
+
+def misdc_mlp_param_count(h):
+    n = C.c_int64()
+    check(lib().misdc_mlp_param_count(h, C.byref(n)))
+    return n.value
+
+
+def misdc_mlp_set_params(h, flat):
+    a = np.ascontiguousarray(flat, dtype=np.float32)
+    check(lib().misdc_mlp_set_params(h, _ptr(a)))
+
+
+def misdc_mlp_get_params(h):
+    a = np.empty(misdc_mlp_param_count(h), dtype=np.float32)
+    check(lib().misdc_mlp_get_params(h, _ptr(a)))
+    return a
+
+
+def misdc_mlp_set_normalization(h, in_mu, in_sd, out_sd):
+    a, b, c = (np.ascontiguousarray(v, dtype=np.float32) for v in (in_mu, in_sd, out_sd))
+    check(lib().misdc_mlp_set_normalization(h, _ptr(a), _ptr(b), _ptr(c)))
+
+
+def misdc_mlp_forward(h, batch, x, y, stream=None):
+    check(lib().misdc_mlp_forward(h, int(batch), _ptr(x), _ptr(y), _stream(stream)))
+
+
+def misdc_mlp_gradients(h, batch, x, t, grad, loss=None, stream=None):
+    check(lib().misdc_mlp_gradients(h, int(batch), _ptr(x), _ptr(t), _ptr(grad), _ptr(loss),
+                                    _stream(stream)))
+
+
+def misdc_mlp_adam_step(h, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    check(lib().misdc_mlp_adam_step(h, _ptr(grad), lr, beta1, beta2, eps, _stream(stream)))
+
+
+def misdc_mlp_train(h, n, x, t, batch, epochs, lr, loss=None, stream=None):
+    check(lib().misdc_mlp_train(h, int(n), _ptr(x), _ptr(t), int(batch), int(epochs), float(lr),
+                                _ptr(loss), _stream(stream)))
+
+
+def misdc_mlp_features(mech, h, n, bY, hh, c, x, stream=None):
+    check(lib().misdc_mlp_features(mech, h, int(n), _ptr(bY), _ptr(hh), _ptr(c), _ptr(x),
+                                   _stream(stream)))
+
+
+def misdc_mlp_targets(mech, h, n, bY, hh, Y, t, stream=None):
+    check(lib().misdc_mlp_targets(mech, h, int(n), _ptr(bY), _ptr(hh), _ptr(Y), _ptr(t),
+                                  _stream(stream)))
+
+
+def misdc_reaction_guess_mlp(mech, h, n, bY, hh, c, Y, choice=None, stream=None):
+    check(lib().misdc_reaction_guess_mlp(mech, h, int(n), _ptr(bY), _ptr(hh), _ptr(c), _ptr(Y),
+                                         _ptr(choice), _stream(stream)))
+
+
+def misdc_integ_set_guess(integ, mlp):
+    check(lib().misdc_integ_set_guess(integ, mlp))
+
+
+def misdc_integ_record(integ, buf, max_tasks):
+    check(lib().misdc_integ_record(integ, _ptr(buf), int(max_tasks)))
+
+
+def misdc_integ_recorded(integ):
+    n = C.c_int64()
+    check(lib().misdc_integ_recorded(integ, C.byref(n)))
+    return n.value
 
 
 def make_opts(n_nodes=5, sweeps=6, nu=1, scheme="cisdcq", qe="cumulative", serialize=False,

@@ -35,16 +35,29 @@ def flame_1d(mech, n=64, dx=0.01):
     return _compose(mech, T), T
 
 
-def flame_2d(mech, nx=256, ny=256, dx=0.01, dy=0.01):
+def flame_2d(mech, nx=256, ny=256, dx=0.01, dy=0.01, seed=None):
     """Periodic 2-D flame: the 1-D slab along x with fronts displaced by
-    0.05 L sin(2 pi y / L_y), so the problem is genuinely two-dimensional."""
+    0.05 L sin(2 pi y / L_y), so the problem is genuinely two-dimensional.
+    With a seed, each front gets its own displacement: amplitudes in
+    [0.02, 0.08] L of the first two modes with random phases."""
     Lx = nx * dx
     Ly = ny * dy
     x = (np.arange(nx) + 0.5) * dx
     y = (np.arange(ny) + 0.5) * dy
     X, Yg = np.meshgrid(x, y)            # (ny, nx), x fastest
-    s = 0.05 * Lx * np.sin(2.0 * np.pi * Yg / Ly)
-    T = _tanh_profile(X, Lx, max(Lx / 32.0, 4.0 * dx), s, -s)
+    if seed is None:
+        s_lo = 0.05 * Lx * np.sin(2.0 * np.pi * Yg / Ly)
+        s_hi = -s_lo
+    else:
+        rng = _rng(seed)
+        shifts = []
+        for _ in range(2):
+            a = rng.uniform(0.02, 0.08, 2) * Lx
+            ph = rng.uniform(0.0, 2.0 * np.pi, 2)
+            shifts.append(a[0] * np.sin(2.0 * np.pi * Yg / Ly + ph[0])
+                          + a[1] * np.sin(4.0 * np.pi * Yg / Ly + ph[1]))
+        s_lo, s_hi = shifts
+    T = _tanh_profile(X, Lx, max(Lx / 32.0, 4.0 * dx), s_lo, s_hi)
     return _compose(mech, T), T
 
 
