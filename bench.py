@@ -336,6 +336,134 @@ def n53_main(args):
     print(json.dumps(line), flush=True)
 
 
+def mlp_main(args):
+    """The 256 x 256 flame with the learned Newton guess: the network
+    (11 -> 256 -> 256 -> 10, BF16 operands, FP32 accumulation) is trained on
+    the GPU on the reaction problems recorded from one step of each of four
+    independent flames (initial-condition seeds 200..203) plus their
+    cold-start relaxation problems, then the benchmark's flame (held out) is
+    stepped with and without it.  Reported: step throughput with the guess,
+    Newton iterations per cell both ways, the cold-start relaxation with
+    and without the guess, and the training throughput."""
+    import numpy as np
+    import torch
+    import synth
+    from oracle import mlp as om
+    from paper_1801_01201_amd import native
+    from paper_1801_01201_amd.flame import (Mechanism, Grid, Integrator, initial_state, GuessNet,
+                                            RELAX_TIME)
+    from paper_1801_01201_amd.guess import record_problems, train
+    native.lib()
+    cfg = synth.config("flame2d_256")
+    mech = synth.make_mechanism(**cfg["mech"])
+    nx, ny = cfg["n"]
+    n = nx * ny
+    M = cfg["n_nodes"] - 1
+    mh = Mechanism(mech)
+    g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
+    kw = dict(n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"], scheme=cfg["scheme"])
+
+    def relax_problem(Y, T):
+        b = torch.tensor(Y.reshape(9, -1), device="cuda")
+        h = torch.empty(n, dtype=torch.float64, device="cuda")
+        native.misdc_enthalpy(mh.handle, n, b, torch.tensor(T.ravel(), device="cuda"), h)
+        return b, h, torch.full((n,), RELAX_TIME, dtype=torch.float64, device="cuda")
+
+    # training data: sweep problems + relaxation problems of four flames
+    t0 = time.perf_counter()
+    states, rb, rh, rc, rY = [], [], [], [], []
+    for seed in (200, 201, 202, 203):
+        Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"], seed=seed)
+        b, h, c = relax_problem(Y, T)
+        Yo = b.clone()
+        it = torch.empty(n, dtype=torch.int32, device="cuda")
+        native.misdc_reaction_solve_batch(mh.handle, n, b, h, c, Yo, None, None, it)
+        rb.append(b), rh.append(h), rc.append(c), rY.append(Yo)
+        st, _ = initial_state(mh, b, torch.tensor(T.ravel(), device="cuda"))
+        states.append(st)
+    bY, hh, cc, Ys = record_problems(mh, g, states, cfg["dt"], **kw)
+    bY = torch.cat([bY] + rb, dim=1).contiguous()
+    hh = torch.cat([hh] + rh).contiguous()
+    cc = torch.cat([cc] + rc).contiguous()
+    Ys = torch.cat([Ys] + rY, dim=1).contiguous()
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    n_train = hh.numel()
+    print(f"[bench] mlp: {n_train} training problems in {t_data:.1f} s", file=sys.stderr, flush=True)
+    net = GuessNet(9, 256, "bf16")
+    net.set_params(om.pack(synth.mlp_init(net.sizes, 7)).astype(np.float32))
+    epochs, batch = 4, 65536
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = train(mh, net, bY, hh, cc, Ys, epochs=epochs, batch=batch, lr=2e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    samples = (n_train // batch) * batch * epochs
+    flop_per_sample = 3 * 2 * sum(a * b for a, b in zip(net.sizes[:-1], net.sizes[1:]))
+    print(f"[bench] mlp: trained {epochs} epochs in {t_train:.2f} s, loss {hist}",
+          file=sys.stderr, flush=True)
+    del bY, hh, cc, Ys, states
+    # held-out benchmark flame: cold-start relaxation and steps, both guesses
+    Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
+    b, h, c = relax_problem(Y, T)
+    relax = {}
+    for name in ("plain", "learned"):
+        Yo = b.clone()
+        if name == "learned":
+            native.misdc_reaction_guess_mlp(mh.handle, net.handle, n, b, h, c, Yo)
+        it = torch.empty(n, dtype=torch.int32, device="cuda")
+        native.misdc_reaction_solve_batch(mh.handle, n, b, h, c, Yo, None, None, it)
+        relax[name] = float(it.double().mean())
+    state, _ = initial_state(mh, b, torch.tensor(T.ravel(), device="cuda"))
+    res = {}
+    for name in ("plain", "learned"):
+        integ = Integrator(mh, g, **kw)
+        if name == "learned":
+            integ.set_guess(net, sweeps=args.guess_sweeps)
+        st = state.clone()
+        for _ in range(args.warmup):
+            integ.step(st, cfg["dt"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            integ.step(st, cfg["dt"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s = integ.stats()
+        integ.close()
+        res[name] = (el, s, st)
+    el, s, st = res["learned"]
+    diff = float(((res["plain"][2] - st).abs().amax(dim=1) /
+                  res["plain"][2].abs().amax(dim=1)).max())
+    updates = n * M * cfg["nu"] * cfg["sweeps"] * args.steps
+    line = {
+        "metric": METRIC, "value": updates / el, "unit": "cell-node updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "flame2d_256_mlp: the 256x256 flame (CISDCQ-1, 5 nodes, 6 sweeps) "
+                               "with the learned Newton guess (11->256->256->10, bf16 MFMA, "
+                               "trained on the GPU on four independent flames)", "cells": n},
+        "newton_iters_per_cell": {k: v[1]["newton_iters"] / max(1, v[1]["newton_solves"])
+                                  for k, v in res.items()},
+        "ms_per_step_plain_guess": res["plain"][0] / args.steps * 1e3,
+        "guess_sweeps": args.guess_sweeps,
+        "learned_guess_taken": s["newton_guess_learned"],
+        "newton_solves": s["newton_solves"],
+        "state_difference_vs_plain_guess": diff,
+        "cold_start_relaxation_newton_iters_per_cell": relax,
+        "training": {"problems": n_train, "epochs": epochs, "batch": batch,
+                     "seconds": t_train, "samples_per_s": samples / t_train,
+                     "gemm_tflops": samples * flop_per_sample / t_train / 1e12,
+                     "bf16_mfma_peak_tflops": 2500.0, "loss_per_epoch": [float(v) for v in hist],
+                     "data_seconds": t_data},
+        "newton_failed": s["newton_failed"], "cg_failed": s["cg_failed"],
+    }
+    net.close()
+    mh.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,7 +477,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the extra timing of the same steps replayed as one HIP graph")
     ap.add_argument("--workload", default="flame2d_256",
-                    choices=["flame2d_256", "ensemble64", "flame2d_512_n53"])
+                    choices=["flame2d_256", "ensemble64", "flame2d_512_n53", "flame2d_256_mlp"])
+    ap.add_argument("--guess-sweeps", type=int, default=1,
+                    help="flame2d_256_mlp: leading sweeps that use the learned guess (0: all)")
     ap.add_argument("--lu", default="fp64", choices=["fp64", "fp32_mfma"],
                     help="flame2d_512_n53: precision of the Newton LU of the timed run")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -373,6 +503,8 @@ def main():
         return ensemble_main(args)
     if args.workload == "flame2d_512_n53":
         return n53_main(args)
+    if args.workload == "flame2d_256_mlp":
+        return mlp_main(args)
     cfg = workload()
     if args.nu:
         cfg["nu"] = args.nu

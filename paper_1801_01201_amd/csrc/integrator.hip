@@ -107,6 +107,7 @@ struct misdc_integ_s {
     double tuned_ms = 0.0;                        // step time measured by the autotuner
     // learned Newton guess (optional) and recording of reaction problems
     MlpImpl* mlp = nullptr;
+    int guess_sweeps = 0;                         // leading sweeps that use it (0: all)
     int32_t* choice = nullptr;                    // cells: learned guess taken
     double* cbuf = nullptr;                       // cells: implicit factor c of the task
     double* rec_buf = nullptr;                    // caller's buffer of recorded problems
@@ -437,7 +438,7 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     if (rc) return rc;
     const double c_scalar = I->dtc ? cf : dt * cf;
     const double* guess = Lp[p].phi;
-    if (I->mlp) {
+    if (I->mlp && (I->guess_sweeps <= 0 || I->sweep_index < I->guess_sweeps)) {
         // the plain guess, replaced cell by cell by the learned one where
         // that has the smaller residual
         if ((rc = launch_copy(out.phi, Lp[p].phi, (int64_t)N * n, I->sR))) return rc;
@@ -1177,8 +1178,9 @@ int misdc_step(misdc_integ_t I, double* state, double dt, const double* dev_dt, 
     return MISDC_OK;
 }
 
-int misdc_integ_set_guess(misdc_integ_t I, misdc_mlp_t mlp) {
+int misdc_integ_set_guess(misdc_integ_t I, misdc_mlp_t mlp, int sweeps) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
+    if (sweeps < 0) return fail(MISDC_EINVAL, "sweeps must be >= 0");
     MISDC_HIP(hipStreamSynchronize(I->sD));
     MISDC_HIP(hipStreamSynchronize(I->sR2));
     if (mlp) {
@@ -1189,6 +1191,7 @@ int misdc_integ_set_guess(misdc_integ_t I, misdc_mlp_t mlp) {
         if (rc) return rc;
     }
     I->mlp = mlp ? mlp->p : nullptr;
+    I->guess_sweeps = sweeps;
     drop_graph(I);
     return MISDC_OK;
 }

@@ -10,9 +10,10 @@
 // Every product runs on the matrix cores: BF16 operands with FP32
 // accumulation (16x16x16 MFMA), or FP32 operands (16x16x4 MFMA) in the FP32
 // mode.  One tiled GEMM kernel serves all of them: C = A B with arbitrary
-// strides (transposed operands for the back-propagation), 64 x 64 output
-// tiles per 256-thread workgroup (each wavefront 2 x 2 MFMA tiles), K staged
-// through LDS in chunks of 16, an epilogue for bias, ReLU and the ReLU mask
+// strides (transposed operands for the back-propagation), 128 x 128 output
+// tiles per 256-thread workgroup (each wavefront 4 x 4 MFMA tiles), K staged
+// through LDS in chunks of 32 with 16-byte loads along each operand's
+// contiguous axis, an epilogue for bias, ReLU and the ReLU mask
 // of the back-propagation, and a split-K mode whose partial sums are reduced
 // in a fixed order (weight gradients over large batches).  Reductions never
 // use atomics, so training is bitwise reproducible.
@@ -57,74 +58,118 @@ struct GemmArgs {
     int kchunk;                            // K range of one split
 };
 
+// Tile loads: 16-byte vectors along the operand's contiguous axis when the
+// tile lies inside the matrix and the rows are 16-byte aligned, else one
+// element at a time with zero padding.
+constexpr int BM = 128, BN = 128, BK = 32, KP = BK + 8;    // LDS rows padded by 8 elements
+
+template <typename T>
+__device__ __forceinline__ void load_tile(T (*S)[KP], const T* X, int64_t s_row, int64_t s_k,
+                                          int r0, int rows, int k0, int k1, bool vec_ok) {
+    constexpr int VE = 16 / sizeof(T);                     // elements per 16-byte vector
+    const int tid = threadIdx.x;
+    const bool kcont = (s_k == 1);
+    const bool inside = (r0 + 128 <= rows) && (k0 + BK <= k1);
+    if (vec_ok && inside) {
+        if (kcont) {
+            // 128 rows x BK: each vector covers VE consecutive k of one row
+            constexpr int PER_ROW = BK / VE;
+            for (int v = tid; v < 128 * PER_ROW; v += 256) {
+                const int r = v / PER_ROW, kk = (v % PER_ROW) * VE;
+                const uint4 q = *(const uint4*)(X + (int64_t)(r0 + r) * s_row + k0 + kk);
+                *(uint4*)&S[r][kk] = q;
+            }
+        } else {
+            // the row index is contiguous: each vector covers VE rows of one k
+            constexpr int PER_K = 128 / VE;
+            for (int v = tid; v < BK * PER_K; v += 256) {
+                const int kk = v / PER_K, r = (v % PER_K) * VE;
+                const uint4 q = *(const uint4*)(X + (int64_t)(k0 + kk) * s_k + r0 + r);
+                const T* e = (const T*)&q;
+#pragma unroll
+                for (int u = 0; u < VE; ++u) S[r + u][kk] = e[u];
+            }
+        }
+    } else {
+        for (int v = tid; v < 128 * BK; v += 256) {
+            const int r = kcont ? v / BK : v % 128;
+            const int kk = kcont ? v % BK : v / 128;
+            const int gr = r0 + r, gk = k0 + kk;
+            S[r][kk] = (gr < rows && gk < k1) ? X[(int64_t)gr * s_row + (int64_t)gk * s_k]
+                                              : from_float<T>(0.f);
+        }
+    }
+}
+
+// C = A B (+ epilogue): A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn];
+// 128 x 128 tiles, four wavefronts of 64 x 64 (4 x 4 MFMA tiles of 16 x 16).
 template <typename T>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
-    __shared__ T As[64][17];
-    __shared__ T Bs[16][65];
+    __shared__ __attribute__((aligned(16))) T As[BM][KP];     // [m][k]
+    __shared__ __attribute__((aligned(16))) T Bt[BN][KP];     // [n][k]
     const T* A = (const T*)g.A;
     const T* B = (const T*)g.B;
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int kz0 = blockIdx.z * g.kchunk;
     const int kz1 = min(g.K, kz0 + g.kchunk);
-    const bool a_mfast = (g.sam == 1);
-    const bool b_kfast = (g.sbk == 1 && g.sbn != 1);
-    const int wr = (wave / 2) * 32, wc = (wave % 2) * 32;
-    v4f acc[2][2];
+    constexpr int VE = 16 / sizeof(T);
+    // vector loads need 16-byte aligned rows along the contiguous axis
+    const bool a_vec = (g.sak == 1 ? (g.sam % VE == 0) : (g.sam == 1 && g.sak % VE == 0)) &&
+                       (((uintptr_t)A & 15) == 0);
+    const bool b_vec = (g.sbk == 1 ? (g.sbn % VE == 0) : (g.sbn == 1 && g.sbk % VE == 0)) &&
+                       (((uintptr_t)B & 15) == 0);
+    const int wr = (wave / 2) * 64, wc = (wave % 2) * 64;
+    const int li = lane % 16, lk = lane / 16;
+    v4f acc[4][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
-    for (int k0 = kz0; k0 < kz1; k0 += 16) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = tid + 256 * e;
-            const int r = a_mfast ? idx % 64 : idx / 16;
-            const int c = a_mfast ? idx / 64 : idx % 16;
-            const int m = m0 + r, k = k0 + c;
-            As[r][c] = (m < g.M && k < kz1) ? A[(int64_t)m * g.sam + (int64_t)k * g.sak] : from_float<T>(0.f);
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = tid + 256 * e;
-            const int r = b_kfast ? idx % 16 : idx / 64;
-            const int c = b_kfast ? idx / 16 : idx % 64;
-            const int k = k0 + r, n = n0 + c;
-            Bs[r][c] = (k < kz1 && n < g.N) ? B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : from_float<T>(0.f);
-        }
+        for (int j = 0; j < 4; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kz0; k0 < kz1; k0 += BK) {
+        load_tile<T>(As, A, g.sam, g.sak, m0, g.M, k0, kz1, a_vec);
+        load_tile<T>(Bt, B, g.sbn, g.sbk, n0, g.N, k0, kz1, b_vec);
         __syncthreads();
-        const int li = lane % 16, lk = lane / 16;
+        if constexpr (sizeof(T) == 2) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int ks = 0; ks < BK; ks += 16) {
+                v4s a[4], b[4];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                if constexpr (sizeof(T) == 2) {
-                    v4s a, b;
+                for (int i = 0; i < 4; ++i) a[i] = *(const v4s*)&As[wr + 16 * i + li][ks + 4 * lk];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        a[v] = (short)As[wr + 16 * i + li][4 * lk + v];
-                        b[v] = (short)Bs[4 * lk + v][wc + 16 * j + li];
-                    }
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i][j], 0, 0, 0);
-                } else {
+                for (int j = 0; j < 4; ++j) b[j] = *(const v4s*)&Bt[wc + 16 * j + li][ks + 4 * lk];
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            (float)As[wr + 16 * i + li][4 * kk + lk],
-                            (float)Bs[4 * kk + lk][wc + 16 * j + li], acc[i][j], 0, 0, 0);
-                }
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
             }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 4) {
+                float a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = (float)As[wr + 16 * i + li][ks + lk];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = (float)Bt[wc + 16 * j + li][ks + lk];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+        }
         __syncthreads();
     }
     const T* mask = (const T*)g.mask;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wr + 16 * i + 4 * (lane / 16) + r;
-                const int n = n0 + wc + 16 * j + lane % 16;
+                const int m = m0 + wr + 16 * i + 4 * lk + r;
+                const int n = n0 + wc + 16 * j + li;
                 if (m >= g.M || n >= g.N) continue;
                 float v = acc[i][j][r];
                 if (g.part) {
@@ -149,16 +194,23 @@ __global__ void __launch_bounds__(256) reduce_parts_kernel(const float* part, in
     out[i] = s;
 }
 
-// column sums of dz (rows [z rows_per, ...)) into part[z][n]
+// column sums of dz over the rows [z rows_per, (z+1) rows_per) into
+// part[z][n]: 64 columns x 4 row groups per workgroup, the groups summed in
+// a fixed order
 __global__ void __launch_bounds__(256) colsum_kernel(const float* dz, int64_t rows, int N,
                                                      int64_t rows_per, float* part) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+    __shared__ float red[4][64];
+    const int c = threadIdx.x % 64, rg = threadIdx.x / 64;
+    const int n = blockIdx.x * 64 + c;
     const int64_t r0 = (int64_t)blockIdx.y * rows_per;
     const int64_t r1 = min(rows, r0 + rows_per);
     float s = 0.f;
-    for (int64_t r = r0; r < r1; ++r) s += dz[r * N + n];
-    part[(int64_t)blockIdx.y * N + n] = s;
+    if (n < N)
+        for (int64_t r = r0 + rg; r < r1; r += 4) s += dz[r * N + n];
+    red[rg][c] = s;
+    __syncthreads();
+    if (rg == 0 && n < N)
+        part[(int64_t)blockIdx.y * N + n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
 // dz = scale (y - t); per-block sums of (y - t)^2 for the loss
@@ -185,13 +237,20 @@ __global__ void __launch_bounds__(256) loss_grad_kernel(const float* y, const fl
     if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
 }
 
+// out = scale * sum of part[0 .. count): strided partial sums per thread,
+// then a fixed tree over the workgroup
 __global__ void __launch_bounds__(256) sum_kernel(const float* part, int count, float scale,
                                                   float* out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        float s = 0.f;
-        for (int i = 0; i < count; ++i) s += part[i];
-        *out = s * scale;
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < count; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
 template <typename T>
@@ -263,8 +322,9 @@ __global__ void __launch_bounds__(256) targets_kernel(MechDev m, NormDev nd, int
     ti[N] = (float)((Ts - Tb) / nd.out_sd[N]);
 }
 
-// learned candidate Y = b_Y + y sd (negative entries of non-negative b_Y
-// are clipped to zero)
+// learned candidate Y = b_Y + y sd, raised to min(b_Y, 0) where it falls
+// below: the Newton iteration rejects every trial below that floor, so a
+// start beneath it could never be left
 __global__ void __launch_bounds__(256) candidate_kernel(int N, NormDev nd, int64_t n,
                                                         const double* bY, const float* y,
                                                         double* Yc) {
@@ -273,9 +333,8 @@ __global__ void __launch_bounds__(256) candidate_kernel(int N, NormDev nd, int64
     const int nout = N + 1;
     for (int k = 0; k < N; ++k) {
         const double b = bY[(int64_t)k * n + i];
-        double v = b + (double)y[i * nout + k] * nd.out_sd[k];
-        if (b >= 0.0 && v < 0.0) v = 0.0;
-        Yc[(int64_t)k * n + i] = v;
+        const double v = b + (double)y[i * nout + k] * nd.out_sd[k];
+        Yc[(int64_t)k * n + i] = fmax(v, fmin(b, 0.0));
     }
 }
 
@@ -436,7 +495,7 @@ int gemm(const MlpImpl& p, GemmArgs g, int splits, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0) return MISDC_OK;
     if (splits > 1) {
         int64_t kc = (g.K + splits - 1) / splits;
-        kc = (kc + 15) / 16 * 16;
+        kc = (kc + BK - 1) / BK * BK;
         g.kchunk = (int)kc;
         splits = (int)((g.K + kc - 1) / kc);
         if ((int64_t)splits * g.M * g.N > PART_FLOATS) return fail(MISDC_EINVAL, "split-K partials too large");
@@ -444,7 +503,7 @@ int gemm(const MlpImpl& p, GemmArgs g, int splits, hipStream_t s) {
         g.kchunk = g.K;
         splits = 1;
     }
-    const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
+    const dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, splits);
     if (p.prec == 0)
         hipLaunchKernelGGL(gemm_kernel<uint16_t>, grid, dim3(256), 0, s, g);
     else
@@ -516,7 +575,7 @@ int backward(MlpImpl& p, int64_t B, const float* t, float* grad, hipStream_t s) 
         hipLaunchKernelGGL(loss_grad_kernel<float>, dim3(nb), dim3(256), 0, s, p.y, t, cnt, scale,
                            p.dz3F, (float*)p.dz3T, p.loss_part);
     MISDC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, s, p.loss_part, (int)nb, 1.0f / (float)cnt,
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, p.loss_part, (int)nb, 1.0f / (float)cnt,
                        p.loss);
     MISDC_HIP(hipGetLastError());
     const void* actT[3] = {p.xT, p.h1T, p.h2T};
@@ -533,19 +592,21 @@ int backward(MlpImpl& p, int64_t B, const float* t, float* grad, hipStream_t s) 
         int rc = gemm(p, g, SPLITS, s);
         if (rc) return rc;
         int64_t kc = (B + SPLITS - 1) / SPLITS;
-        kc = (kc + 15) / 16 * 16;
+        kc = (kc + BK - 1) / BK * BK;
         const int splits = (int)((B + kc - 1) / kc);
         const int64_t wc = (int64_t)fin * fout;
         hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for(wc, 256)), dim3(256), 0, s, p.part,
                            splits, wc, grad + p.off[2 * l]);
         MISDC_HIP(hipGetLastError());
-        // db_l = column sums of dz_l
-        const int64_t rows_per = (B + SPLITS - 1) / SPLITS;
-        hipLaunchKernelGGL(colsum_kernel, dim3(grid_for(fout, 256), SPLITS), dim3(256), 0, s,
+        // db_l = column sums of dz_l (row splits of 256)
+        const int64_t rows_per = 256;
+        const int csplits = (int)((B + rows_per - 1) / rows_per);
+        if ((int64_t)csplits * fout > PART_FLOATS) return fail(MISDC_EINVAL, "batch too large");
+        hipLaunchKernelGGL(colsum_kernel, dim3((fout + 63) / 64, csplits), dim3(256), 0, s,
                            dzF[l], B, fout, rows_per, p.part);
         MISDC_HIP(hipGetLastError());
         hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for(fout, 256)), dim3(256), 0, s, p.part,
-                           SPLITS, (int64_t)fout, grad + p.off[2 * l + 1]);
+                           csplits, (int64_t)fout, grad + p.off[2 * l + 1]);
         MISDC_HIP(hipGetLastError());
         if (l == 0) break;
         // dz_{l-1} = (dz_l W_l^T) masked by act_l > 0

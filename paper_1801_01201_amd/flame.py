@@ -84,10 +84,11 @@ class Integrator:
     def autotune(self, state, dt, dt_per_flame=None, reps=3, stream=None):
         return nat.misdc_autotune(self.handle, state, dt, dt_per_flame, reps, stream)
 
-    def set_guess(self, net):
-        """Start every reaction solve from the learned guess where it has the
-        smaller residual (``net``: a ``GuessNet``, or None)."""
-        nat.misdc_integ_set_guess(self.handle, net.handle if net is not None else None)
+    def set_guess(self, net, sweeps=0):
+        """Start the reaction solves of the first ``sweeps`` sweeps (0: all)
+        from the learned guess where it has the smaller residual (``net``: a
+        ``GuessNet``, or None)."""
+        nat.misdc_integ_set_guess(self.handle, net.handle if net is not None else None, sweeps)
 
     def record(self, buf, max_tasks):
         """Record the reaction problems of later steps into ``buf`` (device,

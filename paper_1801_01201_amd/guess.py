@@ -1,0 +1,70 @@
+"""Training data and training of the learned Newton guess (the network runs
+in the library; this module only moves device arrays between its calls).
+
+Typical use::
+
+    net = GuessNet(N)                              # (N+2) -> 256 -> 256 -> (N+1)
+    net.set_params(initial_params)
+    data = record_problems(mech, grid, states, dt, integ_opts)   # from real steps
+    train(mech, net, *data, epochs=5)
+    integ.set_guess(net)
+"""
+import numpy as np
+
+from . import native as nat
+from .flame import Integrator
+
+
+def record_problems(mech, grid, states, dt, **integ_opts):
+    """Reaction problems (b_Y, h, c, Y*) of one step from each device state
+    in ``states`` (each N+1 x cells, advanced in place), recorded by the
+    integrator.  Returns device tensors b_Y (N, P), h (P), c (P), Y* (N, P)."""
+    import torch
+    N = mech.N
+    n = grid.cells
+    tasks = None
+    parts = []
+    for st in states:
+        integ = Integrator(mech, grid, **integ_opts)
+        nu = integ.opts.nu if integ.opts.scheme == nat.SCHEME["cisdcq"] else 1
+        tasks = integ.opts.n_sweeps * nu * (integ.opts.n_nodes - 1)
+        buf = torch.empty(tasks * (2 * N + 2) * n, dtype=torch.float64, device=st.device)
+        integ.record(buf, tasks)
+        integ.step(st, dt)
+        got = integ.recorded()
+        integ.close()
+        parts.append(buf.view(tasks, 2 * N + 2, n)[:got])
+    rec = torch.cat(parts)
+    bY = rec[:, :N].permute(1, 0, 2).reshape(N, -1).contiguous()
+    h = rec[:, N].reshape(-1).contiguous()
+    c = rec[:, N + 1].reshape(-1).contiguous()
+    Ys = rec[:, N + 2:].permute(1, 0, 2).reshape(N, -1).contiguous()
+    return bY, h, c, Ys
+
+
+def train(mech, net, bY, h, c, Ys, epochs=5, batch=4096, lr=2e-3, seed=0):
+    """Sets the network's normalisation from the data (means and standard
+    deviations of the features and targets; each input scale floored at
+    1e-3 of its mean's magnitude so that constant inputs stay O(1)), then
+    trains on the shuffled pairs.  Returns the per-epoch loss (host)."""
+    import torch
+    n = h.numel()
+    N = net.N
+    net.set_normalization(np.zeros(N + 2, np.float32), np.ones(N + 2, np.float32),
+                          np.ones(N + 1, np.float32))
+    x = torch.empty((n, N + 2), dtype=torch.float32, device=h.device)
+    t = torch.empty((n, N + 1), dtype=torch.float32, device=h.device)
+    nat.misdc_mlp_features(mech.handle, net.handle, n, bY, h, c, x)
+    nat.misdc_mlp_targets(mech.handle, net.handle, n, bY, h, Ys, t)
+    mu = x.double().mean(0).cpu().numpy()
+    sd = np.maximum(x.double().std(0).cpu().numpy(), np.maximum(1e-3 * np.abs(mu), 1e-6))
+    osd = np.maximum(t.double().std(0).cpu().numpy(), 1e-30)
+    net.set_normalization(mu.astype(np.float32), sd.astype(np.float32), osd.astype(np.float32))
+    nat.misdc_mlp_features(mech.handle, net.handle, n, bY, h, c, x)
+    nat.misdc_mlp_targets(mech.handle, net.handle, n, bY, h, Ys, t)
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    perm = torch.randperm(n, generator=gen).to(h.device)
+    x, t = x[perm].contiguous(), t[perm].contiguous()
+    hist = torch.empty(epochs, dtype=torch.float32, device=h.device)
+    nat.misdc_mlp_train(net.handle, n, x, t, batch, epochs, lr, hist)
+    return hist.cpu().numpy()

@@ -139,7 +139,7 @@ def load(path=LIB_PATH):
         "misdc_mlp_features": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, vp]),
         "misdc_mlp_targets": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, vp]),
         "misdc_reaction_guess_mlp": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, vp, vp]),
-        "misdc_integ_set_guess": (C.c_int, [vp, vp]),
+        "misdc_integ_set_guess": (C.c_int, [vp, vp, C.c_int]),
         "misdc_integ_record": (C.c_int, [vp, vp, i64]),
         "misdc_integ_recorded": (C.c_int, [vp, C.POINTER(i64)]),
     }
@@ -410,8 +410,8 @@ def misdc_reaction_guess_mlp(mech, h, n, bY, hh, c, Y, choice=None, stream=None)
                                          _ptr(choice), _stream(stream)))
 
 
-def misdc_integ_set_guess(integ, mlp):
-    check(lib().misdc_integ_set_guess(integ, mlp))
+def misdc_integ_set_guess(integ, mlp, sweeps=0):
+    check(lib().misdc_integ_set_guess(integ, mlp, int(sweeps)))
 
 
 def misdc_integ_record(integ, buf, max_tasks):
