@@ -565,8 +565,15 @@ def main():
         unknowns = 8 * n + n            # 8 diffused species + enthalpy
         traffic = CG_BYTES_PER_UNKNOWN_ITER * unknowns * cg_per_solve
         achieved = traffic / avg_s / 1e9
-        roof = {"kernel": "cg_regs_kernel<9,1,512> (batched pipelined Jacobi-PCG, implicit "
-                          "diffusion of 9 fields)",
+        cg_names = {0: "cg_kernel (vectors in global memory)",
+                    1: "cg_regs_kernel<9,1,512> (register-resident, diagonal preconditioner)",
+                    2: "cg_regs_kernel<9,2,256>", 4: "cg_regs_kernel<9,4,256>",
+                    101: "cg_tile_kernel<9,1> (32x16 tiles, 1 local preconditioner sweep)",
+                    102: "cg_tile_kernel<9,2> (32x16 tiles, 2 local preconditioner sweeps)",
+                    103: "cg_tile_kernel<9,3> (32x16 tiles, 3 local preconditioner sweeps)"}
+        variant = integ.tune()["cg_variant"]
+        roof = {"kernel": cg_names.get(variant, str(variant)) + ": batched pipelined PCG, "
+                          "implicit diffusion of 9 fields",
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic("pmc_cg_kernel_flame2d_256.md",

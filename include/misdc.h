@@ -242,7 +242,7 @@ typedef struct {
     int32_t qe_mode;     /* MISDC_QE_* */
     int32_t serialize;   /* 1: run the two tasks on one stream (same DAG) */
     misdc_newton_opts newton;
-    double cg_rtol;      /* 2-D diffusion CG tolerance (<= 0: 1e-13) */
+    double cg_rtol;      /* 2-D diffusion CG tolerance |r| <= cg_rtol |b| (<= 0: 1e-13) */
     int32_t cg_maxit;    /* (<= 0: 500) */
     int32_t profile;     /* 1: time every diffusion-solve and Newton kernel with
                             HIP events on the stream it runs on (see stats);
@@ -282,7 +282,10 @@ int misdc_step(misdc_integ_t integ, double* dev_state, double dt,
  * the choice only changes speed. */
 typedef struct {
     int32_t cg_variant;   /* 2-D diffusion: 0 vectors in global memory, 1/2/4
-                             cells per thread held in registers */
+                             cells per thread held in registers, 101..103 one
+                             32x16 tile per workgroup with a block-local
+                             preconditioner of 1..3 Jacobi sweeps (needs
+                             cg_blocks = the number of tiles) */
     int32_t cg_blocks;    /* workgroups of the 2-D diffusion solve (<= CUs) */
     int32_t cyclic;       /* 1-D diffusion: 0 one thread per periodic system,
                              1 one wavefront per system (partition method) */
@@ -294,7 +297,8 @@ typedef struct {
  * each, after one warm-up step, on a private copy of dev_state, which is not
  * modified), keeps the fastest one in the integrator and returns it in
  * *best.  Candidates: for 2-D grids every register-resident CG variant that
- * fits with 1/4, 1/2 and all of the CUs, and the global-memory variant; for
+ * fits, the tiled variants when the grid has at most 128 tiles, and the
+ * global-memory variant with 1/4, 1/2 and all of the CUs; for
  * 1-D grids and ensembles both cyclic solvers; each with one and two
  * streams.  Synchronises; allocates a state copy.  Errors as misdc_step. */
 int misdc_autotune(misdc_integ_t integ, const double* dev_state, double dt,
@@ -393,17 +397,20 @@ int misdc_mlp_targets(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, const doubl
                       const double* dev_h, const double* dev_Y, float* dev_t, void* stream);
 /* Initial guess of misdc_reaction_solve_batch: dev_Y (N x n) holds the plain
  * guess on entry; each cell takes the network's guess (b_Y + predicted
- * increment, negative entries of non-negative b_Y clipped to 0) instead if
- * its residual |Y - c FR(Y, T(Y, h)) - b_Y|_2 is smaller.  dev_choice (n
+ * increment) instead if
+ * its residual |Y - c FR(Y, T(Y, h)) - b_Y|_2 is smaller (the network's
+ * guess is first raised to min(b_Y, 0) where it falls below, the floor of
+ * the Newton iteration's trial acceptance).  dev_choice (n
  * int32, may be NULL) records 1 where the learned guess was taken. */
 int misdc_reaction_guess_mlp(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, const double* dev_bY,
                              const double* dev_h, const double* dev_c, double* dev_Y,
                              int32_t* dev_choice, void* stream);
-/* Every reaction task of later steps starts from the learned guess where it
- * has the smaller residual (NULL: the plain guess, the previous iterate).
+/* Every reaction task of the first ``sweeps`` sweeps of later steps (0:
+ * every sweep) starts from the learned guess where it has the smaller
+ * residual (mlp NULL: the plain guess, the previous iterate, everywhere).
  * Allocates the network's buffers for the grid; the network must outlive
  * its use.  Synchronises. */
-int misdc_integ_set_guess(misdc_integ_t integ, misdc_mlp_t mlp);
+int misdc_integ_set_guess(misdc_integ_t integ, misdc_mlp_t mlp, int sweeps);
 /* Records the reaction problems of later steps: task t (in issue order, up
  * to max_tasks) writes (b_Y: N x n, h: n, c: n, Y: N x n) doubles at
  * dev_buf + t (2N + 2) n.  max_tasks = 0 stops recording.  Steps are not

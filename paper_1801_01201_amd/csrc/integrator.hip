@@ -1270,6 +1270,13 @@ int misdc_autotune(misdc_integ_t I, const double* state, double dt, const double
                         cand.push_back(t);
                     }
                 }
+            const int64_t tiles = cg_tile_blocks(g);
+            if (I->N == 9 && tiles >= 1 && tiles <= cap)
+                for (int v : {101, 102, 103}) {
+                    t.cg_variant = v;
+                    t.cg_blocks = (int)tiles;
+                    cand.push_back(t);
+                }
             for (int div : {4, 2, 1}) {
                 t.cg_variant = 0;
                 t.cg_blocks = cap / div > 0 ? cap / div : 1;

@@ -155,7 +155,8 @@ struct DiffusionWork {
     int blocks = 0;
     int threads = 0;
     int fields_cap = 0;
-    int variant = 0;              // 0: vectors in global memory; 1, 2, 4: cells per thread in registers
+    int variant = 0;              // 0: vectors in global memory; 1, 2, 4: cells per thread in
+                                  // registers; 101..103: tiled, 1..3 local preconditioner sweeps
     int cyclic = 1;               // 1-D systems: 0 one thread per system, 1 one wavefront per system
 };
 int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g);
@@ -163,6 +164,8 @@ int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g);
 // registers) and its block count, after checking that it fits
 int diffusion_work_set(DiffusionWork& w, const Mech& m, const Grid& g, int variant, int blocks);
 int64_t cg_regs_min_blocks(int64_t n, int cpt);
+// tiles of the tiled CG variants (0 if the grid is not a single 2-D grid)
+int64_t cg_tile_blocks(const Grid& g);
 int device_cus(int& cus);
 void diffusion_work_free(DiffusionWork& w);
 // Solves all N+1 fields (bath by closure); y may hold the guess (guess_in_y)

@@ -479,6 +479,7 @@ struct CGArgs {
     double rtol2;
     int maxit;
     int guess_in_x;
+    int ntx;                // tiled variant: tiles along x
 };
 
 // A_f v at cell i: v_i - cf (Ke (v_E - v_i) - Kw (v_i - v_W) + Kn (...) - Ks (...))
@@ -898,6 +899,192 @@ __global__ void __launch_bounds__(BS) cg_regs_kernel(CGArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Tiled variant: the same pipelined PCG, with every workgroup owning a
+// TX x TY tile of cells and a block-local preconditioner.  The
+// preconditioner applies KSW Jacobi sweeps, started from zero, to the tile's
+// own operator (the 5-point stencil with the neighbours outside the tile
+// dropped): z = sum_{j <= KSW} (I - D^-1 A_t)^j D^-1 v.  That is a fixed
+// polynomial in the symmetric matrix D^-1/2 A_t D^-1/2 whose eigenvalues lie
+// in (0, 2), so it is symmetric positive definite and CG stays valid.  It
+// couples the cells within a tile through LDS, so it costs no grid barrier,
+// and it replaces the diagonal preconditioner at the two places the
+// pipelined recurrence applies one (u = M^-1 r, m = M^-1 w).
+// ---------------------------------------------------------------------------
+constexpr int TILE_X = 32, TILE_Y = 16, TILE_BS = TILE_X * TILE_Y, TILE_NB = 128;
+constexpr int TILE_GROUP = 5;              // fields per LDS pass
+
+template <int NFD, int KSW>
+__device__ __forceinline__ void tile_precond(const double (&v)[NFD], double (&z)[NFD],
+                                             const double (&dinv)[NFD], const double (&cf)[NFD],
+                                             double ke, double kw, double kn, double ks,
+                                             bool he, bool hw, bool hn, bool hs, double* zt) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int d = 0; d < NFD; ++d) z[d] = dinv[d] * v[d];
+#pragma unroll
+    for (int sw = 0; sw < KSW; ++sw) {
+#pragma unroll
+        for (int g0 = 0; g0 < NFD; g0 += TILE_GROUP) {
+#pragma unroll
+            for (int d = g0; d < NFD && d < g0 + TILE_GROUP; ++d) zt[(d - g0) * TILE_BS + t] = z[d];
+            __syncthreads();
+            double zn[TILE_GROUP];
+#pragma unroll
+            for (int d = g0; d < NFD && d < g0 + TILE_GROUP; ++d) {
+                const double* Z = zt + (d - g0) * TILE_BS;
+                double nb = 0.0;
+                if (he) nb += ke * Z[t + 1];
+                if (hw) nb += kw * Z[t - 1];
+                if (hn) nb += kn * Z[t + TILE_X];
+                if (hs) nb += ks * Z[t - TILE_X];
+                zn[d - g0] = dinv[d] * (v[d] + cf[d] * nb);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int d = g0; d < NFD && d < g0 + TILE_GROUP; ++d) z[d] = zn[d - g0];
+        }
+    }
+}
+
+template <int NFD, int KSW>
+__global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
+    constexpr int BS = TILE_BS;
+    constexpr int NS = 3 * NFD;
+    __shared__ double stage[TILE_NB * NS];
+    __shared__ double red[NS * (BS / 64)];
+    __shared__ double tot[NS];
+    __shared__ double zt[TILE_GROUP * TILE_BS];
+    __shared__ double s_bb[NFD], s_gprev[NFD], s_aprev[NFD], s_alpha[NFD], s_beta[NFD];
+    __shared__ int s_active[NFD];
+    const int tx = threadIdx.x % TILE_X, ty = threadIdx.x / TILE_X;
+    const int gx = (blockIdx.x % a.ntx) * TILE_X + tx, gy = (blockIdx.x / a.ntx) * TILE_Y + ty;
+    const bool own = gx < a.nx && gy < a.ny;
+    const int64_t cell = own ? (int64_t)gy * a.nx + gx : 0;
+    int64_t ie, iw, in_, is_;
+    double ke, kw, kn, ks;
+    stencil_at(a, cell, ie, iw, in_, is_, ke, kw, kn, ks);
+    // neighbours inside this tile (and inside the grid)
+    const bool he = own && tx + 1 < TILE_X && gx + 1 < a.nx;
+    const bool hw = own && tx > 0;
+    const bool hn = own && ty + 1 < TILE_Y && gy + 1 < a.ny;
+    const bool hs = own && ty > 0;
+    double cf[NFD], dinv[NFD];
+#pragma unroll
+    for (int d = 0; d < NFD; ++d) {
+        cf[d] = a.cf[d];
+        dinv[d] = own ? 1.0 / (1.0 + cf[d] * (ke + kw + kn + ks)) : 0.0;
+    }
+    double x[NFD], r[NFD], u[NFD], w[NFD], zz[NFD], qq[NFD], ss[NFD], pp[NFD];
+    unsigned kb = 0;
+    // ---- r = b - A x0, u = M^-1 r (published), partial (b, b) ----
+#pragma unroll
+    for (int d = 0; d < NFD; ++d) {
+        const size_t o = (size_t)a.fmap[d] * a.n;
+        const double* X = a.guess_in_x ? a.x + o : a.b + o;
+        x[d] = r[d] = w[d] = zz[d] = qq[d] = ss[d] = pp[d] = 0.0;
+        double bb = 0.0;
+        if (own) {
+            const double xi = X[cell];
+            const double Ax = xi - cf[d] * (ke * (X[ie] - xi) - kw * (xi - X[iw]) +
+                                            kn * (X[in_] - xi) - ks * (xi - X[is_]));
+            const double bi = a.b[o + cell];
+            x[d] = xi;
+            r[d] = bi - Ax;
+            bb = bi * bi;
+        }
+        wave_put<BS>(bb, red, d);
+    }
+    tile_precond<NFD, KSW>(r, u, dinv, cf, ke, kw, kn, ks, he, hw, hn, hs, zt);
+#pragma unroll
+    for (int d = 0; d < NFD; ++d)
+        if (own) a.r[(size_t)a.fmap[d] * a.n + cell] = u[d];
+    grid_allreduce<BS>(a, kb++, NFD, red, stage, tot);
+    if (threadIdx.x < NFD) s_bb[threadIdx.x] = tot[threadIdx.x];
+    // ---- w = A u ----
+#pragma unroll
+    for (int d = 0; d < NFD; ++d) {
+        const double* U = a.r + (size_t)a.fmap[d] * a.n;
+        if (own) {
+            const double ui = u[d];
+            w[d] = ui - cf[d] * (ke * (U[ie] - ui) - kw * (ui - U[iw]) + kn * (U[in_] - ui) -
+                                 ks * (ui - U[is_]));
+        }
+    }
+    int it = 0;
+    for (; it < a.maxit; ++it) {
+        // ---- m = M^-1 w (published), partials gamma = (r,u), delta = (w,u), rr ----
+        double* Mbuf = (it & 1) ? a.q : a.z;
+        double m[NFD];
+        tile_precond<NFD, KSW>(w, m, dinv, cf, ke, kw, kn, ks, he, hw, hn, hs, zt);
+#pragma unroll
+        for (int d = 0; d < NFD; ++d) {
+            const size_t o = (size_t)a.fmap[d] * a.n;
+            if (own) Mbuf[o + cell] = m[d];
+            wave_put<BS>(own ? r[d] * u[d] : 0.0, red, 3 * d + 0);
+            wave_put<BS>(own ? w[d] * u[d] : 0.0, red, 3 * d + 1);
+            wave_put<BS>(own ? r[d] * r[d] : 0.0, red, 3 * d + 2);
+        }
+        grid_allreduce<BS>(a, kb++, NS, red, stage, tot);
+        if (threadIdx.x < NFD) {
+            const int d = threadIdx.x;
+            const double g = tot[3 * d], de = tot[3 * d + 1], rr = tot[3 * d + 2];
+            const int act = rr > a.rtol2 * s_bb[d];
+            double al = 0.0, be = 0.0;
+            if (act) {
+                if (it == 0) {
+                    al = g / de;
+                } else {
+                    be = g / s_gprev[d];
+                    al = g / (de - be * g / s_aprev[d]);
+                }
+                s_gprev[d] = g;
+                s_aprev[d] = al;
+            }
+            s_active[d] = act;
+            s_alpha[d] = al;
+            s_beta[d] = be;
+        }
+        __syncthreads();
+        int any = 0;
+#pragma unroll
+        for (int d = 0; d < NFD; ++d) any |= s_active[d];
+        if (!any) break;
+        // ---- n = A m ; recurrences ----
+#pragma unroll
+        for (int d = 0; d < NFD; ++d) {
+            const double* Mv = Mbuf + (size_t)a.fmap[d] * a.n;
+            const bool act = s_active[d];
+            const double al = s_alpha[d], be = s_beta[d];
+            if (!own) continue;
+            const double mi = m[d];
+            const double ni = mi - cf[d] * (ke * (Mv[ie] - mi) - kw * (mi - Mv[iw]) +
+                                            kn * (Mv[in_] - mi) - ks * (mi - Mv[is_]));
+            const double z1 = ni + be * zz[d];
+            const double q1 = mi + be * qq[d];
+            const double s1 = w[d] + be * ss[d];
+            const double p1 = u[d] + be * pp[d];
+            zz[d] = act ? z1 : zz[d];
+            qq[d] = act ? q1 : qq[d];
+            ss[d] = act ? s1 : ss[d];
+            pp[d] = act ? p1 : pp[d];
+            x[d] = act ? x[d] + al * p1 : x[d];
+            r[d] = act ? r[d] - al * s1 : r[d];
+            u[d] = act ? u[d] - al * q1 : u[d];
+            w[d] = act ? w[d] - al * z1 : w[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < NFD; ++d)
+        if (own) a.x[(size_t)a.fmap[d] * a.n + cell] = x[d];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.info[0] = it;
+        int any = 0;
+        for (int d = 0; d < NFD; ++d) any |= s_active[d];
+        a.info[1] = (it == a.maxit) ? any : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) diffmax_kernel(int nfields, int64_t n, const double* a,
@@ -960,6 +1147,11 @@ GridDev grid_dev(const Grid& g) {
 
 }  // namespace
 
+int64_t cg_tile_blocks(const Grid& g) {
+    if (g.dim != 2 || g.n_flames > 0) return 0;
+    return ((g.nx + TILE_X - 1) / TILE_X) * ((g.ny + TILE_Y - 1) / TILE_Y);
+}
+
 int64_t cg_regs_min_blocks(int64_t n, int cpt) {
     const int64_t per = (int64_t)cg_regs_block(cpt) * cpt;
     return (n + per - 1) / per;
@@ -1001,6 +1193,23 @@ int diffusion_work_set(DiffusionWork& w, const Mech& m, const Grid& g, int varia
             else
                 MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 4, 256>, 256, 0));
             break;
+        case 101:
+        case 102:
+        case 103: {
+            if (!(NF - 1 == 9 && g.dim == 2 && g.n_flames == 0))
+                return fail(MISDC_EINVAL, "tiled CG variants need a 2-D grid and 9 diffused fields");
+            const int64_t tiles = ((g.nx + TILE_X - 1) / TILE_X) * ((g.ny + TILE_Y - 1) / TILE_Y);
+            if (blocks != tiles || tiles > TILE_NB)
+                return fail(MISDC_EINVAL, "tiled CG: the grid has %lld tiles of %dx%d (at most %d), "
+                            "blocks must equal them", (long long)tiles, TILE_X, TILE_Y, TILE_NB);
+            if (variant == 101)
+                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_tile_kernel<9, 1>, TILE_BS, 0));
+            else if (variant == 102)
+                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_tile_kernel<9, 2>, TILE_BS, 0));
+            else
+                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_tile_kernel<9, 3>, TILE_BS, 0));
+            break;
+        }
         default:
             return fail(MISDC_EINVAL, "unknown CG variant %d", variant);
     }
@@ -1091,7 +1300,13 @@ int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
     w.variant = -1;
     const char* force = std::getenv("MISDC_FORCE_CG_GLOBAL");   // test switch
     const bool allow_regs = !(force && force[0] == '1');
-    if (allow_regs && NF - 1 == 9 && g.dim == 2 && g.n_flames == 0) {
+    // the tiled variant (one 32x16 tile per workgroup, one local
+    // preconditioner sweep) where the grid has at most 128 tiles: fewer
+    // iterations than the diagonal preconditioner at a small cost each
+    const int64_t tiles = cg_tile_blocks(g);
+    if (allow_regs && NF - 1 == 9 && tiles >= 1 && tiles <= cus && tiles <= TILE_NB)
+        (void)diffusion_work_set(w, m, g, 101, (int)tiles);
+    if (allow_regs && w.variant < 0 && NF - 1 == 9 && g.dim == 2 && g.n_flames == 0) {
         // grid barriers cost less with fewer blocks, so take the fewest cells
         // per thread that keeps the grid at most half the CUs, else at most
         // all of them
@@ -1182,10 +1397,14 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
         a.rtol2 = rt * rt;
         a.maxit = maxit > 0 ? maxit : 500;
         a.guess_in_x = guess_in_y;
+        a.ntx = (int)((g.nx + TILE_X - 1) / TILE_X);
         switch (w.variant) {
             case 1: hipLaunchKernelGGL((cg_regs_kernel<9, 1, 512>), dim3(w.blocks), dim3(512), 0, s, a); break;
             case 2: hipLaunchKernelGGL((cg_regs_kernel<9, 2, 256>), dim3(w.blocks), dim3(256), 0, s, a); break;
             case 4: hipLaunchKernelGGL((cg_regs_kernel<9, 4, 256>), dim3(w.blocks), dim3(256), 0, s, a); break;
+            case 101: hipLaunchKernelGGL((cg_tile_kernel<9, 1>), dim3(w.blocks), dim3(TILE_BS), 0, s, a); break;
+            case 102: hipLaunchKernelGGL((cg_tile_kernel<9, 2>), dim3(w.blocks), dim3(TILE_BS), 0, s, a); break;
+            case 103: hipLaunchKernelGGL((cg_tile_kernel<9, 3>), dim3(w.blocks), dim3(TILE_BS), 0, s, a); break;
             default: hipLaunchKernelGGL(cg_kernel, dim3(w.blocks), dim3(CG_THREADS), 0, s, a); break;
         }
         MISDC_HIP(hipGetLastError());

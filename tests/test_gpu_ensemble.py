@@ -289,7 +289,7 @@ def test_autotune_and_set_tune(nat, mech9, mh):
     integ = Integrator(mh, g, n_nodes=5, sweeps=4, scheme="cisdcq")
     tune = integ.autotune(st0, 5e-5, reps=1)
     assert np.array_equal(host(st0), ref_in)
-    assert tune["cg_variant"] in (0, 1, 2, 4) and tune["cg_blocks"] >= 1
+    assert tune["cg_variant"] in (0, 1, 2, 4, 101, 102, 103) and tune["cg_blocks"] >= 1
     assert integ.tune()["cg_variant"] == tune["cg_variant"]
     outs = []
     for cfg in ((tune["cg_variant"], tune["cg_blocks"], 1, tune["serialize"]), (0, 32, 1, 1),
@@ -302,5 +302,7 @@ def test_autotune_and_set_tune(nat, mech9, mh):
         integ.set_tune(1, 1, 1, 0)          # 1 block cannot hold 3072 cells in registers
     integ.close()
     g.close()
+    # each configuration solves to |r| <= 1e-13 |b| with its own reduction
+    # order; Newton and the sweeps carry those differences to ~1e-11
     for o in outs[1:]:
-        assert field_err(o, outs[0]) <= 1e-12
+        assert field_err(o, outs[0]) <= TOL
