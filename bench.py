@@ -577,7 +577,7 @@ def main():
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic("pmc_cg_kernel_flame2d_256.md",
-                                            "paper_1801_01201_amd/csrc/transport.hip"),
+                                            "paper_1801_01201_amd/csrc/cg.hip"),
                 "avg_launch_ms": avg_s * 1e3, "launches": d_n,
                 "algorithmic_bytes_per_launch": traffic,
                 "cg_iterations_per_launch": cg_per_solve}

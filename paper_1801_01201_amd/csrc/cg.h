@@ -1,0 +1,45 @@
+// Persistent conjugate-gradient kernels of the implicit diffusion (steps
+// S3/S4): shared definitions of the launcher and the kernels.
+#pragma once
+
+#include "misdc_impl.h"
+
+namespace misdc {
+
+constexpr int CG_THREADS = 256;
+// block size of the register-resident CG: 512 threads with one cell each
+// (2 waves per SIMD), 256 threads when each thread owns 2 or 4 cells
+constexpr int cg_regs_block(int cpt) { return cpt == 1 ? 512 : 256; }
+constexpr int CG_MAX_FIELDS = 64;
+constexpr int CG_MAX_BLOCKS = 256;
+constexpr int TILE_X = 32, TILE_Y = 16, TILE_BS = TILE_X * TILE_Y, TILE_NB = 128;
+
+struct CGArgs {
+    int64_t n;              // cells
+    int nx, ny;
+    int nf;                 // diffused fields (all but the bath)
+    int fmap[CG_MAX_FIELDS];// field index of diffused field d
+    double cf[CG_MAX_FIELDS];// c * kappa0_f
+    const double* Kx;
+    const double* Ky;
+    const double* b;        // rhs (N+1 fields)
+    double* x;              // solution (N+1 fields, bath untouched)
+    double* r;
+    double* z;
+    double* p;
+    double* q;
+    double* partial;        // blocks x nf x 4
+    double* totals;         // nf x 4 (written by the last block of a fused reduction)
+    unsigned* bar;
+    int32_t* info;          // [0] iterations, [1] failed, [2] barrier timeout
+    double rtol2;
+    int maxit;
+    int guess_in_x;
+    int ntx;                // tiled variant: tiles along x
+};
+
+// launches the CG kernel of a variant (0 global memory, 1/2/4 register
+// resident, 101..103 tiled) with ``blocks`` workgroups
+int launch_cg(const CGArgs& a, int variant, int blocks, hipStream_t s);
+
+}  // namespace misdc

@@ -1,18 +1,16 @@
 // Transport kernels: explicit advection/diffusion operators, the linear
-// combinations that assemble the SDC right-hand sides, and the implicit
-// diffusion solves of steps S3/S4.
+// combinations that assemble the SDC right-hand sides, the face coefficients
+// and the 1-D (cyclic tridiagonal) implicit diffusion solves of steps S3/S4,
+// and the launcher of the 2-D solves, whose persistent conjugate-gradient
+// kernels are in cg.hip.
 //
 // All field arrays are structure of arrays (field-major, cells contiguous,
 // x fastest), so every kernel below reads and writes whole 512-byte
-// wavefront segments.  The 2-D implicit diffusion is a persistent
-// Jacobi-preconditioned conjugate-gradient kernel that solves all diffused
-// fields of one node at once and iterates on the device until every field
-// has converged: one launch per solve, two grid-wide barriers per
-// iteration, deterministic fixed-order reductions (so the result does not
-// depend on scheduling), and a grid sized to be fully co-resident.
+// wavefront segments.
 #include <cmath>
 #include <cstdlib>
 
+#include "cg.h"
 #include "misdc_impl.h"
 #include "wave.h"
 
@@ -415,675 +413,6 @@ __global__ void __launch_bounds__(256) closure_kernel(MechDev m, int64_t n, cons
     y[(size_t)m.bath * n + i] = rhs[(size_t)m.bath * n + i] - s;
 }
 
-constexpr int CG_THREADS = 256;
-// block size of the register-resident CG: 512 threads with one cell each
-// (2 waves per SIMD), 256 threads when each thread owns 2 or 4 cells
-constexpr int cg_regs_block(int cpt) { return cpt == 1 ? 512 : 256; }
-constexpr int CG_MAX_FIELDS = 64;
-constexpr int CG_MAX_BLOCKS = 256;
-
-// ---- grid-wide barrier for the persistent CG kernels -------------------------
-// bar[0]: arrival counter, bar[1]: generation.  The workgroup barrier makes
-// every wave's stores complete; one agent-scope release fence per workgroup
-// then publishes them to the other XCDs (L2 write-back); the last workgroup to
-// arrive resets the counter and bumps the generation; the others poll the
-// generation with relaxed agent-scope loads (bounded: after the limit the
-// kernel records a timeout in info[2] and proceeds, so every wave always
-// terminates); one acquire fence per workgroup makes the other workgroups'
-// data visible before the workgroup barrier releases its waves.
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, int32_t* info) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > (1u << 27)) {
-                    __hip_atomic_store(&info[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-}
-
-
-
-struct CGArgs {
-    int64_t n;              // cells
-    int nx, ny;
-    int nf;                 // diffused fields (all but the bath)
-    int fmap[CG_MAX_FIELDS];// field index of diffused field d
-    double cf[CG_MAX_FIELDS];// c * kappa0_f
-    const double* Kx;
-    const double* Ky;
-    const double* b;        // rhs (N+1 fields)
-    double* x;              // solution (N+1 fields, bath untouched)
-    double* r;
-    double* z;
-    double* p;
-    double* q;
-    double* partial;        // blocks x nf x 4
-    double* totals;         // nf x 4 (written by the last block of a fused reduction)
-    unsigned* bar;
-    int32_t* info;          // [0] iterations, [1] failed, [2] barrier timeout
-    double rtol2;
-    int maxit;
-    int guess_in_x;
-    int ntx;                // tiled variant: tiles along x
-};
-
-// A_f v at cell i: v_i - cf (Ke (v_E - v_i) - Kw (v_i - v_W) + Kn (...) - Ks (...))
-__device__ __forceinline__ void stencil_at(const CGArgs& a, int64_t i, int64_t& e, int64_t& w,
-                                           int64_t& nn, int64_t& s, double& ke, double& kw,
-                                           double& kn, double& ks) {
-    const int64_t iy = i / a.nx, ix = i - iy * a.nx;
-    e = iy * a.nx + (ix + 1 == a.nx ? 0 : ix + 1);
-    w = iy * a.nx + (ix == 0 ? a.nx - 1 : ix - 1);
-    nn = (iy + 1 == a.ny ? 0 : iy + 1) * a.nx + ix;
-    s = (iy == 0 ? a.ny - 1 : iy - 1) * a.nx + ix;
-    ke = a.Kx[i];
-    kw = a.Kx[w];
-    kn = a.Ky[i];
-    ks = a.Ky[s];
-}
-
-// Wave-level sum, lane 0 stores the wave's value into red[slot * nw + wave].
-__device__ __forceinline__ void wave_store(double v, double* red, int slot) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if ((threadIdx.x & 63) == 0) red[slot * (CG_THREADS / 64) + (threadIdx.x >> 6)] = v;
-}
-
-// After __syncthreads: sum the wave values of every slot in a fixed order and
-// write this block's partials to global memory.
-__device__ __forceinline__ void block_publish(const double* red, int nslots, double* partial) {
-    for (int t = threadIdx.x; t < nslots; t += CG_THREADS) {
-        double s = 0.0;
-        for (int k = 0; k < CG_THREADS / 64; ++k) s += red[t * (CG_THREADS / 64) + k];
-        partial[(size_t)blockIdx.x * (CG_MAX_FIELDS * 4) + t] = s;
-    }
-}
-
-// Sum of the partials of every block for slots [0, nslots): each wave handles
-// a subset of slots, its lanes stride over the blocks, fixed order -> every
-// block obtains bitwise the same totals.
-__device__ __forceinline__ void grid_totals(const double* partial, int nslots, double* tot) {
-    const int nb = gridDim.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int t = wave; t < nslots; t += CG_THREADS / 64) {
-        double s = 0.0;
-        for (int b = lane; b < nb; b += 64) s += partial[(size_t)b * (CG_MAX_FIELDS * 4) + t];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) tot[t] = s;
-    }
-    __syncthreads();
-}
-
-__global__ void __launch_bounds__(CG_THREADS) cg_kernel(CGArgs a) {
-    // slot layout: slot = field * 4 + value
-    __shared__ double red[CG_MAX_FIELDS * 4 * (CG_THREADS / 64)];
-    __shared__ double tot[CG_MAX_FIELDS * 4];
-    __shared__ double s_rz[CG_MAX_FIELDS], s_bb[CG_MAX_FIELDS], s_alpha[CG_MAX_FIELDS],
-        s_beta[CG_MAX_FIELDS];
-    __shared__ int s_active[CG_MAX_FIELDS];
-    __shared__ int s_any;
-    const unsigned nb = gridDim.x;
-    const int64_t stride = (int64_t)gridDim.x * CG_THREADS;
-    const int64_t i0 = (int64_t)blockIdx.x * CG_THREADS + threadIdx.x;
-    const int nf = a.nf;
-
-    // ---- r = b - A x0, z = D^{-1} r; partials rz, rr, bb ----
-    for (int d = 0; d < nf; ++d) {
-        const size_t o = (size_t)a.fmap[d] * a.n;
-        const double* X = a.guess_in_x ? a.x + o : a.b + o;
-        const double cf = a.cf[d];
-        double rz = 0.0, rr = 0.0, bb = 0.0;
-        for (int64_t i = i0; i < a.n; i += stride) {
-            int64_t e, w, nn, s;
-            double ke, kw, kn, ks;
-            stencil_at(a, i, e, w, nn, s, ke, kw, kn, ks);
-            const double xi = X[i];
-            const double Ax = xi - cf * (ke * (X[e] - xi) - kw * (xi - X[w]) + kn * (X[nn] - xi) -
-                                         ks * (xi - X[s]));
-            const double bi = a.b[o + i];
-            const double ri = bi - Ax;
-            const double zi = ri / (1.0 + cf * (ke + kw + kn + ks));
-            a.r[o + i] = ri;
-            a.z[o + i] = zi;
-            if (!a.guess_in_x) a.x[o + i] = xi;
-            rz += ri * zi;
-            rr += ri * ri;
-            bb += bi * bi;
-        }
-        wave_store(rz, red, d * 4 + 0);
-        wave_store(rr, red, d * 4 + 1);
-        wave_store(bb, red, d * 4 + 2);
-    }
-    __syncthreads();
-    block_publish(red, nf * 4, a.partial);
-    grid_barrier(a.bar, nb, a.info);
-    grid_totals(a.partial, nf * 4, tot);
-    if (threadIdx.x == 0) {
-        for (int d = 0; d < nf; ++d) {
-            s_rz[d] = tot[d * 4 + 0];
-            s_bb[d] = tot[d * 4 + 2];
-            s_active[d] = tot[d * 4 + 1] > a.rtol2 * s_bb[d];
-            s_beta[d] = 0.0;
-        }
-    }
-    __syncthreads();
-    int it = 0;
-    for (; it < a.maxit; ++it) {
-        if (threadIdx.x == 0) {
-            int any = 0;
-            for (int d = 0; d < nf; ++d) any |= s_active[d];
-            s_any = any;
-        }
-        __syncthreads();
-        if (!s_any) break;
-        // ---- p = z + beta p ; q = A z + beta q  (so q = A p) ; partial pq ----
-        for (int d = 0; d < nf; ++d) {
-            double pq = 0.0;
-            if (s_active[d]) {
-                const size_t o = (size_t)a.fmap[d] * a.n;
-                const double* Z = a.z + o;
-                const double cf = a.cf[d];
-                const double be = s_beta[d];
-                for (int64_t i = i0; i < a.n; i += stride) {
-                    int64_t e, w, nn, s;
-                    double ke, kw, kn, ks;
-                    stencil_at(a, i, e, w, nn, s, ke, kw, kn, ks);
-                    const double zi = Z[i];
-                    const double Az = zi - cf * (ke * (Z[e] - zi) - kw * (zi - Z[w]) +
-                                                 kn * (Z[nn] - zi) - ks * (zi - Z[s]));
-                    const double pi = (it == 0) ? zi : zi + be * a.p[o + i];
-                    const double qi = (it == 0) ? Az : Az + be * a.q[o + i];
-                    a.p[o + i] = pi;
-                    a.q[o + i] = qi;
-                    pq += pi * qi;
-                }
-            }
-            wave_store(pq, red, d * 4 + 0);
-        }
-        __syncthreads();
-        block_publish(red, nf * 4, a.partial);
-        grid_barrier(a.bar, nb, a.info);
-        grid_totals(a.partial, nf * 4, tot);
-        if (threadIdx.x == 0)
-            for (int d = 0; d < nf; ++d) s_alpha[d] = s_active[d] ? s_rz[d] / tot[d * 4 + 0] : 0.0;
-        __syncthreads();
-        // ---- x += alpha p ; r -= alpha q ; z = D^{-1} r ; partials rz, rr ----
-        for (int d = 0; d < nf; ++d) {
-            double rz = 0.0, rr = 0.0;
-            if (s_active[d]) {
-                const size_t o = (size_t)a.fmap[d] * a.n;
-                const double al = s_alpha[d];
-                const double cf = a.cf[d];
-                for (int64_t i = i0; i < a.n; i += stride) {
-                    const int64_t iy = i / a.nx, ix = i - iy * a.nx;
-                    const int64_t w = iy * a.nx + (ix == 0 ? a.nx - 1 : ix - 1);
-                    const int64_t s = (iy == 0 ? a.ny - 1 : iy - 1) * a.nx + ix;
-                    const double ksum = a.Kx[i] + a.Kx[w] + a.Ky[i] + a.Ky[s];
-                    a.x[o + i] += al * a.p[o + i];
-                    const double ri = a.r[o + i] - al * a.q[o + i];
-                    const double zi = ri / (1.0 + cf * ksum);
-                    a.r[o + i] = ri;
-                    a.z[o + i] = zi;
-                    rz += ri * zi;
-                    rr += ri * ri;
-                }
-            }
-            wave_store(rz, red, d * 4 + 0);
-            wave_store(rr, red, d * 4 + 1);
-        }
-        __syncthreads();
-        block_publish(red, nf * 4, a.partial);
-        grid_barrier(a.bar, nb, a.info);
-        grid_totals(a.partial, nf * 4, tot);
-        if (threadIdx.x == 0)
-            for (int d = 0; d < nf; ++d) {
-                if (!s_active[d]) continue;
-                const double rz_new = tot[d * 4 + 0];
-                s_beta[d] = rz_new / s_rz[d];
-                s_rz[d] = rz_new;
-                s_active[d] = tot[d * 4 + 1] > a.rtol2 * s_bb[d];
-            }
-        __syncthreads();
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.info[0] = it;
-        int any = 0;
-        for (int d = 0; d < nf; ++d) any |= s_active[d];
-        a.info[1] = any;
-    }
-}
-
-// Grid barrier number k (0-based) of the current launch, with a monotonic
-// arrival counter that the preceding faces_kernel zeroed: every workgroup
-// publishes its stores with one agent-scope release fence and one relaxed
-// increment, then waits until all workgroups have arrived k+1 times (the
-// increments form one release sequence, so the acquire fence after the wait
-// makes every workgroup's stores visible).  Bounded wait: after the limit the
-// kernel records a timeout in info[2] and proceeds, so every wave terminates.
-__device__ __forceinline__ void grid_sync(unsigned* counter, unsigned nb, unsigned k,
-                                          int32_t* info) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned target = (k + 1u) * nb;
-        unsigned spins = 0;
-        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > (1u << 27)) {
-                __hip_atomic_store(&info[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-}
-
-// All-reduce of nslots values fused with grid barrier k.  red holds one value
-// per (slot, wave) of this workgroup.  The partials go to buffer k % 2 (so a
-// workgroup that is one barrier ahead cannot overwrite values another one is
-// still reading); after the barrier every workgroup loads all partials at
-// once into LDS and sums them in block order: bitwise identical totals in
-// every workgroup, whatever the scheduling.
-template <int BS>
-__device__ __forceinline__ void grid_allreduce(const CGArgs& a, unsigned k, int nslots,
-                                               const double* red, double* stage, double* tot) {
-    constexpr int NW = BS / 64;
-    const unsigned nb = gridDim.x;
-    double* part = a.partial + (size_t)(k & 1u) * CG_MAX_BLOCKS * (CG_MAX_FIELDS * 4);
-    __syncthreads();
-    for (int t = threadIdx.x; t < nslots; t += BS) {
-        double v = 0.0;
-        for (int w = 0; w < NW; ++w) v += red[t * NW + w];
-        part[(size_t)blockIdx.x * (CG_MAX_FIELDS * 4) + t] = v;
-    }
-    grid_sync(a.bar, nb, k, a.info);
-    const int total = (int)nb * nslots;
-    for (int e = threadIdx.x; e < total; e += BS) {
-        const int b = e / nslots, t = e - b * nslots;
-        stage[e] = part[(size_t)b * (CG_MAX_FIELDS * 4) + t];
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int t = wave; t < nslots; t += NW) {
-        double v = 0.0;
-        for (unsigned b = lane; b < nb; b += 64) v += stage[b * nslots + t];
-        v = wave_sum(v);
-        if (lane == 0) tot[t] = v;
-    }
-    __syncthreads();
-}
-
-template <int BS>
-__device__ __forceinline__ void wave_put(double v, double* red, int slot) {
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) red[slot * (BS / 64) + (threadIdx.x >> 6)] = v;
-}
-
-// Register-resident pipelined preconditioned CG (the single-reduction
-// recurrences of Ghysels & Vanroose).  Every thread owns CPT cells for the
-// whole solve and keeps all vectors of the NFD fields in registers; the only
-// vector exchanged through memory is m = D^{-1} w, whose stencil product is
-// taken after the barrier that also reduces (r,u), (w,u) and (r,r) -- one
-// grid barrier per iteration.  m is double-buffered in a.z / a.q.  Fields stop
-// (their updates are masked) once |r|_2 <= rtol |b|_2.
-template <int NFD, int CPT, int BS>
-__global__ void __launch_bounds__(BS) cg_regs_kernel(CGArgs a) {
-    constexpr int NS = 3 * NFD;               // slots: gamma, delta, rr per field
-    __shared__ double stage[CG_MAX_BLOCKS * NS];
-    __shared__ double red[NS * (BS / 64)];
-    __shared__ double tot[NS];
-    __shared__ double s_bb[NFD], s_gprev[NFD], s_aprev[NFD], s_alpha[NFD], s_beta[NFD];
-    __shared__ int s_active[NFD];
-    const unsigned nb = gridDim.x;
-    const int64_t T = (int64_t)gridDim.x * BS;
-    const int64_t t0 = (int64_t)blockIdx.x * BS + threadIdx.x;
-    int64_t cell[CPT], ie[CPT], iw[CPT], in_[CPT], is_[CPT];
-    double ke[CPT], kw[CPT], kn[CPT], ks[CPT];
-    bool own[CPT];
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-        cell[k] = t0 + k * T;
-        own[k] = cell[k] < a.n;
-        const int64_t i = own[k] ? cell[k] : 0;
-        stencil_at(a, i, ie[k], iw[k], in_[k], is_[k], ke[k], kw[k], kn[k], ks[k]);
-    }
-    double x[NFD][CPT], r[NFD][CPT], u[NFD][CPT], w[NFD][CPT];
-    double zz[NFD][CPT], qq[NFD][CPT], ss[NFD][CPT], pp[NFD][CPT];
-    unsigned kb = 0;                          // grid barriers done in this launch
-    // ---- r = b - A x0, u = D^{-1} r (published), partial (b, b) ----
-#pragma unroll
-    for (int d = 0; d < NFD; ++d) {
-        const size_t o = (size_t)a.fmap[d] * a.n;
-        const double* X = a.guess_in_x ? a.x + o : a.b + o;
-        const double cf = a.cf[d];
-        double bb = 0.0;
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-            x[d][k] = r[d][k] = u[d][k] = w[d][k] = 0.0;
-            zz[d][k] = qq[d][k] = ss[d][k] = pp[d][k] = 0.0;
-            if (!own[k]) continue;
-            const int64_t i = cell[k];
-            const double xi = X[i];
-            const double Ax = xi - cf * (ke[k] * (X[ie[k]] - xi) - kw[k] * (xi - X[iw[k]]) +
-                                         kn[k] * (X[in_[k]] - xi) - ks[k] * (xi - X[is_[k]]));
-            const double bi = a.b[o + i];
-            x[d][k] = xi;
-            r[d][k] = bi - Ax;
-            u[d][k] = r[d][k] / (1.0 + cf * (ke[k] + kw[k] + kn[k] + ks[k]));
-            a.r[o + i] = u[d][k];             // exchange buffer of u
-            bb += bi * bi;
-        }
-        wave_put<BS>(bb, red, d);
-    }
-    grid_allreduce<BS>(a, kb++, NFD, red, stage, tot);
-    if (threadIdx.x < NFD) s_bb[threadIdx.x] = tot[threadIdx.x];
-    // ---- w = A u ----
-#pragma unroll
-    for (int d = 0; d < NFD; ++d) {
-        const size_t o = (size_t)a.fmap[d] * a.n;
-        const double* U = a.r + o;
-        const double cf = a.cf[d];
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-            if (!own[k]) continue;
-            const double ui = u[d][k];
-            w[d][k] = ui - cf * (ke[k] * (U[ie[k]] - ui) - kw[k] * (ui - U[iw[k]]) +
-                                 kn[k] * (U[in_[k]] - ui) - ks[k] * (ui - U[is_[k]]));
-        }
-    }
-    int it = 0;
-    for (; it < a.maxit; ++it) {
-        // ---- m = D^{-1} w (published), partials gamma = (r,u), delta = (w,u), rr ----
-        double* Mbuf = (it & 1) ? a.q : a.z;
-#pragma unroll
-        for (int d = 0; d < NFD; ++d) {
-            const size_t o = (size_t)a.fmap[d] * a.n;
-            const double cf = a.cf[d];
-            double g = 0.0, de = 0.0, rr = 0.0;
-#pragma unroll
-            for (int k = 0; k < CPT; ++k) {
-                if (!own[k]) continue;
-                Mbuf[o + cell[k]] = w[d][k] / (1.0 + cf * (ke[k] + kw[k] + kn[k] + ks[k]));
-                g += r[d][k] * u[d][k];
-                de += w[d][k] * u[d][k];
-                rr += r[d][k] * r[d][k];
-            }
-            wave_put<BS>(g, red, 3 * d + 0);
-            wave_put<BS>(de, red, 3 * d + 1);
-            wave_put<BS>(rr, red, 3 * d + 2);
-        }
-        grid_allreduce<BS>(a, kb++, NS, red, stage, tot);
-        // recurrence coefficients, one thread per field
-        if (threadIdx.x < NFD) {
-            const int d = threadIdx.x;
-            const double g = tot[3 * d], de = tot[3 * d + 1], rr = tot[3 * d + 2];
-            const int act = rr > a.rtol2 * s_bb[d];
-            double al = 0.0, be = 0.0;
-            if (act) {
-                if (it == 0) {
-                    al = g / de;
-                } else {
-                    be = g / s_gprev[d];
-                    al = g / (de - be * g / s_aprev[d]);
-                }
-                s_gprev[d] = g;
-                s_aprev[d] = al;
-            }
-            s_active[d] = act;
-            s_alpha[d] = al;
-            s_beta[d] = be;
-        }
-        __syncthreads();
-        int any = 0;
-#pragma unroll
-        for (int d = 0; d < NFD; ++d) any |= s_active[d];
-        if (!any) break;
-        // ---- n = A m ; recurrences ----
-#pragma unroll
-        for (int d = 0; d < NFD; ++d) {
-            const size_t o = (size_t)a.fmap[d] * a.n;
-            const double* Mv = Mbuf + o;
-            const double cf = a.cf[d];
-            const bool act = s_active[d];
-            const double al = s_alpha[d], be = s_beta[d];
-#pragma unroll
-            for (int k = 0; k < CPT; ++k) {
-                if (!own[k]) continue;
-                const double mi = Mv[cell[k]];
-                const double ni = mi - cf * (ke[k] * (Mv[ie[k]] - mi) - kw[k] * (mi - Mv[iw[k]]) +
-                                             kn[k] * (Mv[in_[k]] - mi) - ks[k] * (mi - Mv[is_[k]]));
-                const double z1 = ni + be * zz[d][k];
-                const double q1 = mi + be * qq[d][k];
-                const double s1 = w[d][k] + be * ss[d][k];
-                const double p1 = u[d][k] + be * pp[d][k];
-                zz[d][k] = act ? z1 : zz[d][k];
-                qq[d][k] = act ? q1 : qq[d][k];
-                ss[d][k] = act ? s1 : ss[d][k];
-                pp[d][k] = act ? p1 : pp[d][k];
-                x[d][k] = act ? x[d][k] + al * p1 : x[d][k];
-                r[d][k] = act ? r[d][k] - al * s1 : r[d][k];
-                u[d][k] = act ? u[d][k] - al * q1 : u[d][k];
-                w[d][k] = act ? w[d][k] - al * z1 : w[d][k];
-            }
-        }
-    }
-#pragma unroll
-    for (int d = 0; d < NFD; ++d) {
-        const size_t o = (size_t)a.fmap[d] * a.n;
-#pragma unroll
-        for (int k = 0; k < CPT; ++k)
-            if (own[k]) a.x[o + cell[k]] = x[d][k];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.info[0] = it;
-        int any = 0;
-        for (int d = 0; d < NFD; ++d) any |= s_active[d];
-        a.info[1] = (it == a.maxit) ? any : 0;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Tiled variant: the same pipelined PCG, with every workgroup owning a
-// TX x TY tile of cells and a block-local preconditioner.  The
-// preconditioner applies KSW Jacobi sweeps, started from zero, to the tile's
-// own operator (the 5-point stencil with the neighbours outside the tile
-// dropped): z = sum_{j <= KSW} (I - D^-1 A_t)^j D^-1 v.  That is a fixed
-// polynomial in the symmetric matrix D^-1/2 A_t D^-1/2 whose eigenvalues lie
-// in (0, 2), so it is symmetric positive definite and CG stays valid.  It
-// couples the cells within a tile through LDS, so it costs no grid barrier,
-// and it replaces the diagonal preconditioner at the two places the
-// pipelined recurrence applies one (u = M^-1 r, m = M^-1 w).
-// ---------------------------------------------------------------------------
-constexpr int TILE_X = 32, TILE_Y = 16, TILE_BS = TILE_X * TILE_Y, TILE_NB = 128;
-constexpr int TILE_GROUP = 5;              // fields per LDS pass
-
-template <int NFD, int KSW>
-__device__ __forceinline__ void tile_precond(const double (&v)[NFD], double (&z)[NFD],
-                                             const double (&dinv)[NFD], const double (&cf)[NFD],
-                                             double ke, double kw, double kn, double ks,
-                                             bool he, bool hw, bool hn, bool hs, double* zt) {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int d = 0; d < NFD; ++d) z[d] = dinv[d] * v[d];
-#pragma unroll
-    for (int sw = 0; sw < KSW; ++sw) {
-#pragma unroll
-        for (int g0 = 0; g0 < NFD; g0 += TILE_GROUP) {
-#pragma unroll
-            for (int d = g0; d < NFD && d < g0 + TILE_GROUP; ++d) zt[(d - g0) * TILE_BS + t] = z[d];
-            __syncthreads();
-            double zn[TILE_GROUP];
-#pragma unroll
-            for (int d = g0; d < NFD && d < g0 + TILE_GROUP; ++d) {
-                const double* Z = zt + (d - g0) * TILE_BS;
-                double nb = 0.0;
-                if (he) nb += ke * Z[t + 1];
-                if (hw) nb += kw * Z[t - 1];
-                if (hn) nb += kn * Z[t + TILE_X];
-                if (hs) nb += ks * Z[t - TILE_X];
-                zn[d - g0] = dinv[d] * (v[d] + cf[d] * nb);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int d = g0; d < NFD && d < g0 + TILE_GROUP; ++d) z[d] = zn[d - g0];
-        }
-    }
-}
-
-template <int NFD, int KSW>
-__global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
-    constexpr int BS = TILE_BS;
-    constexpr int NS = 3 * NFD;
-    __shared__ double stage[TILE_NB * NS];
-    __shared__ double red[NS * (BS / 64)];
-    __shared__ double tot[NS];
-    __shared__ double zt[TILE_GROUP * TILE_BS];
-    __shared__ double s_bb[NFD], s_gprev[NFD], s_aprev[NFD], s_alpha[NFD], s_beta[NFD];
-    __shared__ int s_active[NFD];
-    const int tx = threadIdx.x % TILE_X, ty = threadIdx.x / TILE_X;
-    const int gx = (blockIdx.x % a.ntx) * TILE_X + tx, gy = (blockIdx.x / a.ntx) * TILE_Y + ty;
-    const bool own = gx < a.nx && gy < a.ny;
-    const int64_t cell = own ? (int64_t)gy * a.nx + gx : 0;
-    int64_t ie, iw, in_, is_;
-    double ke, kw, kn, ks;
-    stencil_at(a, cell, ie, iw, in_, is_, ke, kw, kn, ks);
-    // neighbours inside this tile (and inside the grid)
-    const bool he = own && tx + 1 < TILE_X && gx + 1 < a.nx;
-    const bool hw = own && tx > 0;
-    const bool hn = own && ty + 1 < TILE_Y && gy + 1 < a.ny;
-    const bool hs = own && ty > 0;
-    double cf[NFD], dinv[NFD];
-#pragma unroll
-    for (int d = 0; d < NFD; ++d) {
-        cf[d] = a.cf[d];
-        dinv[d] = own ? 1.0 / (1.0 + cf[d] * (ke + kw + kn + ks)) : 0.0;
-    }
-    double x[NFD], r[NFD], u[NFD], w[NFD], zz[NFD], qq[NFD], ss[NFD], pp[NFD];
-    unsigned kb = 0;
-    // ---- r = b - A x0, u = M^-1 r (published), partial (b, b) ----
-#pragma unroll
-    for (int d = 0; d < NFD; ++d) {
-        const size_t o = (size_t)a.fmap[d] * a.n;
-        const double* X = a.guess_in_x ? a.x + o : a.b + o;
-        x[d] = r[d] = w[d] = zz[d] = qq[d] = ss[d] = pp[d] = 0.0;
-        double bb = 0.0;
-        if (own) {
-            const double xi = X[cell];
-            const double Ax = xi - cf[d] * (ke * (X[ie] - xi) - kw * (xi - X[iw]) +
-                                            kn * (X[in_] - xi) - ks * (xi - X[is_]));
-            const double bi = a.b[o + cell];
-            x[d] = xi;
-            r[d] = bi - Ax;
-            bb = bi * bi;
-        }
-        wave_put<BS>(bb, red, d);
-    }
-    tile_precond<NFD, KSW>(r, u, dinv, cf, ke, kw, kn, ks, he, hw, hn, hs, zt);
-#pragma unroll
-    for (int d = 0; d < NFD; ++d)
-        if (own) a.r[(size_t)a.fmap[d] * a.n + cell] = u[d];
-    grid_allreduce<BS>(a, kb++, NFD, red, stage, tot);
-    if (threadIdx.x < NFD) s_bb[threadIdx.x] = tot[threadIdx.x];
-    // ---- w = A u ----
-#pragma unroll
-    for (int d = 0; d < NFD; ++d) {
-        const double* U = a.r + (size_t)a.fmap[d] * a.n;
-        if (own) {
-            const double ui = u[d];
-            w[d] = ui - cf[d] * (ke * (U[ie] - ui) - kw * (ui - U[iw]) + kn * (U[in_] - ui) -
-                                 ks * (ui - U[is_]));
-        }
-    }
-    int it = 0;
-    for (; it < a.maxit; ++it) {
-        // ---- m = M^-1 w (published), partials gamma = (r,u), delta = (w,u), rr ----
-        double* Mbuf = (it & 1) ? a.q : a.z;
-        double m[NFD];
-        tile_precond<NFD, KSW>(w, m, dinv, cf, ke, kw, kn, ks, he, hw, hn, hs, zt);
-#pragma unroll
-        for (int d = 0; d < NFD; ++d) {
-            const size_t o = (size_t)a.fmap[d] * a.n;
-            if (own) Mbuf[o + cell] = m[d];
-            wave_put<BS>(own ? r[d] * u[d] : 0.0, red, 3 * d + 0);
-            wave_put<BS>(own ? w[d] * u[d] : 0.0, red, 3 * d + 1);
-            wave_put<BS>(own ? r[d] * r[d] : 0.0, red, 3 * d + 2);
-        }
-        grid_allreduce<BS>(a, kb++, NS, red, stage, tot);
-        if (threadIdx.x < NFD) {
-            const int d = threadIdx.x;
-            const double g = tot[3 * d], de = tot[3 * d + 1], rr = tot[3 * d + 2];
-            const int act = rr > a.rtol2 * s_bb[d];
-            double al = 0.0, be = 0.0;
-            if (act) {
-                if (it == 0) {
-                    al = g / de;
-                } else {
-                    be = g / s_gprev[d];
-                    al = g / (de - be * g / s_aprev[d]);
-                }
-                s_gprev[d] = g;
-                s_aprev[d] = al;
-            }
-            s_active[d] = act;
-            s_alpha[d] = al;
-            s_beta[d] = be;
-        }
-        __syncthreads();
-        int any = 0;
-#pragma unroll
-        for (int d = 0; d < NFD; ++d) any |= s_active[d];
-        if (!any) break;
-        // ---- n = A m ; recurrences ----
-#pragma unroll
-        for (int d = 0; d < NFD; ++d) {
-            const double* Mv = Mbuf + (size_t)a.fmap[d] * a.n;
-            const bool act = s_active[d];
-            const double al = s_alpha[d], be = s_beta[d];
-            if (!own) continue;
-            const double mi = m[d];
-            const double ni = mi - cf[d] * (ke * (Mv[ie] - mi) - kw * (mi - Mv[iw]) +
-                                            kn * (Mv[in_] - mi) - ks * (mi - Mv[is_]));
-            const double z1 = ni + be * zz[d];
-            const double q1 = mi + be * qq[d];
-            const double s1 = w[d] + be * ss[d];
-            const double p1 = u[d] + be * pp[d];
-            zz[d] = act ? z1 : zz[d];
-            qq[d] = act ? q1 : qq[d];
-            ss[d] = act ? s1 : ss[d];
-            pp[d] = act ? p1 : pp[d];
-            x[d] = act ? x[d] + al * p1 : x[d];
-            r[d] = act ? r[d] - al * s1 : r[d];
-            u[d] = act ? u[d] - al * q1 : u[d];
-            w[d] = act ? w[d] - al * z1 : w[d];
-        }
-    }
-#pragma unroll
-    for (int d = 0; d < NFD; ++d)
-        if (own) a.x[(size_t)a.fmap[d] * a.n + cell] = x[d];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.info[0] = it;
-        int any = 0;
-        for (int d = 0; d < NFD; ++d) any |= s_active[d];
-        a.info[1] = (it == a.maxit) ? any : 0;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
@@ -1146,78 +475,6 @@ GridDev grid_dev(const Grid& g) {
 }
 
 }  // namespace
-
-int64_t cg_tile_blocks(const Grid& g) {
-    if (g.dim != 2 || g.n_flames > 0) return 0;
-    return ((g.nx + TILE_X - 1) / TILE_X) * ((g.ny + TILE_Y - 1) / TILE_Y);
-}
-
-int64_t cg_regs_min_blocks(int64_t n, int cpt) {
-    const int64_t per = (int64_t)cg_regs_block(cpt) * cpt;
-    return (n + per - 1) / per;
-}
-
-int device_cus(int& cus) {
-    int dev = 0;
-    MISDC_HIP(hipGetDevice(&dev));
-    MISDC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    return MISDC_OK;
-}
-
-int diffusion_work_set(DiffusionWork& w, const Mech& m, const Grid& g, int variant, int blocks) {
-    const int64_t n = g.cells();
-    const int NF = m.dev.N + 1;
-    int cus = 0;
-    int rc = device_cus(cus);
-    if (rc) return rc;
-    const int cap = cus < CG_MAX_BLOCKS ? cus : CG_MAX_BLOCKS;
-    if (blocks < 1 || blocks > cap)
-        return fail(MISDC_EINVAL, "CG blocks must be in [1, %d], got %d", cap, blocks);
-    int occ = 0;
-    switch (variant) {
-        case 0:
-            MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_kernel, CG_THREADS, 0));
-            break;
-        case 1:
-        case 2:
-        case 4:
-            if (!(NF - 1 == 9 && g.dim == 2 && g.n_flames == 0))
-                return fail(MISDC_EINVAL, "register CG variants need a 2-D grid and 9 diffused fields");
-            if (blocks < cg_regs_min_blocks(n, variant))
-                return fail(MISDC_EINVAL, "CG variant %d needs at least %lld blocks", variant,
-                            (long long)cg_regs_min_blocks(n, variant));
-            if (variant == 1)
-                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 1, 512>, 512, 0));
-            else if (variant == 2)
-                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 2, 256>, 256, 0));
-            else
-                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_regs_kernel<9, 4, 256>, 256, 0));
-            break;
-        case 101:
-        case 102:
-        case 103: {
-            if (!(NF - 1 == 9 && g.dim == 2 && g.n_flames == 0))
-                return fail(MISDC_EINVAL, "tiled CG variants need a 2-D grid and 9 diffused fields");
-            const int64_t tiles = ((g.nx + TILE_X - 1) / TILE_X) * ((g.ny + TILE_Y - 1) / TILE_Y);
-            if (blocks != tiles || tiles > TILE_NB)
-                return fail(MISDC_EINVAL, "tiled CG: the grid has %lld tiles of %dx%d (at most %d), "
-                            "blocks must equal them", (long long)tiles, TILE_X, TILE_Y, TILE_NB);
-            if (variant == 101)
-                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_tile_kernel<9, 1>, TILE_BS, 0));
-            else if (variant == 102)
-                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_tile_kernel<9, 2>, TILE_BS, 0));
-            else
-                MISDC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, cg_tile_kernel<9, 3>, TILE_BS, 0));
-            break;
-        }
-        default:
-            return fail(MISDC_EINVAL, "unknown CG variant %d", variant);
-    }
-    if (occ < 1) return fail(MISDC_EDEVICE, "CG variant %d cannot be resident", variant);
-    w.variant = variant;
-    w.blocks = blocks;
-    return MISDC_OK;
-}
 
 int launch_copy(double* dst, const double* src, int64_t count, hipStream_t s) {
     if (count <= 0) return MISDC_OK;
@@ -1398,16 +655,8 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
         a.maxit = maxit > 0 ? maxit : 500;
         a.guess_in_x = guess_in_y;
         a.ntx = (int)((g.nx + TILE_X - 1) / TILE_X);
-        switch (w.variant) {
-            case 1: hipLaunchKernelGGL((cg_regs_kernel<9, 1, 512>), dim3(w.blocks), dim3(512), 0, s, a); break;
-            case 2: hipLaunchKernelGGL((cg_regs_kernel<9, 2, 256>), dim3(w.blocks), dim3(256), 0, s, a); break;
-            case 4: hipLaunchKernelGGL((cg_regs_kernel<9, 4, 256>), dim3(w.blocks), dim3(256), 0, s, a); break;
-            case 101: hipLaunchKernelGGL((cg_tile_kernel<9, 1>), dim3(w.blocks), dim3(TILE_BS), 0, s, a); break;
-            case 102: hipLaunchKernelGGL((cg_tile_kernel<9, 2>), dim3(w.blocks), dim3(TILE_BS), 0, s, a); break;
-            case 103: hipLaunchKernelGGL((cg_tile_kernel<9, 3>), dim3(w.blocks), dim3(TILE_BS), 0, s, a); break;
-            default: hipLaunchKernelGGL(cg_kernel, dim3(w.blocks), dim3(CG_THREADS), 0, s, a); break;
-        }
-        MISDC_HIP(hipGetLastError());
+        int rc = launch_cg(a, w.variant, w.blocks, s);
+        if (rc) return rc;
     }
     if (core_end) MISDC_HIP(hipEventRecord(core_end, s));
     hipLaunchKernelGGL(closure_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, n, rhs, y);
