@@ -482,38 +482,96 @@ __global__ void __launch_bounds__(BS) cg_regs_kernel(CGArgs a) {
 // and it replaces the diagonal preconditioner at the two places the
 // pipelined recurrence applies one (u = M^-1 r, m = M^-1 w).
 // ---------------------------------------------------------------------------
-constexpr int TILE_GROUP = 5;              // fields per LDS pass
+// Reduction of the partial sums (r,u), (w,u), (r,r) of every field over
+// the blocks, fused with the recurrence coefficients: the wavefront that
+// reduces a field's three sums computes its coefficients.  A field whose
+// residual has met the tolerance stays inactive (its sums are no longer
+// formed).  ``stage`` holds the blocks' partials after the grid barrier.
+template <int BS, int NFD>
+__device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned k, int it,
+                                                      const double* red, double* stage,
+                                                      const double* s_bb, double* s_gprev,
+                                                      double* s_aprev, double* s_alpha,
+                                                      double* s_beta, int* s_active) {
+    constexpr int NW = BS / 64, NS = 3 * NFD;
+    const unsigned nb = gridDim.x;
+    double* part = a.partial + (size_t)(k & 1u) * CG_MAX_BLOCKS * (CG_MAX_FIELDS * 4);
+    __syncthreads();
+    for (int t = threadIdx.x; t < NS; t += BS) {
+        double v = 0.0;
+        for (int w = 0; w < NW; ++w) v += red[t * NW + w];
+        part[(size_t)blockIdx.x * (CG_MAX_FIELDS * 4) + t] = v;
+    }
+    grid_sync(a.bar, nb, k, a.info);
+    const int total = (int)nb * NS;
+    for (int e = threadIdx.x; e < total; e += BS) {
+        const int b = e / NS, t = e - b * NS;
+        stage[e] = part[(size_t)b * (CG_MAX_FIELDS * 4) + t];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int d = wave; d < NFD; d += NW) {
+        if (!s_active[d]) continue;                   // uniform over the wavefront
+        double g = 0.0, de = 0.0, rr = 0.0;
+        for (unsigned b = lane; b < nb; b += 64) {
+            g += stage[b * NS + 3 * d];
+            de += stage[b * NS + 3 * d + 1];
+            rr += stage[b * NS + 3 * d + 2];
+        }
+        g = wave_sum(g);
+        de = wave_sum(de);
+        rr = wave_sum(rr);
+        if (lane == 0) {
+            const int act = rr > a.rtol2 * s_bb[d];
+            double al = 0.0, be = 0.0;
+            if (act) {
+                if (it == 0) {
+                    al = g / de;
+                } else {
+                    be = g / s_gprev[d];
+                    al = g / (de - be * g / s_aprev[d]);
+                }
+                s_gprev[d] = g;
+                s_aprev[d] = al;
+            }
+            s_active[d] = act;
+            s_alpha[d] = al;
+            s_beta[d] = be;
+        }
+    }
+    __syncthreads();
+}
 
+// z = M^-1 v for the fields marked in ``live`` (others untouched); every
+// thread of the workgroup must call it (it synchronises)
 template <int NFD, int KSW>
 __device__ __forceinline__ void tile_precond(const double (&v)[NFD], double (&z)[NFD],
                                              const double (&dinv)[NFD], const double (&cf)[NFD],
                                              double ke, double kw, double kn, double ks,
-                                             bool he, bool hw, bool hn, bool hs, double* zt) {
+                                             bool he, bool hw, bool hn, bool hs, double* zt,
+                                             const int* live) {
     const int t = threadIdx.x;
 #pragma unroll
-    for (int d = 0; d < NFD; ++d) z[d] = dinv[d] * v[d];
+    for (int d = 0; d < NFD; ++d)
+        if (live[d]) z[d] = dinv[d] * v[d];
 #pragma unroll
     for (int sw = 0; sw < KSW; ++sw) {
 #pragma unroll
-        for (int g0 = 0; g0 < NFD; g0 += TILE_GROUP) {
+        for (int d = 0; d < NFD; ++d)
+            if (live[d]) zt[d * TILE_BS + t] = z[d];
+        __syncthreads();
 #pragma unroll
-            for (int d = g0; d < NFD && d < g0 + TILE_GROUP; ++d) zt[(d - g0) * TILE_BS + t] = z[d];
-            __syncthreads();
-            double zn[TILE_GROUP];
-#pragma unroll
-            for (int d = g0; d < NFD && d < g0 + TILE_GROUP; ++d) {
-                const double* Z = zt + (d - g0) * TILE_BS;
-                double nb = 0.0;
-                if (he) nb += ke * Z[t + 1];
-                if (hw) nb += kw * Z[t - 1];
-                if (hn) nb += kn * Z[t + TILE_X];
-                if (hs) nb += ks * Z[t - TILE_X];
-                zn[d - g0] = dinv[d] * (v[d] + cf[d] * nb);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int d = g0; d < NFD && d < g0 + TILE_GROUP; ++d) z[d] = zn[d - g0];
+        for (int d = 0; d < NFD; ++d) {
+            if (!live[d]) continue;
+            const double* Z = zt + d * TILE_BS;
+            double nb = 0.0;
+            if (he) nb += ke * Z[t + 1];
+            if (hw) nb += kw * Z[t - 1];
+            if (hn) nb += kn * Z[t + TILE_X];
+            if (hs) nb += ks * Z[t - TILE_X];
+            z[d] = dinv[d] * (v[d] + cf[d] * nb);
         }
+        __syncthreads();
     }
 }
 
@@ -521,12 +579,18 @@ template <int NFD, int KSW>
 __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
     constexpr int BS = TILE_BS;
     constexpr int NS = 3 * NFD;
-    __shared__ double stage[TILE_NB * NS];
+    // the preconditioner's tile and the reduction's staging area are used
+    // at different times: one buffer
+    constexpr int WORK = (TILE_NB * NS > NFD * TILE_BS) ? TILE_NB * NS : NFD * TILE_BS;
+    __shared__ double work[WORK];
+    double* const stage = work;
+    double* const zt = work;
     __shared__ double red[NS * (BS / 64)];
     __shared__ double tot[NS];
-    __shared__ double zt[TILE_GROUP * TILE_BS];
     __shared__ double s_bb[NFD], s_gprev[NFD], s_aprev[NFD], s_alpha[NFD], s_beta[NFD];
     __shared__ int s_active[NFD];
+    if (threadIdx.x < NFD) s_active[threadIdx.x] = 1;
+    __syncthreads();
     const int tx = threadIdx.x % TILE_X, ty = threadIdx.x / TILE_X;
     const int gx = (blockIdx.x % a.ntx) * TILE_X + tx, gy = (blockIdx.x / a.ntx) * TILE_Y + ty;
     const bool own = gx < a.nx && gy < a.ny;
@@ -565,7 +629,9 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
         }
         wave_put<BS>(bb, red, d);
     }
-    tile_precond<NFD, KSW>(r, u, dinv, cf, ke, kw, kn, ks, he, hw, hn, hs, zt);
+#pragma unroll
+    for (int d = 0; d < NFD; ++d) u[d] = 0.0;
+    tile_precond<NFD, KSW>(r, u, dinv, cf, ke, kw, kn, ks, he, hw, hn, hs, zt, s_active);
 #pragma unroll
     for (int d = 0; d < NFD; ++d)
         if (own) a.r[(size_t)a.fmap[d] * a.n + cell] = u[d];
@@ -586,36 +652,20 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
         // ---- m = M^-1 w (published), partials gamma = (r,u), delta = (w,u), rr ----
         double* Mbuf = (it & 1) ? a.q : a.z;
         double m[NFD];
-        tile_precond<NFD, KSW>(w, m, dinv, cf, ke, kw, kn, ks, he, hw, hn, hs, zt);
+#pragma unroll
+        for (int d = 0; d < NFD; ++d) m[d] = 0.0;
+        tile_precond<NFD, KSW>(w, m, dinv, cf, ke, kw, kn, ks, he, hw, hn, hs, zt, s_active);
 #pragma unroll
         for (int d = 0; d < NFD; ++d) {
+            if (!s_active[d]) continue;               // converged: nothing to reduce
             const size_t o = (size_t)a.fmap[d] * a.n;
             if (own) Mbuf[o + cell] = m[d];
             wave_put<BS>(own ? r[d] * u[d] : 0.0, red, 3 * d + 0);
             wave_put<BS>(own ? w[d] * u[d] : 0.0, red, 3 * d + 1);
             wave_put<BS>(own ? r[d] * r[d] : 0.0, red, 3 * d + 2);
         }
-        grid_allreduce<BS>(a, kb++, NS, red, stage, tot);
-        if (threadIdx.x < NFD) {
-            const int d = threadIdx.x;
-            const double g = tot[3 * d], de = tot[3 * d + 1], rr = tot[3 * d + 2];
-            const int act = rr > a.rtol2 * s_bb[d];
-            double al = 0.0, be = 0.0;
-            if (act) {
-                if (it == 0) {
-                    al = g / de;
-                } else {
-                    be = g / s_gprev[d];
-                    al = g / (de - be * g / s_aprev[d]);
-                }
-                s_gprev[d] = g;
-                s_aprev[d] = al;
-            }
-            s_active[d] = act;
-            s_alpha[d] = al;
-            s_beta[d] = be;
-        }
-        __syncthreads();
+        grid_allreduce_coeffs<BS, NFD>(a, kb++, it, red, stage, s_bb, s_gprev, s_aprev, s_alpha,
+                                       s_beta, s_active);
         int any = 0;
 #pragma unroll
         for (int d = 0; d < NFD; ++d) any |= s_active[d];
@@ -626,7 +676,7 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
             const double* Mv = Mbuf + (size_t)a.fmap[d] * a.n;
             const bool act = s_active[d];
             const double al = s_alpha[d], be = s_beta[d];
-            if (!own) continue;
+            if (!own || !act) continue;
             const double mi = m[d];
             const double ni = mi - cf[d] * (ke * (Mv[ie] - mi) - kw * (mi - Mv[iw]) +
                                             kn * (Mv[in_] - mi) - ks * (mi - Mv[is_]));

@@ -283,8 +283,6 @@ int eval_ops(misdc_integ_s* I, const NodeBuf& b, double* th, hipStream_t s, bool
     return MISDC_OK;
 }
 
-int accum_cg(misdc_integ_s* I, hipStream_t s);
-
 hipEvent_t pool_event(misdc_integ_s* I) {
     if (!I->ev_pool.empty()) {
         hipEvent_t e = I->ev_pool.back();
@@ -372,30 +370,29 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
         b.addS(o, cf, Lp[p].FR, N);
         T_lag = (ell == 0) ? L0[p].T : Lp[p].T;
     }
-    int rc = launch_lincomb(b.lc, I->sD);
-    if (rc) return rc;
-    // initial guess of the iterative solve: the lagged state at this node
+    // initial guess of the iterative solve, the lagged state at this node,
+    // copied into the solution array by the same kernel
     const double* guess = (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell > 0) ? Lp[p].phi : L0[p].phi;
-    rc = launch_copy(I->phiAD[p], guess, (int64_t)NF * n, I->sD);
+    const int og = b.out(I->phiAD[p]);
+    b.add(og, 1.0, guess, NF);
+    // the same pass computes the face coefficients of the lagged operator
+    int rc = launch_lincomb_faces(b.lc, *I->grid, T_lag, I->dw, I->sD);
     if (rc) return rc;
     // with profiling, the events bracket the solve kernel itself (CG or cyclic)
     const bool timed = I->opt.profile && !I->capturing;
     hipEvent_t t0 = timed ? pool_event(I) : nullptr;
     hipEvent_t t1 = timed ? pool_event(I) : nullptr;
+    const bool lag_init = (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell == 0);
     rc = launch_diffusion_solve(*I->mech, *I->grid, I->dw, dt * cf, I->dtf, cf, T_lag, I->rD,
-                                I->phiAD[p], 1, I->opt.cg_rtol, I->opt.cg_maxit, I->sD, t0, t1);
+                                I->phiAD[p], 1, I->opt.cg_rtol, I->opt.cg_maxit, I->sD, t0, t1,
+                                I->TAD[p], I->cgstats, lag_init ? I->thD : nullptr, true);
     if (rc) return rc;
     if (t0 && t1) I->timed.push_back({t0, t1, 0});
-    if (I->grid->dim == 2 && I->grid->n_flames == 0) {
-        rc = accum_cg(I, I->sD);
-        if (rc) return rc;
-    }
-    rc = launch_state_temperature(*I->mech, n, I->phiAD[p], I->TAD[p], I->sD);
-    if (rc) return rc;
-    if (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell == 0) {
+    if (lag_init) {
         // lag initialisation (initial_lagged_values_A/D): FA, FD at phi_AD^{p,(k+1,1)}
+        // (theta of T(phi_AD) written by the solve's closure)
         rc = launch_transport(*I->mech, *I->grid, I->phiAD[p], I->TAD[p], I->hatA[p], I->hatD[p],
-                              I->thD, I->sD);
+                              I->thD, I->sD, true);
         if (rc) return rc;
     }
     (void)M;
@@ -483,21 +480,6 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     rc = eval_ops(I, out, I->thR, I->sR, false);
     (void)NF;
     return rc;
-}
-
-__global__ void cg_accum_kernel(int32_t* info, int32_t* st) {
-    st[0] += info[0];
-    st[1] = info[0] > st[1] ? info[0] : st[1];
-    st[2] += info[1];
-    st[3] += 1;
-    st[4] += info[2];
-    info[2] = 0;
-}
-
-int accum_cg(misdc_integ_s* I, hipStream_t s) {
-    hipLaunchKernelGGL(cg_accum_kernel, dim3(1), dim3(1), 0, s, I->dw.info, I->cgstats);
-    MISDC_HIP(hipGetLastError());
-    return MISDC_OK;
 }
 
 // sweep-start constants (all terms of sweep k)

@@ -136,8 +136,10 @@ int launch_expand_flames(const Grid& g, const double* v, double* out, hipStream_
 // T (cells) from a state with N+1 fields
 int launch_state_temperature(const Mech& m, int64_t n, const double* state, double* T, hipStream_t s);
 // FA and FD (N+1 fields) at a state whose temperature is T; either output may be null
+// (theta_ready: work_theta already holds (T/300)^1.7)
 int launch_transport(const Mech& m, const Grid& g, const double* state, const double* T,
-                     double* FA, double* FD, double* work_theta, hipStream_t s);
+                     double* FA, double* FD, double* work_theta, hipStream_t s,
+                     bool theta_ready = false);
 
 struct DiffusionWork {
     double* theta = nullptr;      // cells
@@ -168,12 +170,21 @@ int64_t cg_regs_min_blocks(int64_t n, int cpt);
 int64_t cg_tile_blocks(const Grid& g);
 int device_cus(int& cus);
 void diffusion_work_free(DiffusionWork& w);
-// Solves all N+1 fields (bath by closure); y may hold the guess (guess_in_y)
+// Solves all N+1 fields (bath by closure); y may hold the guess (guess_in_y);
+// T_out (optional) receives T(y) and th_out (optional, with T_out) its
+// (T/300)^1.7; cgstats (optional, 2-D solves) accumulates the CG statistics
 int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, double c,
                            const double* dt_flame, double c_factor,
                            const double* T_lag, const double* rhs, double* y, int guess_in_y,
                            double rtol, int maxit, hipStream_t s,
-                           hipEvent_t core_begin = nullptr, hipEvent_t core_end = nullptr);
+                           hipEvent_t core_begin = nullptr, hipEvent_t core_end = nullptr,
+                           double* T_out = nullptr, int32_t* cgstats = nullptr,
+                           double* th_out = nullptr, bool faces_ready = false);
+// right-hand side (a linear combination over the grid's cells) together with
+// the face coefficients of the lagged operator at T_lag, for a solve called
+// with faces_ready
+int launch_lincomb_faces(const LinComb& lc, const Grid& g, const double* T_lag, DiffusionWork& w,
+                         hipStream_t s);
 
 // max_i |a - b| and max_i |a| per field into out[2*f], out[2*f+1] (device)
 int launch_field_diff_max(int nfields, int64_t n, const double* a, const double* b,

@@ -186,14 +186,8 @@ __global__ void __launch_bounds__(256) transport_kernel(GridDev g, MechDev m, in
 
 // face coefficients of the lagged operator: Kx[i] = east face / dx^2, Ky[i] =
 // north face / dy^2, both from theta = (T_lag/300)^1.7.
-__global__ void __launch_bounds__(256) faces_kernel(GridDev g, int64_t n, const double* T,
-                                                    double* th, double* Kx, double* Ky,
-                                                    unsigned* bar) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // the persistent CG kernel that follows on this stream counts its grid
-    // barriers from zero
-    if (i == 0 && bar) { bar[0] = 0u; bar[1] = 0u; }
-    if (i >= n) return;
+__device__ __forceinline__ void faces_at(const GridDev& g, int64_t i, const double* T, double* th,
+                                         double* Kx, double* Ky) {
     const Row r = row_of(g, i);
     const int64_t xp1 = r.base + wrap(r.pos + 1, r.len);
     const double t0 = pow(T[i] / T_DIFF_REF, THETA_EXP);
@@ -205,6 +199,46 @@ __global__ void __launch_bounds__(256) faces_kernel(GridDev g, int64_t n, const 
         const int64_t yp1 = wrap(iy + 1, g.ny) * g.nx + ix;
         const double t2 = pow(T[yp1] / T_DIFF_REF, THETA_EXP);
         Ky[i] = 0.5 * (t0 + t2) / (g.dy * g.dy);
+    }
+}
+
+__global__ void __launch_bounds__(256) faces_kernel(GridDev g, int64_t n, const double* T,
+                                                    double* th, double* Kx, double* Ky,
+                                                    unsigned* bar) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the persistent CG kernel that follows on this stream counts its grid
+    // barriers from zero
+    if (i == 0 && bar) { bar[0] = 0u; bar[1] = 0u; }
+    if (i >= n) return;
+    faces_at(g, i, T, th, Kx, Ky);
+}
+
+// The right-hand side of a diffusion solve and, in the same pass, the face
+// coefficients of its lagged operator (cells are the elements of field 0).
+__global__ void __launch_bounds__(256) lincomb_faces_kernel(LinComb lc, GridDev g, const double* T,
+                                                            double* th, double* Kx, double* Ky,
+                                                            unsigned* bar) {
+    const int64_t total = (int64_t)lc.nfields * lc.ncells;
+    const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e0 == 0 && bar) { bar[0] = 0u; bar[1] = 0u; }
+    for (int64_t e = e0; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int f = (int)(e / lc.ncells);
+        if (f == 0) faces_at(g, e, T, th, Kx, Ky);
+        double acc[LC_MAX_OUT];
+#pragma unroll
+        for (int p = 0; p < LC_MAX_OUT; ++p) acc[p] = 0.0;
+        const double sc = lc.smask ? lc.scale[e - (int64_t)f * lc.ncells] : 1.0;
+        for (int t = 0; t < lc.nterms; ++t) {
+            if (f >= lc.nf[t]) continue;
+            double v = lc.X[t][e];
+            if ((lc.smask >> t) & 1u) v *= sc;
+#pragma unroll
+            for (int p = 0; p < LC_MAX_OUT; ++p)
+                if (p < lc.nout) acc[p] += lc.W[p][t] * v;
+        }
+#pragma unroll
+        for (int p = 0; p < LC_MAX_OUT; ++p)
+            if (p < lc.nout) lc.out[p][e] = acc[p];
     }
 }
 
@@ -404,13 +438,36 @@ __global__ void __launch_bounds__(64) cyclic_wave_kernel(GridDev g, MechDev m, i
 
 // bath closure y_i0 = r_i0 - sum_{k != i0, k < N} (y_k - r_k)
 __global__ void __launch_bounds__(256) closure_kernel(MechDev m, int64_t n, const double* rhs,
-                                                      double* y) {
+                                                      double* y, double* T_out, double* th_out,
+                                                      int32_t* info, int32_t* cgstats) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && cgstats) {
+        // accumulate the statistics of the CG solve that preceded on this
+        // stream: [0] iterations, [1] max, [2] failures, [3] solves, [4] timeouts
+        cgstats[0] += info[0];
+        cgstats[1] = info[0] > cgstats[1] ? info[0] : cgstats[1];
+        cgstats[2] += info[1];
+        cgstats[3] += 1;
+        cgstats[4] += info[2];
+        info[2] = 0;
+    }
     if (i >= n) return;
     double s = 0.0;
     for (int k = 0; k < m.N; ++k)
         if (k != m.bath) s += y[(size_t)k * n + i] - rhs[(size_t)k * n + i];
     y[(size_t)m.bath * n + i] = rhs[(size_t)m.bath * n + i] - s;
+    if (T_out) {
+        // temperature of the solved state, closed form for constant cp
+        double hform = 0.0, cpm = 0.0;
+        for (int k = 0; k < m.N; ++k) {
+            const double yk = y[(size_t)k * n + i];
+            hform += yk * m.hf[k] * m.invW[k];
+            cpm += yk * m.cp[k] * m.invW[k];
+        }
+        const double Ti = T_REF + (y[(size_t)m.N * n + i] - hform) / cpm;
+        T_out[i] = Ti;
+        if (th_out) th_out[i] = pow(Ti / T_DIFF_REF, THETA_EXP);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -506,6 +563,23 @@ int launch_expand_flames(const Grid& g, const double* v, double* out, hipStream_
     return MISDC_OK;
 }
 
+int launch_lincomb_faces(const LinComb& lc, const Grid& g, const double* T_lag, DiffusionWork& w,
+                         hipStream_t s) {
+    const int64_t total = (int64_t)lc.nfields * lc.ncells;
+    if (total == 0) return MISDC_OK;
+    if (lc.nterms > LC_MAX_TERMS || lc.nout > LC_MAX_OUT || lc.nout < 1)
+        return fail(MISDC_EINVAL, "linear combination too large (%d terms, %d outputs)", lc.nterms,
+                    lc.nout);
+    if (lc.smask && !lc.scale) return fail(MISDC_EINVAL, "scaled terms without a scale array");
+    if (lc.ncells != g.cells()) return fail(MISDC_EINVAL, "linear combination and grid differ");
+    unsigned blocks = grid_for(total, 256);
+    if (blocks > 65536u) blocks = 65536u;
+    hipLaunchKernelGGL(lincomb_faces_kernel, dim3(blocks), dim3(256), 0, s, lc, grid_dev(g), T_lag,
+                       w.theta, w.Kx, w.Ky, w.barrier);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
 int launch_lincomb(const LinComb& lc, hipStream_t s) {
     const int64_t total = (int64_t)lc.nfields * lc.ncells;
     if (total == 0) return MISDC_OK;
@@ -521,11 +595,13 @@ int launch_lincomb(const LinComb& lc, hipStream_t s) {
 }
 
 int launch_transport(const Mech& m, const Grid& g, const double* state, const double* T,
-                     double* FA, double* FD, double* work_theta, hipStream_t s) {
+                     double* FA, double* FD, double* work_theta, hipStream_t s, bool theta_ready) {
     const int64_t n = g.cells();
     if (n == 0) return MISDC_OK;
-    hipLaunchKernelGGL(theta_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, n, T, work_theta);
-    MISDC_HIP(hipGetLastError());
+    if (!theta_ready) {
+        hipLaunchKernelGGL(theta_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, n, T, work_theta);
+        MISDC_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(transport_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, grid_dev(g),
                        m.dev, n, state, work_theta, FA, FD);
     MISDC_HIP(hipGetLastError());
@@ -608,13 +684,16 @@ void diffusion_work_free(DiffusionWork& w) {
 int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, double c,
                            const double* dt_flame, double c_factor, const double* T_lag,
                            const double* rhs, double* y, int guess_in_y, double rtol, int maxit,
-                           hipStream_t s, hipEvent_t core_begin, hipEvent_t core_end) {
+                           hipStream_t s, hipEvent_t core_begin, hipEvent_t core_end,
+                           double* T_out, int32_t* cgstats, double* th_out, bool faces_ready) {
     const int64_t n = g.cells();
     if (n == 0) return MISDC_OK;
     const GridDev gd = grid_dev(g);
-    hipLaunchKernelGGL(faces_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, gd, n, T_lag,
-                       w.theta, w.Kx, w.Ky, w.barrier);
-    MISDC_HIP(hipGetLastError());
+    if (!faces_ready) {
+        hipLaunchKernelGGL(faces_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, gd, n, T_lag,
+                           w.theta, w.Kx, w.Ky, w.barrier);
+        MISDC_HIP(hipGetLastError());
+    }
     if (core_begin) MISDC_HIP(hipEventRecord(core_begin, s));
     const int NF = m.dev.N + 1;
     if (g.dim == 1 || g.n_flames > 0) {
@@ -659,7 +738,9 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
         if (rc) return rc;
     }
     if (core_end) MISDC_HIP(hipEventRecord(core_end, s));
-    hipLaunchKernelGGL(closure_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, n, rhs, y);
+    const bool cg2d = !(g.dim == 1 || g.n_flames > 0);
+    hipLaunchKernelGGL(closure_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, n, rhs, y,
+                       T_out, T_out ? th_out : nullptr, w.info, cg2d ? cgstats : nullptr);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;
 }
