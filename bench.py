@@ -125,7 +125,8 @@ def graph_leg(integ, mh, g, cfg, state, args, tune):
     gi = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
                     scheme=cfg["scheme"], use_graph=True)
     if tune:
-        gi.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"])
+        gi.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"],
+                    tune["cu_split"], tune["stagger"])
     st = state.clone()
     for _ in range(max(1, args.warmup)):
         gi.step(st, cfg["dt"])
@@ -176,7 +177,8 @@ def ensemble_main(args):
         if tune is None and not args.no_autotune:
             tune = integ.autotune(state, 0.0, dt_per_flame=d_dt, reps=3)
         elif tune is not None:
-            integ.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"])
+            integ.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"],
+                           tune["cu_split"], tune["stagger"])
         st = state.clone()
         for _ in range(max(1, args.warmup)):
             integ.step(st, 0.0, dt_per_flame=d_dt)

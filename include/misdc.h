@@ -290,6 +290,15 @@ typedef struct {
     int32_t cyclic;       /* 1-D diffusion: 0 one thread per periodic system,
                              1 one wavefront per system (partition method) */
     int32_t serialize;    /* 1: both tasks on one stream */
+    int32_t cu_split;     /* two streams only: 0 both streams on every CU;
+                             1..3 the reaction stream limited to that many
+                             quarters of each XCD's CUs (a CU-masked stream),
+                             the diffusion stream on all CUs */
+    int32_t stagger;      /* two streams, CISDCQ only: 1 the Newton solve of
+                             node m waits until the diffusion solve of node
+                             m+1 is next on its stream, so that the persistent
+                             CG takes its CUs first (a start-order dependency:
+                             results are unchanged) */
     double step_ms;       /* measured by misdc_autotune: mean time of one step */
 } misdc_tune;
 
@@ -299,12 +308,16 @@ typedef struct {
  * *best.  Candidates: for 2-D grids every register-resident CG variant that
  * fits, the tiled variants when the grid has at most 128 tiles, and the
  * global-memory variant with 1/4, 1/2 and all of the CUs; for
- * 1-D grids and ensembles both cyclic solvers; each with one and two
- * streams.  Synchronises; allocates a state copy.  Errors as misdc_step. */
+ * 1-D grids and ensembles both cyclic solvers; each with one stream, and
+ * with two streams with the reaction stream on all, 3/4 or 1/2 of the CUs
+ * (staggered or not on all and on 3/4).
+ * Synchronises; allocates a state copy.  Errors as misdc_step. */
 int misdc_autotune(misdc_integ_t integ, const double* dev_state, double dt,
                    const double* dev_dt, int reps, misdc_tune* best, void* stream);
 /* Reads / sets the launch configuration (set: MISDC_EINVAL if the CG
- * variant cannot hold the grid or the block count exceeds the CUs). */
+ * variant cannot hold the grid, the block count exceeds the CUs or cu_split
+ * is outside [0, 3], stagger is not 0 or 1, or the CU count is not a multiple of 32; MISDC_EDEVICE if
+ * the runtime does not apply the CU mask). */
 int misdc_get_tune(misdc_integ_t integ, misdc_tune* tune);
 int misdc_set_tune(misdc_integ_t integ, const misdc_tune* tune);
 

@@ -70,8 +70,11 @@ struct misdc_integ_s {
     Tables tab;
     int M = 0, N = 0, NF = 0, nu = 1, levels = 2;
     int64_t n = 0;
-    hipStream_t sD = nullptr, sR = nullptr;       // sR is sR2, or sD when serialised
+    hipStream_t sD = nullptr, sR = nullptr;       // sR is sR2 (or sRm), or sD when serialised
     hipStream_t sR2 = nullptr;
+    hipStream_t sRm = nullptr;                    // reaction stream on part of the CUs
+    int cu_split = 0, sRm_split = 0;              // quarters of the CUs given to sRm
+    int stagger = 0;                              // Newton waits for the next CG's start
     std::vector<std::vector<NodeBuf>> lev;        // [levels][M+1]
     std::vector<double*> phiAD, TAD, hatA, hatD;  // [M+1]
     std::vector<double*> C, CR;                   // [M+1] sweep constants (diffusion, reaction)
@@ -89,6 +92,7 @@ struct misdc_integ_s {
     DiffusionWork dw;
     std::vector<void*> allocs;
     std::vector<hipEvent_t> evD, evR;             // [(levels) x (M+1)]
+    std::vector<hipEvent_t> evC;                  // diffusion task's solve about to start
     hipEvent_t ev_in = nullptr, ev_outD = nullptr, ev_outR = nullptr;
     int last_sweeps = 0;
     int sweep_index = 0;                          // sweep being issued within the step
@@ -122,6 +126,7 @@ struct misdc_integ_s {
 
     hipEvent_t& D_ev(int l, int p) { return evD[(size_t)l * (M + 1) + p]; }
     hipEvent_t& R_ev(int l, int p) { return evR[(size_t)l * (M + 1) + p]; }
+    hipEvent_t& C_ev(int l, int p) { return evC[(size_t)l * (M + 1) + p]; }
 };
 
 namespace {
@@ -378,6 +383,8 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     // the same pass computes the face coefficients of the lagged operator
     int rc = launch_lincomb_faces(b.lc, *I->grid, T_lag, I->dw, I->sD);
     if (rc) return rc;
+    // the solve is next on this stream: a staggered reaction task waits for this
+    if (I->stagger && I->sR != I->sD) MISDC_HIP(hipEventRecord(I->C_ev(ell + 1, p), I->sD));
     // with profiling, the events bracket the solve kernel itself (CG or cyclic)
     const bool timed = I->opt.profile && !I->capturing;
     hipEvent_t t0 = timed ? pool_event(I) : nullptr;
@@ -464,6 +471,12 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     a.lu_info = (I->opt.newton.lu == MISDC_LU_FP32_MFMA) ? I->lu_info : nullptr;
     a.stats = I->nstats;
     a.opt = I->opt.newton;
+    // staggered: the Newton solve of node p starts once the diffusion solve
+    // of node p+1 (issued just before this task) is about to start, so that
+    // the persistent solve's workgroups take their CUs before the Newton
+    // waves fill the device
+    if (I->stagger && I->sR != I->sD && I->opt.scheme == MISDC_SCHEME_CISDCQ && p < I->M)
+        MISDC_HIP(hipStreamWaitEvent(I->sR, I->C_ev(ell + 1, p + 1), 0));
     hipEvent_t t0 = timing_begin(I, I->sR);
     rc = launch_reaction_newton(*I->mech, a, I->sR);
     if (rc) return rc;
@@ -1077,9 +1090,11 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     const size_t nev = (size_t)I->levels * (M + 1);
     I->evD.assign(nev, nullptr);
     I->evR.assign(nev, nullptr);
+    I->evC.assign(nev, nullptr);
     for (size_t k = 0; k < nev && e == hipSuccess; ++k) {
         e = hipEventCreateWithFlags(&I->evD[k], hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->evR[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->evC[k], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_outD, hipEventDisableTiming);
@@ -1095,10 +1110,13 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (!I) return MISDC_OK;
     if (I->sD) (void)hipStreamSynchronize(I->sD);
     if (I->sR2) (void)hipStreamSynchronize(I->sR2);
+    if (I->sRm) (void)hipStreamSynchronize(I->sRm);
     if (I->gexec) (void)hipGraphExecDestroy(I->gexec);
     for (hipEvent_t ev : I->evD)
         if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : I->evR)
+        if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : I->evC)
         if (ev) (void)hipEventDestroy(ev);
     for (auto& t : I->timed) {
         (void)hipEventDestroy(t.a);
@@ -1111,6 +1129,7 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (I->ev_fork) (void)hipEventDestroy(I->ev_fork);
     if (I->ev_join) (void)hipEventDestroy(I->ev_join);
     if (I->sR2) (void)hipStreamDestroy(I->sR2);
+    if (I->sRm) (void)hipStreamDestroy(I->sRm);
     if (I->sD) (void)hipStreamDestroy(I->sD);
     diffusion_work_free(I->dw);
     for (void* p : I->allocs) (void)hipFree(p);
@@ -1164,6 +1183,7 @@ int misdc_integ_set_guess(misdc_integ_t I, misdc_mlp_t mlp, int sweeps) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
     if (sweeps < 0) return fail(MISDC_EINVAL, "sweeps must be >= 0");
     MISDC_HIP(hipStreamSynchronize(I->sD));
+    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
     MISDC_HIP(hipStreamSynchronize(I->sR2));
     if (mlp) {
         if (mlp_dims(mlp->p, 0) != I->N + 2 || mlp_dims(mlp->p, 3) != I->N + 1)
@@ -1182,6 +1202,7 @@ int misdc_integ_record(misdc_integ_t I, double* dev_buf, int64_t max_tasks) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
     if (max_tasks < 0 || (max_tasks > 0 && !dev_buf)) return fail(MISDC_EINVAL, "invalid buffer");
     MISDC_HIP(hipStreamSynchronize(I->sD));
+    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
     MISDC_HIP(hipStreamSynchronize(I->sR2));
     I->rec_buf = max_tasks > 0 ? dev_buf : nullptr;
     I->rec_cap = max_tasks;
@@ -1196,12 +1217,51 @@ int misdc_integ_recorded(misdc_integ_t I, int64_t* tasks) {
     return MISDC_OK;
 }
 
+// The reaction stream can be confined to part of the CUs, so that the
+// persistent diffusion solve, whose workgroups must all be resident at once,
+// finds CUs free of Newton waves when it starts instead of waiting for them
+// to drain.  Mask bit i is set when (i / 8) mod 4 < quarters.  The driver
+// hands mask bits to the XCDs either round-robin (bit i to XCD i mod 8) or in
+// runs of 32 consecutive bits; either way every XCD keeps quarters/4 of its
+// CUs, so each XCD can run its share of a launch's workgroups.  The diffusion
+// stream is never masked.  The mask read back from the runtime must equal the
+// one requested.
+int reaction_stream_split(misdc_integ_s* I, int quarters) {
+    if (quarters == 0 || (I->sRm && I->sRm_split == quarters)) return MISDC_OK;
+    int cus = 0;
+    int rc = device_cus(cus);
+    if (rc) return rc;
+    if (cus < 32 || cus % 32)
+        return fail(MISDC_EINVAL, "cu_split needs a multiple of 32 CUs (device has %d)", cus);
+    const size_t words = (size_t)cus / 32;
+    std::vector<uint32_t> mask(words, 0u), back(words, 0u);
+    for (int i = 0; i < cus; ++i)
+        if ((i / 8) % 4 < quarters) mask[(size_t)i / 32] |= 1u << (i % 32);
+    hipStream_t s = nullptr;
+    MISDC_HIP(hipExtStreamCreateWithCUMask(&s, (uint32_t)words, mask.data()));
+    hipError_t e = hipExtStreamGetCUMask(s, (uint32_t)words, back.data());
+    if (e != hipSuccess || back != mask) {
+        (void)hipStreamDestroy(s);
+        return fail(MISDC_EDEVICE, "CU mask of the reaction stream not applied (%s)",
+                    e != hipSuccess ? hipGetErrorString(e) : "mask differs");
+    }
+    if (I->sRm) {
+        (void)hipStreamSynchronize(I->sRm);
+        (void)hipStreamDestroy(I->sRm);
+    }
+    I->sRm = s;
+    I->sRm_split = quarters;
+    return MISDC_OK;
+}
+
 int misdc_get_tune(misdc_integ_t I, misdc_tune* t) {
     if (!I || !t) return fail(MISDC_EINVAL, "NULL argument");
     t->cg_variant = I->dw.variant;
     t->cg_blocks = I->dw.blocks;
     t->cyclic = I->dw.cyclic;
     t->serialize = I->sR == I->sD ? 1 : 0;
+    t->cu_split = I->cu_split;
+    t->stagger = I->stagger;
     t->step_ms = I->tuned_ms;
     return MISDC_OK;
 }
@@ -1210,8 +1270,11 @@ int misdc_set_tune(misdc_integ_t I, const misdc_tune* t) {
     if (!I || !t) return fail(MISDC_EINVAL, "NULL argument");
     if (t->cyclic != 0 && t->cyclic != 1) return fail(MISDC_EINVAL, "cyclic must be 0 or 1");
     if (t->serialize != 0 && t->serialize != 1) return fail(MISDC_EINVAL, "serialize must be 0 or 1");
+    if (t->cu_split < 0 || t->cu_split > 3) return fail(MISDC_EINVAL, "cu_split must be in [0, 3]");
+    if (t->stagger != 0 && t->stagger != 1) return fail(MISDC_EINVAL, "stagger must be 0 or 1");
     const Grid& g = *I->grid;
     MISDC_HIP(hipStreamSynchronize(I->sD));
+    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
     MISDC_HIP(hipStreamSynchronize(I->sR2));
     if (g.dim == 2 && g.n_flames == 0) {
         DiffusionWork probe = I->dw;
@@ -1220,8 +1283,14 @@ int misdc_set_tune(misdc_integ_t I, const misdc_tune* t) {
         I->dw.variant = probe.variant;
         I->dw.blocks = probe.blocks;
     }
+    if (!t->serialize && t->cu_split) {
+        int rc = reaction_stream_split(I, t->cu_split);
+        if (rc) return rc;
+    }
     I->dw.cyclic = t->cyclic;
-    I->sR = t->serialize ? I->sD : I->sR2;
+    I->cu_split = t->serialize ? 0 : t->cu_split;
+    I->stagger = t->serialize ? 0 : t->stagger;
+    I->sR = t->serialize ? I->sD : (I->cu_split ? I->sRm : I->sR2);
     drop_graph(I);
     return MISDC_OK;
 }
@@ -1238,9 +1307,15 @@ int misdc_autotune(misdc_integ_t I, const double* state, double dt, const double
     std::vector<misdc_tune> cand;
     misdc_tune base;
     misdc_get_tune(I, &base);
-    for (int ser = 0; ser <= 1; ++ser) {
+    for (int k = 0; k < 6; ++k) {
+        // (serialize, cu_split, stagger): two streams on all CUs, staggered
+        // or not; the reaction stream on 3/4 or 1/2 of the CUs; one stream
+        static const int SER[6] = {0, 0, 0, 0, 0, 1}, SPLIT[6] = {0, 0, 3, 3, 2, 0},
+                         STAG[6] = {0, 1, 0, 1, 0, 0};
         misdc_tune t = base;
-        t.serialize = ser;
+        t.serialize = SER[k];
+        t.cu_split = SPLIT[k];
+        t.stagger = STAG[k];
         if (g.dim == 2 && g.n_flames == 0) {
             const int cap = cus < 256 ? cus : 256;
             if (I->N == 9)
@@ -1317,6 +1392,7 @@ int misdc_autotune(misdc_integ_t I, const double* state, double dt, const double
 int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
     if (!I || !st) return fail(MISDC_EINVAL, "NULL argument");
     MISDC_HIP(hipStreamSynchronize(I->sD));
+    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
     MISDC_HIP(hipStreamSynchronize(I->sR2));
     std::memset(st, 0, sizeof(*st));
     unsigned long long ns[8];
@@ -1361,6 +1437,7 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
 int misdc_reset_profile(misdc_integ_t I) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
     MISDC_HIP(hipStreamSynchronize(I->sD));
+    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
     MISDC_HIP(hipStreamSynchronize(I->sR2));
     int rc = drain_timing(I);
     if (rc) return rc;

@@ -101,8 +101,9 @@ class Integrator:
     def tune(self):
         return nat.misdc_get_tune(self.handle)
 
-    def set_tune(self, cg_variant, cg_blocks, cyclic, serialize):
-        nat.misdc_set_tune(self.handle, cg_variant, cg_blocks, cyclic, serialize)
+    def set_tune(self, cg_variant, cg_blocks, cyclic, serialize, cu_split=0, stagger=0):
+        nat.misdc_set_tune(self.handle, cg_variant, cg_blocks, cyclic, serialize, cu_split,
+                           stagger)
 
     def stats(self):
         return nat.misdc_get_stats(self.handle)

@@ -290,10 +290,11 @@ def test_autotune_and_set_tune(nat, mech9, mh):
     tune = integ.autotune(st0, 5e-5, reps=1)
     assert np.array_equal(host(st0), ref_in)
     assert tune["cg_variant"] in (0, 1, 2, 4, 101, 102, 103) and tune["cg_blocks"] >= 1
+    assert tune["cu_split"] in (0, 2, 3) and not (tune["serialize"] and tune["cu_split"])
     assert integ.tune()["cg_variant"] == tune["cg_variant"]
     outs = []
     for cfg in ((tune["cg_variant"], tune["cg_blocks"], 1, tune["serialize"]), (0, 32, 1, 1),
-                (1, 8, 1, 0)):
+                (1, 8, 1, 0), (1, 8, 1, 0, 3)):
         integ.set_tune(*cfg)
         st = st0.clone()
         integ.step(st, 5e-5)

@@ -269,6 +269,25 @@ def test_concurrent_equals_serialized_bitwise(nat, mech9, mh):
                               n_nodes=5, sweeps=3, nu=2, scheme="cisdcq", serialize=ser)
         outs.append(out)
     assert np.array_equal(outs[0], outs[1])
+    # the reaction stream on half of the CUs (a CU-masked stream), and the
+    # Newton solves started after the next diffusion solve
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    g = Grid(2, [40, 32], [0.01, 0.01], [100.0, 0.0])
+    integ = Integrator(mh, g, n_nodes=5, sweeps=3, nu=2, scheme="cisdcq")
+    t = integ.tune()
+    for split, stagger in ((2, 0), (0, 1), (3, 1)):
+        integ.set_tune(t["cg_variant"], t["cg_blocks"], t["cyclic"], 0, split, stagger)
+        got = integ.tune()
+        assert (got["cu_split"], got["stagger"], got["serialize"]) == (split, stagger, 0)
+        st = _gpu_initial(nat, mh, Y, T)
+        integ.step(st, 5e-5)
+        assert np.array_equal(outs[0], host(st)), (split, stagger)
+    with pytest.raises(nat.MisdcError):
+        integ.set_tune(t["cg_variant"], t["cg_blocks"], t["cyclic"], 0, 4)
+    with pytest.raises(nat.MisdcError):
+        integ.set_tune(t["cg_variant"], t["cg_blocks"], t["cyclic"], 0, 0, 2)
+    integ.close()
+    g.close()
 
 
 def test_full_size_step_properties(nat, mech9, mh):
