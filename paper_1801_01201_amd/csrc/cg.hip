@@ -482,18 +482,58 @@ __global__ void __launch_bounds__(BS) cg_regs_kernel(CGArgs a) {
 // and it replaces the diagonal preconditioner at the two places the
 // pipelined recurrence applies one (u = M^-1 r, m = M^-1 w).
 // ---------------------------------------------------------------------------
+// Halo of a tile: the cells next to its four sides (periodic wrap),
+// TILE_HALO slots per field: [0, TX) the row above (+y), [TX, 2 TX) the row
+// below, then TY slots for the column to the right (+x) and TY for the column
+// to the left.  Slots beyond a ragged tile's width or height are unused.
+constexpr int TILE_HALO = 2 * TILE_X + 2 * TILE_Y;
+
+// Cell of halo slot s of the tile with origin (x0, y0) and extent wt x ht
+// (-1 when the slot is unused).
+__device__ __forceinline__ int64_t halo_cell(const CGArgs& a, int x0, int y0, int wt, int ht,
+                                             int s) {
+    int x, y;
+    if (s < TILE_X) {
+        if (s >= wt) return -1;
+        x = x0 + s;
+        y = (y0 + ht) % a.ny;
+    } else if (s < 2 * TILE_X) {
+        s -= TILE_X;
+        if (s >= wt) return -1;
+        x = x0 + s;
+        y = (y0 - 1 + a.ny) % a.ny;
+    } else if (s < 2 * TILE_X + TILE_Y) {
+        s -= 2 * TILE_X;
+        if (s >= ht) return -1;
+        y = y0 + s;
+        x = (x0 + wt) % a.nx;
+    } else {
+        s -= 2 * TILE_X + TILE_Y;
+        if (s >= ht) return -1;
+        y = y0 + s;
+        x = (x0 - 1 + a.nx) % a.nx;
+    }
+    return (int64_t)y * a.nx + x;
+}
+
 // Reduction of the partial sums (r,u), (w,u), (r,r) of every field over
 // the blocks, fused with the recurrence coefficients: the wavefront that
 // reduces a field's three sums computes its coefficients.  A field whose
 // residual has met the tolerance stays inactive (its sums are no longer
-// formed).  ``stage`` holds the blocks' partials after the grid barrier.
-template <int BS, int NFD>
+// formed).  After the grid barrier every thread issues all of its loads at
+// once -- its share of the blocks' partials (into ``stage``) and of the
+// tile's halo of m (hsrc: element offsets into Mbuf, -1 for none; into
+// ``halo``) -- so the exchange costs one memory latency.
+template <int BS, int NFD, int HPT>
 __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned k, int it,
                                                       const double* red, double* stage,
+                                                      const double* Mbuf,
+                                                      const int64_t (&hsrc)[HPT], double* halo,
                                                       const double* s_bb, double* s_gprev,
                                                       double* s_aprev, double* s_alpha,
                                                       double* s_beta, int* s_active) {
     constexpr int NW = BS / 64, NS = 3 * NFD;
+    constexpr int PPT = (TILE_NB * NS + BS - 1) / BS;
     const unsigned nb = gridDim.x;
     double* part = a.partial + (size_t)(k & 1u) * CG_MAX_BLOCKS * (CG_MAX_FIELDS * 4);
     __syncthreads();
@@ -504,9 +544,24 @@ __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned 
     }
     grid_sync(a.bar, nb, k, a.info);
     const int total = (int)nb * NS;
-    for (int e = threadIdx.x; e < total; e += BS) {
+    double pv[PPT], hv[HPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int e = threadIdx.x + j * BS;
         const int b = e / NS, t = e - b * NS;
-        stage[e] = part[(size_t)b * (CG_MAX_FIELDS * 4) + t];
+        pv[j] = e < total ? part[(size_t)b * (CG_MAX_FIELDS * 4) + t] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) hv[j] = hsrc[j] >= 0 ? Mbuf[hsrc[j]] : 0.0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int e = threadIdx.x + j * BS;
+        if (e < total) stage[e] = pv[j];
+    }
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const int e = threadIdx.x + j * BS;
+        if (e < NFD * TILE_HALO) halo[e] = hv[j];
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -542,18 +597,21 @@ __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned 
     __syncthreads();
 }
 
-// z = M^-1 v for the fields marked in ``live`` (others untouched); every
-// thread of the workgroup must call it (it synchronises)
+// z = M^-1 v for the fields marked in ``live`` (others untouched); dinv
+// holds D^-1 per field and cell of the tile (LDS); every thread of the
+// workgroup must call it (it synchronises, first so that earlier readers of
+// zt are done)
 template <int NFD, int KSW>
 __device__ __forceinline__ void tile_precond(const double (&v)[NFD], double (&z)[NFD],
-                                             const double (&dinv)[NFD], const double (&cf)[NFD],
+                                             const double* dinv, const double (&cf)[NFD],
                                              double ke, double kw, double kn, double ks,
                                              bool he, bool hw, bool hn, bool hs, double* zt,
                                              const int* live) {
     const int t = threadIdx.x;
+    __syncthreads();
 #pragma unroll
     for (int d = 0; d < NFD; ++d)
-        if (live[d]) z[d] = dinv[d] * v[d];
+        if (live[d]) z[d] = dinv[d * TILE_BS + t] * v[d];
 #pragma unroll
     for (int sw = 0; sw < KSW; ++sw) {
 #pragma unroll
@@ -569,7 +627,7 @@ __device__ __forceinline__ void tile_precond(const double (&v)[NFD], double (&z)
             if (hw) nb += kw * Z[t - 1];
             if (hn) nb += kn * Z[t + TILE_X];
             if (hs) nb += ks * Z[t - TILE_X];
-            z[d] = dinv[d] * (v[d] + cf[d] * nb);
+            z[d] = dinv[d * TILE_BS + t] * (v[d] + cf[d] * nb);
         }
         __syncthreads();
     }
@@ -579,12 +637,18 @@ template <int NFD, int KSW>
 __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
     constexpr int BS = TILE_BS;
     constexpr int NS = 3 * NFD;
-    // the preconditioner's tile and the reduction's staging area are used
-    // at different times: one buffer
-    constexpr int WORK = (TILE_NB * NS > NFD * TILE_BS) ? TILE_NB * NS : NFD * TILE_BS;
-    __shared__ double work[WORK];
-    double* const stage = work;
-    double* const zt = work;
+    constexpr int HPT = (NFD * TILE_HALO + BS - 1) / BS;   // halo slots per thread
+    // one workgroup per CU (register bound), so LDS is plentiful: the
+    // preconditioner's work tile, which then holds m of this tile (the
+    // stencil's neighbours inside the tile) until the next preconditioner
+    // call; D^-1 and the iterate x (kept out of registers); the halo of m
+    // and the partials of all blocks
+    __shared__ double zt[NFD * BS];
+    double* const mt = zt;
+    __shared__ double dinv[NFD * BS];
+    __shared__ double xt[NFD * BS];
+    __shared__ double halo[NFD * TILE_HALO];
+    __shared__ double stage[TILE_NB * NS];
     __shared__ double red[NS * (BS / 64)];
     __shared__ double tot[NS];
     __shared__ double s_bb[NFD], s_gprev[NFD], s_aprev[NFD], s_alpha[NFD], s_beta[NFD];
@@ -603,27 +667,41 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
     const bool hw = own && tx > 0;
     const bool hn = own && ty + 1 < TILE_Y && gy + 1 < a.ny;
     const bool hs = own && ty > 0;
-    double cf[NFD], dinv[NFD];
+    // the halo slots this thread loads after every barrier
+    int64_t hsrc[HPT];
+    {
+        const int x0 = (blockIdx.x % a.ntx) * TILE_X, y0 = (blockIdx.x / a.ntx) * TILE_Y;
+        const int wt = min(TILE_X, a.nx - x0), ht = min(TILE_Y, a.ny - y0);
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            const int e = threadIdx.x + j * BS;
+            const int d = e / TILE_HALO;
+            const int64_t c = e < NFD * TILE_HALO ? halo_cell(a, x0, y0, wt, ht, e % TILE_HALO) : -1;
+            hsrc[j] = c >= 0 ? (int64_t)a.fmap[d] * a.n + c : -1;
+        }
+    }
+    double cf[NFD];
 #pragma unroll
     for (int d = 0; d < NFD; ++d) {
         cf[d] = a.cf[d];
-        dinv[d] = own ? 1.0 / (1.0 + cf[d] * (ke + kw + kn + ks)) : 0.0;
+        dinv[d * BS + threadIdx.x] = own ? 1.0 / (1.0 + cf[d] * (ke + kw + kn + ks)) : 0.0;
     }
-    double x[NFD], r[NFD], u[NFD], w[NFD], zz[NFD], qq[NFD], ss[NFD], pp[NFD];
+    double r[NFD], u[NFD], w[NFD], zz[NFD], qq[NFD], ss[NFD], pp[NFD];
     unsigned kb = 0;
     // ---- r = b - A x0, u = M^-1 r (published), partial (b, b) ----
 #pragma unroll
     for (int d = 0; d < NFD; ++d) {
         const size_t o = (size_t)a.fmap[d] * a.n;
         const double* X = a.guess_in_x ? a.x + o : a.b + o;
-        x[d] = r[d] = w[d] = zz[d] = qq[d] = ss[d] = pp[d] = 0.0;
+        r[d] = w[d] = zz[d] = qq[d] = ss[d] = pp[d] = 0.0;
+        xt[d * BS + threadIdx.x] = 0.0;
         double bb = 0.0;
         if (own) {
             const double xi = X[cell];
             const double Ax = xi - cf[d] * (ke * (X[ie] - xi) - kw * (xi - X[iw]) +
                                             kn * (X[in_] - xi) - ks * (xi - X[is_]));
             const double bi = a.b[o + cell];
-            x[d] = xi;
+            xt[d * BS + threadIdx.x] = xi;
             r[d] = bi - Ax;
             bb = bi * bi;
         }
@@ -660,26 +738,33 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
             if (!s_active[d]) continue;               // converged: nothing to reduce
             const size_t o = (size_t)a.fmap[d] * a.n;
             if (own) Mbuf[o + cell] = m[d];
+            mt[d * BS + threadIdx.x] = m[d];
             wave_put<BS>(own ? r[d] * u[d] : 0.0, red, 3 * d + 0);
             wave_put<BS>(own ? w[d] * u[d] : 0.0, red, 3 * d + 1);
             wave_put<BS>(own ? r[d] * r[d] : 0.0, red, 3 * d + 2);
         }
-        grid_allreduce_coeffs<BS, NFD>(a, kb++, it, red, stage, s_bb, s_gprev, s_aprev, s_alpha,
-                                       s_beta, s_active);
+        grid_allreduce_coeffs<BS, NFD, HPT>(a, kb++, it, red, stage, Mbuf, hsrc, halo, s_bb,
+                                            s_gprev, s_aprev, s_alpha, s_beta, s_active);
         int any = 0;
 #pragma unroll
         for (int d = 0; d < NFD; ++d) any |= s_active[d];
         if (!any) break;
-        // ---- n = A m ; recurrences ----
+        // ---- n = A m (neighbours from the tile and its halo in LDS) ; recurrences ----
 #pragma unroll
         for (int d = 0; d < NFD; ++d) {
-            const double* Mv = Mbuf + (size_t)a.fmap[d] * a.n;
+            const double* Mt = mt + d * BS;
+            const double* H = halo + d * TILE_HALO;
             const bool act = s_active[d];
             const double al = s_alpha[d], be = s_beta[d];
             if (!own || !act) continue;
-            const double mi = m[d];
-            const double ni = mi - cf[d] * (ke * (Mv[ie] - mi) - kw * (mi - Mv[iw]) +
-                                            kn * (Mv[in_] - mi) - ks * (mi - Mv[is_]));
+            const int t = threadIdx.x;
+            const double mi = Mt[t];      // m of this cell, kept in LDS across the barrier
+            const double mE = he ? Mt[t + 1] : H[2 * TILE_X + ty];
+            const double mW = hw ? Mt[t - 1] : H[2 * TILE_X + TILE_Y + ty];
+            const double mN = hn ? Mt[t + TILE_X] : H[tx];
+            const double mS = hs ? Mt[t - TILE_X] : H[TILE_X + tx];
+            const double ni = mi - cf[d] * (ke * (mE - mi) - kw * (mi - mW) +
+                                            kn * (mN - mi) - ks * (mi - mS));
             const double z1 = ni + be * zz[d];
             const double q1 = mi + be * qq[d];
             const double s1 = w[d] + be * ss[d];
@@ -688,7 +773,7 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
             qq[d] = act ? q1 : qq[d];
             ss[d] = act ? s1 : ss[d];
             pp[d] = act ? p1 : pp[d];
-            x[d] = act ? x[d] + al * p1 : x[d];
+            xt[d * BS + t] = xt[d * BS + t] + al * p1;     // own && act here
             r[d] = act ? r[d] - al * s1 : r[d];
             u[d] = act ? u[d] - al * q1 : u[d];
             w[d] = act ? w[d] - al * z1 : w[d];
@@ -696,7 +781,7 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
     }
 #pragma unroll
     for (int d = 0; d < NFD; ++d)
-        if (own) a.x[(size_t)a.fmap[d] * a.n + cell] = x[d];
+        if (own) a.x[(size_t)a.fmap[d] * a.n + cell] = xt[d * BS + threadIdx.x];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.info[0] = it;
         int any = 0;
