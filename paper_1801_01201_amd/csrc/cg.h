@@ -13,6 +13,10 @@ constexpr int cg_regs_block(int cpt) { return cpt == 1 ? 512 : 256; }
 constexpr int CG_MAX_FIELDS = 64;
 constexpr int CG_MAX_BLOCKS = 256;
 constexpr int TILE_X = 32, TILE_Y = 16, TILE_BS = TILE_X * TILE_Y, TILE_NB = 128;
+// cells on the four sides of a tile (its edges, and the halo around it)
+constexpr int TILE_HALO = 2 * TILE_X + 2 * TILE_Y;
+// edge buffer of the tiled kernels: 2 (iteration parity) x tiles x 9 fields x TILE_HALO
+constexpr size_t TILE_EDGE_DOUBLES = (size_t)2 * TILE_NB * 9 * TILE_HALO;
 
 struct CGArgs {
     int64_t n;              // cells
@@ -29,6 +33,7 @@ struct CGArgs {
     double* p;
     double* q;
     double* partial;        // blocks x nf x 4
+    double* edge;           // tiled variants: TILE_EDGE_DOUBLES
     double* totals;         // nf x 4 (written by the last block of a fused reduction)
     unsigned* bar;
     int32_t* info;          // [0] iterations, [1] failed, [2] barrier timeout

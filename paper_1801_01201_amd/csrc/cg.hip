@@ -482,53 +482,83 @@ __global__ void __launch_bounds__(BS) cg_regs_kernel(CGArgs a) {
 // and it replaces the diagonal preconditioner at the two places the
 // pipelined recurrence applies one (u = M^-1 r, m = M^-1 w).
 // ---------------------------------------------------------------------------
-// Halo of a tile: the cells next to its four sides (periodic wrap),
-// TILE_HALO slots per field: [0, TX) the row above (+y), [TX, 2 TX) the row
-// below, then TY slots for the column to the right (+x) and TY for the column
-// to the left.  Slots beyond a ragged tile's width or height are unused.
-constexpr int TILE_HALO = 2 * TILE_X + 2 * TILE_Y;
-
-// Cell of halo slot s of the tile with origin (x0, y0) and extent wt x ht
-// (-1 when the slot is unused).
-__device__ __forceinline__ int64_t halo_cell(const CGArgs& a, int x0, int y0, int wt, int ht,
-                                             int s) {
-    int x, y;
-    if (s < TILE_X) {
+// Edges and halo of a tile, TILE_HALO slots per field each.  Edge slots of
+// a tile: [0, TX) its top row (+y side), [TX, 2 TX) its bottom row, then TY
+// slots for its right column (+x side) and TY for its left column.  Halo
+// slots, in the same order: the row above, the row below, the column to the
+// right and the column to the left (periodic wrap) -- each is an edge of the
+// neighbouring tile on that side: the row above is the bottom edge of the
+// tile above, and so on.  Slots beyond a ragged tile's width or height are
+// unused.  Returns the offset of halo slot s of field d of tile (bx, by) in
+// one parity half of the edge buffer (-1 when the slot is unused).
+__device__ __forceinline__ int halo_source(const CGArgs& a, int nty, int bx, int by, int wt,
+                                           int ht, int d, int s) {
+    int tile, slot;
+    if (s < TILE_X) {                                      // above: its bottom row
         if (s >= wt) return -1;
-        x = x0 + s;
-        y = (y0 + ht) % a.ny;
-    } else if (s < 2 * TILE_X) {
+        tile = ((by + 1) % nty) * a.ntx + bx;
+        slot = TILE_X + s;
+    } else if (s < 2 * TILE_X) {                           // below: its top row
         s -= TILE_X;
         if (s >= wt) return -1;
-        x = x0 + s;
-        y = (y0 - 1 + a.ny) % a.ny;
-    } else if (s < 2 * TILE_X + TILE_Y) {
+        tile = ((by - 1 + nty) % nty) * a.ntx + bx;
+        slot = s;
+    } else if (s < 2 * TILE_X + TILE_Y) {                  // right: its left column
         s -= 2 * TILE_X;
         if (s >= ht) return -1;
-        y = y0 + s;
-        x = (x0 + wt) % a.nx;
-    } else {
+        tile = by * a.ntx + (bx + 1) % a.ntx;
+        slot = 2 * TILE_X + TILE_Y + s;
+    } else {                                               // left: its right column
         s -= 2 * TILE_X + TILE_Y;
         if (s >= ht) return -1;
-        y = y0 + s;
-        x = (x0 - 1 + a.nx) % a.nx;
+        tile = by * a.ntx + (bx - 1 + a.ntx) % a.ntx;
+        slot = 2 * TILE_X + s;
     }
-    return (int64_t)y * a.nx + x;
+    return (tile * 9 + d) * TILE_HALO + slot;
+}
+
+// Grid barrier k without cache maintenance, for data exchanged only through
+// agent-scope atomic stores and loads (which the hardware keeps coherent
+// across the XCDs without writing back or invalidating the L2): every wave
+// waits until its stores have completed, then the workgroup arrives; the
+// wait is bounded as in grid_sync.
+__device__ __forceinline__ void grid_sync_direct(unsigned* counter, unsigned nb, unsigned k,
+                                                 int32_t* info) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = (k + 1u) * nb;
+        unsigned spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1u << 27)) {
+                __hip_atomic_store(&info[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __syncthreads();
 }
 
 // Reduction of the partial sums (r,u), (w,u), (r,r) of every field over
 // the blocks, fused with the recurrence coefficients: the wavefront that
 // reduces a field's three sums computes its coefficients.  A field whose
 // residual has met the tolerance stays inactive (its sums are no longer
-// formed).  After the grid barrier every thread issues all of its loads at
-// once -- its share of the blocks' partials (into ``stage``) and of the
-// tile's halo of m (hsrc: element offsets into Mbuf, -1 for none; into
-// ``halo``) -- so the exchange costs one memory latency.
+// formed).  The partials and the tile's edges of m (copied from the tile
+// ``mt`` in LDS: elds holds the LDS index of each of this thread's edge
+// slots, -1 for none) travel through agent-scope atomic stores and loads, so
+// the barrier needs no cache write-back or invalidation.  After it every
+// thread issues all of its loads at once -- its share of the blocks'
+// partials (into ``stage``) and of the tile's halo of m (hsrc: offsets into
+// the edge half ``eb``, -1 for none; into ``halo``) -- so the exchange costs
+// one memory latency.
 template <int BS, int NFD, int HPT>
 __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned k, int it,
                                                       const double* red, double* stage,
-                                                      const double* Mbuf,
-                                                      const int64_t (&hsrc)[HPT], double* halo,
+                                                      const double* mt, const int (&elds)[HPT],
+                                                      double* eb,
+                                                      const int (&hsrc)[HPT], double* halo,
                                                       const double* s_bb, double* s_gprev,
                                                       double* s_aprev, double* s_alpha,
                                                       double* s_beta, int* s_active) {
@@ -540,19 +570,33 @@ __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned 
     for (int t = threadIdx.x; t < NS; t += BS) {
         double v = 0.0;
         for (int w = 0; w < NW; ++w) v += red[t * NW + w];
-        part[(size_t)blockIdx.x * (CG_MAX_FIELDS * 4) + t] = v;
+        __hip_atomic_store(&part[(size_t)blockIdx.x * (CG_MAX_FIELDS * 4) + t], v,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    grid_sync(a.bar, nb, k, a.info);
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const int e = threadIdx.x + j * BS;                // (field, slot) of this tile
+        if (elds[j] >= 0 && s_active[e / TILE_HALO])
+            __hip_atomic_store(&eb[(size_t)blockIdx.x * (NFD * TILE_HALO) + e], mt[elds[j]],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    grid_sync_direct(a.bar, nb, k, a.info);
     const int total = (int)nb * NS;
     double pv[PPT], hv[HPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int e = threadIdx.x + j * BS;
         const int b = e / NS, t = e - b * NS;
-        pv[j] = e < total ? part[(size_t)b * (CG_MAX_FIELDS * 4) + t] : 0.0;
+        pv[j] = e < total ? __hip_atomic_load(&part[(unsigned)(b * (CG_MAX_FIELDS * 4) + t)],
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                          : 0.0;
     }
 #pragma unroll
-    for (int j = 0; j < HPT; ++j) hv[j] = hsrc[j] >= 0 ? Mbuf[hsrc[j]] : 0.0;
+    for (int j = 0; j < HPT; ++j)
+        hv[j] = hsrc[j] >= 0
+                    ? __hip_atomic_load(&eb[(unsigned)hsrc[j]], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT)
+                    : 0.0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int e = threadIdx.x + j * BS;
@@ -635,6 +679,7 @@ __device__ __forceinline__ void tile_precond(const double (&v)[NFD], double (&z)
 
 template <int NFD, int KSW>
 __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
+    static_assert(NFD == 9, "the edge buffer holds 9 fields per tile");
     constexpr int BS = TILE_BS;
     constexpr int NS = 3 * NFD;
     constexpr int HPT = (NFD * TILE_HALO + BS - 1) / BS;   // halo slots per thread
@@ -667,18 +712,39 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
     const bool hw = own && tx > 0;
     const bool hn = own && ty + 1 < TILE_Y && gy + 1 < a.ny;
     const bool hs = own && ty > 0;
-    // the halo slots this thread loads after every barrier
-    int64_t hsrc[HPT];
+    // the halo slots this thread loads after every barrier, and the edges
+    // of this tile that its cell lies on
+    int hsrc[HPT];
+    const int x0 = (blockIdx.x % a.ntx) * TILE_X, y0 = (blockIdx.x / a.ntx) * TILE_Y;
+    const int wt = min(TILE_X, a.nx - x0), ht = min(TILE_Y, a.ny - y0);
     {
-        const int x0 = (blockIdx.x % a.ntx) * TILE_X, y0 = (blockIdx.x / a.ntx) * TILE_Y;
-        const int wt = min(TILE_X, a.nx - x0), ht = min(TILE_Y, a.ny - y0);
+        const int nty = (a.ny + TILE_Y - 1) / TILE_Y;
+        const int bx = blockIdx.x % a.ntx, by = blockIdx.x / a.ntx;
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
             const int e = threadIdx.x + j * BS;
-            const int d = e / TILE_HALO;
-            const int64_t c = e < NFD * TILE_HALO ? halo_cell(a, x0, y0, wt, ht, e % TILE_HALO) : -1;
-            hsrc[j] = c >= 0 ? (int64_t)a.fmap[d] * a.n + c : -1;
+            hsrc[j] = e < NFD * TILE_HALO
+                          ? halo_source(a, nty, bx, by, wt, ht, e / TILE_HALO, e % TILE_HALO)
+                          : -1;
         }
+    }
+    // the edge slots this thread publishes: LDS index of the cell in mt
+    int elds[HPT];
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const int e = threadIdx.x + j * BS;
+        int sl = e % TILE_HALO, lx = -1, ly = -1;
+        if (e >= NFD * TILE_HALO) {
+        } else if (sl < TILE_X) {
+            if (sl < wt) lx = sl, ly = ht - 1;
+        } else if (sl < 2 * TILE_X) {
+            if (sl - TILE_X < wt) lx = sl - TILE_X, ly = 0;
+        } else if (sl < 2 * TILE_X + TILE_Y) {
+            if (sl - 2 * TILE_X < ht) lx = wt - 1, ly = sl - 2 * TILE_X;
+        } else {
+            if (sl - 2 * TILE_X - TILE_Y < ht) lx = 0, ly = sl - 2 * TILE_X - TILE_Y;
+        }
+        elds[j] = lx >= 0 ? (e / TILE_HALO) * BS + ly * TILE_X + lx : -1;
     }
     double cf[NFD];
 #pragma unroll
@@ -727,8 +793,8 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
     }
     int it = 0;
     for (; it < a.maxit; ++it) {
-        // ---- m = M^-1 w (published), partials gamma = (r,u), delta = (w,u), rr ----
-        double* Mbuf = (it & 1) ? a.q : a.z;
+        // ---- m = M^-1 w (its tile edges published), partials gamma = (r,u), delta = (w,u), rr ----
+        double* eb = a.edge + (size_t)(it & 1) * (TILE_EDGE_DOUBLES / 2);
         double m[NFD];
 #pragma unroll
         for (int d = 0; d < NFD; ++d) m[d] = 0.0;
@@ -736,14 +802,12 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
 #pragma unroll
         for (int d = 0; d < NFD; ++d) {
             if (!s_active[d]) continue;               // converged: nothing to reduce
-            const size_t o = (size_t)a.fmap[d] * a.n;
-            if (own) Mbuf[o + cell] = m[d];
             mt[d * BS + threadIdx.x] = m[d];
             wave_put<BS>(own ? r[d] * u[d] : 0.0, red, 3 * d + 0);
             wave_put<BS>(own ? w[d] * u[d] : 0.0, red, 3 * d + 1);
             wave_put<BS>(own ? r[d] * r[d] : 0.0, red, 3 * d + 2);
         }
-        grid_allreduce_coeffs<BS, NFD, HPT>(a, kb++, it, red, stage, Mbuf, hsrc, halo, s_bb,
+        grid_allreduce_coeffs<BS, NFD, HPT>(a, kb++, it, red, stage, mt, elds, eb, hsrc, halo, s_bb,
                                             s_gprev, s_aprev, s_alpha, s_beta, s_active);
         int any = 0;
 #pragma unroll
@@ -844,6 +908,7 @@ int diffusion_work_set(DiffusionWork& w, const Mech& m, const Grid& g, int varia
         case 103: {
             if (!(NF - 1 == 9 && g.dim == 2 && g.n_flames == 0))
                 return fail(MISDC_EINVAL, "tiled CG variants need a 2-D grid and 9 diffused fields");
+            if (!w.edge) return fail(MISDC_EINVAL, "tiled CG: no edge buffer");
             const int64_t tiles = ((g.nx + TILE_X - 1) / TILE_X) * ((g.ny + TILE_Y - 1) / TILE_Y);
             if (blocks != tiles || tiles > TILE_NB)
                 return fail(MISDC_EINVAL, "tiled CG: the grid has %lld tiles of %dx%d (at most %d), "

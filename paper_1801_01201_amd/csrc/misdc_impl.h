@@ -151,6 +151,7 @@ struct DiffusionWork {
     double* p = nullptr;
     double* q = nullptr;
     double* partial = nullptr;    // blocks x fields x 4
+    double* edge = nullptr;       // tiled CG: edges of m of every tile (2-D, 9 diffused fields)
     double* totals = nullptr;     // fields x 4
     unsigned* barrier = nullptr;  // 4 words
     int32_t* info = nullptr;      // [0] iterations, [1] failed, [2] barrier timeout

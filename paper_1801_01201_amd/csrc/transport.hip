@@ -623,6 +623,8 @@ int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
     MISDC_HIP(hipMalloc(&w.z, cells_bytes * NF));
     MISDC_HIP(hipMalloc(&w.p, cells_bytes * NF));
     MISDC_HIP(hipMalloc(&w.q, cells_bytes * NF));
+    if (g.dim == 2 && g.n_flames == 0 && NF - 1 == 9)
+        MISDC_HIP(hipMalloc(&w.edge, TILE_EDGE_DOUBLES * sizeof(double)));
     int cus = 0;
     int rc = device_cus(cus);
     if (rc) return rc;
@@ -673,7 +675,7 @@ int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
 }
 
 void diffusion_work_free(DiffusionWork& w) {
-    double* ptrs[] = {w.theta, w.Kx, w.Ky, w.x, w.r, w.z, w.p, w.q, w.partial, w.totals};
+    double* ptrs[] = {w.theta, w.Kx, w.Ky, w.x, w.r, w.z, w.p, w.q, w.partial, w.totals, w.edge};
     for (double* p : ptrs)
         if (p) (void)hipFree(p);
     if (w.barrier) (void)hipFree(w.barrier);
@@ -726,6 +728,7 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
         a.p = w.p;
         a.q = w.q;
         a.partial = w.partial;
+        a.edge = w.edge;
         a.totals = w.totals;
         a.bar = w.barrier;
         a.info = w.info;
