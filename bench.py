@@ -174,7 +174,10 @@ def ensemble_main(args):
     tune = None
     for mode in ("graph", "profile"):
         integ = Integrator(mh, g, use_graph=(mode == "graph"), profile=(mode == "profile"), **kw)
-        if tune is None and not args.no_autotune:
+        if tune is None and args.tune:
+            integ.set_tune(*[int(v) for v in args.tune.split(",")])
+            tune = integ.tune()
+        elif tune is None and not args.no_autotune:
             tune = integ.autotune(state, 0.0, dt_per_flame=d_dt, reps=3)
         elif tune is not None:
             integ.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"],
@@ -476,6 +479,9 @@ def main():
     ap.add_argument("--nu", type=int, default=None)
     ap.add_argument("--serialize", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune", default=None,
+                    help="launch configuration instead of autotuning: cg_variant,cg_blocks,"
+                         "cyclic,serialize,cu_split,stagger")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the extra timing of the same steps replayed as one HIP graph")
     ap.add_argument("--workload", default="flame2d_256",
@@ -534,7 +540,10 @@ def main():
     integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
                        scheme=cfg["scheme"], serialize=args.serialize, profile=True)
     tune = None
-    if not args.no_autotune:
+    if args.tune:
+        integ.set_tune(*[int(v) for v in args.tune.split(",")])
+        tune = integ.tune()
+    elif not args.no_autotune:
         # untimed: pick the launch configuration on this workload (the state
         # is not modified)
         tune = integ.autotune(state, cfg["dt"], reps=2)

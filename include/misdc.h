@@ -298,7 +298,8 @@ typedef struct {
                              node m waits until the diffusion solve of node
                              m+1 is next on its stream, so that the persistent
                              CG takes its CUs first (a start-order dependency:
-                             results are unchanged) */
+                             results are unchanged); the default with two
+                             streams */
     double step_ms;       /* measured by misdc_autotune: mean time of one step */
 } misdc_tune;
 

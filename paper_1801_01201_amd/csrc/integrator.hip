@@ -1087,6 +1087,7 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->sR2, hipStreamNonBlocking);
     if (e != hipSuccess) return bail(fail(MISDC_EDEVICE, "stream: %s", hipGetErrorString(e)));
     I->sR = opts->serialize ? I->sD : I->sR2;
+    I->stagger = opts->serialize ? 0 : 1;
     const size_t nev = (size_t)I->levels * (M + 1);
     I->evD.assign(nev, nullptr);
     I->evR.assign(nev, nullptr);
