@@ -322,7 +322,6 @@ __global__ void __launch_bounds__(BS) cg_regs_kernel(CGArgs a) {
     __shared__ double tot[NS];
     __shared__ double s_bb[NFD], s_gprev[NFD], s_aprev[NFD], s_alpha[NFD], s_beta[NFD];
     __shared__ int s_active[NFD];
-    const unsigned nb = gridDim.x;
     const int64_t T = (int64_t)gridDim.x * BS;
     const int64_t t0 = (int64_t)blockIdx.x * BS + threadIdx.x;
     int64_t cell[CPT], ie[CPT], iw[CPT], in_[CPT], is_[CPT];

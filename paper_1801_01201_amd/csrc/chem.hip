@@ -254,17 +254,20 @@ __global__ void __launch_bounds__(64) newton_kernel(MechDev m, NewtonArgs a) {
 }
 
 // wave-aggregated statistics: [0] solves, [1] iterations, [2] failures, [3] max
+// (grid-stride over few workgroups: the counters take one atomic per
+// workgroup, and many workgroups contending for them cost more than the sum)
 template <int NS>
 __global__ void __launch_bounds__(256) newton_stats_kernel(int64_t n, const int32_t* iters,
                                                            unsigned long long* stats) {
     __shared__ unsigned long long s_sum[4], s_bad[4], s_max[4];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long v = 0, b = 0, mx = 0;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t it = iters[i];
-        v = it > 0 ? (unsigned long long)it : 0ull;
-        b = it < 0 ? 1ull : 0ull;
-        mx = v;
+        const unsigned long long vi = it > 0 ? (unsigned long long)it : 0ull;
+        v += vi;
+        b += it < 0 ? 1ull : 0ull;
+        mx = vi > mx ? vi : mx;
     }
     for (int off = 32; off > 0; off >>= 1) {
         v += __shfl_xor(v, off);
@@ -283,9 +286,7 @@ __global__ void __launch_bounds__(256) newton_stats_kernel(int64_t n, const int3
             B += s_bad[w];
             X = s_max[w] > X ? s_max[w] : X;
         }
-        const int64_t lo = (int64_t)blockIdx.x * blockDim.x;
-        const int64_t cnt = (n - lo) < (int64_t)blockDim.x ? (n - lo) : (int64_t)blockDim.x;
-        atomicAdd(&stats[0], (unsigned long long)cnt);
+        if (blockIdx.x == 0) atomicAdd(&stats[0], (unsigned long long)n);
         atomicAdd(&stats[1], S);
         atomicAdd(&stats[2], B);
         atomicMax(&stats[3], X);
@@ -387,7 +388,8 @@ int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(newton_kernel<9>, dim3(grid_for(a.n, 64)), dim3(64), 0, s, m.dev, a);
     MISDC_HIP(hipGetLastError());
     if (a.stats && a.iters) {
-        hipLaunchKernelGGL(newton_stats_kernel<9>, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a.n,
+        const int64_t gb = grid_for(a.n, 256 * 16);
+        hipLaunchKernelGGL(newton_stats_kernel<9>, dim3(gb < 32 ? gb : 32), dim3(256), 0, s, a.n,
                            a.iters, a.stats);
         MISDC_HIP(hipGetLastError());
     }

@@ -641,13 +641,22 @@ int issue_step(misdc_integ_s* I, double* state, double dt, const double* dtf) {
     if ((rc = launch_copy(b0.phi, state, (int64_t)NF * n, I->sD))) return rc;
     if ((rc = launch_state_temperature(*I->mech, n, b0.phi, b0.T, I->sD))) return rc;
     if ((rc = eval_ops(I, b0, I->thD, I->sD, true))) return rc;
-    for (int p = 1; p <= M; ++p) {
-        NodeBuf& b = I->lev[0][p];
-        if ((rc = launch_copy(b.phi, b0.phi, (int64_t)NF * n, I->sD))) return rc;
-        if ((rc = launch_copy(b.T, b0.T, n, I->sD))) return rc;
-        if ((rc = launch_copy(b.FA, b0.FA, (int64_t)NF * n, I->sD))) return rc;
-        if ((rc = launch_copy(b.FD, b0.FD, (int64_t)NF * n, I->sD))) return rc;
-        if ((rc = launch_copy(b.FR, b0.FR, (int64_t)N * n, I->sD))) return rc;
+    {
+        Broadcast bc;
+        bc.narr = 5;
+        const double* src[5] = {b0.phi, b0.T, b0.FA, b0.FD, b0.FR};
+        const int64_t len[5] = {(int64_t)NF * n, n, (int64_t)NF * n, (int64_t)NF * n, (int64_t)N * n};
+        for (int k = 0; k < 5; ++k) {
+            bc.src[k] = src[k];
+            bc.len[k] = len[k];
+        }
+        bc.ndst = M;
+        for (int p = 1; p <= M; ++p) {
+            NodeBuf& b = I->lev[0][p];
+            double* dst[5] = {b.phi, b.T, b.FA, b.FD, b.FR};
+            for (int k = 0; k < 5; ++k) bc.dst[p - 1][k] = dst[k];
+        }
+        if ((rc = launch_broadcast(bc, I->sD))) return rc;
     }
     // node 0 is shared by every nested-iteration level
     for (int l = 1; l < I->levels; ++l) I->lev[l][0] = b0;

@@ -129,6 +129,16 @@ struct LinComb {
 int launch_lincomb(const LinComb& lc, hipStream_t s);
 // device-side copy and fill (stream-ordered kernels, safe under graph capture)
 int launch_copy(double* dst, const double* src, int64_t count, hipStream_t s);
+// copies narr source arrays (lengths len, every len > 0) into each of ndst
+// destination sets, in one launch
+struct Broadcast {
+    static constexpr int MAX_ARR = 6, MAX_DST = 8;
+    int narr = 0, ndst = 0;
+    const double* src[MAX_ARR] = {};
+    int64_t len[MAX_ARR] = {};
+    double* dst[MAX_DST][MAX_ARR] = {};
+};
+int launch_broadcast(const Broadcast& b, hipStream_t s);
 int launch_zero(void* dst, int64_t bytes, hipStream_t s);
 // per-cell value of a per-flame array: out[i] = v[flame of cell i]
 int launch_expand_flames(const Grid& g, const double* v, double* out, hipStream_t s);

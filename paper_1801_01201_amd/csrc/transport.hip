@@ -54,6 +54,21 @@ __global__ void __launch_bounds__(256) copy_kernel(double* dst, const double* sr
         dst[i] = src[i];
 }
 
+// every destination set receives a copy of the source arrays (one pass over
+// the sources)
+__global__ void __launch_bounds__(256) broadcast_kernel(Broadcast b) {
+    int64_t total = 0;
+    for (int k = 0; k < b.narr; ++k) total += b.len[k];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int k = 0;
+        int64_t o = e;
+        while (o >= b.len[k]) o -= b.len[k++];
+        const double v = b.src[k][o];
+        for (int d = 0; d < b.ndst; ++d) b.dst[d][k][o] = v;
+    }
+}
+
 __global__ void __launch_bounds__(256) zero_kernel(unsigned* dst, int64_t words) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -74,11 +89,6 @@ __global__ void __launch_bounds__(256) expand_kernel(int n_flames, const int64_t
 // ---------------------------------------------------------------------------
 // explicit operators
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) theta_kernel(int64_t n, const double* T, double* th) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) th[i] = pow(T[i] / T_DIFF_REF, THETA_EXP);
-}
-
 struct GridDev {
     int dim;
     int64_t nx, ny;
@@ -124,12 +134,18 @@ __device__ __forceinline__ Row row_of(const GridDev& g, int64_t i) {
 }
 
 // FA and FD for every field of one cell.  FD of the bath species is minus the
-// sum of the other species' FD.
+// sum of the other species' FD.  FROM_T: theta = (T/300)^1.7 of the cell and
+// its neighbours is computed here from T (and the cell's own value stored in
+// th) instead of being read from th.
+template <bool FROM_T>
 __global__ void __launch_bounds__(256) transport_kernel(GridDev g, MechDev m, int64_t n,
-                                                        const double* st, const double* th,
-                                                        double* FA, double* FD) {
+                                                        const double* st, const double* T,
+                                                        double* th, double* FA, double* FD) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    auto theta = [&](int64_t j) {
+        return FROM_T ? pow(T[j] / T_DIFF_REF, THETA_EXP) : th[j];
+    };
     const Row r = row_of(g, i);
     const int64_t xm2 = r.base + wrap(r.pos - 2, r.len), xm1 = r.base + wrap(r.pos - 1, r.len);
     const int64_t xp1 = r.base + wrap(r.pos + 1, r.len), xp2 = r.base + wrap(r.pos + 2, r.len);
@@ -142,14 +158,15 @@ __global__ void __launch_bounds__(256) transport_kernel(GridDev g, MechDev m, in
         yp1 = wrap(iy + 1, g.ny) * g.nx + ix;
         yp2 = wrap(iy + 2, g.ny) * g.nx + ix;
     }
-    const double t0 = th[i];
+    const double t0 = theta(i);
+    if (FROM_T) th[i] = t0;
     const double idx2 = 1.0 / (r.dx * r.dx);
-    const double kxe = 0.5 * (t0 + th[xp1]) * idx2, kxw = 0.5 * (t0 + th[xm1]) * idx2;
+    const double kxe = 0.5 * (t0 + theta(xp1)) * idx2, kxw = 0.5 * (t0 + theta(xm1)) * idx2;
     double kyn = 0.0, kys = 0.0;
     if (two_d) {
         const double idy2 = 1.0 / (g.dy * g.dy);
-        kyn = 0.5 * (t0 + th[yp1]) * idy2;
-        kys = 0.5 * (t0 + th[ym1]) * idy2;
+        kyn = 0.5 * (t0 + theta(yp1)) * idy2;
+        kys = 0.5 * (t0 + theta(ym1)) * idy2;
     }
     const double ax = r.u / r.dx;
     const double ay = two_d ? g.uy / g.dy : 0.0;
@@ -542,6 +559,19 @@ int launch_copy(double* dst, const double* src, int64_t count, hipStream_t s) {
     return MISDC_OK;
 }
 
+int launch_broadcast(const Broadcast& b, hipStream_t s) {
+    if (b.narr < 1 || b.narr > Broadcast::MAX_ARR || b.ndst < 0 || b.ndst > Broadcast::MAX_DST)
+        return fail(MISDC_EINVAL, "broadcast: %d arrays to %d destinations", b.narr, b.ndst);
+    int64_t total = 0;
+    for (int k = 0; k < b.narr; ++k) total += b.len[k];
+    if (total <= 0 || b.ndst == 0) return MISDC_OK;
+    unsigned blocks = grid_for(total, 256);
+    if (blocks > 8192u) blocks = 8192u;
+    hipLaunchKernelGGL(broadcast_kernel, dim3(blocks), dim3(256), 0, s, b);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
 int launch_zero(void* dst, int64_t bytes, hipStream_t s) {
     if (bytes <= 0) return MISDC_OK;
     if (bytes % 4) return fail(MISDC_EINVAL, "zero fill of %lld bytes: not whole words", (long long)bytes);
@@ -598,12 +628,13 @@ int launch_transport(const Mech& m, const Grid& g, const double* state, const do
                      double* FA, double* FD, double* work_theta, hipStream_t s, bool theta_ready) {
     const int64_t n = g.cells();
     if (n == 0) return MISDC_OK;
-    if (!theta_ready) {
-        hipLaunchKernelGGL(theta_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, n, T, work_theta);
-        MISDC_HIP(hipGetLastError());
-    }
-    hipLaunchKernelGGL(transport_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, grid_dev(g),
-                       m.dev, n, state, work_theta, FA, FD);
+    // theta from T inside the same kernel unless the caller already has it
+    if (theta_ready)
+        hipLaunchKernelGGL(transport_kernel<false>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                           grid_dev(g), m.dev, n, state, T, work_theta, FA, FD);
+    else
+        hipLaunchKernelGGL(transport_kernel<true>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                           grid_dev(g), m.dev, n, state, T, work_theta, FA, FD);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;
 }
