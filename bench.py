@@ -598,7 +598,9 @@ def main():
         achieved = flops / avg_s / 1e12
         roof = {"kernel": "newton_kernel<9> (per-cell reaction solve)", "bound": "alu",
                 "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": measured_traffic("pmc_newton_kernel_flame2d_256.md",
+                                            "paper_1801_01201_amd/csrc/chem.hip"),
                 "avg_launch_ms": avg_s * 1e3, "launches": r_n}
     other = {"diffusion_solve_ms_per_launch": d_ms / max(1, d_n),
              "newton_ms_per_launch": r_ms / max(1, r_n),
