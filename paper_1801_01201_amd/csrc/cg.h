@@ -13,6 +13,11 @@ constexpr int cg_regs_block(int cpt) { return cpt == 1 ? 512 : 256; }
 constexpr int CG_MAX_FIELDS = 64;
 constexpr int CG_MAX_BLOCKS = 256;
 constexpr int TILE_X = 32, TILE_Y = 16, TILE_BS = TILE_X * TILE_Y, TILE_NB = 128;
+// grid-barrier words: [0] arrivals, [1] generation; the two-level barrier
+// of the tiled kernel: BAR_GROUPS group counters at word BAR_STRIDE * (1 + g)
+// and its count of arrived groups at BAR_GLOBAL, each on its own 128-byte line
+constexpr int BAR_GROUPS = 8, BAR_STRIDE = 32, BAR_GLOBAL = BAR_STRIDE * (1 + BAR_GROUPS),
+              BAR_WORDS = BAR_GLOBAL + BAR_STRIDE;
 // cells on the four sides of a tile (its edges, and the halo around it)
 constexpr int TILE_HALO = 2 * TILE_X + 2 * TILE_Y;
 // edge buffer of the tiled kernels: 2 (iteration parity) x tiles x 9 fields x TILE_HALO

@@ -519,15 +519,26 @@ __device__ __forceinline__ int halo_source(const CGArgs& a, int nty, int bx, int
 // Grid barrier k without cache maintenance, for data exchanged only through
 // agent-scope atomic stores and loads (which the hardware keeps coherent
 // across the XCDs without writing back or invalidating the L2): every wave
-// waits until its stores have completed, then the workgroup arrives; the
-// wait is bounded as in grid_sync.
-__device__ __forceinline__ void grid_sync_direct(unsigned* counter, unsigned nb, unsigned k,
+// waits until its stores have completed, then the workgroup arrives.
+// Arrival is two-level, so that no counter takes more than 16 atomics per
+// barrier: workgroup b counts into group b mod 8 (its own cache line), and
+// the last arrival of a group counts the group into bar[BAR_GLOBAL], on which
+// every workgroup waits (bounded as in grid_sync).  k counts these barriers
+// only (from 0 in each launch; the counters are zeroed before it).
+__device__ __forceinline__ void grid_sync_direct(unsigned* bar, unsigned nb, unsigned k,
                                                  int32_t* info) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned target = (k + 1u) * nb;
+        unsigned* counter = bar + BAR_GLOBAL;
+        const unsigned g = blockIdx.x % BAR_GROUPS;
+        const unsigned gsize = (nb - 1u - g) / BAR_GROUPS + 1u;      // workgroups of group g
+        const unsigned ngroups = nb < (unsigned)BAR_GROUPS ? nb : (unsigned)BAR_GROUPS;
+        const unsigned before = __hip_atomic_fetch_add(&bar[BAR_STRIDE * (1 + g)], 1u,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (before + 1u == (k + 1u) * gsize)
+            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = (k + 1u) * ngroups;
         unsigned spins = 0;
         while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
@@ -579,7 +590,7 @@ __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned 
             __hip_atomic_store(&eb[(size_t)blockIdx.x * (NFD * TILE_HALO) + e], mt[elds[j]],
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    grid_sync_direct(a.bar, nb, k, a.info);
+    grid_sync_direct(a.bar, nb, (unsigned)it, a.info);
     const int total = (int)nb * NS;
     double pv[PPT], hv[HPT];
 #pragma unroll

@@ -219,13 +219,21 @@ __device__ __forceinline__ void faces_at(const GridDev& g, int64_t i, const doub
     }
 }
 
+// every counter of the grid barriers (see BAR_WORDS)
+__device__ __forceinline__ void zero_barrier(unsigned* bar) {
+    bar[0] = 0u;
+    bar[1] = 0u;
+    for (int g = 0; g < BAR_GROUPS; ++g) bar[BAR_STRIDE * (1 + g)] = 0u;
+    bar[BAR_GLOBAL] = 0u;
+}
+
 __global__ void __launch_bounds__(256) faces_kernel(GridDev g, int64_t n, const double* T,
                                                     double* th, double* Kx, double* Ky,
                                                     unsigned* bar) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // the persistent CG kernel that follows on this stream counts its grid
     // barriers from zero
-    if (i == 0 && bar) { bar[0] = 0u; bar[1] = 0u; }
+    if (i == 0 && bar) zero_barrier(bar);
     if (i >= n) return;
     faces_at(g, i, T, th, Kx, Ky);
 }
@@ -237,7 +245,7 @@ __global__ void __launch_bounds__(256) lincomb_faces_kernel(LinComb lc, GridDev 
                                                             unsigned* bar) {
     const int64_t total = (int64_t)lc.nfields * lc.ncells;
     const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e0 == 0 && bar) { bar[0] = 0u; bar[1] = 0u; }
+    if (e0 == 0 && bar) zero_barrier(bar);
     for (int64_t e = e0; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int f = (int)(e / lc.ncells);
         if (f == 0) faces_at(g, e, T, th, Kx, Ky);
@@ -697,8 +705,8 @@ int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
     w.threads = CG_THREADS;
     MISDC_HIP(hipMalloc(&w.partial, sizeof(double) * 2 * (size_t)CG_MAX_BLOCKS * CG_MAX_FIELDS * 4));
     MISDC_HIP(hipMalloc(&w.totals, sizeof(double) * CG_MAX_FIELDS * 4));
-    MISDC_HIP(hipMalloc(&w.barrier, sizeof(unsigned) * 4));
-    MISDC_HIP(hipMemset(w.barrier, 0, sizeof(unsigned) * 4));
+    MISDC_HIP(hipMalloc(&w.barrier, sizeof(unsigned) * BAR_WORDS));
+    MISDC_HIP(hipMemset(w.barrier, 0, sizeof(unsigned) * BAR_WORDS));
     MISDC_HIP(hipMalloc(&w.info, sizeof(int32_t) * 4));
     MISDC_HIP(hipMemset(w.info, 0, sizeof(int32_t) * 4));
     w.fields_cap = NF;
