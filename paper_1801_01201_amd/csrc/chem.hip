@@ -214,7 +214,8 @@ __global__ void __launch_bounds__(64) newton_kernel(MechDev m, NewtonArgs a) {
     constexpr int NR = INERT_LAST ? NS - 1 : NS;    // species in the coupled system
     constexpr int NX = NR + 1;                      // ... and T
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+    int code = 0;                   // iterations, -1 when not converged
+    if (i < a.n) {
     const double c = a.c ? a.c[i] * a.c_scalar : a.c_scalar;
     const double h = a.h[i];
     // b_Y (and the floor of Y) are re-read when needed rather than held in
@@ -318,8 +319,32 @@ __global__ void __launch_bounds__(64) newton_kernel(MechDev m, NewtonArgs a) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) a.FR[k * a.ldf + i] = FR[k];
     }
-    const int code = conv ? it : -1;
+    code = conv ? it : -1;
     if (a.iters) a.iters[i] = code;
+    }
+    if (a.buckets) {
+        // statistics of the wavefront (all 64 lanes take part), one set of
+        // atomics per wavefront into one of NEWTON_BUCKETS counter sets
+        int solves = (i < a.n) ? 1 : 0, sum = code > 0 ? code : 0, bad = code < 0 ? 1 : 0;
+        int mx = sum;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            solves += __shfl_xor(solves, off);
+            sum += __shfl_xor(sum, off);
+            bad += __shfl_xor(bad, off);
+            const int o = __shfl_xor(mx, off);
+            mx = o > mx ? o : mx;
+        }
+        if ((threadIdx.x & 63) == 0) {
+            unsigned long long* b = a.buckets + (size_t)((blockIdx.x * (blockDim.x / 64) +
+                                                          threadIdx.x / 64) % NEWTON_BUCKETS) *
+                                                     NEWTON_BUCKET_STRIDE;
+            atomicAdd(&b[0], (unsigned long long)solves);
+            atomicAdd(&b[1], (unsigned long long)sum);
+            if (bad) atomicAdd(&b[2], (unsigned long long)bad);
+            atomicMax(&b[3], (unsigned long long)mx);
+        }
+    }
 }
 
 // wave-aggregated statistics: [0] solves, [1] iterations, [2] failures, [3] max
@@ -459,7 +484,7 @@ int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s) {
     else
         hipLaunchKernelGGL((newton_kernel<9, false>), dim3(grid_for(a.n, 64)), dim3(64), 0, s, m.dev, a);
     MISDC_HIP(hipGetLastError());
-    if (a.stats && a.iters) {
+    if (a.stats && a.iters && !a.buckets) {
         const int64_t gb = grid_for(a.n, 256 * 16);
         hipLaunchKernelGGL(newton_stats_kernel<9>, dim3(gb < 32 ? gb : 32), dim3(256), 0, s, a.n,
                            a.iters, a.stats);

@@ -84,6 +84,7 @@ struct misdc_integ_s {
     double* thR = nullptr;                        // theta work (reaction stream)
     int32_t* iters = nullptr;                     // Newton iterations (cells)
     unsigned long long* nstats = nullptr;         // Newton statistics (8)
+    unsigned long long* nbuckets = nullptr;       // per-thread Newton kernel's counter sets
     int32_t* lu_info = nullptr;                   // FP32 LU refinement record (cells)
     int32_t* cgstats = nullptr;                   // CG: [0] sum, [1] max, [2] failed, [3] solves, [4] timeouts
     double* inc = nullptr;                        // sweep increments: 64 x NF x 2
@@ -470,6 +471,7 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     a.iters = I->iters;
     a.lu_info = (I->opt.newton.lu == MISDC_LU_FP32_MFMA) ? I->lu_info : nullptr;
     a.stats = I->nstats;
+    a.buckets = I->nbuckets;
     a.opt = I->opt.newton;
     // staggered: the Newton solve of node p starts once the diffusion solve
     // of node p+1 (issued just before this task) is about to start, so that
@@ -635,6 +637,9 @@ int issue_step(misdc_integ_s* I, double* state, double dt, const double* dtf) {
         dt = 1.0;      // every dt-carrying term takes dtc[cell] (or dtf[flame])
     }
     if ((rc = launch_zero(I->nstats, 8 * sizeof(unsigned long long), I->sD))) return rc;
+    if ((rc = launch_zero(I->nbuckets, sizeof(unsigned long long) * NEWTON_BUCKETS *
+                                           NEWTON_BUCKET_STRIDE, I->sD)))
+        return rc;
     if ((rc = launch_zero(I->cgstats, 8 * sizeof(int32_t), I->sD))) return rc;
     // I1, I2, I4: every node of sweep 0 holds phi^n and F(phi^n)
     NodeBuf& b0 = I->lev[0][0];
@@ -1084,6 +1089,10 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if ((rc = dalloc(I, &I->thR, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->iters, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->nstats, 8))) return bail(rc);
+    if ((rc = dalloc(I, &I->nbuckets, (size_t)NEWTON_BUCKETS * NEWTON_BUCKET_STRIDE))) return bail(rc);
+    if (hipMemset(I->nbuckets, 0, sizeof(unsigned long long) * NEWTON_BUCKETS * NEWTON_BUCKET_STRIDE) !=
+        hipSuccess)
+        return bail(fail(MISDC_EDEVICE, "clear the Newton counters"));
     if ((rc = dalloc(I, &I->lu_info, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->choice, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->cbuf, (size_t)n))) return bail(rc);
@@ -1408,6 +1417,19 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
     unsigned long long ns[8];
     int32_t cg[8];
     MISDC_HIP(hipMemcpy(ns, I->nstats, sizeof(ns), hipMemcpyDeviceToHost));
+    {
+        // counters the per-thread Newton kernel keeps itself
+        std::vector<unsigned long long> b((size_t)NEWTON_BUCKETS * NEWTON_BUCKET_STRIDE);
+        MISDC_HIP(hipMemcpy(b.data(), I->nbuckets, sizeof(unsigned long long) * b.size(),
+                            hipMemcpyDeviceToHost));
+        for (int k = 0; k < NEWTON_BUCKETS; ++k) {
+            const unsigned long long* s = b.data() + (size_t)k * NEWTON_BUCKET_STRIDE;
+            ns[0] += s[0];
+            ns[1] += s[1];
+            ns[2] += s[2];
+            ns[3] = s[3] > ns[3] ? s[3] : ns[3];
+        }
+    }
     MISDC_HIP(hipMemcpy(cg, I->cgstats, sizeof(cg), hipMemcpyDeviceToHost));
     st->newton_solves = (int64_t)ns[0];
     st->newton_iters = (int64_t)ns[1];

@@ -101,8 +101,13 @@ struct NewtonArgs {
     int32_t* lu_info = nullptr;             // n out, may be null: FP32 solves | FP64 fallbacks << 16
     unsigned long long* stats;              // [0] solves, [1] iters, [2] failed, [3] max,
                                             // [4] FP32 solves, [5] fallbacks; may be null
+    // per-thread kernel only, may be null: the kernel itself adds [0..3] of
+    // each wavefront into NEWTON_BUCKETS sets of counters (set b at
+    // b * NEWTON_BUCKET_STRIDE), and no statistics kernel follows
+    unsigned long long* buckets = nullptr;
     misdc_newton_opts opt;
 };
+constexpr int NEWTON_BUCKETS = 32, NEWTON_BUCKET_STRIDE = 16;   // 128-byte apart
 int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s);
 // one wavefront per cell (any species count up to 63): FP64 LU, or an FP32
 // LU on the matrix cores refined against the FP64 matrix
