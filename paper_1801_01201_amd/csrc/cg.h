@@ -46,6 +46,19 @@ struct CGArgs {
     int maxit;
     int guess_in_x;
     int ntx;                // tiled variant: tiles along x
+    // tiled variants: the bath closure of the solution in the same launch
+    // (close = 1): y_bath = r_bath - sum over the other species of (y_k - r_k),
+    // then (optional) T and theta = (T/300)^1.7 of the closed state, and the
+    // solve's statistics added to cgstats
+    int close;
+    int N, bath;
+    int dmap[CG_MAX_FIELDS + 1];   // field -> diffused index (the bath: -1)
+    const double* hf;
+    const double* cp;
+    const double* invW;
+    double* T_out;
+    double* th_out;
+    int32_t* cgstats;       // [0] iterations, [1] max, [2] failures, [3] solves, [4] timeouts
 };
 
 // launches the CG kernel of a variant (0 global memory, 1/2/4 register

@@ -856,11 +856,45 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
 #pragma unroll
     for (int d = 0; d < NFD; ++d)
         if (own) a.x[(size_t)a.fmap[d] * a.n + cell] = xt[d * BS + threadIdx.x];
+    if (a.close && own) {
+        // bath closure of this cell, then T and theta of the closed state
+        // (species in order, as a separate closure pass would take them)
+        const int t = threadIdx.x;
+        double sum = 0.0;
+        for (int k = 0; k < a.N; ++k) {
+            if (k == a.bath) continue;
+            sum += xt[a.dmap[k] * BS + t] - a.b[(size_t)k * a.n + cell];
+        }
+        const double yb = a.b[(size_t)a.bath * a.n + cell] - sum;
+        a.x[(size_t)a.bath * a.n + cell] = yb;
+        if (a.T_out) {
+            double hform = 0.0, cpm = 0.0;
+            for (int k = 0; k < a.N; ++k) {
+                const double yk = (k == a.bath) ? yb : xt[a.dmap[k] * BS + t];
+                hform += yk * a.hf[k] * a.invW[k];
+                cpm += yk * a.cp[k] * a.invW[k];
+            }
+            const double Ti = T_REF + (xt[a.dmap[a.N] * BS + t] - hform) / cpm;
+            a.T_out[cell] = Ti;
+            if (a.th_out) a.th_out[cell] = pow(Ti / T_DIFF_REF, THETA_EXP);
+        }
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.info[0] = it;
         int any = 0;
         for (int d = 0; d < NFD; ++d) any |= s_active[d];
         a.info[1] = (it == a.maxit) ? any : 0;
+        if (a.close && a.cgstats) {
+            // a barrier timeout flagged by another workgroup after this one
+            // got here is counted with the next solve
+            const int to = __hip_atomic_exchange(&a.info[2], 0, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            a.cgstats[0] += it;
+            a.cgstats[1] = it > a.cgstats[1] ? it : a.cgstats[1];
+            a.cgstats[2] += a.info[1];
+            a.cgstats[3] += 1;
+            a.cgstats[4] += to;
+        }
     }
 }
 

@@ -776,8 +776,24 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
         a.maxit = maxit > 0 ? maxit : 500;
         a.guess_in_x = guess_in_y;
         a.ntx = (int)((g.nx + TILE_X - 1) / TILE_X);
+        // the tiled kernels close the bath themselves
+        a.close = (w.variant >= 101) ? 1 : 0;
+        a.N = m.dev.N;
+        a.bath = m.dev.bath;
+        for (int f = 0; f <= CG_MAX_FIELDS; ++f) a.dmap[f] = -1;
+        for (int d = 0; d < a.nf; ++d) a.dmap[a.fmap[d]] = d;
+        a.hf = m.dev.hf;
+        a.cp = m.dev.cp;
+        a.invW = m.dev.invW;
+        a.T_out = T_out;
+        a.th_out = T_out ? th_out : nullptr;
+        a.cgstats = cgstats;
         int rc = launch_cg(a, w.variant, w.blocks, s);
         if (rc) return rc;
+        if (a.close) {
+            if (core_end) MISDC_HIP(hipEventRecord(core_end, s));
+            return MISDC_OK;
+        }
     }
     if (core_end) MISDC_HIP(hipEventRecord(core_end, s));
     const bool cg2d = !(g.dim == 1 || g.n_flames > 0);
