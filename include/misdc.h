@@ -220,8 +220,10 @@ int misdc_transport_operators(misdc_mech_t mech, misdc_grid_t grid,
 /* Implicit diffusion (steps S3/S4): for every field except the bath solve
  * (I - c kappa0_f L_theta) y_f = r_f, theta = (T_lag/300)^1.7, then
  * y_bath = r_bath - sum_{k != bath} (y_k - r_k).  1-D grids: direct cyclic
- * tridiagonal solve; 2-D grids: Jacobi-preconditioned conjugate gradients on
- * all fields at once until |r_f|_2 <= rtol |b_f|_2 (rtol <= 0: 1e-13,
+ * tridiagonal solve; 2-D grids: preconditioned conjugate gradients on all
+ * fields at once (diagonal preconditioner, or, on grids of at most 128 tiles
+ * of 32 x 16 cells, Jacobi sweeps on each tile's own operator) until
+ * |r_f|_2 <= rtol |b_f|_2 (rtol <= 0: 1e-13,
  * maxit <= 0: 500).  dev_rhs, dev_y: N+1 fields; dev_T_lag: cells;
  * dev_iters_out (int32, may be NULL) receives the iteration count.  The
  * initial guess is dev_y's content if guess_in_y is non-zero, else rhs. */

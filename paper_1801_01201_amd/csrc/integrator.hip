@@ -1098,7 +1098,11 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if ((rc = dalloc(I, &I->cbuf, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->cgstats, 8))) return bail(rc);
     if ((rc = dalloc(I, &I->inc, (size_t)64 * NF * 2))) return bail(rc);
-    if ((rc = dalloc(I, &I->inc_partial, (size_t)I->inc_blocks * NF * 2))) return bail(rc);
+    // partials, then the arrival counter of the reduction (zero between uses)
+    if ((rc = dalloc(I, &I->inc_partial, (size_t)I->inc_blocks * NF * 2 + 8))) return bail(rc);
+    if (hipMemset(I->inc_partial, 0, sizeof(double) * ((size_t)I->inc_blocks * NF * 2 + 8)) !=
+        hipSuccess)
+        return bail(fail(MISDC_EDEVICE, "clear the reduction partials"));
     if ((rc = diffusion_work_alloc(I->dw, mech->m, grid->g))) return bail(rc);
     if (grid->g.n_flames > 0 && (rc = dalloc(I, &I->dt_cell, (size_t)n))) return bail(rc);
     hipError_t e = hipStreamCreateWithFlags(&I->sD, hipStreamNonBlocking);

@@ -202,7 +202,9 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
 int launch_lincomb_faces(const LinComb& lc, const Grid& g, const double* T_lag, DiffusionWork& w,
                          hipStream_t s);
 
-// max_i |a - b| and max_i |a| per field into out[2*f], out[2*f+1] (device)
+// max_i |a - b| and max_i |a| per field into out[2*f], out[2*f+1] (device);
+// partial holds nfields * partial_blocks * 2 doubles followed by a zeroed
+// 32-bit arrival counter (left zero after each launch)
 int launch_field_diff_max(int nfields, int64_t n, const double* a, const double* b,
                           double* partial, int partial_blocks, double* out, hipStream_t s);
 

@@ -498,9 +498,14 @@ __global__ void __launch_bounds__(256) closure_kernel(MechDev m, int64_t n, cons
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
+// max |a - b| and max |a| per field: per-block partials, and the block that
+// finishes last reduces them in block order (one launch; the arrival counter
+// `done` is reset by that block)
 __global__ void __launch_bounds__(256) diffmax_kernel(int nfields, int64_t n, const double* a,
-                                                      const double* b, double* partial) {
+                                                      const double* b, double* partial,
+                                                      double* out, unsigned* done) {
     __shared__ double sd[4], sa[4];
+    __shared__ int s_last;
     const int f = blockIdx.y;
     double md = 0.0, ma = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -525,19 +530,25 @@ __global__ void __launch_bounds__(256) diffmax_kernel(int nfields, int64_t n, co
         }
         partial[((size_t)f * gridDim.x + blockIdx.x) * 2 + 0] = md;
         partial[((size_t)f * gridDim.x + blockIdx.x) * 2 + 1] = ma;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned total = gridDim.x * gridDim.y;
+        s_last = __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                 total - 1u;
     }
-}
-
-__global__ void diffmax_final(int nfields, int nblocks, const double* partial, double* out) {
-    const int f = threadIdx.x;
-    if (f >= nfields) return;
-    double md = 0.0, ma = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-        md = fmax(md, partial[((size_t)f * nblocks + b) * 2 + 0]);
-        ma = fmax(ma, partial[((size_t)f * nblocks + b) * 2 + 1]);
+    __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int nblocks = (int)gridDim.x;
+    for (int g = threadIdx.x; g < nfields; g += blockDim.x) {
+        double gd = 0.0, ga = 0.0;
+        for (int bk = 0; bk < nblocks; ++bk) {
+            gd = fmax(gd, partial[((size_t)g * nblocks + bk) * 2 + 0]);
+            ga = fmax(ga, partial[((size_t)g * nblocks + bk) * 2 + 1]);
+        }
+        out[2 * g] = gd;
+        out[2 * g + 1] = ga;
     }
-    out[2 * f] = md;
-    out[2 * f + 1] = ma;
+    if (threadIdx.x == 0) *done = 0u;
 }
 
 GridDev grid_dev(const Grid& g) {
@@ -806,11 +817,10 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
 int launch_field_diff_max(int nfields, int64_t n, const double* a, const double* b,
                           double* partial, int partial_blocks, double* out, hipStream_t s) {
     if (n == 0) return MISDC_OK;
+    // the arrival counter follows the partials (zero between launches)
+    unsigned* done = reinterpret_cast<unsigned*>(partial + (size_t)nfields * partial_blocks * 2);
     hipLaunchKernelGGL(diffmax_kernel, dim3(partial_blocks, nfields), dim3(256), 0, s, nfields, n,
-                       a, b, partial);
-    MISDC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(diffmax_final, dim3(1), dim3(64), 0, s, nfields, partial_blocks, partial,
-                       out);
+                       a, b, partial, out, done);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;
 }
