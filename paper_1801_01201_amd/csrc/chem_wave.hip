@@ -182,35 +182,48 @@ __device__ __forceinline__ void species_state(const MechDev& m, const Lds& L, do
 // F_R of species lane k (and, with JAC, the rows of I - c J in LDS:
 // M[k][l] -= c dFR_k/dY_l, returns dFR_k/dT in *fT).  The matrix rows must
 // hold the identity part before the call.
+// The entries of a chunk are taken EB at a time with all of their table
+// loads issued first (no load depends on another), in list order.
 template <bool JAC>
 __device__ __forceinline__ double source_and_rows(const MechDev& m, const Lds& L, int ld, double T,
                                                   double c, double* fT) {
+    constexpr int EB = 4;
     const int lane = threadIdx.x;
     const double lnT = log(T), invT = 1.0 / T;
     double fr = 0.0, ft = 0.0;
-    int e = 0, e_end = 0;
-    if (lane < m.N) {
-        e = m.rowp[lane];
-        e_end = m.rowp[lane + 1];
-    }
-    for (int base = 0; base < m.R; base += WV) {
+    const int* rc = m.rowc + (size_t)(lane < m.N ? lane : 0) * (m.nch + 1);
+    for (int base = 0, ch = 0; base < m.R; base += WV, ++ch) {
         chunk_rates<JAC>(m, L, base + lane, T, lnT, invT);
         __syncthreads();
-        while (e < e_end && m.rowj[e] < base + WV) {
-            const int j = m.rowj[e];
-            const int jj = j - base;
-            const double u = m.rowu[e];
-            fr += u * L.q[jj];
-            if (JAC) {
-                ft += u * L.qT[jj];
-                double* row = L.M + (size_t)lane * ld;
+        if (lane < m.N) {
+            const int e1 = rc[ch + 1];
+            for (int e = rc[ch]; e < e1; e += EB) {
+                int jj[EB], sl[EB][4];
+                double u[EB];
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int l = m.slots[4 * j + s];
-                    if (l >= 0) row[l] -= c * u * L.D[s * WV + jj];
+                for (int q = 0; q < EB; ++q) {
+                    const int ee = e + q < e1 ? e + q : e;
+                    jj[q] = m.rowj[ee] - base;
+                    u[q] = m.rowu[ee];
+                    if (JAC)
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) sl[q][s] = m.rowl[4 * ee + s];
+                }
+#pragma unroll
+                for (int q = 0; q < EB; ++q) {
+                    if (e + q >= e1) break;
+                    fr += u[q] * L.q[jj[q]];
+                    if (JAC) {
+                        ft += u[q] * L.qT[jj[q]];
+                        double* row = L.M + (size_t)lane * ld;
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const int l = sl[q][s];
+                            if (l >= 0) row[l] -= c * u[q] * L.D[s * WV + jj[q]];
+                        }
+                    }
                 }
             }
-            ++e;
         }
         __syncthreads();
     }

@@ -740,9 +740,20 @@ int misdc_mech_create(const misdc_mech_desc* d, misdc_mech_t* out) {
         rowp[k + 1] = (int)rowj.size();
     }
     const size_t nnz = rowj.size();
+    const int nch = (R + 63) / 64;
+    std::vector<int> rowl(4 * nnz), rowc((size_t)N * (nch + 1));
+    for (size_t e = 0; e < nnz; ++e)
+        for (int s = 0; s < 4; ++s) rowl[4 * e + s] = slots[4 * (size_t)rowj[e] + s];
+    for (int k = 0; k < N; ++k)
+        for (int c = 0; c <= nch; ++c) {
+            int e = rowp[k];
+            while (e < rowp[k + 1] && rowj[e] < 64 * c) ++e;
+            rowc[(size_t)k * (nch + 1) + c] = e;
+        }
     // one device block: doubles then ints
     const size_t nd = (size_t)R * 5 + (size_t)R * N + (size_t)N * 6 + (N + 1) + nnz;
-    const size_t bytes = nd * sizeof(double) + (slots.size() + rowp.size() + nnz) * sizeof(int) + 64;
+    const size_t nints = slots.size() + rowp.size() + nnz + rowl.size() + rowc.size();
+    const size_t bytes = nd * sizeof(double) + nints * sizeof(int) + 64;
     hipError_t e = hipGetDevice(&m.device);
     if (e != hipSuccess) {
         delete h;
@@ -772,6 +783,9 @@ int misdc_mech_create(const misdc_mech_desc* d, misdc_mech_t* out) {
     if (!slots.empty()) std::memcpy(ip, slots.data(), slots.size() * sizeof(int));
     std::memcpy(ip + slots.size(), rowp.data(), rowp.size() * sizeof(int));
     if (nnz) std::memcpy(ip + slots.size() + rowp.size(), rowj.data(), nnz * sizeof(int));
+    if (nnz) std::memcpy(ip + slots.size() + rowp.size() + nnz, rowl.data(), rowl.size() * sizeof(int));
+    std::memcpy(ip + slots.size() + rowp.size() + nnz + rowl.size(), rowc.data(),
+                rowc.size() * sizeof(int));
     e = hipMemcpy(m.block, host.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(m.block);
@@ -805,6 +819,9 @@ int misdc_mech_create(const misdc_mech_desc* d, misdc_mech_t* out) {
     md.rowu = base + oru;
     md.rowp = md.slots + slots.size();
     md.rowj = md.rowp + rowp.size();
+    md.rowl = md.rowj + nnz;
+    md.rowc = md.rowl + rowl.size();
+    md.nch = nch;
     m.W.assign(d->W, d->W + N);
     m.cp.assign(d->cp, d->cp + N);
     m.hf.assign(d->hf, d->hf + N);

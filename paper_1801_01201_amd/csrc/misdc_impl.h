@@ -53,6 +53,13 @@ struct MechDev {
     const int* rowp;              // N+1
     const int* rowj;              // nnz
     const double* rowu;           // nnz
+    // the same lists for the chunked evaluation (reactions in chunks of 64):
+    // rowl[4 e + s] = slot species s of reaction rowj[e] (so an entry needs no
+    // second, dependent lookup), and rowc[k (nch + 1) + c] = the first entry
+    // of species k whose reaction is in chunk c or later
+    const int* rowl;              // 4 nnz
+    const int* rowc;              // N (nch + 1)
+    int nch;                      // chunks of 64 reactions
 };
 
 struct Mech {
