@@ -248,25 +248,24 @@ __device__ __forceinline__ double lu_solve_lanes(double (&a)[NXP], double g, con
         int p = first_lane(__ballot(!done && cand == mx));
         if (p < 0) p = first_lane(__ballot(!done));       // NaN column: any remaining row
         p = __builtin_amdgcn_readfirstlane(p);
+        // the pivot row reaches the other lanes through scalar registers
+        // (lane reads of the pivot lane), not through LDS
+        const double pinv = 1.0 / lane_read(a[c], p);
+        const double pg = lane_read(g, p);
         if (lane == p) {
-#pragma unroll
-            for (int l = c; l < NXP; ++l) L.piv[l] = a[l];
-            L.piv[NXP] = g;
-            dinv = 1.0 / a[c];
-            L.piv[NXP + 1] = dinv;
+            dinv = pinv;
             L.plane[c] = p;
             done = true;
         }
-        __syncthreads();
         if (!done) {
-            const double f = a[c] * L.piv[NXP + 1];
+            const double f = a[c] * pinv;
             a[c] = f;
 #pragma unroll
-            for (int l = c + 1; l < NXP; ++l) a[l] -= f * L.piv[l];
-            g -= f * L.piv[NXP];
+            for (int l = c + 1; l < NXP; ++l) a[l] -= f * lane_read(a[l], p);
+            g -= f * pg;
         }
-        __syncthreads();
     }
+    __syncthreads();
     double x = 0.0;
 #pragma unroll
     for (int c = NXP - 1; c >= 0; --c) {
@@ -655,6 +654,10 @@ int launch_reaction_newton_wave(const Mech& m, const NewtonArgs& a, int lu, hipS
     } else if (n <= 32) {
         const size_t lds = lds_doubles<32, false>(n, ld) * sizeof(double);
         hipLaunchKernelGGL((newton_wave_kernel<32, 0>), grid, block, lds, s, m.dev, a);
+    } else if (n <= 56) {
+        // (the LU runs over NXP columns: the tighter the padding, the fewer)
+        const size_t lds = lds_doubles<56, false>(n, ld) * sizeof(double);
+        hipLaunchKernelGGL((newton_wave_kernel<56, 0>), grid, block, lds, s, m.dev, a);
     } else {
         const size_t lds = lds_doubles<64, false>(n, ld) * sizeof(double);
         hipLaunchKernelGGL((newton_wave_kernel<64, 0>), grid, block, lds, s, m.dev, a);
