@@ -316,24 +316,21 @@ __device__ __forceinline__ void lu32_factor(const Lds32& S, int* plane, int& myp
             int p = first_lane(__ballot(!done && cand == mx));
             if (p < 0) p = first_lane(__ballot(!done));
             p = __builtin_amdgcn_readfirstlane(p);
+            // the pivot row of the panel reaches the other lanes by lane reads
+            const float pinv = 1.f / lane_readf(pan[t], p);
             if (lane == p) {
-#pragma unroll
-                for (int u = t; u < 16; ++u) S.piv[u] = pan[u];
-                myinv = 1.f / pan[t];
-                S.piv[16] = myinv;
+                myinv = pinv;
                 plane[k0 + t] = p;
                 S.pos[lane] = k0 + t;
                 mypos = k0 + t;
                 done = true;
             }
-            __syncthreads();
             if (!done) {
-                const float f = pan[t] * S.piv[16];
+                const float f = pan[t] * pinv;
                 pan[t] = f;
 #pragma unroll
-                for (int u = t + 1; u < 16; ++u) pan[u] -= f * S.piv[u];
+                for (int u = t + 1; u < 16; ++u) pan[u] -= f * lane_readf(pan[u], p);
             }
-            __syncthreads();
         }
 #pragma unroll
         for (int t = 0; t < 16; ++t) S.A[lane * LDA32 + k0 + t] = pan[t];
