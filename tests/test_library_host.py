@@ -115,3 +115,25 @@ def test_null_handles_rejected(nat):
     o = nat.misdc_opts_default()
     assert (o.n_nodes, o.n_sweeps, o.nu, o.scheme) == (5, 6, 1, 2)
     assert o.use_graph == 0
+
+
+def _header_struct_fields(name):
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    m = re.search(r"typedef struct\s*\{([^{}]*)\}\s*" + name + r"\s*;", text)
+    assert m, name
+    fields = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        fields.append(re.findall(r"([A-Za-z_][A-Za-z_0-9]*)\s*(?:\[[^\]]*\])?\s*$", decl)[0])
+    return fields
+
+
+@pytest.mark.parametrize("name", ["misdc_tune", "misdc_opts", "misdc_newton_opts", "misdc_stats"])
+def test_binding_structs_match_header(nat, name):
+    """The Python binding's ctypes structures list the header's fields in
+    the header's order (the C ABI passes them by pointer)."""
+    cls = getattr(nat, name)
+    assert [f[0] for f in cls._fields_] == _header_struct_fields(name)
