@@ -39,6 +39,29 @@ NEWTON_BYTES_PER_SOLVE_9 = 316.0
 NEWTON_FLOP_PER_ITER_53 = 1.49e5
 
 
+def newton_sweep_stats(integ, sweeps):
+    """Per-sweep Newton iterations per cell-node solve of the last step:
+    mean, p50, p99 and max, from the library's outcome histograms."""
+    out = []
+    for k in range(sweeps):
+        h = integ.newton_histogram(k)
+        tot = sum(h[1:])
+        if tot == 0:
+            out.append({"sweep": k, "solves": 0})
+            continue
+        cum, pct = 0, {}
+        for v in range(1, len(h)):
+            cum += h[v]
+            for q in (0.5, 0.99):
+                if q not in pct and cum >= q * tot:
+                    pct[q] = v
+        out.append({"sweep": k, "solves": sum(h), "failed": h[0],
+                    "mean": sum(v * h[v] for v in range(1, len(h))) / tot,
+                    "p50": pct[0.5], "p99": pct[0.99],
+                    "max": max(v for v in range(1, len(h)) if h[v])})
+    return out
+
+
 def measured_traffic(profile_name, source_rel):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or
     None when the kernel source has changed since the counters were taken."""
@@ -192,11 +215,12 @@ def ensemble_main(args):
         for _ in range(args.steps):
             integ.step(st, 0.0, dt_per_flame=d_dt)
         torch.cuda.synchronize()
-        res[mode] = (time.perf_counter() - t0, integ.stats())
+        res[mode] = (time.perf_counter() - t0, integ.stats(),
+                     newton_sweep_stats(integ, cfg["sweeps"]))
         integ.close()
     execution = "graph" if res["graph"][0] <= res["eager"][0] else "eager"
-    el, stats = res[execution]
-    elp, sp = res["profile"]
+    el, stats, newton_sweeps = res[execution]
+    elp, sp, _ = res["profile"]
     updates = n * M * cfg["nu"] * cfg["sweeps"] * args.steps
     d_ms, d_n = sp["diffusion_kernel_ms"], sp["diffusion_kernel_launches"]
     r_ms, r_n = sp["newton_kernel_ms"], sp["newton_kernel_launches"]
@@ -229,6 +253,7 @@ def ensemble_main(args):
                                f"CISDCQ-{cfg['nu']}, {cfg['n_nodes']} nodes, {cfg['sweeps']} sweeps",
                    "cells": n, "flames": nf},
         "newton_iters_per_cell": newton_per_cell,
+        "newton_iters_per_sweep": newton_sweeps,
         "execution": execution,
         "graph_ms_per_step": res["graph"][0] / args.steps * 1e3,
         "eager_ms_per_step": res["eager"][0] / args.steps * 1e3,
@@ -288,6 +313,7 @@ def n53_main(args):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         stats = integ.stats()
+        stats["per_sweep"] = newton_sweep_stats(integ, cfg["sweeps"])
         integ.close()
         runs[lu] = (el, stats, st)
         print(f"[bench] n53 {lu}: {el / args.steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
@@ -332,6 +358,7 @@ def n53_main(args):
                                f"{cfg['sweeps']} sweeps, dt {cfg['dt']} s, Newton LU {args.lu}",
                    "cells": n},
         "newton_iters_per_cell": newton_per_cell,
+        "newton_iters_per_sweep": stats["per_sweep"],
         "cg_iters_per_solve": cg_per_solve,
         "roofline": roof,
         "kernel_split": {"diffusion_solve_ms_per_launch": d_ms / max(1, d_n),
@@ -570,6 +597,7 @@ def main():
     updates = n * M * cfg["nu"] * cfg["sweeps"] * args.steps
     value = updates / elapsed
     newton_per_cell = stats["newton_iters"] / max(1, stats["newton_solves"])
+    newton_sweeps = newton_sweep_stats(integ, cfg["sweeps"])
     cg_per_solve = stats["cg_iters"] / max(1, stats["cg_solves"])
     graph = None if args.no_graph else graph_leg(integ, mh, g, cfg, state, args, tune)
 
@@ -626,6 +654,7 @@ def main():
                    "cells": n, "nodes": cfg["n_nodes"], "sweeps": cfg["sweeps"],
                    "nu": cfg["nu"], "scheme": cfg["scheme"], "serialize": args.serialize},
         "newton_iters_per_cell": newton_per_cell,
+        "newton_iters_per_sweep": newton_sweeps,
         "cg_iters_per_solve": cg_per_solve,
         "cell_node_updates_per_step_incl_node0": n * (M + 1) * cfg["nu"] * cfg["sweeps"],
         "roofline": roof,

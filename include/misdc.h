@@ -355,6 +355,15 @@ typedef struct {
     int64_t newton_guess_learned;
 } misdc_stats;
 
+/* Outcomes of the last step's cell-node Newton solves in sweep k (0 <= k <
+ * n_sweeps of that step; MISDC_EINVAL otherwise), for the per-sweep
+ * iteration statistics of the reaction step S5: counts[0] = solves that did
+ * not converge, counts[v] = solves that converged after v linear solves
+ * (1 <= v <= 62), counts[63] = after 63 or more.  counts is a host array of
+ * 64 entries owned by the caller.  Synchronises with the integrator's
+ * streams.  The counts of a sweep add up to cells x M x nu. */
+int misdc_get_newton_histogram(misdc_integ_t integ, int sweep, int64_t* counts);
+
 /* Clears the accumulated kernel timings of opts.profile. */
 int misdc_reset_profile(misdc_integ_t integ);
 

@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include "misdc_impl.h"
+#include "newton_hist.h"
 
 namespace misdc {
 
@@ -344,24 +345,37 @@ __global__ void __launch_bounds__(64) newton_kernel(MechDev m, NewtonArgs a) {
             if (bad) atomicAdd(&b[2], (unsigned long long)bad);
             atomicMax(&b[3], (unsigned long long)mx);
         }
+        if (a.hist)
+            wave_hist_add(a.hist + (size_t)((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) %
+                                            NEWTON_HIST_SETS) * NEWTON_HIST_BINS,
+                          i < a.n, code);
     }
 }
 
 // wave-aggregated statistics: [0] solves, [1] iterations, [2] failures, [3] max
 // (grid-stride over few workgroups: the counters take one atomic per
-// workgroup, and many workgroups contending for them cost more than the sum)
+// workgroup, and many workgroups contending for them cost more than the sum);
+// with hist, the histogram of the outcomes as well
 template <int NS>
 __global__ void __launch_bounds__(256) newton_stats_kernel(int64_t n, const int32_t* iters,
-                                                           unsigned long long* stats) {
+                                                           unsigned long long* stats,
+                                                           unsigned long long* hist) {
     __shared__ unsigned long long s_sum[4], s_bad[4], s_max[4];
     unsigned long long v = 0, b = 0, mx = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t it = iters[i];
+    unsigned long long* set =
+        hist ? hist + (size_t)((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) %
+                               NEWTON_HIST_SETS) * NEWTON_HIST_BINS
+             : nullptr;
+    // the loop bound is the same for all lanes of a wavefront
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const int32_t it = i < n ? iters[i] : 0;
         const unsigned long long vi = it > 0 ? (unsigned long long)it : 0ull;
         v += vi;
-        b += it < 0 ? 1ull : 0ull;
+        b += (i < n && it < 0) ? 1ull : 0ull;
         mx = vi > mx ? vi : mx;
+        if (set) wave_hist_add(set, i < n, it);
     }
     for (int off = 32; off > 0; off >>= 1) {
         v += __shfl_xor(v, off);
@@ -487,7 +501,7 @@ int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s) {
     if (a.stats && a.iters && !a.buckets) {
         const int64_t gb = grid_for(a.n, 256 * 16);
         hipLaunchKernelGGL(newton_stats_kernel<9>, dim3(gb < 32 ? gb : 32), dim3(256), 0, s, a.n,
-                           a.iters, a.stats);
+                           a.iters, a.stats, a.hist);
         MISDC_HIP(hipGetLastError());
     }
     return MISDC_OK;

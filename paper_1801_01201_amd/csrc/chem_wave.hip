@@ -31,6 +31,7 @@
 #include <cmath>
 
 #include "misdc_impl.h"
+#include "newton_hist.h"
 #include "wave.h"
 
 namespace misdc {
@@ -582,15 +583,18 @@ inline unsigned grid_for(int64_t n, int threads) {
 }
 
 // [0] solves, [1] iterations, [2] failures, [3] max iterations,
-// [4] FP32 refinement solves, [5] FP64 fallbacks (with lu_info)
+// [4] FP32 refinement solves, [5] FP64 fallbacks (with lu_info); with hist,
+// the histogram of the outcomes as well
 __global__ void __launch_bounds__(256) wave_stats_kernel(int64_t n, const int32_t* iters,
                                                          const int32_t* lu_info,
-                                                         unsigned long long* stats) {
+                                                         unsigned long long* stats,
+                                                         unsigned long long* hist) {
     __shared__ unsigned long long s_sum[4], s_bad[4], s_max[4], s_ref[4], s_fb[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long v = 0, b = 0, mx = 0, rf = 0, fb = 0;
+    int32_t itc = 0;
     if (i < n) {
-        const int32_t itc = iters[i];
+        itc = iters[i];
         v = itc > 0 ? (unsigned long long)itc : 0ull;
         b = itc < 0 ? 1ull : 0ull;
         mx = v;
@@ -599,6 +603,10 @@ __global__ void __launch_bounds__(256) wave_stats_kernel(int64_t n, const int32_
             fb = (unsigned long long)((unsigned)lu_info[i] >> 16);
         }
     }
+    if (hist)
+        wave_hist_add(hist + (size_t)((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) %
+                                      NEWTON_HIST_SETS) * NEWTON_HIST_BINS,
+                      i < n, itc);
     for (int off = 32; off > 0; off >>= 1) {
         v += __shfl_xor(v, off);
         b += __shfl_xor(b, off);
@@ -662,7 +670,7 @@ int launch_reaction_newton_wave(const Mech& m, const NewtonArgs& a, int lu, hipS
     MISDC_HIP(hipGetLastError());
     if (a.stats && a.iters) {
         hipLaunchKernelGGL(wave_stats_kernel, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a.n,
-                           a.iters, a.lu_info, a.stats);
+                           a.iters, a.lu_info, a.stats, a.hist);
         MISDC_HIP(hipGetLastError());
     }
     return MISDC_OK;

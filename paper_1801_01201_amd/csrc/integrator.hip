@@ -85,6 +85,7 @@ struct misdc_integ_s {
     int32_t* iters = nullptr;                     // Newton iterations (cells)
     unsigned long long* nstats = nullptr;         // Newton statistics (8)
     unsigned long long* nbuckets = nullptr;       // per-thread Newton kernel's counter sets
+    unsigned long long* nhist = nullptr;          // Newton outcome histograms [sweep][set][bin]
     int32_t* lu_info = nullptr;                   // FP32 LU refinement record (cells)
     int32_t* cgstats = nullptr;                   // CG: [0] sum, [1] max, [2] failed, [3] solves, [4] timeouts
     double* inc = nullptr;                        // sweep increments: 64 x NF x 2
@@ -472,6 +473,7 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     a.lu_info = (I->opt.newton.lu == MISDC_LU_FP32_MFMA) ? I->lu_info : nullptr;
     a.stats = I->nstats;
     a.buckets = I->nbuckets;
+    a.hist = I->nhist + (size_t)I->sweep_index * NEWTON_HIST_SETS * NEWTON_HIST_BINS;
     a.opt = I->opt.newton;
     // staggered: the Newton solve of node p starts once the diffusion solve
     // of node p+1 (issued just before this task) is about to start, so that
@@ -639,6 +641,9 @@ int issue_step(misdc_integ_s* I, double* state, double dt, const double* dtf) {
     if ((rc = launch_zero(I->nstats, 8 * sizeof(unsigned long long), I->sD))) return rc;
     if ((rc = launch_zero(I->nbuckets, sizeof(unsigned long long) * NEWTON_BUCKETS *
                                            NEWTON_BUCKET_STRIDE, I->sD)))
+        return rc;
+    if ((rc = launch_zero(I->nhist, sizeof(unsigned long long) * I->opt.n_sweeps *
+                                        NEWTON_HIST_SETS * NEWTON_HIST_BINS, I->sD)))
         return rc;
     if ((rc = launch_zero(I->cgstats, 8 * sizeof(int32_t), I->sD))) return rc;
     // I1, I2, I4: every node of sweep 0 holds phi^n and F(phi^n)
@@ -1110,6 +1115,10 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if (hipMemset(I->nbuckets, 0, sizeof(unsigned long long) * NEWTON_BUCKETS * NEWTON_BUCKET_STRIDE) !=
         hipSuccess)
         return bail(fail(MISDC_EDEVICE, "clear the Newton counters"));
+    if ((rc = dalloc(I, &I->nhist, (size_t)64 * NEWTON_HIST_SETS * NEWTON_HIST_BINS))) return bail(rc);
+    if (hipMemset(I->nhist, 0, sizeof(unsigned long long) * 64 * NEWTON_HIST_SETS * NEWTON_HIST_BINS) !=
+        hipSuccess)
+        return bail(fail(MISDC_EDEVICE, "clear the Newton histograms"));
     if ((rc = dalloc(I, &I->lu_info, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->choice, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->cbuf, (size_t)n))) return bail(rc);
@@ -1483,6 +1492,25 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
             }
             st->sweep_increment[k] = worst;
         }
+    }
+    return MISDC_OK;
+}
+
+int misdc_get_newton_histogram(misdc_integ_t I, int sweep, int64_t* counts) {
+    if (!I || !counts) return fail(MISDC_EINVAL, "NULL argument");
+    if (sweep < 0 || sweep >= I->last_sweeps)
+        return fail(MISDC_EINVAL, "sweep %d outside the last step's %d sweeps", sweep,
+                    I->last_sweeps);
+    MISDC_HIP(hipStreamSynchronize(I->sD));
+    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
+    MISDC_HIP(hipStreamSynchronize(I->sR2));
+    std::vector<unsigned long long> h((size_t)NEWTON_HIST_SETS * NEWTON_HIST_BINS);
+    MISDC_HIP(hipMemcpy(h.data(), I->nhist + (size_t)sweep * NEWTON_HIST_SETS * NEWTON_HIST_BINS,
+                        sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
+    for (int b = 0; b < NEWTON_HIST_BINS; ++b) {
+        unsigned long long c = 0;
+        for (int k = 0; k < NEWTON_HIST_SETS; ++k) c += h[(size_t)k * NEWTON_HIST_BINS + b];
+        counts[b] = (int64_t)c;
     }
     return MISDC_OK;
 }

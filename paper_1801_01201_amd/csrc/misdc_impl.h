@@ -112,9 +112,15 @@ struct NewtonArgs {
     // each wavefront into NEWTON_BUCKETS sets of counters (set b at
     // b * NEWTON_BUCKET_STRIDE), and no statistics kernel follows
     unsigned long long* buckets = nullptr;
+    // may be null: histogram of the solves' outcomes in NEWTON_HIST_SETS sets
+    // of NEWTON_HIST_BINS counters (bin 0: not converged; bin v: converged
+    // after v linear solves, the last bin also counting more); wavefront w of
+    // the launch adds to set w % NEWTON_HIST_SETS
+    unsigned long long* hist = nullptr;
     misdc_newton_opts opt;
 };
 constexpr int NEWTON_BUCKETS = 32, NEWTON_BUCKET_STRIDE = 16;   // 128-byte apart
+constexpr int NEWTON_HIST_BINS = 64, NEWTON_HIST_SETS = 8;
 int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s);
 // one wavefront per cell (any species count up to 63): FP64 LU, or an FP32
 // LU on the matrix cores refined against the FP64 matrix

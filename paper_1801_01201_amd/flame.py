@@ -108,6 +108,9 @@ class Integrator:
     def stats(self):
         return nat.misdc_get_stats(self.handle)
 
+    def newton_histogram(self, sweep):
+        return nat.misdc_get_newton_histogram(self.handle, sweep)
+
     def close(self):
         if self.handle:
             nat.misdc_integ_destroy(self.handle)

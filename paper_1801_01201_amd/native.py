@@ -31,7 +31,7 @@ EXPORTED = [
     "misdc_grid_create_ensemble", "misdc_grid_destroy", "misdc_grid_cells",
     "misdc_transport_operators", "misdc_diffusion_solve", "misdc_opts_default",
     "misdc_integ_create", "misdc_integ_destroy", "misdc_step", "misdc_get_stats",
-    "misdc_reset_profile", "misdc_autotune", "misdc_get_tune", "misdc_set_tune",
+    "misdc_get_newton_histogram", "misdc_reset_profile", "misdc_autotune", "misdc_get_tune", "misdc_set_tune",
     "misdc_mlp_create", "misdc_mlp_destroy", "misdc_mlp_param_count", "misdc_mlp_set_params",
     "misdc_mlp_get_params", "misdc_mlp_set_normalization", "misdc_mlp_forward",
     "misdc_mlp_gradients", "misdc_mlp_adam_step", "misdc_mlp_train", "misdc_mlp_features",
@@ -123,6 +123,7 @@ def load(path=LIB_PATH):
         "misdc_integ_destroy": (C.c_int, [vp]),
         "misdc_step": (C.c_int, [vp, vp, dbl, vp, vp]),
         "misdc_get_stats": (C.c_int, [vp, C.POINTER(misdc_stats)]),
+        "misdc_get_newton_histogram": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int64)]),
         "misdc_reset_profile": (C.c_int, [vp]),
         "misdc_autotune": (C.c_int, [vp, vp, dbl, vp, C.c_int, C.POINTER(misdc_tune), vp]),
         "misdc_get_tune": (C.c_int, [vp, C.POINTER(misdc_tune)]),
@@ -321,6 +322,18 @@ def misdc_get_stats(integ):
     s = misdc_stats()
     check(lib().misdc_get_stats(integ, C.byref(s)))
     return s.as_dict()
+
+
+NEWTON_HIST_BINS = 64
+
+
+def misdc_get_newton_histogram(integ, sweep):
+    """Outcomes of the last step's Newton solves in one sweep: a list of 64
+    counts, [0] not converged, [v] converged after v linear solves, [63]
+    after 63 or more."""
+    counts = (C.c_int64 * NEWTON_HIST_BINS)()
+    check(lib().misdc_get_newton_histogram(integ, int(sweep), counts))
+    return list(counts)
 
 
 def misdc_reset_profile(integ):

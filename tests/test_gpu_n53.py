@@ -164,10 +164,14 @@ def test_step_53(nat, mech53, mh53, scheme, nu, sweeps):
     integ = Integrator(mh53, g, n_nodes=5, sweeps=sweeps, nu=nu, scheme=scheme)
     integ.step(st, dt)
     stats = integ.stats()
+    # the wavefront kernel's statistics pass fills the per-sweep histograms
+    hists = np.array([integ.newton_histogram(k) for k in range(sweeps)])
     out = host(st)
     integ.close()
     g.close()
     assert stats["newton_failed"] == 0 and stats["cg_failed"] == 0
+    assert np.all(hists.sum(axis=1) == nx * ny * 4 * (nu if scheme == "cisdcq" else 1))
+    assert int((np.arange(64) * hists.sum(axis=0)).sum()) == stats["newton_iters"]
     err = field_err(out, ref.reshape(54, -1))
     assert err <= TOL, err
 

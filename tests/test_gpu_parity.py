@@ -253,6 +253,60 @@ def test_step_parity(nat, mech9, mh, case):
     assert err <= TOL, err
 
 
+def _histogram(it):
+    """Outcome histogram of per-cell Newton counts in the library's bins:
+    [0] not converged, [v] v linear solves, [63] 63 or more."""
+    it = np.asarray(it).ravel()
+    h = np.zeros(64, dtype=np.int64)
+    np.add.at(h, np.where(it < 0, 0, np.minimum(it, 63)), 1)
+    return h
+
+
+def test_newton_histogram_per_sweep(nat, mech9, mh):
+    """Per-sweep Newton iteration histograms (S5 solves of one CISDCQ-2 step):
+    every cell-node solve of a sweep is counted once, the histograms add up
+    to the step's counters, and each sweep's distribution is the oracle's
+    (counts decided in FP64 on both sides; see _iteration_counts_agree)."""
+    name, dim, shape, dx, u, n_nodes, sweeps, steps, scheme, nu = STEP_CASES[4]
+    Y, T = synth.flame_2d(mech9, shape[1], shape[0], dx[0], dx[1])
+    prob = FlameProblem(mech9, dx, u)
+    phi = relaxed_initial_state(prob, Y, T)
+    prob.newton_iters.clear()
+    dt = 5e-5
+    sdc_step(prob, phi, dt, n_nodes, sweeps, scheme, nu=nu)
+    M = n_nodes - 1
+    assert len(prob.newton_iters) == sweeps * M * nu
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    g = Grid(dim, [shape[1], shape[0]], list(dx), list(u))
+    integ = Integrator(mh, g, n_nodes=n_nodes, sweeps=sweeps, nu=nu, scheme=scheme)
+    st = _gpu_initial(nat, mh, Y, T)
+    integ.step(st, dt)
+    stats = integ.stats()
+    hists = np.array([integ.newton_histogram(k) for k in range(sweeps)])
+    with pytest.raises(nat.MisdcError):
+        integ.newton_histogram(sweeps)
+    with pytest.raises(nat.MisdcError):
+        integ.newton_histogram(-1)
+    integ.close()
+    g.close()
+    cells = shape[0] * shape[1]
+    assert np.all(hists.sum(axis=1) == cells * M * nu)
+    tot = hists.sum(axis=0)
+    v = np.arange(64)
+    assert tot[63] == 0
+    assert tot[0] == stats["newton_failed"] == 0
+    assert int((v * tot).sum()) == stats["newton_iters"]
+    assert v[tot > 0].max() == stats["newton_max"]
+    for k in range(sweeps):
+        ref = _histogram(np.concatenate(prob.newton_iters[k * M * nu:(k + 1) * M * nu]))
+        assert ref.sum() == hists[k].sum()
+        # same distribution: >= 90 % of the solves in common bins, mean within 2 %
+        assert np.minimum(ref, hists[k]).sum() >= 0.90 * ref.sum(), (k, ref[:12], hists[k][:12])
+        mean_ref = (v * ref).sum() / ref.sum()
+        mean_gpu = (v * hists[k]).sum() / hists[k].sum()
+        assert abs(mean_gpu - mean_ref) <= 0.02 * mean_ref, (k, mean_gpu, mean_ref)
+
+
 def test_step_parity_global_memory_cg(nat, mech9, mh, monkeypatch):
     """The CG variant that keeps its vectors in global memory (used when the
     register-resident one does not fit) gives the same step."""
