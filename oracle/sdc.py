@@ -101,7 +101,26 @@ def sweep_misdcq(prob, phi, F, dt, tab):
     return new_phi, new_F
 
 
-def sweep_cisdcq(prob, phi, F, dt, tab, nu):
+def relative_change(new, old):
+    """max over fields of max_i |new_f - old_f| / max_i |new_f| (fields on the
+    first axis; a 0-d or 1-d state is one field).  A field with max |new_f| = 0
+    counts 0 if it did not change and infinity otherwise."""
+    new = np.asarray(new, dtype=np.float64)
+    old = np.asarray(old, dtype=np.float64)
+    if new.ndim <= 1:
+        new, old = new.reshape(1, -1), old.reshape(1, -1)
+    else:
+        new, old = new.reshape(new.shape[0], -1), old.reshape(old.shape[0], -1)
+    out = 0.0
+    for f in range(new.shape[0]):
+        d = float(np.max(np.abs(new[f] - old[f])))
+        m = float(np.max(np.abs(new[f])))
+        r = d / m if m > 0 else (0.0 if d == 0 else np.inf)
+        out = max(out, r)
+    return out
+
+
+def sweep_cisdcq(prob, phi, F, dt, tab, nu, nu_tol=None, passes=None, changes=None):
     """One CISDCQ-nu sweep: nu nested iterations over the nodes.
 
     Buffers: ``prev`` holds the values of nested iteration l (l = 0 is the lag
@@ -109,6 +128,14 @@ def sweep_cisdcq(prob, phi, F, dt, tab, nu):
     diffusion update at node m+1 uses iteration-(l+1) values at nodes
     j <= m-1 and iteration-l (lagged) values at nodes m and m+1; the reaction
     update is the correction form of eq. ..._R_alt.
+
+    Adaptive nested iterations (``nu_tol``; the paper leaves the rule to
+    future work in its sections 4.1-4.3): nu is then the largest number of
+    passes.  delta_l = relative_change of the node-M state made by pass l
+    (delta_1 against sweep k's values).  After pass l >= 2 the sweep stops
+    if delta_l <= nu_tol * delta_1: the nested iteration has stalled
+    relative to the sweep's own change.  The number of passes done is
+    appended to ``passes``, the list of the sweep's delta_l to ``changes``.
     """
     M = tab["M"]
     Q, QI, QE = tab["Q"], tab["QI"], tab["QE"]
@@ -118,6 +145,7 @@ def sweep_cisdcq(prob, phi, F, dt, tab, nu):
     prev_phi = list(phi)
     prev_F = list(F)
     ad_F = [None] * (M + 1)         # FA, FD at phi_AD^{m,(k+1,1)} (lag init A/D)
+    deltas = []
     for ell in range(nu):
         cur_phi = [phi0] + [None] * M
         cur_F = [F[0]] + [None] * M
@@ -153,7 +181,19 @@ def sweep_cisdcq(prob, phi, F, dt, tab, nu):
             b = b - c * prev_F[p].R
             cur_phi[p] = prob.solve_R(c, b, prev_phi[p])
             cur_F[p] = _evalF(prob, cur_phi[p])
+        done = ell + 1
+        stop = False
+        if nu_tol is not None:
+            delta = relative_change(cur_phi[M], prev_phi[M])
+            deltas.append(delta)
+            stop = ell >= 1 and delta <= nu_tol * deltas[0]
         prev_phi, prev_F = cur_phi, cur_F
+        if stop:
+            break
+    if passes is not None:
+        passes.append(done)
+    if changes is not None:
+        changes.append(deltas)
     return prev_phi, prev_F          # S7
 
 
@@ -179,14 +219,18 @@ def sweep_imexq(prob, phi, F, dt, tab):
 
 
 def sdc_step(prob, phi_n, dt, n_nodes, sweeps, scheme, nu=1, qe="cumulative",
-             increments=None, stop_tol=None, norm=None):
+             increments=None, stop_tol=None, norm=None, nu_tol=None, passes=None,
+             changes=None):
     """Advance phi_n by one step of size dt.
 
     I1-I2: node 0 and every node of sweep 0 hold phi^n; I4: the operator values
     at phi^n serve for the first sweep's quadrature.  After each sweep the
     increment |phi^{M,(k+1)} - phi^{M,(k)}| (``norm``, default max-abs) is
     appended to ``increments``.  With ``stop_tol`` the step stops at the first
-    sweep whose increment is <= stop_tol.  Returns (phi^{n+1}, sweeps done).
+    sweep whose increment is <= stop_tol.  CISDCQ with ``nu_tol`` adapts the
+    number of nested iterations of each sweep (see sweep_cisdcq); the passes
+    done per sweep are appended to ``passes`` and their changes to
+    ``changes``.  Returns (phi^{n+1}, sweeps done).
     """
     tab = scheme_tables(n_nodes, scheme, qe)
     S = node_to_node_weights(n_nodes) if scheme == "misdc" else None
@@ -202,7 +246,7 @@ def sdc_step(prob, phi_n, dt, n_nodes, sweeps, scheme, nu=1, qe="cumulative",
         elif scheme == "misdcq":
             new_phi, new_F = sweep_misdcq(prob, phi, F, dt, tab)
         elif scheme == "cisdcq":
-            new_phi, new_F = sweep_cisdcq(prob, phi, F, dt, tab, nu)
+            new_phi, new_F = sweep_cisdcq(prob, phi, F, dt, tab, nu, nu_tol, passes, changes)
         elif scheme == "imexq":
             new_phi, new_F = sweep_imexq(prob, phi, F, dt, tab)
         else:

@@ -143,3 +143,62 @@ def test_cost_ratio_formula():
         alpha = (ups_ad + ups_r) / max(ups_ad, ups_r)
         direct = NM * M * (ups_ad + ups_r) / (NC * (nu * (ups_ad + ups_r) + (M - 1) * max(ups_ad, ups_r)))
         assert abs(cost_ratio(NM, NC, nu, M, alpha) - direct) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# adaptive nested iterations (the paper's future-work item of sections 4.1-4.3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n_nodes", [3, 5])
+@pytest.mark.parametrize("adr", [(1.0, -2.0, -4.0), (0.5, -1.0, -1.0), (0.2, -3.0, -0.5)])
+def test_adaptive_nested_iterations_reach_the_imexq_sweep(n_nodes, adr):
+    """At a fixed point of the nested iterations (the same values in passes
+    l and l+1 at every node) the reaction update returns the diffusion
+    output, and the diffusion update with the lagged terms at their fixed
+    values is the coupled implicit update of the IMEXQ sweep (section 3.3's
+    comparison scheme; the coefficients of the linear problem do not depend
+    on the lagged state).  Nested iterations run until they stall must
+    therefore give IMEXQ's sweeps."""
+    a, d, r = adr
+    for sweeps in (1, 3):
+        ps = []
+        out, _ = sdc_step(LinearModel(a, d, r), np.array(1.0), 1.0, n_nodes, sweeps, "cisdcq",
+                          nu=400, nu_tol=1e-15, passes=ps)
+        ref, _ = sdc_step(LinearModel(a, d, r), np.array(1.0), 1.0, n_nodes, sweeps, "imexq")
+        assert len(ps) == sweeps and all(2 <= v < 400 for v in ps), ps
+        assert abs(float(out) - float(ref)) <= 1e-13 * abs(float(ref)), (out, ref)
+
+
+def test_adaptive_pass_count_follows_the_stall_rule():
+    """The passes done are the first l >= 2 whose change of the node-M value
+    is at most nu_tol times the first pass's change, with the changes taken
+    from separate fixed-nu sweeps (a fixed-nu sweep with nu = l ends with the
+    values of pass l)."""
+    model, n_nodes = LinearModel(0.5, -1.0, -1.0), 5
+    vals = [float(sdc_step(model, np.array(1.0), 1.0, n_nodes, 1, "cisdcq", nu=l)[0])
+            for l in range(1, 9)]
+    delta = [abs(vals[0] - 1.0) / abs(vals[0])]
+    delta += [abs(vals[l] - vals[l - 1]) / abs(vals[l]) for l in range(1, 8)]
+    ratios = np.array(delta[1:]) / delta[0]
+    assert np.all(np.diff(ratios) < 0)            # the nested iteration contracts
+    for tol in (1e-2, 1e-4, 1e-7):
+        assert np.min(np.abs(ratios - tol)) > 1e-3 * tol
+        expect = next(l + 1 for l in range(1, 8) if delta[l] <= tol * delta[0])
+        ps = []
+        sdc_step(model, np.array(1.0), 1.0, n_nodes, 1, "cisdcq", nu=8, nu_tol=tol, passes=ps)
+        assert ps == [expect], (tol, ps, ratios)
+
+
+@pytest.mark.parametrize("n_nodes", [3, 5])
+def test_adaptive_limits_are_fixed_nu(n_nodes):
+    """nu_tol = 0 never stops a pass that still changes the state (fixed
+    nu = nu_max); an infinite nu_tol stops after the second pass (fixed
+    nu = 2): bitwise the fixed-nu sweeps."""
+    model = LinearModel(1.0, -2.0, -4.0)
+    fixed3 = sdc_step(model, np.array(1.0), 1.0, n_nodes, 4, "cisdcq", nu=3)[0]
+    fixed2 = sdc_step(model, np.array(1.0), 1.0, n_nodes, 4, "cisdcq", nu=2)[0]
+    p0, pinf = [], []
+    a0 = sdc_step(model, np.array(1.0), 1.0, n_nodes, 4, "cisdcq", nu=3, nu_tol=0.0, passes=p0)[0]
+    ainf = sdc_step(model, np.array(1.0), 1.0, n_nodes, 4, "cisdcq", nu=3, nu_tol=np.inf,
+                    passes=pinf)[0]
+    assert float(a0) == float(fixed3) and p0 == [3] * 4
+    assert float(ainf) == float(fixed2) and pinf == [2] * 4
