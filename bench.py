@@ -99,11 +99,14 @@ def cpu_baseline_leg(cfg):
     phi = relaxed_initial_state(prob, Y, T)
     w0, c0 = time.perf_counter(), time.process_time()
     sweeps = 3
-    sdc_step(prob, phi, cfg["dt"], cfg["n_nodes"], sweeps, cfg["scheme"], nu=cfg["nu"])
+    nu_tol = cfg.get("nu_tol", 0.0)
+    ps = []
+    sdc_step(prob, phi, cfg["dt"], cfg["n_nodes"], sweeps, cfg["scheme"], nu=cfg["nu"],
+             nu_tol=nu_tol if nu_tol > 0 else None, passes=ps)
     wall = time.perf_counter() - w0
     cpu = time.process_time() - c0
     M = cfg["n_nodes"] - 1
-    updates = nx * ny * M * cfg["nu"] * sweeps
+    updates = nx * ny * M * (sum(ps) if ps else cfg["nu"] * sweeps)
     return {"value": updates / wall, "unit": "cell-node updates/s",
             "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
             "sample": f"{sweeps} CISDCQ-{cfg['nu']} sweeps ({M} nodes) of the same flame workload on "
@@ -123,20 +126,26 @@ def accuracy_gate(cfg, mech, mh):
     nx, ny = 48, 40
     Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
     prob = FlameProblem(mech, cfg["dx"], cfg["u"])
+    nu_tol = cfg.get("nu_tol", 0.0)
+    ps = []
     ref, _ = sdc_step(prob, relaxed_initial_state(prob, Y, T), cfg["dt"], cfg["n_nodes"],
-                      cfg["sweeps"], cfg["scheme"], nu=cfg["nu"])
+                      cfg["sweeps"], cfg["scheme"], nu=cfg["nu"],
+                      nu_tol=nu_tol if nu_tol > 0 else None, passes=ps)
     st, _ = initial_state(mh, torch.tensor(Y.reshape(9, -1), device="cuda"),
                           torch.tensor(T.ravel(), device="cuda"))
     g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
     integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
-                       scheme=cfg["scheme"])
+                       scheme=cfg["scheme"], nu_tol=nu_tol)
     integ.step(st, cfg["dt"])
     out = st.cpu().numpy()
+    gpu_passes = integ.stats()["nested_passes"]
     integ.close()
     g.close()
     ref = ref.reshape(10, -1)
     err = float((np.abs(out - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
-    return {"err": err, "tol": 1e-8, "passed": bool(err <= 1e-8), "grid": f"{nx}x{ny}"}
+    ok = err <= 1e-8 and (nu_tol <= 0 or gpu_passes == ps)
+    return {"err": err, "tol": 1e-8, "passed": bool(ok), "grid": f"{nx}x{ny}",
+            "nested_passes": gpu_passes}
 
 
 def graph_leg(integ, mh, g, cfg, state, args, tune):
@@ -509,6 +518,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gate", action="store_true")
     ap.add_argument("--nu", type=int, default=None)
+    ap.add_argument("--sweeps", type=int, default=None)
+    ap.add_argument("--nu-tol", type=float, default=0.0,
+                    help="adaptive nested iterations (CISDCQ, --nu >= 3 passes at most): a "
+                         "sweep stops after pass l >= 2 once that pass changed the state by at "
+                         "most nu_tol times the first pass's change")
     ap.add_argument("--serialize", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune", default=None,
@@ -548,6 +562,9 @@ def main():
     cfg = workload()
     if args.nu:
         cfg["nu"] = args.nu
+    if args.sweeps:
+        cfg["sweeps"] = args.sweeps
+    cfg["nu_tol"] = args.nu_tol
     # the CPU leg runs first, before anything touches the GPU
     cpu = None if args.no_cpu_baseline else cpu_baseline_leg(cfg)
     if cpu:
@@ -570,7 +587,8 @@ def main():
     state, _ = initial_state(mh, torch.tensor(Y.reshape(9, -1), device="cuda"),
                              torch.tensor(T.ravel(), device="cuda"))
     integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
-                       scheme=cfg["scheme"], serialize=args.serialize, profile=True)
+                       scheme=cfg["scheme"], serialize=args.serialize, profile=True,
+                       nu_tol=args.nu_tol)
     tune = None
     if args.tune:
         integ.set_tune(*[int(v) for v in args.tune.split(",")])
@@ -587,19 +605,34 @@ def main():
     torch.cuda.synchronize()
     native.misdc_reset_profile(integ.handle)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        integ.step(state, cfg["dt"])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stats = integ.stats()          # last step's counters + timings over all timed steps
-    elapsed = t1 - t0
-    updates = n * M * cfg["nu"] * cfg["sweeps"] * args.steps
+    if args.nu_tol > 0:
+        # adaptive nested iterations: the passes of every step are counted
+        # (read between steps, outside the timed intervals)
+        elapsed, passes = 0.0, []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            integ.step(state, cfg["dt"])
+            torch.cuda.synchronize()
+            elapsed += time.perf_counter() - t0
+            passes.append(integ.stats()["nested_passes"])
+        stats = integ.stats()
+        updates = n * M * sum(sum(p) for p in passes)
+    else:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            integ.step(state, cfg["dt"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stats = integ.stats()          # last step's counters + timings over all timed steps
+        elapsed = t1 - t0
+        passes = None
+        updates = n * M * cfg["nu"] * cfg["sweeps"] * args.steps
     value = updates / elapsed
     newton_per_cell = stats["newton_iters"] / max(1, stats["newton_solves"])
     newton_sweeps = newton_sweep_stats(integ, cfg["sweeps"])
     cg_per_solve = stats["cg_iters"] / max(1, stats["cg_solves"])
-    graph = None if args.no_graph else graph_leg(integ, mh, g, cfg, state, args, tune)
+    graph = None if (args.no_graph or args.nu_tol > 0) else graph_leg(integ, mh, g, cfg, state,
+                                                                      args, tune)
 
     # roofline of the dominant kernel
     d_ms, d_n = stats["diffusion_kernel_ms"], stats["diffusion_kernel_launches"]
@@ -649,10 +682,16 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"flame2d_256: 2-D periodic {nx}x{ny} flame, 9 species / 21 "
-                               f"reactions, CISDCQ-{cfg['nu']}, {cfg['n_nodes']} Gauss-Lobatto "
+                               f"reactions, CISDCQ-{cfg['nu']}"
+                               + (f" (adaptive, at most {cfg['nu']} passes, nu_tol "
+                                  f"{args.nu_tol})" if args.nu_tol > 0 else "")
+                               + f", {cfg['n_nodes']} Gauss-Lobatto "
                                f"nodes, {cfg['sweeps']} sweeps, dt {cfg['dt']} s",
                    "cells": n, "nodes": cfg["n_nodes"], "sweeps": cfg["sweeps"],
-                   "nu": cfg["nu"], "scheme": cfg["scheme"], "serialize": args.serialize},
+                   "nu": cfg["nu"], "scheme": cfg["scheme"], "serialize": args.serialize,
+                   "nu_tol": args.nu_tol},
+        "nested_passes_per_step": passes,
+        "sweep_increment_last_step": stats["sweep_increment"],
         "newton_iters_per_cell": newton_per_cell,
         "newton_iters_per_sweep": newton_sweeps,
         "cg_iters_per_solve": cg_per_solve,

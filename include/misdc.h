@@ -253,6 +253,16 @@ typedef struct {
                             event dependencies) into one HIP graph on its first
                             call and replay it while dev_state, dt and dev_dt
                             are unchanged; a change re-captures */
+    double nu_tol;       /* > 0: adaptive nested iterations (CISDCQ, nu >= 3;
+                            the paper's future-work item of sections 4.1-4.3).
+                            nu is then the largest number of passes.  With
+                            delta_l the change of the node-M state made by
+                            pass l (max over fields of max_i |new - old| /
+                            max_i |new|; pass 1 against sweep k), the sweep
+                            stops after pass l >= 2 if delta_l <= nu_tol *
+                            delta_1.  The host waits for each delta_l, so
+                            use_graph must be 0 (MISDC_EINVAL otherwise).
+                            <= 0: nu passes in every sweep */
 } misdc_opts;
 
 /* Fills the defaults: 5 nodes, 6 sweeps, nu 1, CISDCQ, cumulative QE. */
@@ -353,6 +363,9 @@ typedef struct {
     /* with a learned guess (misdc_integ_set_guess, last step): cell-node
      * solves that started from the network's guess */
     int64_t newton_guess_learned;
+    /* nested iterations done in each sweep of the last step (nu, or fewer
+     * with opts.nu_tol) */
+    int32_t nested_passes[64];
 } misdc_stats;
 
 /* Outcomes of the last step's cell-node Newton solves in sweep k (0 <= k <
@@ -361,7 +374,8 @@ typedef struct {
  * not converge, counts[v] = solves that converged after v linear solves
  * (1 <= v <= 62), counts[63] = after 63 or more.  counts is a host array of
  * 64 entries owned by the caller.  Synchronises with the integrator's
- * streams.  The counts of a sweep add up to cells x M x nu. */
+ * streams.  The counts of a sweep add up to cells x M x (the sweep's
+ * nested passes: nu, or fewer with opts.nu_tol). */
 int misdc_get_newton_histogram(misdc_integ_t integ, int sweep, int64_t* counts);
 
 /* Clears the accumulated kernel timings of opts.profile. */

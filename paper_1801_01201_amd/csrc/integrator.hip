@@ -91,6 +91,9 @@ struct misdc_integ_s {
     double* inc = nullptr;                        // sweep increments: 64 x NF x 2
     double* inc_partial = nullptr;
     int inc_blocks = 64;
+    double* pinc = nullptr;                       // per-pass changes at node M: 16 x NF x 2
+    double* pinc_host = nullptr;                  // pinned host copy of pinc
+    int passes[64] = {};                          // nested iterations done per sweep
     DiffusionWork dw;
     std::vector<void*> allocs;
     std::vector<hipEvent_t> evD, evR;             // [(levels) x (M+1)]
@@ -200,6 +203,11 @@ int check_opts(const misdc_opts* o) {
         return fail(MISDC_EINVAL, "nu > 1 needs the concurrent scheme");
     if (o->qe_mode != MISDC_QE_CUMULATIVE && o->qe_mode != MISDC_QE_LITERAL)
         return fail(MISDC_EINVAL, "unknown qe_mode %d", o->qe_mode);
+    if (!(o->nu_tol == o->nu_tol)) return fail(MISDC_EINVAL, "nu_tol is NaN");
+    if (o->nu_tol > 0 && o->scheme != MISDC_SCHEME_CISDCQ)
+        return fail(MISDC_EINVAL, "adaptive nested iterations need the concurrent scheme");
+    if (o->nu_tol > 0 && o->use_graph)
+        return fail(MISDC_EINVAL, "adaptive nested iterations cannot be replayed as a graph");
     return MISDC_OK;
 }
 
@@ -547,9 +555,23 @@ int sweep_constants(misdc_integ_s* I, double dt) {
     return MISDC_OK;
 }
 
+// max over fields of max_i |new - old| / max_i |new| from the (difference,
+// magnitude) pairs of a field_diff_max reduction; a field that is zero
+// everywhere counts 0 if unchanged, infinity otherwise
+double pass_change(const double* pairs, int nf) {
+    double worst = 0.0;
+    for (int f = 0; f < nf; ++f) {
+        const double d = pairs[2 * f], a = pairs[2 * f + 1];
+        const double r = a > 0 ? d / a : (d == 0 ? 0.0 : HUGE_VAL);
+        worst = r > worst ? r : worst;
+    }
+    return worst;
+}
+
 int run_sweep(misdc_integ_s* I, int k, double dt) {
     const int M = I->M;
     const int nu = (I->opt.scheme == MISDC_SCHEME_CISDCQ) ? I->nu : 1;
+    int done = nu;                    // nested iterations done in this sweep
     int rc;
     // the constants read every reaction output of the previous sweep
     MISDC_HIP(hipStreamWaitEvent(I->sD, I->R_ev(0, M), 0));
@@ -567,6 +589,7 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
             MISDC_HIP(hipEventRecord(I->R_ev(1, p), I->sR));
         }
     } else {
+        const bool adapt = I->opt.nu_tol > 0 && nu >= 3;
         for (int ell = 0; ell < nu; ++ell) {
             for (int s = 0; s <= M; ++s) {
                 const int pd = s + 1;     // diffusion node
@@ -585,10 +608,31 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
                     MISDC_HIP(hipEventRecord(I->R_ev(ell + 1, pr), I->sR));
                 }
             }
+            if (adapt && ell + 1 < nu) {
+                // change of the node-M state made by pass ell+1 (pass 1
+                // against sweep k), on the reaction stream after its last task
+                rc = launch_field_diff_max(I->NF, I->n, I->lev[ell + 1][M].phi,
+                                           I->lev[ell][M].phi, I->inc_partial, I->inc_blocks,
+                                           I->pinc + (size_t)ell * I->NF * 2, I->sR);
+                if (rc) return rc;
+                if (ell >= 1) {
+                    MISDC_HIP(hipMemcpyAsync(I->pinc_host, I->pinc,
+                                             sizeof(double) * (size_t)(ell + 1) * I->NF * 2,
+                                             hipMemcpyDeviceToHost, I->sR));
+                    MISDC_HIP(hipStreamSynchronize(I->sR));
+                    const double d1 = pass_change(I->pinc_host, I->NF);
+                    const double dl = pass_change(I->pinc_host + (size_t)ell * I->NF * 2, I->NF);
+                    if (dl <= I->opt.nu_tol * d1) {
+                        done = ell + 1;
+                        break;
+                    }
+                }
+            }
         }
     }
+    I->passes[k] = done;
     // sweep increment at node M (reaction stream, after the last reaction task)
-    const int lv = nu;
+    const int lv = done;
     rc = launch_field_diff_max(I->NF, I->n, I->lev[lv][M].phi, I->lev[0][M].phi, I->inc_partial,
                                I->inc_blocks, I->inc + (size_t)k * I->NF * 2, I->sR);
     if (rc) return rc;
@@ -1041,6 +1085,7 @@ void misdc_opts_default(misdc_opts* o) {
     o->cg_maxit = 500;
     o->profile = 0;
     o->use_graph = 0;
+    o->nu_tol = 0.0;
 }
 
 int misdc_integ_destroy(misdc_integ_t I);
@@ -1124,6 +1169,12 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if ((rc = dalloc(I, &I->cbuf, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->cgstats, 8))) return bail(rc);
     if ((rc = dalloc(I, &I->inc, (size_t)64 * NF * 2))) return bail(rc);
+    if ((rc = dalloc(I, &I->pinc, (size_t)16 * NF * 2))) return bail(rc);
+    if (hipHostMalloc((void**)&I->pinc_host, sizeof(double) * 16 * NF * 2, hipHostMallocDefault) !=
+        hipSuccess) {
+        I->pinc_host = nullptr;
+        return bail(fail(MISDC_ENOMEM, "pinned host buffer"));
+    }
     // partials, then the arrival counter of the reduction (zero between uses)
     if ((rc = dalloc(I, &I->inc_partial, (size_t)I->inc_blocks * NF * 2 + 8))) return bail(rc);
     if (hipMemset(I->inc_partial, 0, sizeof(double) * ((size_t)I->inc_blocks * NF * 2 + 8)) !=
@@ -1181,6 +1232,7 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (I->sRm) (void)hipStreamDestroy(I->sRm);
     if (I->sD) (void)hipStreamDestroy(I->sD);
     diffusion_work_free(I->dw);
+    if (I->pinc_host) (void)hipHostFree(I->pinc_host);
     for (void* p : I->allocs) (void)hipFree(p);
     delete I;
     return MISDC_OK;
@@ -1468,6 +1520,7 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
     st->newton_lu_solves = (int64_t)ns[4];
     st->newton_lu_fallbacks = (int64_t)ns[5];
     st->newton_guess_learned = (int64_t)ns[6];
+    for (int k = 0; k < I->last_sweeps && k < 64; ++k) st->nested_passes[k] = I->passes[k];
     st->cg_iters = cg[0];
     st->cg_max = cg[1];
     st->cg_failed = cg[2] + cg[4];

@@ -307,6 +307,46 @@ def test_newton_histogram_per_sweep(nat, mech9, mh):
         assert abs(mean_gpu - mean_ref) <= 0.02 * mean_ref, (k, mean_gpu, mean_ref)
 
 
+def test_adaptive_nested_iterations(nat, mech9, mh):
+    """CISDCQ with adaptive nested iterations (at most 4 passes, nu_tol 0.1)
+    on the CISDCQ-2 case: the passes done in each sweep and the step equal
+    the oracle's.  Every pass-change ratio delta_l / delta_1 of the oracle is
+    at least 5 % away from nu_tol, so the two sides cannot take different
+    decisions from rounding; the two-stream and one-stream runs are bitwise
+    equal."""
+    name, dim, shape, dx, u, n_nodes, sweeps, steps, scheme, nu = STEP_CASES[4]
+    nu_max, nu_tol, dt = 4, 0.1, 5e-5
+    Y, T = synth.flame_2d(mech9, shape[1], shape[0], dx[0], dx[1])
+    prob = FlameProblem(mech9, dx, u)
+    phi = relaxed_initial_state(prob, Y, T)
+    ps, ch = [], []
+    ref, _ = sdc_step(prob, phi, dt, n_nodes, sweeps, "cisdcq", nu=nu_max, nu_tol=nu_tol,
+                      passes=ps, changes=ch)
+    ratios = [d / c[0] for c in ch for d in c[1:]]
+    assert min(abs(r - nu_tol) for r in ratios) > 0.05 * nu_tol, ratios
+    assert len(set(ps)) > 1 and max(ps) < nu_max, ps      # the rule both stops and continues
+    grid_args = (dim, [shape[1], shape[0]], list(dx), list(u))
+    outs = []
+    for ser in (False, True):
+        st = _gpu_initial(nat, mh, Y, T)
+        out, stats = _run_gpu(nat, mh, grid_args, st, dt, 1, n_nodes=n_nodes, sweeps=sweeps,
+                              nu=nu_max, scheme="cisdcq", nu_tol=nu_tol, serialize=ser)
+        assert stats["nested_passes"] == ps, (stats["nested_passes"], ps)
+        assert stats["newton_failed"] == 0 and stats["cg_failed"] == 0
+        assert stats["newton_solves"] == shape[0] * shape[1] * (n_nodes - 1) * sum(ps)
+        outs.append(out)
+    err = field_err(outs[0], ref.reshape(10, -1))
+    assert err <= TOL, err
+    assert np.array_equal(outs[0], outs[1])
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    g = Grid(*grid_args)
+    for bad in (dict(nu=4, nu_tol=0.1, use_graph=True), dict(scheme="misdcq", nu_tol=0.1),
+                dict(nu=4, nu_tol=float("nan"))):
+        with pytest.raises(nat.MisdcError):
+            Integrator(mh, g, **bad)
+    g.close()
+
+
 def test_step_parity_global_memory_cg(nat, mech9, mh, monkeypatch):
     """The CG variant that keeps its vectors in global memory (used when the
     register-resident one does not fit) gives the same step."""
