@@ -347,6 +347,72 @@ def test_adaptive_nested_iterations(nat, mech9, mh):
     g.close()
 
 
+def test_empty_batch_is_a_no_op(nat, mh):
+    """n = 0 launches nothing and needs no arrays; n < 0 is rejected."""
+    lib = nat.lib()
+    assert lib.misdc_reaction_solve_batch(mh.handle, 0, None, None, None, None, None, None, None,
+                                          None, None) == nat.MISDC_OK
+    assert lib.misdc_reaction_solve_batch(mh.handle, -1, None, None, None, None, None, None, None,
+                                          None, None) == nat.MISDC_EINVAL
+
+
+DEGENERATE = [
+    # (name, dim, shape, scheme, nu): the smallest grids the library accepts
+    # (4 cells per direction; in 2-D one partial CG tile), and a 1-D grid one
+    # cell above the minimum
+    ("1d_4_cisdcq2", 1, (4,), "cisdcq", 2),
+    ("1d_5_misdc", 1, (5,), "misdc", 1),
+    ("2d_4x4_cisdcq1", 2, (4, 4), "cisdcq", 1),
+    ("2d_4x33_misdcq", 2, (4, 33), "misdcq", 1),
+]
+
+
+@pytest.mark.parametrize("case", DEGENERATE, ids=[c[0] for c in DEGENERATE])
+def test_step_parity_smallest_grids(nat, mech9, mh, case):
+    name, dim, shape, scheme, nu = case
+    dx, dt = 0.01, 5e-5
+    if dim == 1:
+        Y, T = synth.flame_1d(mech9, shape[0], dx)
+        u = (100.0,)
+    else:
+        Y, T = synth.flame_2d(mech9, shape[1], shape[0], dx, dx)
+        u = (100.0, -30.0)
+    prob = FlameProblem(mech9, (dx,) * dim, u)
+    phi = relaxed_initial_state(prob, Y, T)
+    ref, _ = sdc_step(prob, phi, dt, 5, 3, scheme, nu=nu)
+    st = _gpu_initial(nat, mh, Y, T)
+    n = [shape[1], shape[0]] if dim == 2 else [shape[0]]
+    out, stats = _run_gpu(nat, mh, (dim, n, [dx] * dim, list(u)), st, dt, 1, n_nodes=5, sweeps=3,
+                          nu=nu, scheme=scheme)
+    assert stats["newton_failed"] == 0 and stats["cg_failed"] == 0
+    err = field_err(out, ref.reshape(10, -1))
+    assert err <= TOL, err
+
+
+def test_uniform_state_is_pure_reaction(nat, mech9, mh):
+    """A spatially uniform state has no advective or diffusive flux, so every
+    cell follows the same reaction-only trajectory: the GPU step keeps the
+    state uniform (to the parity tolerance: the tile preconditioner treats a
+    tile's edge cells differently, so the solves are uniform only to their
+    1e-13 residual, which the reaction solves of four sweeps carry to about
+    3e-12) and matches the oracle's step."""
+    Y, T = synth.flame_2d(mech9, 24, 20, 0.01, 0.01)
+    j = int(np.argmax(T.ravel()))                   # a hot cell
+    Yu = np.repeat(Y.reshape(9, -1)[:, j:j + 1], 24 * 20, axis=1).reshape(Y.shape)
+    Tu = np.full(T.shape, T.ravel()[j])
+    prob = FlameProblem(mech9, (0.01, 0.01), (100.0, 0.0))
+    phi = relaxed_initial_state(prob, Yu, Tu)
+    ref, _ = sdc_step(prob, phi, 5e-5, 5, 4, "cisdcq", nu=1)
+    st = _gpu_initial(nat, mh, Yu, Tu)
+    out, stats = _run_gpu(nat, mh, (2, [24, 20], [0.01, 0.01], [100.0, 0.0]), st, 5e-5, 1,
+                          n_nodes=5, sweeps=4, nu=1, scheme="cisdcq")
+    assert stats["newton_failed"] == 0 and stats["cg_failed"] == 0
+    spread = np.abs(out - out[:, :1]).max(axis=1) / np.abs(out).max(axis=1)
+    assert spread.max() <= TOL, spread
+    err = field_err(out, ref.reshape(10, -1))
+    assert err <= TOL, err
+
+
 def test_step_parity_global_memory_cg(nat, mech9, mh, monkeypatch):
     """The CG variant that keeps its vectors in global memory (used when the
     register-resident one does not fit) gives the same step."""
