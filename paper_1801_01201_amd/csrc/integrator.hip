@@ -482,6 +482,10 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     a.stats = I->nstats;
     a.buckets = I->nbuckets;
     a.hist = I->nhist + (size_t)I->sweep_index * NEWTON_HIST_SETS * NEWTON_HIST_BINS;
+    if (I->grid->dim == 2 && I->grid->n_flames == 0) {
+        a.tile_nx = (int)I->grid->nx;
+        a.tile_ny = (int)I->grid->ny;
+    }
     a.opt = I->opt.newton;
     // staggered: the Newton solve of node p starts once the diffusion solve
     // of node p+1 (issued just before this task) is about to start, so that

@@ -117,6 +117,10 @@ struct NewtonArgs {
     // after v linear solves, the last bin also counting more); wavefront w of
     // the launch adds to set w % NEWTON_HIST_SETS
     unsigned long long* hist = nullptr;
+    // per-thread kernel only: > 0 for the cells of a 2-D grid of tile_nx x
+    // tile_ny cells (x fastest, tile_nx * tile_ny = n); each 64-thread block
+    // then takes one 8 x 8 tile of cells instead of 64 consecutive cells
+    int tile_nx = 0, tile_ny = 0;
     misdc_newton_opts opt;
 };
 constexpr int NEWTON_BUCKETS = 32, NEWTON_BUCKET_STRIDE = 16;   // 128-byte apart
