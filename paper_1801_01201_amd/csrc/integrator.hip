@@ -635,14 +635,17 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
         }
     }
     I->passes[k] = done;
-    // sweep increment at node M (reaction stream, after the last reaction task)
     const int lv = done;
+    // the next sweep's constants need the reaction outputs only, so they are
+    // released before the increment below (which reads buffers that only
+    // later work of this same stream overwrites)
+    MISDC_HIP(hipEventRecord(I->R_ev(0, M), I->sR));
+    // sweep increment at node M (reaction stream, after the last reaction task)
     rc = launch_field_diff_max(I->NF, I->n, I->lev[lv][M].phi, I->lev[0][M].phi, I->inc_partial,
                                I->inc_blocks, I->inc + (size_t)k * I->NF * 2, I->sR);
     if (rc) return rc;
     // S7: the last nested iteration becomes sweep k+1 (swap buffer sets)
     for (int p = 1; p <= M; ++p) std::swap(I->lev[0][p], I->lev[lv][p]);
-    MISDC_HIP(hipEventRecord(I->R_ev(0, M), I->sR));
     return MISDC_OK;
 }
 
