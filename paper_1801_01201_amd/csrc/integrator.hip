@@ -101,6 +101,8 @@ struct misdc_integ_s {
     hipEvent_t ev_in = nullptr, ev_outD = nullptr, ev_outR = nullptr;
     int last_sweeps = 0;
     int sweep_index = 0;                          // sweep being issued within the step
+    bool d1_ready = false;                        // the sweep constants' pass also formed D_1's
+                                                  // right-hand side, guess and face coefficients
     double dt = 0.0;
     // kernel timing (opts.profile): event pairs recorded around launches
     struct Timed { hipEvent_t a, b; int kind; };
@@ -264,8 +266,21 @@ struct LC {
     }
     // add weight w (to output o) of array X with nf fields; merges duplicates
     bool sc[LC_MAX_TERMS] = {};
+    // fold: an array that is an output of this same pass enters as that
+    // output's weights (its old content is not read)
+    bool fold = false;
     void put(int o, double w, const double* X, int nf, bool scaled) {
         if (w == 0.0 || !X) return;
+        if (fold)
+            for (int q = 0; q < lc.nout; ++q)
+                if (lc.out[q] == X && q != o) {
+                    if (scaled && dtc) {           // would scale its terms twice
+                        lc.nterms = LC_MAX_TERMS + 1;
+                        return;
+                    }
+                    for (int t = 0; t < lc.nterms; ++t) lc.W[o][t] += w * lc.W[q][t];
+                    return;
+                }
         for (int t = 0; t < lc.nterms; ++t)
             if (lc.X[t] == X && sc[t] == scaled) {
                 lc.W[o][t] += w;
@@ -339,15 +354,17 @@ void timing_end(misdc_integ_s* I, hipEvent_t start, hipStream_t s, int kind) {
 }
 
 // ---- diffusion task at node p of nested iteration ell (writes phiAD[p]) ----
-int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
+// Adds to b the outputs of the diffusion task's right-hand side pass: the
+// right-hand side (rD) and the solve's initial guess (phiAD[p]); returns the
+// implicit factor cf (c = dt * cf) and the lagged temperature of the operator.
+void diffusion_rhs(misdc_integ_s* I, int ell, int p, LC& b, double& cf_out,
+                   const double*& T_lag_out) {
     const int M = I->M, N = I->N, NF = I->NF;
-    const int64_t n = I->n;
     const Tables& t = I->tab;
     const int m = p - 1;
     auto& L0 = I->lev[0];
     auto& Lc = I->lev[ell + 1];       // iteration ell+1 (serial schemes: the new sweep)
     auto& Lp = I->lev[ell];           // iteration ell (lagged); ell = 0: sweep k
-    LC b(NF, n, dt, I->dtc);
     const int o = b.out(I->rD);
     double cf = 0.0;                  // implicit factor c = dt * cf
     const double* T_lag = nullptr;
@@ -390,9 +407,25 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     const double* guess = (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell > 0) ? Lp[p].phi : L0[p].phi;
     const int og = b.out(I->phiAD[p]);
     b.add(og, 1.0, guess, NF);
-    // the same pass computes the face coefficients of the lagged operator
-    int rc = launch_lincomb_faces(b.lc, *I->grid, T_lag, I->dw, I->sD);
-    if (rc) return rc;
+    cf_out = cf;
+    T_lag_out = T_lag;
+    (void)M;
+}
+
+int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
+    const int NF = I->NF;
+    const int64_t n = I->n;
+    double cf = 0.0;
+    const double* T_lag = nullptr;
+    LC b(NF, n, dt, I->dtc);
+    diffusion_rhs(I, ell, p, b, cf, T_lag);
+    int rc;
+    if (ell == 0 && p == 1 && I->d1_ready) {
+        I->d1_ready = false;          // formed by the sweep constants' pass
+    } else {
+        // the same pass computes the face coefficients of the lagged operator
+        if ((rc = launch_lincomb_faces(b.lc, *I->grid, T_lag, I->dw, I->sD))) return rc;
+    }
     // the solve is next on this stream: a staggered reaction task waits for this
     if (I->stagger && I->sR != I->sD) MISDC_HIP(hipEventRecord(I->C_ev(ell + 1, p), I->sD));
     // with profiling, the events bracket the solve kernel itself (CG or cyclic)
@@ -412,7 +445,6 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
                               I->thD, I->sD, true);
         if (rc) return rc;
     }
-    (void)M;
     return MISDC_OK;
 }
 
@@ -545,18 +577,32 @@ int sweep_constants(misdc_integ_s* I, double dt) {
             }
         }
     }
-    int rc = launch_lincomb(b.lc, I->sD);
-    if (rc) return rc;
+    int rc;
     if (I->opt.scheme == MISDC_SCHEME_MISDCQ) {
         LC r(N, n, dt, I->dtc);
         for (int p = 1; p <= M; ++p) {
             const int o = r.out(I->CR[p]);
             for (int j = 1; j <= p; ++j) r.addS(o, -t.QI[p - 1][j - 1], L0[j].FR, N);
         }
-        rc = launch_lincomb(r.lc, I->sD);
-        if (rc) return rc;
+        if ((rc = launch_lincomb(r.lc, I->sD))) return rc;
     }
-    return MISDC_OK;
+    // the first diffusion task's right-hand side (which contains C^1, folded
+    // in as its weights), initial guess and face coefficients in the same
+    // pass: one launch fewer between the sweeps on the critical path
+    I->d1_ready = false;
+    if (M + 2 <= LC_MAX_OUT) {
+        LC f = b;
+        f.fold = true;
+        double cf = 0.0;
+        const double* T_lag = nullptr;
+        diffusion_rhs(I, 0, 1, f, cf, T_lag);
+        if (f.lc.nterms <= LC_MAX_TERMS && f.lc.nout <= LC_MAX_OUT) {
+            if ((rc = launch_lincomb_faces(f.lc, *I->grid, T_lag, I->dw, I->sD))) return rc;
+            I->d1_ready = true;
+            return MISDC_OK;
+        }
+    }
+    return launch_lincomb(b.lc, I->sD);
 }
 
 // max over fields of max_i |new - old| / max_i |new| from the (difference,
