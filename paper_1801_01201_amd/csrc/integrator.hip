@@ -432,20 +432,24 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     const bool timed = I->opt.profile && !I->capturing;
     hipEvent_t t0 = timed ? pool_event(I) : nullptr;
     hipEvent_t t1 = timed ? pool_event(I) : nullptr;
-    const bool lag_init = (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell == 0);
+    const bool lag_init = (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell == 0 && p < I->M);
     rc = launch_diffusion_solve(*I->mech, *I->grid, I->dw, dt * cf, I->dtf, cf, T_lag, I->rD,
                                 I->phiAD[p], 1, I->opt.cg_rtol, I->opt.cg_maxit, I->sD, t0, t1,
                                 I->TAD[p], I->cgstats, lag_init ? I->thD : nullptr, true);
     if (rc) return rc;
     if (t0 && t1) I->timed.push_back({t0, t1, 0});
-    if (lag_init) {
-        // lag initialisation (initial_lagged_values_A/D): FA, FD at phi_AD^{p,(k+1,1)}
-        // (theta of T(phi_AD) written by the solve's closure)
-        rc = launch_transport(*I->mech, *I->grid, I->phiAD[p], I->TAD[p], I->hatA[p], I->hatD[p],
-                              I->thD, I->sD, true);
-        if (rc) return rc;
-    }
     return MISDC_OK;
+}
+
+// Lag initialisation (initial_lagged_values_A/D) of the concurrent scheme's
+// first nested iteration: FA, FD at phi_AD^{p,(k+1,1)} (theta of T(phi_AD)
+// written by the solve's closure), read only by the diffusion task of node
+// p+1, so none for the last node.  Issued after the event that releases the
+// reaction task of node p, which does not read them.
+int lag_transport(misdc_integ_s* I, int ell, int p) {
+    if (I->opt.scheme != MISDC_SCHEME_CISDCQ || ell != 0 || p >= I->M) return MISDC_OK;
+    return launch_transport(*I->mech, *I->grid, I->phiAD[p], I->TAD[p], I->hatA[p], I->hatD[p],
+                            I->thD, I->sD, true);
 }
 
 // ---- reaction task at node p of nested iteration ell (writes lev[ell+1][p]) ----
@@ -650,6 +654,7 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
                     rc = diffusion_task(I, ell, pd, dt);
                     if (rc) return rc;
                     MISDC_HIP(hipEventRecord(I->D_ev(ell + 1, pd), I->sD));
+                    if ((rc = lag_transport(I, ell, pd))) return rc;
                 }
                 if (pr >= 1) {
                     MISDC_HIP(hipStreamWaitEvent(I->sR, I->D_ev(ell + 1, pr), 0));
