@@ -78,6 +78,41 @@ def measured_traffic(profile_name, source_rel):
     return val if cur == sha else None
 
 
+def measured_fp64_ops(kernel, source_rel):
+    """FP64 lane operations per launch of a kernel from the committed
+    rocprofv3 FLOP-counter summary, or None when the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "pmc_fp64_ops_flame2d_256.md")
+    try:
+        text = open(path).read()
+        m = re.search(r"fp64_ops_per_launch: " + re.escape(kernel) +
+                      r": ([0-9.eE+]+) source_sha1: ([0-9a-f]+)", text)
+        val, sha = float(m.group(1)), m.group(2)
+        cur = hashlib.sha1(open(os.path.join(ROOT, source_rel), "rb").read()).hexdigest()
+    except (OSError, AttributeError, ValueError):
+        return None
+    return val if cur == sha else None
+
+
+def fp64_counter_rates(d_ms, d_n, r_ms, r_n):
+    """Counted FP64 lane operations of the two leaves against the FP64 vector
+    peak, with this run's average launch durations."""
+    out = {}
+    for kernel, src, ms, cnt in (("cg_tile_kernel<9, 1>", "paper_1801_01201_amd/csrc/cg.hip", d_ms, d_n),
+                                 ("newton_kernel<9, true>", "paper_1801_01201_amd/csrc/chem.hip",
+                                  r_ms, r_n)):
+        ops = measured_fp64_ops(kernel, src)
+        if ops is None or cnt == 0:
+            out[kernel] = None
+            continue
+        tf = ops / (ms / cnt * 1e-3) / 1e12
+        out[kernel] = {"ops_per_launch": ops, "tflops": tf,
+                       "frac_of_fp64_peak": tf / FP64_VECTOR_PEAK_TFLOPS}
+    return out
+
+
 def workload():
     import synth
     c = synth.config("flame2d_256")
@@ -697,6 +732,7 @@ def main():
         "cg_iters_per_solve": cg_per_solve,
         "cell_node_updates_per_step_incl_node0": n * (M + 1) * cfg["nu"] * cfg["sweeps"],
         "roofline": roof,
+        "fp64_counters": fp64_counter_rates(d_ms, d_n, r_ms, r_n),
         "kernel_split": other,
         "autotune": tune,
         "graph_replay": graph,
