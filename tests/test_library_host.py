@@ -137,3 +137,15 @@ def test_binding_structs_match_header(nat, name):
     the header's order (the C ABI passes them by pointer)."""
     cls = getattr(nat, name)
     assert [f[0] for f in cls._fields_] == _header_struct_fields(name)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message
+    before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
