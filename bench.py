@@ -586,7 +586,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              f"design is described in DESIGN.md and not built", file=sys.stderr)
+              f"path (spatial slabs, halo exchange, all-reduces) is not built", file=sys.stderr)
         sys.exit(2)
     if args.workload == "ensemble64":
         return ensemble_main(args)
