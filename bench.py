@@ -170,7 +170,7 @@ def accuracy_gate(cfg, mech, mh):
                           torch.tensor(T.ravel(), device="cuda"))
     g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
     integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
-                       scheme=cfg["scheme"], nu_tol=nu_tol)
+                       scheme=cfg["scheme"], nu_tol=nu_tol, cg_rtol=cfg.get("cg_rtol", 1e-13))
     integ.step(st, cfg["dt"])
     out = st.cpu().numpy()
     gpu_passes = integ.stats()["nested_passes"]
@@ -190,7 +190,7 @@ def graph_leg(integ, mh, g, cfg, state, args, tune):
     import torch
     from paper_1801_01201_amd.flame import Integrator
     gi = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
-                    scheme=cfg["scheme"], use_graph=True)
+                    scheme=cfg["scheme"], use_graph=True, cg_rtol=cfg.get("cg_rtol", 1e-13))
     if tune:
         gi.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"],
                     tune["cu_split"], tune["stagger"])
@@ -554,6 +554,9 @@ def main():
     ap.add_argument("--no-gate", action="store_true")
     ap.add_argument("--nu", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=None)
+    ap.add_argument("--cg-rtol", type=float, default=1e-13,
+                    help="relative residual of the implicit diffusion solves (the accuracy gate "
+                         "runs with the same value)")
     ap.add_argument("--nu-tol", type=float, default=0.0,
                     help="adaptive nested iterations (CISDCQ, --nu >= 3 passes at most): a "
                          "sweep stops after pass l >= 2 once that pass changed the state by at "
@@ -600,6 +603,7 @@ def main():
     if args.sweeps:
         cfg["sweeps"] = args.sweeps
     cfg["nu_tol"] = args.nu_tol
+    cfg["cg_rtol"] = args.cg_rtol
     # the CPU leg runs first, before anything touches the GPU
     cpu = None if args.no_cpu_baseline else cpu_baseline_leg(cfg)
     if cpu:
@@ -623,7 +627,7 @@ def main():
                              torch.tensor(T.ravel(), device="cuda"))
     integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
                        scheme=cfg["scheme"], serialize=args.serialize, profile=True,
-                       nu_tol=args.nu_tol)
+                       nu_tol=args.nu_tol, cg_rtol=args.cg_rtol)
     tune = None
     if args.tune:
         integ.set_tune(*[int(v) for v in args.tune.split(",")])
@@ -724,7 +728,7 @@ def main():
                                f"nodes, {cfg['sweeps']} sweeps, dt {cfg['dt']} s",
                    "cells": n, "nodes": cfg["n_nodes"], "sweeps": cfg["sweeps"],
                    "nu": cfg["nu"], "scheme": cfg["scheme"], "serialize": args.serialize,
-                   "nu_tol": args.nu_tol},
+                   "nu_tol": args.nu_tol, "cg_rtol": args.cg_rtol},
         "nested_passes_per_step": passes,
         "sweep_increment_last_step": stats["sweep_increment"],
         "newton_iters_per_cell": newton_per_cell,
