@@ -389,6 +389,24 @@ def test_step_parity_smallest_grids(nat, mech9, mh, case):
     assert err <= TOL, err
 
 
+@pytest.mark.parametrize("n_nodes,scheme", [(7, "cisdcq"), (9, "cisdcq"), (9, "misdcq")])
+def test_step_parity_many_nodes(nat, mech9, mh, n_nodes, scheme):
+    """7 Gauss-Lobatto nodes: the sweep constants and the first diffusion
+    task's right-hand side, guess and faces fill the 8 outputs of one pass;
+    9 nodes: they do not fit, and the constants take a pass of their own."""
+    shape, dx, u, dt = (12, 16), (0.01, 0.01), (100.0, -30.0), 5e-5
+    Y, T = synth.flame_2d(mech9, shape[1], shape[0], dx[0], dx[1])
+    prob = FlameProblem(mech9, dx, u)
+    phi = relaxed_initial_state(prob, Y, T)
+    ref, _ = sdc_step(prob, phi, dt, n_nodes, 2, scheme, nu=1)
+    st = _gpu_initial(nat, mh, Y, T)
+    out, stats = _run_gpu(nat, mh, (2, [shape[1], shape[0]], list(dx), list(u)), st, dt, 1,
+                          n_nodes=n_nodes, sweeps=2, nu=1, scheme=scheme)
+    assert stats["newton_failed"] == 0 and stats["cg_failed"] == 0
+    err = field_err(out, ref.reshape(10, -1))
+    assert err <= TOL, err
+
+
 def test_uniform_state_is_pure_reaction(nat, mech9, mh):
     """A spatially uniform state has no advective or diffusive flux, so every
     cell follows the same reaction-only trajectory: the GPU step keeps the
