@@ -52,7 +52,8 @@ enum {
     MISDC_ENOMEM = -2,      /* device or host allocation failed */
     MISDC_EDEVICE = -3,     /* HIP runtime error */
     MISDC_ENOTCONV = -4,    /* a solver did not converge (see the stats) */
-    MISDC_EUNSUPPORTED = -5 /* valid request outside what is built */
+    MISDC_EUNSUPPORTED = -5, /* valid request outside what is built */
+    MISDC_ESTATE = -6       /* call out of order (a sweep without an open step, ...) */
 };
 
 enum { MISDC_SCHEME_MISDC = 0, MISDC_SCHEME_MISDCQ = 1, MISDC_SCHEME_CISDCQ = 2 };
@@ -288,6 +289,23 @@ int misdc_integ_destroy(misdc_integ_t integ);
  * that is not an ensemble). */
 int misdc_step(misdc_integ_t integ, double* dev_state, double dt,
                const double* dev_dt, void* stream);
+
+/* The same step one sweep at a time (section 3, steps S1-S7 per call of
+ * misdc_sweep), for callers that choose the number of sweeps as they go,
+ * e.g. until the sweep increment of misdc_get_stats falls below a tolerance:
+ * misdc_step_begin does I1-I4 (ordered after prior work on ``stream``),
+ * each misdc_sweep issues one more correction sweep (at most 64 per step),
+ * and misdc_step_end writes node M of the last sweep into dev_state (later
+ * work on ``stream`` is ordered after it).  misdc_get_stats between sweeps
+ * synchronises and reports the sweeps done so far.  Sweeps run eagerly (no
+ * graph replay).  Begin and end with the same arguments and K sweeps give
+ * misdc_step with n_sweeps = K bit for bit.  Errors: as misdc_step;
+ * MISDC_ESTATE for begin while a step is open, a sweep or end without one,
+ * or misdc_step while one is open. */
+int misdc_step_begin(misdc_integ_t integ, double* dev_state, double dt, const double* dev_dt,
+                     void* stream);
+int misdc_sweep(misdc_integ_t integ, void* stream);
+int misdc_step_end(misdc_integ_t integ, void* stream);
 
 /* Launch configuration of an integrator, chosen by misdc_autotune or set by
  * the caller.  Results agree to the solvers' tolerances across choices;

@@ -101,6 +101,12 @@ struct misdc_integ_s {
     hipEvent_t ev_in = nullptr, ev_outD = nullptr, ev_outR = nullptr;
     int last_sweeps = 0;
     int sweep_index = 0;                          // sweep being issued within the step
+    // a step opened by misdc_step_begin: its state, the dt its sweeps take and
+    // the sweeps done so far
+    bool open = false;
+    double* open_state = nullptr;
+    double open_dt = 0.0;
+    int open_sweeps = 0;
     bool d1_ready = false;                        // the sweep constants' pass also formed D_1's
                                                   // right-hand side, guess and face coefficients
     double dt = 0.0;
@@ -725,7 +731,12 @@ void drop_graph(misdc_integ_s* I) {
 // reaction stream forks from it at the start and joins it at the end, so the
 // whole step can be captured from sD into one graph.  Only kernels, event
 // records and event waits are issued (no memset or memcpy nodes).
-int issue_step(misdc_integ_s* I, double* state, double dt, const double* dtf) {
+// I1-I4 of a step: the reaction stream forks from sD, the counters are
+// cleared (the Newton histograms of zero_sweeps sweeps), every node of sweep 0
+// receives phi^n and F(phi^n).  Returns the dt that the sweeps take (1 with
+// per-flame step sizes, whose terms are scaled per cell).
+int issue_begin(misdc_integ_s* I, double* state, double dt, const double* dtf, int zero_sweeps,
+                double& dt_sweep) {
     const int M = I->M, N = I->N, NF = I->NF;
     const int64_t n = I->n;
     int rc;
@@ -744,7 +755,7 @@ int issue_step(misdc_integ_s* I, double* state, double dt, const double* dtf) {
     if ((rc = launch_zero(I->nbuckets, sizeof(unsigned long long) * NEWTON_BUCKETS *
                                            NEWTON_BUCKET_STRIDE, I->sD)))
         return rc;
-    if ((rc = launch_zero(I->nhist, sizeof(unsigned long long) * I->opt.n_sweeps *
+    if ((rc = launch_zero(I->nhist, sizeof(unsigned long long) * zero_sweeps *
                                         NEWTON_HIST_SETS * NEWTON_HIST_BINS, I->sD)))
         return rc;
     if ((rc = launch_zero(I->cgstats, 8 * sizeof(int32_t), I->sD))) return rc;
@@ -774,16 +785,31 @@ int issue_step(misdc_integ_s* I, double* state, double dt, const double* dtf) {
     for (int l = 1; l < I->levels; ++l) I->lev[l][0] = b0;
     // "previous sweep finished" marker for the first sweep's constants
     MISDC_HIP(hipEventRecord(I->R_ev(0, M), I->sD));
-    for (int k = 0; k < I->opt.n_sweeps; ++k) {
-        I->sweep_index = k;
-        if ((rc = run_sweep(I, k, dt))) return rc;
-    }
-    if ((rc = launch_copy(state, I->lev[0][M].phi, (int64_t)NF * n, I->sR))) return rc;
+    dt_sweep = dt;
+    return MISDC_OK;
+}
+
+// The end of a step: node M of the last sweep back into the state, and the
+// reaction stream joins sD.
+int issue_end(misdc_integ_s* I, double* state) {
+    int rc;
+    if ((rc = launch_copy(state, I->lev[0][I->M].phi, (int64_t)I->NF * I->n, I->sR))) return rc;
     if (I->sR != I->sD) {
         MISDC_HIP(hipEventRecord(I->ev_join, I->sR));
         MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_join, 0));
     }
     return MISDC_OK;
+}
+
+int issue_step(misdc_integ_s* I, double* state, double dt, const double* dtf) {
+    double dts = dt;
+    int rc = issue_begin(I, state, dt, dtf, I->opt.n_sweeps, dts);
+    if (rc) return rc;
+    for (int k = 0; k < I->opt.n_sweeps; ++k) {
+        I->sweep_index = k;
+        if ((rc = run_sweep(I, k, dts))) return rc;
+    }
+    return issue_end(I, state);
 }
 
 }  // namespace
@@ -1299,6 +1325,7 @@ int misdc_integ_destroy(misdc_integ_t I) {
 int misdc_step(misdc_integ_t I, double* state, double dt, const double* dev_dt, void* stream) {
     int rc = check_step_args(I, state, dt, dev_dt);
     if (rc) return rc;
+    if (I->open) return fail(MISDC_ESTATE, "a step opened by misdc_step_begin is not ended");
     hipStream_t cs = (hipStream_t)stream;
     // order after the caller's stream
     MISDC_HIP(hipEventRecord(I->ev_in, cs));
@@ -1335,6 +1362,53 @@ int misdc_step(misdc_integ_t I, double* state, double dt, const double* dev_dt, 
     MISDC_HIP(hipStreamWaitEvent(cs, I->ev_outD, 0));
     I->last_sweeps = I->opt.n_sweeps;
     I->dt = dt;
+    return MISDC_OK;
+}
+
+int misdc_step_begin(misdc_integ_t I, double* state, double dt, const double* dev_dt,
+                     void* stream) {
+    int rc = check_step_args(I, state, dt, dev_dt);
+    if (rc) return rc;
+    if (I->open) return fail(MISDC_ESTATE, "a step is already open");
+    hipStream_t cs = (hipStream_t)stream;
+    MISDC_HIP(hipEventRecord(I->ev_in, cs));
+    MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_in, 0));
+    double dts = dt;
+    if ((rc = issue_begin(I, state, dt, dev_dt, MAX_STEP_SWEEPS, dts))) return rc;
+    I->open = true;
+    I->open_state = state;
+    I->open_dt = dts;
+    I->open_sweeps = 0;
+    I->last_sweeps = 0;
+    I->dt = dt;
+    return MISDC_OK;
+}
+
+int misdc_sweep(misdc_integ_t I, void* stream) {
+    if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
+    if (!I->open) return fail(MISDC_ESTATE, "no step is open (misdc_step_begin)");
+    if (I->open_sweeps >= MAX_STEP_SWEEPS)
+        return fail(MISDC_EINVAL, "at most %d sweeps per step", MAX_STEP_SWEEPS);
+    const int k = I->open_sweeps;
+    I->sweep_index = k;
+    int rc = run_sweep(I, k, I->open_dt);
+    if (rc) return rc;
+    I->open_sweeps = k + 1;
+    I->last_sweeps = k + 1;             // misdc_get_stats reports the sweeps done so far
+    (void)stream;
+    return MISDC_OK;
+}
+
+int misdc_step_end(misdc_integ_t I, void* stream) {
+    if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
+    if (!I->open) return fail(MISDC_ESTATE, "no step is open (misdc_step_begin)");
+    int rc = issue_end(I, I->open_state);
+    if (rc) return rc;
+    hipStream_t cs = (hipStream_t)stream;
+    MISDC_HIP(hipEventRecord(I->ev_outD, I->sD));
+    MISDC_HIP(hipStreamWaitEvent(cs, I->ev_outD, 0));
+    I->open = false;
+    I->open_state = nullptr;
     return MISDC_OK;
 }
 
@@ -1459,6 +1533,7 @@ int misdc_autotune(misdc_integ_t I, const double* state, double dt, const double
     int rc = check_step_args(I, state, dt, dev_dt);
     if (rc) return rc;
     if (reps < 1 || reps > 100) return fail(MISDC_EINVAL, "reps must be in [1, 100]");
+    if (I->open) return fail(MISDC_ESTATE, "a step opened by misdc_step_begin is not ended");
     hipStream_t cs = (hipStream_t)stream;
     const Grid& g = *I->grid;
     int cus = 0;

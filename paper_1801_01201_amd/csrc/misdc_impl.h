@@ -28,6 +28,7 @@ constexpr double T_REF = 298.15;        // thermodynamic reference temperature
 constexpr double T_DIFF_REF = 300.0;    // reference of the (T/300)^1.7 law
 constexpr double THETA_EXP = 1.7;
 constexpr int MAX_NODES = 9;
+constexpr int MAX_STEP_SWEEPS = 64;      // sweeps of one step (statistics arrays)
 
 // ---- device mechanism tables (passed to kernels by value) ------------------
 struct MechDev {

@@ -81,6 +81,18 @@ class Integrator:
         ensemble grid) replaces the scalar ``dt``."""
         nat.misdc_step(self.handle, state, dt, dt_per_flame, stream)
 
+    def begin(self, state, dt, dt_per_flame=None, stream=None):
+        """Open a step (I1-I4) to be advanced one sweep at a time."""
+        nat.misdc_step_begin(self.handle, state, dt, dt_per_flame, stream)
+
+    def sweep(self, stream=None):
+        """One more correction sweep of the open step."""
+        nat.misdc_sweep(self.handle, stream)
+
+    def end(self, stream=None):
+        """Write the open step's result into its state."""
+        nat.misdc_step_end(self.handle, stream)
+
     def autotune(self, state, dt, dt_per_flame=None, reps=3, stream=None):
         return nat.misdc_autotune(self.handle, state, dt, dt_per_flame, reps, stream)
 

@@ -20,6 +20,7 @@ MISDC_ENOMEM = -2
 MISDC_EDEVICE = -3
 MISDC_ENOTCONV = -4
 MISDC_EUNSUPPORTED = -5
+MISDC_ESTATE = -6
 SCHEME = {"misdc": 0, "misdcq": 1, "cisdcq": 2}
 QE = {"cumulative": 0, "literal": 1}
 QI = {"lu": 0, "be": 1}
@@ -30,7 +31,8 @@ EXPORTED = [
     "misdc_reaction_source", "misdc_reaction_solve_batch", "misdc_grid_create",
     "misdc_grid_create_ensemble", "misdc_grid_destroy", "misdc_grid_cells",
     "misdc_transport_operators", "misdc_diffusion_solve", "misdc_opts_default",
-    "misdc_integ_create", "misdc_integ_destroy", "misdc_step", "misdc_get_stats",
+    "misdc_integ_create", "misdc_integ_destroy", "misdc_step", "misdc_step_begin",
+    "misdc_sweep", "misdc_step_end", "misdc_get_stats",
     "misdc_get_newton_histogram", "misdc_reset_profile", "misdc_autotune", "misdc_get_tune", "misdc_set_tune",
     "misdc_mlp_create", "misdc_mlp_destroy", "misdc_mlp_param_count", "misdc_mlp_set_params",
     "misdc_mlp_get_params", "misdc_mlp_set_normalization", "misdc_mlp_forward",
@@ -127,6 +129,9 @@ def load(path=LIB_PATH):
         "misdc_step": (C.c_int, [vp, vp, dbl, vp, vp]),
         "misdc_get_stats": (C.c_int, [vp, C.POINTER(misdc_stats)]),
         "misdc_get_newton_histogram": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int64)]),
+        "misdc_step_begin": (C.c_int, [vp, vp, C.c_double, vp, vp]),
+        "misdc_sweep": (C.c_int, [vp, vp]),
+        "misdc_step_end": (C.c_int, [vp, vp]),
         "misdc_reset_profile": (C.c_int, [vp]),
         "misdc_autotune": (C.c_int, [vp, vp, dbl, vp, C.c_int, C.POINTER(misdc_tune), vp]),
         "misdc_get_tune": (C.c_int, [vp, C.POINTER(misdc_tune)]),
@@ -319,6 +324,19 @@ def misdc_integ_destroy(h):
 
 def misdc_step(integ, state, dt, dt_per_flame=None, stream=None):
     check(lib().misdc_step(integ, _ptr(state), float(dt), _ptr(dt_per_flame), _stream(stream)))
+
+
+def misdc_step_begin(integ, state, dt, dt_per_flame=None, stream=None):
+    check(lib().misdc_step_begin(integ, _ptr(state), float(dt), _ptr(dt_per_flame),
+                                 _stream(stream)))
+
+
+def misdc_sweep(integ, stream=None):
+    check(lib().misdc_sweep(integ, _stream(stream)))
+
+
+def misdc_step_end(integ, stream=None):
+    check(lib().misdc_step_end(integ, _stream(stream)))
 
 
 def misdc_get_stats(integ):

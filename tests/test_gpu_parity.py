@@ -468,6 +468,64 @@ def test_concurrent_equals_serialized_bitwise(nat, mech9, mh):
     g.close()
 
 
+def test_step_one_sweep_at_a_time(nat, mech9, mh):
+    """misdc_step_begin, K calls of misdc_sweep and misdc_step_end give the
+    step of K sweeps bit for bit, with the same sweep increments (read
+    between the sweeps); sweeping until the increment falls below a
+    tolerance stops where those increments say; calls out of order are
+    refused."""
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    Y, T = synth.flame_2d(mech9, 40, 32)
+    g = Grid(2, [40, 32], [0.01, 0.01], [100.0, 0.0])
+    dt, K = 5e-5, 4
+    ref = Integrator(mh, g, n_nodes=5, sweeps=K, nu=2, scheme="cisdcq")
+    st1 = _gpu_initial(nat, mh, Y, T)
+    ref.step(st1, dt)
+    inc_ref = ref.stats()["sweep_increment"]
+    ref.close()
+    integ = Integrator(mh, g, n_nodes=5, sweeps=1, nu=2, scheme="cisdcq")
+    for call in (integ.sweep, integ.end):
+        with pytest.raises(nat.MisdcError) as e:
+            call()
+        assert e.value.code == nat.MISDC_ESTATE
+    st2 = _gpu_initial(nat, mh, Y, T)
+    integ.begin(st2, dt)
+    with pytest.raises(nat.MisdcError) as e:
+        integ.begin(st2, dt)
+    assert e.value.code == nat.MISDC_ESTATE
+    with pytest.raises(nat.MisdcError) as e:
+        integ.step(st2, dt)
+    assert e.value.code == nat.MISDC_ESTATE
+    inc = []
+    for k in range(K):
+        integ.sweep()
+        s = integ.stats()
+        assert s["n_sweeps"] == k + 1
+        inc.append(s["sweep_increment"][-1])
+    integ.end()
+    assert inc == inc_ref
+    assert np.array_equal(host(st1), host(st2))
+    # sweep until the increment is below a tolerance between the 2nd and 3rd
+    tol = (inc_ref[1] * inc_ref[2]) ** 0.5
+    st3 = _gpu_initial(nat, mh, Y, T)
+    integ.begin(st3, dt)
+    done = 0
+    while True:
+        integ.sweep()
+        done += 1
+        if integ.stats()["sweep_increment"][-1] <= tol:
+            break
+    integ.end()
+    assert done == 3
+    integ.close()
+    three = Integrator(mh, g, n_nodes=5, sweeps=3, nu=2, scheme="cisdcq")
+    st4 = _gpu_initial(nat, mh, Y, T)
+    three.step(st4, dt)
+    three.close()
+    g.close()
+    assert np.array_equal(host(st3), host(st4))
+
+
 def test_full_size_step_properties(nat, mech9, mh):
     """The 256x256 workload: conservation and convergence properties that
     hold at any size (the oracle is compared element-wise at small sizes)."""

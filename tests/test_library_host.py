@@ -112,6 +112,9 @@ def test_null_handles_rejected(nat):
     assert lib.misdc_get_tune(None, None) == nat.MISDC_EINVAL
     assert lib.misdc_set_tune(None, None) == nat.MISDC_EINVAL
     assert lib.misdc_autotune(None, None, 1.0, None, 1, None, None) == nat.MISDC_EINVAL
+    assert lib.misdc_step_begin(None, None, 1.0, None, None) == nat.MISDC_EINVAL
+    assert lib.misdc_sweep(None, None) == nat.MISDC_EINVAL
+    assert lib.misdc_step_end(None, None) == nat.MISDC_EINVAL
     o = nat.misdc_opts_default()
     assert (o.n_nodes, o.n_sweeps, o.nu, o.scheme) == (5, 6, 1, 2)
     assert o.use_graph == 0
