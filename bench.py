@@ -545,6 +545,83 @@ def mlp_main(args):
     print(json.dumps(line), flush=True)
 
 
+def rnu_main(args):
+    """The paper's cost ratio R_nu measured in time on the 256x256 flame: each
+    scheme sweeps (misdc_sweep) until its sweep increment is at most
+    --rnu-tol, then a step of that many sweeps is timed; R_nu = t(MISDCQ) /
+    t(CISDCQ-nu).  MISDCQ runs its D and R tasks in turn (its dependencies
+    leave nothing to overlap), CISDCQ-nu on the two streams."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1801_01201_amd import native
+    from paper_1801_01201_amd.flame import Mechanism, Grid, Integrator, initial_state
+    native.lib()
+    cfg = workload()
+    mech = synth.make_mechanism(**cfg["mech"])
+    nx, ny = cfg["n"]
+    n = nx * ny
+    mh = Mechanism(mech)
+    g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
+    Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
+    state, _ = initial_state(mh, torch.tensor(Y.reshape(9, -1), device="cuda"),
+                             torch.tensor(T.ravel(), device="cuda"))
+    torch.cuda.synchronize()
+    runs = {}
+    for name, scheme, nu in (("MISDCQ", "misdcq", 1), ("CISDCQ-1", "cisdcq", 1),
+                             ("CISDCQ-2", "cisdcq", 2), ("CISDCQ-3", "cisdcq", 3)):
+        probe = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=1, nu=nu, scheme=scheme)
+        st = state.clone()
+        probe.begin(st, cfg["dt"])
+        incs = []
+        while len(incs) < 64:
+            probe.sweep()
+            incs.append(probe.stats()["sweep_increment"][-1])
+            if incs[-1] <= args.rnu_tol:
+                break
+        probe.end()
+        probe.close()
+        K = len(incs)
+        integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=K, nu=nu, scheme=scheme)
+        st = state.clone()
+        for _ in range(max(1, args.warmup)):
+            integ.step(st, cfg["dt"])
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            st = state.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            integ.step(st, cfg["dt"])
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        integ.close()
+        runs[name] = {"sweeps": K, "ms_per_step": float(np.median(ts)) * 1e3,
+                      "final_increment": incs[-1], "converged": incs[-1] <= args.rnu_tol}
+        print(f"[bench] rnu {name}: {K} sweeps, {runs[name]['ms_per_step']:.2f} ms",
+              file=sys.stderr, flush=True)
+    base = runs["MISDCQ"]["ms_per_step"]
+    ratios = {k: base / v["ms_per_step"] for k, v in runs.items() if k != "MISDCQ"}
+    best = max(ratios, key=ratios.get)
+    M = cfg["n_nodes"] - 1
+    line = {
+        "metric": "R_nu = time of MISDCQ / time of CISDCQ-nu to reach the sweep-increment "
+                  "tolerance", "value": ratios[best], "unit": "ratio", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": runs[best]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"flame2d_256_rnu: 2-D periodic {nx}x{ny} flame, 9 species / "
+                               f"21 reactions, {cfg['n_nodes']} Gauss-Lobatto nodes, dt "
+                               f"{cfg['dt']} s, sweeps until the increment is <= {args.rnu_tol}",
+                   "cells": n, "best": best},
+        "R_nu": ratios, "runs": runs,
+        "cell_node_updates_per_s": {k: n * M * v["sweeps"] * (int(k[-1]) if k != "MISDCQ" else 1)
+                                    / (v["ms_per_step"] * 1e-3) for k, v in runs.items()},
+    }
+    g.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -569,7 +646,10 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the extra timing of the same steps replayed as one HIP graph")
     ap.add_argument("--workload", default="flame2d_256",
-                    choices=["flame2d_256", "ensemble64", "flame2d_512_n53", "flame2d_256_mlp"])
+                    choices=["flame2d_256", "ensemble64", "flame2d_512_n53", "flame2d_256_mlp",
+                             "flame2d_256_rnu"])
+    ap.add_argument("--rnu-tol", type=float, default=1e-8,
+                    help="flame2d_256_rnu: sweeps continue until the sweep increment is below this")
     ap.add_argument("--guess-sweeps", type=int, default=1,
                     help="flame2d_256_mlp: leading sweeps that use the learned guess (0: all)")
     ap.add_argument("--lu", default="fp64", choices=["fp64", "fp32_mfma"],
@@ -595,6 +675,8 @@ def main():
         return ensemble_main(args)
     if args.workload == "flame2d_512_n53":
         return n53_main(args)
+    if args.workload == "flame2d_256_rnu":
+        return rnu_main(args)
     if args.workload == "flame2d_256_mlp":
         return mlp_main(args)
     cfg = workload()
