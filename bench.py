@@ -557,14 +557,15 @@ def rnu_main(args):
     from paper_1801_01201_amd import native
     from paper_1801_01201_amd.flame import Mechanism, Grid, Integrator, initial_state
     native.lib()
-    cfg = workload()
+    cfg = synth.config(args.rnu_base)
     mech = synth.make_mechanism(**cfg["mech"])
+    N = mech["N"]
     nx, ny = cfg["n"]
     n = nx * ny
     mh = Mechanism(mech)
     g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
     Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
-    state, _ = initial_state(mh, torch.tensor(Y.reshape(9, -1), device="cuda"),
+    state, _ = initial_state(mh, torch.tensor(Y.reshape(N, -1), device="cuda"),
                              torch.tensor(T.ravel(), device="cuda"))
     torch.cuda.synchronize()
     runs = {}
@@ -610,8 +611,9 @@ def rnu_main(args):
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": runs[best]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"flame2d_256_rnu: 2-D periodic {nx}x{ny} flame, 9 species / "
-                               f"21 reactions, {cfg['n_nodes']} Gauss-Lobatto nodes, dt "
+        "config": {"workload": f"flame2d_256_rnu ({args.rnu_base}): 2-D periodic {nx}x{ny} "
+                               f"flame, {N} species / {mech['R']} reactions, "
+                               f"{cfg['n_nodes']} Gauss-Lobatto nodes, dt "
                                f"{cfg['dt']} s, sweeps until the increment is <= {args.rnu_tol}",
                    "cells": n, "best": best},
         "R_nu": ratios, "runs": runs,
@@ -650,6 +652,8 @@ def main():
                              "flame2d_256_rnu"])
     ap.add_argument("--rnu-tol", type=float, default=1e-8,
                     help="flame2d_256_rnu: sweeps continue until the sweep increment is below this")
+    ap.add_argument("--rnu-base", default="flame2d_256", choices=["flame2d_256", "flame2d_512_n53"],
+                    help="flame2d_256_rnu: the workload whose schemes are compared")
     ap.add_argument("--guess-sweeps", type=int, default=1,
                     help="flame2d_256_mlp: leading sweeps that use the learned guess (0: all)")
     ap.add_argument("--lu", default="fp64", choices=["fp64", "fp32_mfma"],
