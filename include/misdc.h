@@ -301,7 +301,7 @@ int misdc_step(misdc_integ_t integ, double* dev_state, double dt,
  * graph replay).  Begin and end with the same arguments and K sweeps give
  * misdc_step with n_sweeps = K bit for bit.  Errors: as misdc_step;
  * MISDC_ESTATE for begin while a step is open, a sweep or end without one,
- * or misdc_step while one is open. */
+ * or misdc_step, misdc_autotune or misdc_set_tune while one is open. */
 int misdc_step_begin(misdc_integ_t integ, double* dev_state, double dt, const double* dev_dt,
                      void* stream);
 int misdc_sweep(misdc_integ_t integ, void* stream);

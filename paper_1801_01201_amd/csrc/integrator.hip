@@ -1501,6 +1501,7 @@ int misdc_get_tune(misdc_integ_t I, misdc_tune* t) {
 
 int misdc_set_tune(misdc_integ_t I, const misdc_tune* t) {
     if (!I || !t) return fail(MISDC_EINVAL, "NULL argument");
+    if (I->open) return fail(MISDC_ESTATE, "a step opened by misdc_step_begin is not ended");
     if (t->cyclic != 0 && t->cyclic != 1) return fail(MISDC_EINVAL, "cyclic must be 0 or 1");
     if (t->serialize != 0 && t->serialize != 1) return fail(MISDC_EINVAL, "serialize must be 0 or 1");
     if (t->cu_split < 0 || t->cu_split > 3) return fail(MISDC_EINVAL, "cu_split must be in [0, 3]");

@@ -496,6 +496,10 @@ def test_step_one_sweep_at_a_time(nat, mech9, mh):
     with pytest.raises(nat.MisdcError) as e:
         integ.step(st2, dt)
     assert e.value.code == nat.MISDC_ESTATE
+    t = integ.tune()
+    with pytest.raises(nat.MisdcError) as e:       # the streams stay those of the open step
+        integ.set_tune(t["cg_variant"], t["cg_blocks"], t["cyclic"], 1)
+    assert e.value.code == nat.MISDC_ESTATE
     inc = []
     for k in range(K):
         integ.sweep()
