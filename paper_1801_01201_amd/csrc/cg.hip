@@ -563,6 +563,73 @@ __device__ __forceinline__ void grid_sync_direct(unsigned* bar, unsigned nb, uns
 // partials (into ``stage``) and of the tile's halo of m (hsrc: offsets into
 // the edge half ``eb``, -1 for none; into ``halo``) -- so the exchange costs
 // one memory latency.
+// Exchange 0 of the tiled kernel (its prologue): the blocks' partial sums of
+// NFD fields and the tile's edges of mt (u of every field) travel through
+// agent-scope atomic stores and loads around the barrier without cache
+// maintenance, as in the iterations; afterwards tot holds the NFD totals and
+// halo the tile's halo of u.
+template <int BS, int NFD, int HPT>
+__device__ __forceinline__ void grid_exchange_first(const CGArgs& a, const double* red,
+                                                    double* stage, double* tot, const double* mt,
+                                                    const int (&elds)[HPT], const int (&hsrc)[HPT],
+                                                    double* halo) {
+    constexpr int NW = BS / 64;
+    constexpr int PPT = (TILE_NB * NFD + BS - 1) / BS;
+    const unsigned nb = gridDim.x;
+    double* part = a.partial;                                // parity of exchange 0
+    double* eb = a.edge;                                     // edge half of exchange 0
+    __syncthreads();
+    for (int t = threadIdx.x; t < NFD; t += BS) {
+        double v = 0.0;
+        for (int w = 0; w < NW; ++w) v += red[t * NW + w];
+        __hip_atomic_store(&part[(size_t)blockIdx.x * (CG_MAX_FIELDS * 4) + t], v,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const int e = threadIdx.x + j * BS;                // (field, slot) of this tile
+        if (elds[j] >= 0)
+            __hip_atomic_store(&eb[(size_t)blockIdx.x * (NFD * TILE_HALO) + e], mt[elds[j]],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    grid_sync_direct(a.bar, nb, 0u, a.info);
+    const int total = (int)nb * NFD;
+    double pv[PPT], hv[HPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int e = threadIdx.x + j * BS;
+        const int b = e / NFD, t = e - b * NFD;
+        pv[j] = e < total ? __hip_atomic_load(&part[(unsigned)(b * (CG_MAX_FIELDS * 4) + t)],
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                          : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < HPT; ++j)
+        hv[j] = hsrc[j] >= 0
+                    ? __hip_atomic_load(&eb[(unsigned)hsrc[j]], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT)
+                    : 0.0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int e = threadIdx.x + j * BS;
+        if (e < total) stage[e] = pv[j];
+    }
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const int e = threadIdx.x + j * BS;
+        if (e < NFD * TILE_HALO) halo[e] = hv[j];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = wave; t < NFD; t += NW) {
+        double v = 0.0;
+        for (unsigned b = lane; b < nb; b += 64) v += stage[b * NFD + t];
+        v = wave_sum(v);
+        if (lane == 0) tot[t] = v;
+    }
+    __syncthreads();
+}
+
 template <int BS, int NFD, int HPT>
 __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned k, int it,
                                                       const double* red, double* stage,
@@ -590,7 +657,7 @@ __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned 
             __hip_atomic_store(&eb[(size_t)blockIdx.x * (NFD * TILE_HALO) + e], mt[elds[j]],
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    grid_sync_direct(a.bar, nb, (unsigned)it, a.info);
+    grid_sync_direct(a.bar, nb, k, a.info);
     const int total = (int)nb * NS;
     double pv[PPT], hv[HPT];
 #pragma unroll
@@ -786,25 +853,34 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
 #pragma unroll
     for (int d = 0; d < NFD; ++d) u[d] = 0.0;
     tile_precond<NFD, KSW>(r, u, dinv, cf, ke, kw, kn, ks, he, hw, hn, hs, zt, s_active);
+    // u of the tile into mt (the preconditioner has synchronised), its edges
+    // and the partials (b, b) exchanged as in the iterations (exchange 0)
 #pragma unroll
-    for (int d = 0; d < NFD; ++d)
-        if (own) a.r[(size_t)a.fmap[d] * a.n + cell] = u[d];
-    grid_allreduce<BS>(a, kb++, NFD, red, stage, tot);
+    for (int d = 0; d < NFD; ++d) mt[d * BS + threadIdx.x] = u[d];
+    grid_exchange_first<BS, NFD, HPT>(a, red, stage, tot, mt, elds, hsrc, halo);
+    ++kb;
     if (threadIdx.x < NFD) s_bb[threadIdx.x] = tot[threadIdx.x];
-    // ---- w = A u ----
+    // ---- w = A u (neighbours from the tile and its halo in LDS) ----
 #pragma unroll
     for (int d = 0; d < NFD; ++d) {
-        const double* U = a.r + (size_t)a.fmap[d] * a.n;
+        const double* Ut = mt + d * BS;
+        const double* H = halo + d * TILE_HALO;
         if (own) {
+            const int t = threadIdx.x;
             const double ui = u[d];
-            w[d] = ui - cf[d] * (ke * (U[ie] - ui) - kw * (ui - U[iw]) + kn * (U[in_] - ui) -
-                                 ks * (ui - U[is_]));
+            const double uE = he ? Ut[t + 1] : H[2 * TILE_X + ty];
+            const double uW = hw ? Ut[t - 1] : H[2 * TILE_X + TILE_Y + ty];
+            const double uN = hn ? Ut[t + TILE_X] : H[tx];
+            const double uS = hs ? Ut[t - TILE_X] : H[TILE_X + tx];
+            w[d] = ui - cf[d] * (ke * (uE - ui) - kw * (ui - uW) + kn * (uN - ui) -
+                                 ks * (ui - uS));
         }
     }
     int it = 0;
     for (; it < a.maxit; ++it) {
         // ---- m = M^-1 w (its tile edges published), partials gamma = (r,u), delta = (w,u), rr ----
-        double* eb = a.edge + (size_t)(it & 1) * (TILE_EDGE_DOUBLES / 2);
+        // exchange kb (the prologue's was exchange 0) uses edge half kb & 1
+        double* eb = a.edge + (size_t)(kb & 1) * (TILE_EDGE_DOUBLES / 2);
         double m[NFD];
 #pragma unroll
         for (int d = 0; d < NFD; ++d) m[d] = 0.0;
