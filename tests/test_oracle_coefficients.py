@@ -67,3 +67,56 @@ def test_node_to_node_weights_integrate_polynomials(n_nodes):
     for deg in range(n_nodes):
         exact = (tau[1:] ** (deg + 1) - tau[:-1] ** (deg + 1)) / (deg + 1)
         np.testing.assert_allclose(S @ tau ** deg, exact, rtol=0, atol=5e-16)
+
+
+@pytest.mark.parametrize("n_nodes", [7, 9])
+def test_many_node_tables(n_nodes):
+    """Pins of the 7- and 9-node tables (the library accepts up to 9 nodes).
+
+    The interior Gauss-Lobatto nodes are the roots of P'_M, taken here from
+    NumPy's Legendre series (not the recurrence and root finder of the
+    oracle); the last row of Q holds the Lobatto weights, exact for
+    polynomials of degree <= 2M - 1; every row of Q integrates polynomials of
+    degree <= M exactly; Q~I is the transpose of the upper Doolittle factor
+    of transpose(Q~).
+    """
+    M = n_nodes - 1
+    t = sdc_tables(n_nodes)
+    dP = np.polynomial.legendre.Legendre.basis(M).deriv()
+    inner = np.sort(dP.roots().real)
+    np.testing.assert_allclose(t["tau"], np.concatenate([[0.0], (inner + 1) / 2, [1.0]]),
+                               rtol=0, atol=1e-15)
+    # a Newton step on P'_M from each oracle node moves it by at most ~ulp
+    x = 2 * t["tau"][1:-1] - 1
+    assert np.all(np.abs(dP(x) / dP.deriv()(x)) <= 2e-15)
+    # symmetry of the nodes about 1/2
+    np.testing.assert_allclose(t["tau"] + t["tau"][::-1], 1.0, rtol=0, atol=4e-16)
+    w = t["Q"][-1]
+    for deg in range(2 * M):
+        assert abs(w @ t["tau"] ** deg - 1.0 / (deg + 1)) <= 2e-15, deg
+    # not exact one degree higher (Lobatto: exactly 2M - 1)
+    assert abs(w @ t["tau"] ** (2 * M) - 1.0 / (2 * M + 1)) > 1e-11
+    for deg in range(M + 1):
+        np.testing.assert_allclose(t["Q"] @ t["tau"] ** deg, t["tau"][1:] ** (deg + 1) / (deg + 1),
+                                   rtol=0, atol=2e-15)
+    QI = t["QI"]
+    assert np.all(np.triu(QI, 1) == 0.0)
+    L = t["Qt"].T @ np.linalg.inv(QI.T)
+    np.testing.assert_allclose(np.diag(L), 1.0, atol=1e-13)
+    np.testing.assert_allclose(np.triu(L, 1), 0.0, atol=1e-13)
+    np.testing.assert_allclose(QI[:, 0], t["Qt"][:, 0], rtol=0, atol=1e-16)
+    # backward-Euler and forward-Euler tables follow the node spacing
+    dtau = np.diff(t["tau"])
+    be = sdc_tables(n_nodes, qi="be")
+    for p in range(1, M + 1):
+        np.testing.assert_allclose(be["QI"][p - 1, :p], dtau[:p], atol=1e-16)
+        np.testing.assert_allclose(be["QE"][p - 1, :p - 1], dtau[1:p], atol=1e-16)
+
+
+@pytest.mark.parametrize("n_nodes", [7, 8, 9])
+def test_node_to_node_weights_many_nodes(n_nodes):
+    S = node_to_node_weights(n_nodes)
+    tau = sdc_tables(n_nodes)["tau"]
+    for deg in range(n_nodes):
+        exact = (tau[1:] ** (deg + 1) - tau[:-1] ** (deg + 1)) / (deg + 1)
+        np.testing.assert_allclose(S @ tau ** deg, exact, rtol=0, atol=2e-15)

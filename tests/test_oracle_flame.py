@@ -92,3 +92,22 @@ def test_flame_step_conservation(scheme, nu):
     np.testing.assert_allclose(out[N].sum(), phi0[N].sum(), rtol=1e-13)
     assert np.all(np.isfinite(out))
     assert all(np.all(it > 0) for it in prob.newton_iters)
+
+
+@pytest.fixture(scope="module")
+def nagumo_fine_reference():
+    return _nagumo_solution("misdcq", 1, 0.1 / 64, 8)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+def test_nagumo_misdc_order_per_sweep(nagumo_fine_reference, sweeps):
+    # node-to-node MISDC from the spread initial value: each sweep of the
+    # first-order correction raises the order by one, up to 2M (sections 3.1,
+    # 5.2); the third sweep is still pre-asymptotic at these step sizes
+    errs = []
+    for dt in (0.05, 0.025, 0.0125):
+        errs.append(np.mean(np.abs(_nagumo_solution("misdc", 1, dt, sweeps) - nagumo_fine_reference)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] > sweeps - 0.2, (errs, rates)
+    assert rates[-1] < sweeps + 0.5, (errs, rates)

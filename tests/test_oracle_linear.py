@@ -15,6 +15,7 @@ import pytest
 from oracle.linear import (LinearModel, sweeps_to_tolerance, cost_ratio,
                            iteration_matrix, spectral_radius)
 from oracle.sdc import sdc_step
+from oracle.coefficients import sdc_tables, node_to_node_weights
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")
 
@@ -202,3 +203,59 @@ def test_adaptive_limits_are_fixed_nu(n_nodes):
                     passes=pinf)[0]
     assert float(a0) == float(fixed3) and p0 == [3] * 4
     assert float(ainf) == float(fixed2) and pinf == [2] * 4
+
+
+def _misdc_one_stage(a, d, r, n_nodes, sweeps, dt=1.0):
+    """K node-to-node MISDC sweeps on phi' = (a + d + r) phi, phi^n = 1, written
+    as a single implicit Euler stage per sub-interval.
+
+    Eliminating phi_AD between the diffusion and the reaction update of MISDC
+    (eqs. update_equation_misdc_discrete_form_D/R) leaves, with delta = dt^m,
+        (1 - delta d)(1 - delta r) phi^{m+1,(k+1)} = phi^{m,(k+1)}
+            + delta a (phi^{m,(k+1)} - phi^{m,(k)})
+            - delta (d + r - delta d r) phi^{m+1,(k)} + dt S^{m:m+1} F^{(k)}:
+    a one-stage form in which a dropped or misweighted bracket of either
+    stage changes the result after the first sweep.
+    """
+    tau = sdc_tables(n_nodes)["tau"]
+    S = node_to_node_weights(n_nodes)
+    M = n_nodes - 1
+    z = a + d + r
+    old = np.ones(M + 1)
+    for _ in range(sweeps):
+        new = np.empty(M + 1)
+        new[0] = 1.0
+        for m in range(M):
+            de = dt * (tau[m + 1] - tau[m])
+            rhs = (new[m] + de * a * (new[m] - old[m]) - de * (d + r - de * d * r) * old[m + 1]
+                   + dt * (S[m] @ (z * old)))
+            new[m + 1] = rhs / ((1.0 - de * d) * (1.0 - de * r))
+        old = new
+    return old[M]
+
+
+@pytest.mark.parametrize("n_nodes", [3, 5])
+@pytest.mark.parametrize("adr", [(1.0, -2.0, -4.0), (0.5, -7.0, -0.3), (-1.5, -0.2, -30.0)])
+def test_misdc_sweeps_equal_one_stage_form(n_nodes, adr):
+    a, d, r = adr
+    for K in range(1, 6):
+        out, _ = sdc_step(LinearModel(a, d, r), np.array(1.0), 0.7, n_nodes, K, "misdc")
+        ref = _misdc_one_stage(a, d, r, n_nodes, K, dt=0.7)
+        assert abs(float(out) - ref) <= 1e-14 * max(1.0, abs(ref)), (K, float(out), ref)
+
+
+@pytest.mark.parametrize("n_nodes", [3, 5])
+@pytest.mark.parametrize("r", [-10.0, -100.0, -1000.0])
+@pytest.mark.parametrize("dmode", ["half", "fixed"])
+def test_gamma_lu_weights_beat_backward_euler(n_nodes, r, dmode):
+    """Section 3.1: the LU-trick implicit weights make the sweeps converge
+    faster than node-to-node backward Euler, and MISDCQ needs fewer sweeps
+    than MISDC on stiff problems."""
+    d = r / 2 if dmode == "half" else -5.0
+    g_be = _gamma(1.0, d, r, "misdc", 1, n_nodes)
+    g_lu = _gamma(1.0, d, r, "misdcq", 1, n_nodes)
+    assert g_be > g_lu + 5e-3, (g_be, g_lu)
+    n_be = sweeps_to_tolerance(1.0, d, r, "misdc", n_nodes=n_nodes, max_sweeps=3000)
+    n_lu = sweeps_to_tolerance(1.0, d, r, "misdcq", n_nodes=n_nodes, max_sweeps=3000)
+    assert n_lu is not None
+    assert n_be is None or n_be > n_lu
