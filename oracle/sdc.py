@@ -220,17 +220,21 @@ def sweep_imexq(prob, phi, F, dt, tab):
 
 def sdc_step(prob, phi_n, dt, n_nodes, sweeps, scheme, nu=1, qe="cumulative",
              increments=None, stop_tol=None, norm=None, nu_tol=None, passes=None,
-             changes=None):
+             changes=None, field_increments=None, progress=None):
     """Advance phi_n by one step of size dt.
 
     I1-I2: node 0 and every node of sweep 0 hold phi^n; I4: the operator values
     at phi^n serve for the first sweep's quadrature.  After each sweep the
     increment |phi^{M,(k+1)} - phi^{M,(k)}| (``norm``, default max-abs) is
-    appended to ``increments``.  With ``stop_tol`` the step stops at the first
-    sweep whose increment is <= stop_tol.  CISDCQ with ``nu_tol`` adapts the
-    number of nested iterations of each sweep (see sweep_cisdcq); the passes
-    done per sweep are appended to ``passes`` and their changes to
-    ``changes``.  Returns (phi^{n+1}, sweeps done).
+    appended to ``increments``, and, for states with a leading field axis,
+    the pair (max over cells of |phi^{M,(k+1)} - phi^{M,(k)}|, max over cells
+    of |phi^{M,(k+1)}|) of every field to ``field_increments``; ``progress``
+    (if given) is called with (sweep index, increment) after each sweep.
+    With ``stop_tol`` the step stops at the first sweep whose increment is <=
+    stop_tol.  CISDCQ with ``nu_tol`` adapts the number of nested iterations
+    of each sweep (see sweep_cisdcq); the passes done per sweep are appended
+    to ``passes`` and their changes to ``changes``.  Returns (phi^{n+1},
+    sweeps done).
     """
     tab = scheme_tables(n_nodes, scheme, qe)
     S = node_to_node_weights(n_nodes) if scheme == "misdc" else None
@@ -254,6 +258,13 @@ def sdc_step(prob, phi_n, dt, n_nodes, sweeps, scheme, nu=1, qe="cumulative",
         inc = norm(new_phi[M] - phi[M])
         if increments is not None:
             increments.append(inc)
+        if field_increments is not None:
+            nf = new_phi[M].shape[0]
+            diff = np.abs(new_phi[M] - phi[M]).reshape(nf, -1).max(axis=1)
+            mag = np.abs(new_phi[M]).reshape(nf, -1).max(axis=1)
+            field_increments.append(np.stack([diff, mag], axis=1))
+        if progress is not None:
+            progress(done, inc)
         phi, F = new_phi, new_F
         done += 1
         if stop_tol is not None and inc <= stop_tol:

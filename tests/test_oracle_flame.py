@@ -111,3 +111,25 @@ def test_nagumo_misdc_order_per_sweep(nagumo_fine_reference, sweeps):
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert rates[-1] > sweeps - 0.2, (errs, rates)
     assert rates[-1] < sweeps + 0.5, (errs, rates)
+
+
+def test_field_increments_and_progress_record_the_sweep_changes():
+    """The per-field increment record of sdc_step: its differences are those
+    of successive sweeps' node-M states, computed here by running the step
+    with 1, 2 and 3 sweeps; the overall max-abs increment is the largest
+    field difference; the progress callback sees every sweep in order."""
+    mech = synth.make_mechanism(9, 21, 0)
+    Y, T = synth.flame_2d(mech, 12, 10)
+    prob = FlameProblem(mech, (0.01, 0.01), (100.0, 0.0))
+    phi = relaxed_initial_state(prob, Y, T)
+    fi, inc, seen = [], [], []
+    sdc_step(prob, phi, 5e-5, 3, 3, "cisdcq", increments=inc, field_increments=fi,
+             progress=lambda k, v: seen.append((k, v)))
+    assert [k for k, _ in seen] == [0, 1, 2] and [v for _, v in seen] == inc
+    states = [phi] + [sdc_step(prob, phi, 5e-5, 3, k, "cisdcq")[0] for k in (1, 2, 3)]
+    for k in range(3):
+        d = np.abs(states[k + 1] - states[k]).reshape(10, -1).max(axis=1)
+        a = np.abs(states[k + 1]).reshape(10, -1).max(axis=1)
+        np.testing.assert_allclose(fi[k][:, 0], d, rtol=1e-12, atol=1e-300)
+        np.testing.assert_allclose(fi[k][:, 1], a, rtol=1e-15)
+        assert inc[k] == fi[k][:, 0].max()
