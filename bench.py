@@ -12,8 +12,11 @@ metric: cell-node updates per second per concurrent sweep
         = cells * M * nu * sweeps * steps / timed seconds.
 Also reported: Newton iterations per cell-node solve, the roofline of the
 dominant kernel (live HIP-event timing inside the library, on the stream the
-kernel runs on), the FP64 oracle timed on the host for one sweep of the same
-workload, and an accuracy gate (GPU vs oracle on a 48 x 40 step, <= 1e-8).
+kernel runs on), the FP64 oracle timed on the host for a sample of the same
+workload, and an accuracy gate: one GPU step of the timed workload at its
+full size and launch configuration against the oracle's step (<= 1e-8), with
+the sweep increments compared in the same norm.  A run with unconverged
+solves or a failed gate prints its line with "valid": false and exits 3.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -119,68 +122,122 @@ def workload():
     return c
 
 
-def cpu_baseline_leg(cfg):
-    """The FP64 oracle, as it stands, on one sweep of the same workload."""
-    import numpy as np
+def host_description():
+    """CPU model and the cores this process may use (for the CPU baseline)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def _oracle_sample(cfg, nx, ny, sweeps):
+    """Wall and CPU seconds of the oracle's step (``sweeps`` sweeps) on an
+    nx x ny version of the workload, and the cell-node updates it made."""
     import synth
     from oracle.adr import FlameProblem, relaxed_initial_state
     from oracle.sdc import sdc_step
     mech = synth.make_mechanism(**cfg["mech"])
-    # bounded sample: the same flame, mechanism, step and scheme on a
-    # 128 x 128 grid (a quarter of the cells), three sweeps
-    nx, ny = 128, 128
     Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
     prob = FlameProblem(mech, cfg["dx"], cfg["u"])
     phi = relaxed_initial_state(prob, Y, T)
-    w0, c0 = time.perf_counter(), time.process_time()
-    sweeps = 3
     nu_tol = cfg.get("nu_tol", 0.0)
     ps = []
+    w0, c0 = time.perf_counter(), time.process_time()
     sdc_step(prob, phi, cfg["dt"], cfg["n_nodes"], sweeps, cfg["scheme"], nu=cfg["nu"],
              nu_tol=nu_tol if nu_tol > 0 else None, passes=ps)
     wall = time.perf_counter() - w0
     cpu = time.process_time() - c0
     M = cfg["n_nodes"] - 1
-    updates = nx * ny * M * (sum(ps) if ps else cfg["nu"] * sweeps)
-    return {"value": updates / wall, "unit": "cell-node updates/s",
-            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
-            "sample": f"{sweeps} CISDCQ-{cfg['nu']} sweeps ({M} nodes) of the same flame workload on "
-                      f"{nx}x{ny} cells (one quarter of the cells), wall {wall:.1f} s; "
-                      f"the metric is per cell-node update",
-            "seconds": wall}
+    return wall, cpu, nx * ny * M * (sum(ps) if ps else cfg["nu"] * sweeps)
 
 
-def accuracy_gate(cfg, mech, mh):
-    """GPU step vs oracle step on a 48 x 40 version of the workload."""
+def cpu_baseline_leg(cfg):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload:
+    the same flame, mechanism, step and scheme on 128 x 128 cells (a quarter
+    of the cells) for three sweeps, with the threads it takes by itself (its
+    per-field diffusion systems in parallel, NumPy's own threading), and
+    once more on 64 x 64 cells with every thread pool limited to one."""
+    from threadpoolctl import threadpool_limits
+    import oracle.transport as otr
+    wall, cpu, updates = _oracle_sample(cfg, 128, 128, 3)
+    saved = otr.SOLVE_THREADS
+    try:
+        otr.SOLVE_THREADS = 1
+        with threadpool_limits(limits=1):
+            w1, _, u1 = _oracle_sample(cfg, 64, 64, 3)
+    finally:
+        otr.SOLVE_THREADS = saved
+    M = cfg["n_nodes"] - 1
+    out = {"value": updates / wall, "unit": "cell-node updates/s",
+           "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+           "sample": f"3 CISDCQ-{cfg['nu']} sweeps ({M} nodes) of the same flame workload on "
+                     f"128x128 cells (one quarter of the cells), wall {wall:.1f} s, CPU "
+                     f"{cpu:.1f} s; the metric is per cell-node update",
+           "seconds": wall,
+           "one_thread": {"value": u1 / w1, "sample": "3 sweeps on 64x64 cells, every thread "
+                                                       f"pool limited to one, wall {w1:.1f} s"}}
+    out.update(host_description())
+    return out
+
+
+def accuracy_gate(cfg, mech, mh, state0, tune):
+    """The timed workload at its full size and launch configuration: one GPU
+    step from the benchmark's initial state against the oracle's step from
+    the same synthetic input (field-normalised max error <= 1e-8), and the
+    GPU's sweep increments against the oracle's in the same norm."""
     import numpy as np
-    import torch
     import synth
     from oracle.adr import FlameProblem, relaxed_initial_state
     from oracle.sdc import sdc_step
-    from paper_1801_01201_amd.flame import Grid, Integrator, initial_state
-    nx, ny = 48, 40
-    Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
-    prob = FlameProblem(mech, cfg["dx"], cfg["u"])
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    nx, ny = cfg["n"]
     nu_tol = cfg.get("nu_tol", 0.0)
-    ps = []
-    ref, _ = sdc_step(prob, relaxed_initial_state(prob, Y, T), cfg["dt"], cfg["n_nodes"],
-                      cfg["sweeps"], cfg["scheme"], nu=cfg["nu"],
-                      nu_tol=nu_tol if nu_tol > 0 else None, passes=ps)
-    st, _ = initial_state(mh, torch.tensor(Y.reshape(9, -1), device="cuda"),
-                          torch.tensor(T.ravel(), device="cuda"))
+    st = state0.clone()
     g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
     integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
                        scheme=cfg["scheme"], nu_tol=nu_tol, cg_rtol=cfg.get("cg_rtol", 1e-13))
+    if tune:
+        integ.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"],
+                       tune["cu_split"], tune["stagger"])
     integ.step(st, cfg["dt"])
     out = st.cpu().numpy()
-    gpu_passes = integ.stats()["nested_passes"]
+    s = integ.stats()
     integ.close()
     g.close()
+    print(f"[bench] gate: GPU step done, oracle step on {nx}x{ny} follows", file=sys.stderr,
+          flush=True)
+    Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
+    prob = FlameProblem(mech, cfg["dx"], cfg["u"])
+    ps, fi = [], []
+
+    def progress(k, inc):
+        print(f"[bench] gate: oracle sweep {k} done", file=sys.stderr, flush=True)
+
+    w0 = time.perf_counter()
+    ref, _ = sdc_step(prob, relaxed_initial_state(prob, Y, T), cfg["dt"], cfg["n_nodes"],
+                      cfg["sweeps"], cfg["scheme"], nu=cfg["nu"],
+                      nu_tol=nu_tol if nu_tol > 0 else None, passes=ps, field_increments=fi,
+                      progress=progress)
+    wall = time.perf_counter() - w0
     ref = ref.reshape(10, -1)
     err = float((np.abs(out - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
-    ok = err <= 1e-8 and (nu_tol <= 0 or gpu_passes == ps)
+    inc_ref = [float((f[:, 0] / f[:, 1]).max()) for f in fi]
+    inc_err = max(abs(a - b) for a, b in zip(s["sweep_increment"], inc_ref))
+    ok = (err <= 1e-8 and s["converged"] and len(inc_ref) == len(s["sweep_increment"])
+          and (nu_tol <= 0 or s["nested_passes"] == ps))
     return {"err": err, "tol": 1e-8, "passed": bool(ok), "grid": f"{nx}x{ny}",
-            "nested_passes": gpu_passes}
+            "launch_config": tune, "sweep_increment_gpu": s["sweep_increment"],
+            "sweep_increment_oracle": inc_ref, "sweep_increment_max_abs_diff": inc_err,
+            "nested_passes": s["nested_passes"], "oracle_seconds": wall}
 
 
 def graph_leg(integ, mh, g, cfg, state, args, tune):
@@ -208,7 +265,8 @@ def graph_leg(integ, mh, g, cfg, state, args, tune):
     nx, ny = cfg["n"]
     upd = nx * ny * (cfg["n_nodes"] - 1) * cfg["nu"] * cfg["sweeps"] * args.steps
     return {"value": upd / el, "ms_per_step": el / args.steps * 1e3,
-            "newton_failed": s["newton_failed"], "cg_failed": s["cg_failed"]}
+            "newton_failed": s["newton_failed"], "cg_failed": s["cg_failed"],
+            "converged": s["converged"]}
 
 
 def ensemble_main(args):
@@ -725,6 +783,7 @@ def main():
         if args.serialize:
             integ.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], 1)
         print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
+    state0 = None if args.no_gate else state.clone()
     for _ in range(args.warmup):
         integ.step(state, cfg["dt"])
     torch.cuda.synchronize()
@@ -798,7 +857,7 @@ def main():
              "newton_ms_per_launch": r_ms / max(1, r_n),
              "diffusion_solve_share_of_step": d_ms / (elapsed * 1e3),
              "newton_share_of_step": r_ms / (elapsed * 1e3)}
-    gate = None if args.no_gate else accuracy_gate(cfg, mech, mh)
+    gate = None if args.no_gate else accuracy_gate(cfg, mech, mh, state0, tune)
     integ.close()
     g.close()
     line = {
@@ -830,7 +889,13 @@ def main():
         "accuracy_gate": gate,
         "newton_failed": stats["newton_failed"], "cg_failed": stats["cg_failed"],
     }
+    # a run with unconverged solves or a failed gate is not a measurement
+    line["valid"] = bool(stats["converged"] and (gate is None or gate["passed"])
+                         and (graph is None or graph["converged"]))
     print(json.dumps(line), flush=True)
+    if not line["valid"]:
+        print("[bench] INVALID: unconverged solves or failed accuracy gate", file=sys.stderr)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -40,6 +40,7 @@
 #ifndef MISDC_H
 #define MISDC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -131,13 +132,39 @@ typedef struct {
     double R_c;
 } misdc_mech_desc;
 
-/* Validates and copies the mechanism to the current HIP device.
- * Supported species counts for the reaction solve: 9 (FP64, one thread per
- * cell); other counts are accepted by the operator kernels only. */
+/* Validates and copies the mechanism to the current HIP device (2 to 256
+ * species).  What each part supports:
+ *   - enthalpy, temperature and the explicit transport operators: any
+ *     count;
+ *   - the reaction source and the reaction solve: up to 63 species (one
+ *     64-lane wavefront per cell, FP64 or FP32-MFMA LU); for exactly 9
+ *     species also one thread per cell (MISDC_NEWTON_THREAD); for at most 12
+ *     species a one-thread-per-cell kernel generated for the mechanism
+ *     (MISDC_NEWTON_SPECIALIZED, the default wherever it is loaded);
+ *   - the implicit diffusion solve: up to 64 diffused fields (N - 1 species
+ *     plus h);
+ *   - the integrator: up to 63 species (MISDC_EUNSUPPORTED beyond). */
 int misdc_mech_create(const misdc_mech_desc* desc, misdc_mech_t* out);
 int misdc_mech_destroy(misdc_mech_t mech);
 /* Species count of a mechanism (host, no GPU work). */
 int misdc_mech_species(misdc_mech_t mech, int32_t* n_species);
+/* The reaction solve generated for this mechanism (MISDC_NEWTON_SPECIALIZED):
+ * misdc_mech_create writes the source of a one-thread-per-cell Newton kernel
+ * (section 3.3, step S5) in which every rate constant and species index is a
+ * literal, compiles it with hiprtc for the current device (once per process,
+ * device and mechanism) and loads it.  Mechanisms of at most 12 species.
+ * *available is 1 if it is loaded, else 0 and the generic kernels serve;
+ * *status (may be NULL) points to a message owned by the mechanism saying
+ * which (for instance why it was not generated).  Host only. */
+int misdc_mech_specialized(misdc_mech_t mech, int32_t* available, const char** status);
+/* The source text that misdc_mech_create generates for a mechanism
+ * descriptor, without a device: validates the descriptor, writes the text
+ * (NUL-terminated) into buf when *len is large enough and sets *len to the
+ * bytes needed (buf NULL: size query).  With compile != 0 the text is also
+ * compiled with hiprtc for gfx950 (no GPU needed): MISDC_EDEVICE with the
+ * compiler's log in misdc_last_error if that fails.  MISDC_EUNSUPPORTED
+ * above 12 species. */
+int misdc_mech_generate(const misdc_mech_desc* desc, int compile, char* buf, size_t* len);
 
 /* h = sum_k Y_k h_k(T) / W_k for n cells.  dev_Y: N x n, dev_T, dev_h: n. */
 int misdc_enthalpy(misdc_mech_t mech, int64_t n, const double* dev_Y,
@@ -150,9 +177,13 @@ int misdc_reaction_source(misdc_mech_t mech, int64_t n, const double* dev_Y,
                           const double* dev_h, double* dev_FR, void* stream);
 
 enum {
-    MISDC_NEWTON_AUTO = 0,
+    MISDC_NEWTON_AUTO = 0,       /* the generated kernel where it exists (FP64 LU),
+                                    else one thread per cell for 9 species, else
+                                    one wavefront per cell */
     MISDC_NEWTON_THREAD = 1,     /* one thread per cell (9 species only) */
-    MISDC_NEWTON_WAVE = 2        /* one 64-lane wavefront per cell (<= 63 species) */
+    MISDC_NEWTON_WAVE = 2,       /* one 64-lane wavefront per cell (<= 63 species) */
+    MISDC_NEWTON_SPECIALIZED = 3 /* one thread per cell, source generated for the
+                                    mechanism (see misdc_mech_specialized) */
 };
 enum {
     MISDC_LU_FP64 = 0,           /* LU with partial pivoting in FP64 */
@@ -273,7 +304,25 @@ void misdc_opts_default(misdc_opts* opts);
  * workspace and two streams (diffusion, reaction) of default priority. */
 int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* opts,
                        misdc_integ_t* out);
+/* Destroys the integrator after its streams have drained; frees its device
+ * workspace and the streams it created (never a caller's). */
 int misdc_integ_destroy(misdc_integ_t integ);
+
+/* The two streams the tasks of a sweep run on (section 3.2.2: the
+ * diffusion steps S3-S4 on one, the reaction steps S5-S6 on the other):
+ * hipStream_t values passed as void*, for example two torch streams, used
+ * in place of the integrator's own; NULL selects the integrator's own
+ * stream again (so the null/default stream itself cannot be passed).  The
+ * caller keeps ownership and must keep the streams alive while the
+ * integrator uses them (until misdc_integ_destroy or another call of this).
+ * Both streams must have the default priority.  Synchronises the streams
+ * in use before the switch.  A step captured as a graph is captured again.
+ * A caller's reaction stream replaces a CU-masked one (misdc_tune.cu_split
+ * falls to 0 and cannot be set while it is in use).  Results do not depend
+ * on the streams.  Errors: MISDC_EINVAL (equal non-NULL streams: use
+ * misdc_tune.serialize for one stream), MISDC_ESTATE (a step opened by
+ * misdc_step_begin is not ended). */
+int misdc_set_streams(misdc_integ_t integ, void* diffusion_stream, void* reaction_stream);
 
 /* One time step of size dt (dev_dt: NULL for a scalar dt; for an ensemble
  * grid a device array of one dt per flame, in which case dt is ignored):
@@ -294,14 +343,20 @@ int misdc_step(misdc_integ_t integ, double* dev_state, double dt,
  * misdc_sweep), for callers that choose the number of sweeps as they go,
  * e.g. until the sweep increment of misdc_get_stats falls below a tolerance:
  * misdc_step_begin does I1-I4 (ordered after prior work on ``stream``),
- * each misdc_sweep issues one more correction sweep (at most 64 per step),
- * and misdc_step_end writes node M of the last sweep into dev_state (later
- * work on ``stream`` is ordered after it).  misdc_get_stats between sweeps
- * synchronises and reports the sweeps done so far.  Sweeps run eagerly (no
- * graph replay).  Begin and end with the same arguments and K sweeps give
- * misdc_step with n_sweeps = K bit for bit.  Errors: as misdc_step;
- * MISDC_ESTATE for begin while a step is open, a sweep or end without one,
- * or misdc_step, misdc_autotune or misdc_set_tune while one is open. */
+ * each misdc_sweep issues one more correction sweep (at most 64 per step;
+ * ordered after prior work on its ``stream``), and misdc_step_end writes
+ * node M of the last sweep into dev_state (later work on ``stream`` is
+ * ordered after it), then synchronises with the integrator's streams and
+ * returns MISDC_ENOTCONV if any cell-node Newton solve of the step did not
+ * converge or any diffusion solve stopped at its iteration limit (the state
+ * is written either way; misdc_get_stats has the counts).  misdc_get_stats
+ * between sweeps synchronises and reports the sweeps done so far.  Sweeps
+ * run eagerly (no graph replay).  Begin and end with the same arguments and
+ * K sweeps give misdc_step with n_sweeps = K bit for bit.  Errors: as
+ * misdc_step; MISDC_ESTATE for begin while a step is open, a sweep or end
+ * without one, or misdc_step, misdc_autotune, misdc_set_tune,
+ * misdc_set_streams, misdc_integ_set_guess or misdc_integ_record while one
+ * is open. */
 int misdc_step_begin(misdc_integ_t integ, double* dev_state, double dt, const double* dev_dt,
                      void* stream);
 int misdc_sweep(misdc_integ_t integ, void* stream);
@@ -354,7 +409,12 @@ int misdc_set_tune(misdc_integ_t integ, const misdc_tune* tune);
 
 /* Statistics of the last step (synchronises with the integrator's streams).
  * sweep_increment[k] = max over fields of max_i |phi^{M,(k+1)} - phi^{M,(k)}|
- * normalised by max_i |phi^{M,(k+1)}| of that field. */
+ * normalised by max_i |phi^{M,(k+1)}| of that field.
+ * misdc_step is asynchronous and returns before its solves finish, so this
+ * call reports their outcome: it fills *stats and returns MISDC_ENOTCONV if
+ * newton_failed or cg_failed is above zero (cells whose Newton iteration
+ * reached newton.maxit or stalled; diffusion solves that reached cg_maxit or
+ * whose workgroups timed out waiting for each other), else MISDC_OK. */
 typedef struct {
     int64_t newton_solves;      /* cell-node Newton solves */
     int64_t newton_iters;       /* total linear solves */
@@ -452,6 +512,19 @@ int misdc_mlp_features(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, const doub
                        const double* dev_h, const double* dev_c, float* dev_x, void* stream);
 int misdc_mlp_targets(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, const double* dev_bY,
                       const double* dev_h, const double* dev_Y, float* dev_t, void* stream);
+/* Training set of n reaction problems (dev_bY: N x n, dev_h, dev_c: n) and
+ * their solutions dev_Y (N x n), 2 <= n <= 2^31: sets the network's
+ * normalisation from the data and writes the normalised features (dev_x,
+ * n x (N+2)) and targets (dev_t, n x (N+1)) in shuffled row order, ready for
+ * misdc_mlp_train.  The statistics are FP64 column sums in a fixed order:
+ * in_mu = mean of each raw feature, in_sd = its sample standard deviation
+ * floored at max(1e-3 |in_mu|, 1e-6), out_sd = the sample standard
+ * deviation of each raw target floored at 1e-30.  Problem i goes to row
+ * (a i + b) mod n, with a coprime to n and b drawn from ``seed``
+ * (SplitMix64).  Work buffers are allocated and freed on the stream. */
+int misdc_mlp_prepare_training(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, const double* dev_bY,
+                               const double* dev_h, const double* dev_c, const double* dev_Y,
+                               uint64_t seed, float* dev_x, float* dev_t, void* stream);
 /* Initial guess of misdc_reaction_solve_batch: dev_Y (N x n) holds the plain
  * guess on entry; each cell takes the network's guess (b_Y + predicted
  * increment) instead if
@@ -466,7 +539,8 @@ int misdc_reaction_guess_mlp(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, cons
  * every sweep) starts from the learned guess where it has the smaller
  * residual (mlp NULL: the plain guess, the previous iterate, everywhere).
  * Allocates the network's buffers for the grid; the network must outlive
- * its use.  Synchronises. */
+ * its use.  Synchronises.  MISDC_ESTATE while a step opened by
+ * misdc_step_begin is not ended (as for misdc_integ_record). */
 int misdc_integ_set_guess(misdc_integ_t integ, misdc_mlp_t mlp, int sweeps);
 /* Records the reaction problems of later steps: task t (in issue order, up
  * to max_tasks) writes (b_Y: N x n, h: n, c: n, Y: N x n) doubles at

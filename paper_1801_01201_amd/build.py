@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmisdc.so")
-SOURCES = ["tables.cpp", "chem.hip", "chem_wave.hip", "transport.hip", "cg.hip", "mlp.hip", "integrator.hip"]
+SOURCES = ["tables.cpp", "chem.hip", "chem_spec.cpp", "chem_wave.hip", "transport.hip", "cg.hip", "mlp.hip", "integrator.hip"]
 ARCH = os.environ.get("MISDC_OFFLOAD_ARCH", "gfx950")
 
 
@@ -51,7 +51,10 @@ def build(verbose=False, jobs=4):
             procs = []
     _wait(procs)
     tmp = LIB + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    # hiprtc compiles the reaction solve generated for each mechanism
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(cc)), "lib")
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L" + rocm_lib, "-lhiprtc", "-Wl,-rpath," + rocm_lib]
     out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if out.returncode != 0:
         raise RuntimeError("link failed:\n" + out.stdout)

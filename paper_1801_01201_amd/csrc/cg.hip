@@ -516,6 +516,15 @@ __device__ __forceinline__ int halo_source(const CGArgs& a, int nty, int bx, int
     return (tile * 9 + d) * TILE_HALO + slot;
 }
 
+// The exchange around this barrier orders relaxed agent-scope atomics with
+// s_waitcnt and workgroup barriers only, with no release/acquire pair.  That
+// another XCD then sees the data is how gfx950 executes such atomics (they
+// bypass the non-coherent per-CU caches and are ordered once complete), not
+// a guarantee of the HIP memory model, so any other target is refused.
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(__gfx950__)
+#error "the fence-free grid exchange of the tiled CG is written for gfx950 only"
+#endif
+
 // Grid barrier k without cache maintenance, for data exchanged only through
 // agent-scope atomic stores and loads (which the hardware keeps coherent
 // across the XCDs without writing back or invalidating the L2): every wave

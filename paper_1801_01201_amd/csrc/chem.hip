@@ -503,9 +503,26 @@ int launch_reaction_source(const Mech& m, int64_t n, const double* Y, const doub
 int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s) {
     if (a.n == 0) return MISDC_OK;
     const int kind = a.opt.kernel;
-    const bool thread = (kind == MISDC_NEWTON_THREAD) || (kind == MISDC_NEWTON_AUTO && m.dev.N == 9);
-    if (thread && a.opt.lu != MISDC_LU_FP64)
-        return fail(MISDC_EINVAL, "the per-thread reaction solve computes its LU in FP64 only");
+    if (kind < MISDC_NEWTON_AUTO || kind > MISDC_NEWTON_SPECIALIZED)
+        return fail(MISDC_EINVAL, "unknown reaction solve kernel %d", kind);
+    // the generated kernel where it exists (automatic choice for an FP64 LU)
+    const bool spec = (kind == MISDC_NEWTON_SPECIALIZED) ||
+                      (kind == MISDC_NEWTON_AUTO && m.spec_fn && a.opt.lu == MISDC_LU_FP64);
+    const bool thread = !spec && ((kind == MISDC_NEWTON_THREAD) ||
+                                  (kind == MISDC_NEWTON_AUTO && m.dev.N == 9));
+    if ((thread || spec) && a.opt.lu != MISDC_LU_FP64)
+        return fail(MISDC_EINVAL, "the per-thread reaction solves compute their LU in FP64 only");
+    if (spec) {
+        int rc = launch_newton_spec(m, a, s);
+        if (rc) return rc;
+        if (a.stats && a.iters && !a.buckets) {
+            const int64_t gb = grid_for(a.n, 256 * 16);
+            hipLaunchKernelGGL(newton_stats_kernel<9>, dim3(gb < 32 ? gb : 32), dim3(256), 0, s,
+                               a.n, a.iters, a.stats, a.hist);
+            MISDC_HIP(hipGetLastError());
+        }
+        return MISDC_OK;
+    }
     if (!thread) return launch_reaction_newton_wave(m, a, a.opt.lu, s);
     if (m.dev.N != 9)
         return fail(MISDC_EUNSUPPORTED, "per-thread reaction solve: %d species not built", m.dev.N);

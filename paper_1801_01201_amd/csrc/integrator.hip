@@ -71,8 +71,10 @@ struct misdc_integ_s {
     int M = 0, N = 0, NF = 0, nu = 1, levels = 2;
     int64_t n = 0;
     hipStream_t sD = nullptr, sR = nullptr;       // sR is sR2 (or sRm), or sD when serialised
-    hipStream_t sR2 = nullptr;
+    hipStream_t sR2 = nullptr;                    // reaction stream (own, or the caller's)
     hipStream_t sRm = nullptr;                    // reaction stream on part of the CUs
+    hipStream_t sD_own = nullptr, sR2_own = nullptr;   // the streams the library created
+    bool caller_R = false;                        // sR2 is a stream of the caller's
     int cu_split = 0, sRm_split = 0;              // quarters of the CUs given to sRm
     int stagger = 0;                              // Newton waits for the next CG's start
     std::vector<std::vector<NodeBuf>> lev;        // [levels][M+1]
@@ -706,6 +708,35 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
     return MISDC_OK;
 }
 
+// Waits for all work of the integrator's streams.
+int sync_streams(misdc_integ_s* I) {
+    MISDC_HIP(hipStreamSynchronize(I->sD));
+    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
+    MISDC_HIP(hipStreamSynchronize(I->sR2));
+    return MISDC_OK;
+}
+
+// MISDC_ENOTCONV (with a message naming the counters) if the step whose
+// counters are on the device left a Newton solve or a diffusion solve
+// unconverged; the streams must be synchronised.
+int convergence_status(misdc_integ_s* I) {
+    unsigned long long ns[8];
+    int32_t cg[8];
+    MISDC_HIP(hipMemcpy(ns, I->nstats, sizeof(ns), hipMemcpyDeviceToHost));
+    unsigned long long failed = ns[2];
+    std::vector<unsigned long long> b((size_t)NEWTON_BUCKETS * NEWTON_BUCKET_STRIDE);
+    MISDC_HIP(hipMemcpy(b.data(), I->nbuckets, sizeof(unsigned long long) * b.size(),
+                        hipMemcpyDeviceToHost));
+    for (int k = 0; k < NEWTON_BUCKETS; ++k) failed += b[(size_t)k * NEWTON_BUCKET_STRIDE + 2];
+    MISDC_HIP(hipMemcpy(cg, I->cgstats, sizeof(cg), hipMemcpyDeviceToHost));
+    if (failed > 0 || cg[2] > 0 || cg[4] > 0)
+        return fail(MISDC_ENOTCONV,
+                    "unconverged solves in the last step: %llu cell-node Newton solves, "
+                    "%d diffusion solves at their iteration limit, %d barrier timeouts",
+                    failed, cg[2], cg[4]);
+    return MISDC_OK;
+}
+
 // Validates the arguments of a step (also used by the autotuner).
 int check_step_args(misdc_integ_s* I, const double* state, double dt, const double* dev_dt) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
@@ -819,6 +850,81 @@ extern "C" {
 const char* misdc_last_error(void) { return g_err; }
 
 const char* misdc_version(void) { return "misdc-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"
+
+namespace {
+
+// Host tables of a validated mechanism descriptor (those the generated
+// reaction solve is written from).
+void mech_tables(const misdc_mech_desc* d, MechTables& t) {
+    const int N = d->n_species, R = d->n_reactions;
+    t.N = N;
+    t.R = R;
+    t.bath = d->bath;
+    t.slots.assign(4 * (size_t)R, -1);
+    t.Ta.assign(R, 0.0);
+    t.dn.assign(R, 0.0);
+    t.uW.assign((size_t)R * N, 0.0);
+    for (int j = 0; j < R; ++j) {
+        for (int s = 0; s < 2; ++s) {
+            t.slots[4 * j + s] = d->react[2 * j + s];
+            t.slots[4 * j + 2 + s] = d->prod[2 * j + s];
+            if (d->react[2 * j + s] >= 0) {
+                t.uW[(size_t)j * N + d->react[2 * j + s]] -= d->W[d->react[2 * j + s]] / d->rho0;
+                t.dn[j] -= 1;
+            }
+            if (d->prod[2 * j + s] >= 0) {
+                t.uW[(size_t)j * N + d->prod[2 * j + s]] += d->W[d->prod[2 * j + s]] / d->rho0;
+                t.dn[j] += 1;
+            }
+        }
+        t.Ta[j] = d->Ea[j] / d->R_c;
+    }
+    t.A.assign(d->A, d->A + R);
+    t.beta.assign(d->beta, d->beta + R);
+    t.W.assign(d->W, d->W + N);
+    t.invW.resize(N);
+    double scale = 0;
+    for (int k = 0; k < N; ++k) {
+        t.invW[k] = 1.0 / d->W[k];
+        scale += d->cp[k] / d->W[k];
+    }
+    t.cp.assign(d->cp, d->cp + N);
+    t.hf.assign(d->hf, d->hf + N);
+    t.s0.assign(d->s0, d->s0 + N);
+    t.rho0 = d->rho0;
+    t.R_u = d->R_u;
+    t.newton_scale = scale / N;
+    t.ln_patm_over_Ru = std::log(d->p_atm / d->R_u);
+}
+
+}  // namespace
+
+extern "C" {
+
+int misdc_mech_generate(const misdc_mech_desc* d, int compile, char* buf, size_t* len) {
+    if (!len) return fail(MISDC_EINVAL, "len is NULL");
+    int rc = check_mech_desc(d);
+    if (rc) return rc;
+    if (d->n_species > NEWTON_SPEC_MAX_SPECIES)
+        return fail(MISDC_EUNSUPPORTED, "the generated reaction solve holds at most %d species",
+                    NEWTON_SPEC_MAX_SPECIES);
+    MechTables t;
+    mech_tables(d, t);
+    const std::string src = newton_spec_source(t);
+    if (compile) {
+        std::string msg;
+        if (newton_spec_compile_check(src, msg) != 0)
+            return fail(MISDC_EDEVICE, "generated reaction solve does not compile: %s", msg.c_str());
+    }
+    const size_t need = src.size() + 1;
+    if (buf && *len >= need) std::memcpy(buf, src.c_str(), need);
+    const bool fits = buf && *len >= need;
+    *len = need;
+    if (buf && !fits) return fail(MISDC_EINVAL, "buffer of %zu bytes, %zu needed", *len, need);
+    return MISDC_OK;
+}
 
 int misdc_mech_create(const misdc_mech_desc* d, misdc_mech_t* out) {
     if (!out) return fail(MISDC_EINVAL, "output handle pointer is NULL");
@@ -959,7 +1065,19 @@ int misdc_mech_create(const misdc_mech_desc* d, misdc_mech_t* out) {
     m.cp.assign(d->cp, d->cp + N);
     m.hf.assign(d->hf, d->hf + N);
     m.kappa0 = kappa0;
+    // the reaction solve generated for this mechanism (the generic kernels
+    // serve where it cannot be built)
+    MechTables t;
+    mech_tables(d, t);
+    (void)newton_spec_prepare(m, t);
     *out = h;
+    return MISDC_OK;
+}
+
+int misdc_mech_specialized(misdc_mech_t mech, int32_t* available, const char** status) {
+    if (!mech || !available) return fail(MISDC_EINVAL, "NULL argument");
+    *available = mech->m.spec_fn ? 1 : 0;
+    if (status) *status = mech->m.spec_status.c_str();
     return MISDC_OK;
 }
 
@@ -1266,9 +1384,11 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
         return bail(fail(MISDC_EDEVICE, "clear the reduction partials"));
     if ((rc = diffusion_work_alloc(I->dw, mech->m, grid->g))) return bail(rc);
     if (grid->g.n_flames > 0 && (rc = dalloc(I, &I->dt_cell, (size_t)n))) return bail(rc);
-    hipError_t e = hipStreamCreateWithFlags(&I->sD, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->sR2, hipStreamNonBlocking);
+    hipError_t e = hipStreamCreateWithFlags(&I->sD_own, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->sR2_own, hipStreamNonBlocking);
     if (e != hipSuccess) return bail(fail(MISDC_EDEVICE, "stream: %s", hipGetErrorString(e)));
+    I->sD = I->sD_own;
+    I->sR2 = I->sR2_own;
     I->sR = opts->serialize ? I->sD : I->sR2;
     I->stagger = opts->serialize ? 0 : 1;
     const size_t nev = (size_t)I->levels * (M + 1);
@@ -1295,6 +1415,8 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (I->sD) (void)hipStreamSynchronize(I->sD);
     if (I->sR2) (void)hipStreamSynchronize(I->sR2);
     if (I->sRm) (void)hipStreamSynchronize(I->sRm);
+    if (I->sD_own) (void)hipStreamSynchronize(I->sD_own);
+    if (I->sR2_own) (void)hipStreamSynchronize(I->sR2_own);
     if (I->gexec) (void)hipGraphExecDestroy(I->gexec);
     for (hipEvent_t ev : I->evD)
         if (ev) (void)hipEventDestroy(ev);
@@ -1312,9 +1434,10 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (I->ev_outR) (void)hipEventDestroy(I->ev_outR);
     if (I->ev_fork) (void)hipEventDestroy(I->ev_fork);
     if (I->ev_join) (void)hipEventDestroy(I->ev_join);
-    if (I->sR2) (void)hipStreamDestroy(I->sR2);
+    // only the streams the library created (a caller's streams stay theirs)
+    if (I->sR2_own) (void)hipStreamDestroy(I->sR2_own);
     if (I->sRm) (void)hipStreamDestroy(I->sRm);
-    if (I->sD) (void)hipStreamDestroy(I->sD);
+    if (I->sD_own) (void)hipStreamDestroy(I->sD_own);
     diffusion_work_free(I->dw);
     if (I->pinc_host) (void)hipHostFree(I->pinc_host);
     for (void* p : I->allocs) (void)hipFree(p);
@@ -1389,19 +1512,23 @@ int misdc_sweep(misdc_integ_t I, void* stream) {
     if (!I->open) return fail(MISDC_ESTATE, "no step is open (misdc_step_begin)");
     if (I->open_sweeps >= MAX_STEP_SWEEPS)
         return fail(MISDC_EINVAL, "at most %d sweeps per step", MAX_STEP_SWEEPS);
+    // ordered after prior work on the caller's stream
+    MISDC_HIP(hipEventRecord(I->ev_in, (hipStream_t)stream));
+    MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_in, 0));
     const int k = I->open_sweeps;
     I->sweep_index = k;
     int rc = run_sweep(I, k, I->open_dt);
     if (rc) return rc;
     I->open_sweeps = k + 1;
     I->last_sweeps = k + 1;             // misdc_get_stats reports the sweeps done so far
-    (void)stream;
     return MISDC_OK;
 }
 
 int misdc_step_end(misdc_integ_t I, void* stream) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
     if (!I->open) return fail(MISDC_ESTATE, "no step is open (misdc_step_begin)");
+    MISDC_HIP(hipEventRecord(I->ev_in, (hipStream_t)stream));
+    MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_in, 0));
     int rc = issue_end(I, I->open_state);
     if (rc) return rc;
     hipStream_t cs = (hipStream_t)stream;
@@ -1409,21 +1536,22 @@ int misdc_step_end(misdc_integ_t I, void* stream) {
     MISDC_HIP(hipStreamWaitEvent(cs, I->ev_outD, 0));
     I->open = false;
     I->open_state = nullptr;
-    return MISDC_OK;
+    // synchronising end: the step's solver outcome is the return value
+    if ((rc = sync_streams(I))) return rc;
+    return convergence_status(I);
 }
 
 int misdc_integ_set_guess(misdc_integ_t I, misdc_mlp_t mlp, int sweeps) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
     if (sweeps < 0) return fail(MISDC_EINVAL, "sweeps must be >= 0");
-    MISDC_HIP(hipStreamSynchronize(I->sD));
-    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
-    MISDC_HIP(hipStreamSynchronize(I->sR2));
+    if (I->open) return fail(MISDC_ESTATE, "a step opened by misdc_step_begin is not ended");
+    int rc;
+    if ((rc = sync_streams(I))) return rc;
     if (mlp) {
         if (mlp_dims(mlp->p, 0) != I->N + 2 || mlp_dims(mlp->p, 3) != I->N + 1)
             return fail(MISDC_EINVAL, "network widths do not match %d species", I->N);
         // every buffer a step needs is allocated now (none during a step)
-        int rc = mlp_reserve(mlp->p, I->n);
-        if (rc) return rc;
+        if ((rc = mlp_reserve(mlp->p, I->n))) return rc;
     }
     I->mlp = mlp ? mlp->p : nullptr;
     I->guess_sweeps = sweeps;
@@ -1434,9 +1562,9 @@ int misdc_integ_set_guess(misdc_integ_t I, misdc_mlp_t mlp, int sweeps) {
 int misdc_integ_record(misdc_integ_t I, double* dev_buf, int64_t max_tasks) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
     if (max_tasks < 0 || (max_tasks > 0 && !dev_buf)) return fail(MISDC_EINVAL, "invalid buffer");
-    MISDC_HIP(hipStreamSynchronize(I->sD));
-    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
-    MISDC_HIP(hipStreamSynchronize(I->sR2));
+    if (I->open) return fail(MISDC_ESTATE, "a step opened by misdc_step_begin is not ended");
+    int rc;
+    if ((rc = sync_streams(I))) return rc;
     I->rec_buf = max_tasks > 0 ? dev_buf : nullptr;
     I->rec_cap = max_tasks;
     I->rec_count = 0;
@@ -1487,6 +1615,27 @@ int reaction_stream_split(misdc_integ_s* I, int quarters) {
     return MISDC_OK;
 }
 
+int misdc_set_streams(misdc_integ_t I, void* diffusion_stream, void* reaction_stream) {
+    if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
+    if (I->open) return fail(MISDC_ESTATE, "a step opened by misdc_step_begin is not ended");
+    if (diffusion_stream && diffusion_stream == reaction_stream)
+        return fail(MISDC_EINVAL, "the two streams must differ (one stream: set_tune serialize)");
+    int rc;
+    if ((rc = sync_streams(I))) return rc;
+    const bool serial = I->sR == I->sD;
+    const bool masked = I->sRm && I->sR == I->sRm;
+    I->sD = diffusion_stream ? (hipStream_t)diffusion_stream : I->sD_own;
+    I->sR2 = reaction_stream ? (hipStream_t)reaction_stream : I->sR2_own;
+    I->caller_R = reaction_stream != nullptr;
+    if (I->caller_R && masked) {
+        // a caller's reaction stream replaces the library's CU-masked one
+        I->cu_split = 0;
+    }
+    I->sR = serial ? I->sD : ((masked && !I->caller_R) ? I->sRm : I->sR2);
+    drop_graph(I);
+    return MISDC_OK;
+}
+
 int misdc_get_tune(misdc_integ_t I, misdc_tune* t) {
     if (!I || !t) return fail(MISDC_EINVAL, "NULL argument");
     t->cg_variant = I->dw.variant;
@@ -1506,19 +1655,21 @@ int misdc_set_tune(misdc_integ_t I, const misdc_tune* t) {
     if (t->serialize != 0 && t->serialize != 1) return fail(MISDC_EINVAL, "serialize must be 0 or 1");
     if (t->cu_split < 0 || t->cu_split > 3) return fail(MISDC_EINVAL, "cu_split must be in [0, 3]");
     if (t->stagger != 0 && t->stagger != 1) return fail(MISDC_EINVAL, "stagger must be 0 or 1");
+    if (t->cu_split && !t->serialize && I->caller_R)
+        return fail(MISDC_EINVAL, "cu_split needs the library's own reaction stream "
+                                  "(misdc_set_streams gave one of the caller's)");
     const Grid& g = *I->grid;
-    MISDC_HIP(hipStreamSynchronize(I->sD));
-    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
-    MISDC_HIP(hipStreamSynchronize(I->sR2));
+    int rc;
+    if ((rc = sync_streams(I))) return rc;
     if (g.dim == 2 && g.n_flames == 0) {
         DiffusionWork probe = I->dw;
-        int rc = diffusion_work_set(probe, *I->mech, g, t->cg_variant, t->cg_blocks);
+        rc = diffusion_work_set(probe, *I->mech, g, t->cg_variant, t->cg_blocks);
         if (rc) return rc;
         I->dw.variant = probe.variant;
         I->dw.blocks = probe.blocks;
     }
     if (!t->serialize && t->cu_split) {
-        int rc = reaction_stream_split(I, t->cu_split);
+        rc = reaction_stream_split(I, t->cu_split);
         if (rc) return rc;
     }
     I->dw.cyclic = t->cyclic;
@@ -1626,9 +1777,8 @@ int misdc_autotune(misdc_integ_t I, const double* state, double dt, const double
 
 int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
     if (!I || !st) return fail(MISDC_EINVAL, "NULL argument");
-    MISDC_HIP(hipStreamSynchronize(I->sD));
-    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
-    MISDC_HIP(hipStreamSynchronize(I->sR2));
+    int rc;
+    if ((rc = sync_streams(I))) return rc;
     std::memset(st, 0, sizeof(*st));
     unsigned long long ns[8];
     int32_t cg[8];
@@ -1661,8 +1811,7 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
     st->cg_solves = cg[3];
     const int K = I->last_sweeps;
     st->n_sweeps = K;
-    int rc = drain_timing(I);
-    if (rc) return rc;
+    if ((rc = drain_timing(I))) return rc;
     st->diffusion_kernel_ms = I->t_ms[0];
     st->diffusion_kernel_launches = I->t_cnt[0];
     st->newton_kernel_ms = I->t_ms[1];
@@ -1680,6 +1829,12 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
             st->sweep_increment[k] = worst;
         }
     }
+    // the statistics are filled either way; unconverged solves make the status
+    if (st->newton_failed > 0 || st->cg_failed > 0)
+        return fail(MISDC_ENOTCONV,
+                    "unconverged solves in the last step: %lld cell-node Newton solves, "
+                    "%d diffusion solves at their iteration limit or barrier timeout",
+                    (long long)st->newton_failed, st->cg_failed);
     return MISDC_OK;
 }
 
@@ -1688,9 +1843,8 @@ int misdc_get_newton_histogram(misdc_integ_t I, int sweep, int64_t* counts) {
     if (sweep < 0 || sweep >= I->last_sweeps)
         return fail(MISDC_EINVAL, "sweep %d outside the last step's %d sweeps", sweep,
                     I->last_sweeps);
-    MISDC_HIP(hipStreamSynchronize(I->sD));
-    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
-    MISDC_HIP(hipStreamSynchronize(I->sR2));
+    int rc;
+    if ((rc = sync_streams(I))) return rc;
     std::vector<unsigned long long> h((size_t)NEWTON_HIST_SETS * NEWTON_HIST_BINS);
     MISDC_HIP(hipMemcpy(h.data(), I->nhist + (size_t)sweep * NEWTON_HIST_SETS * NEWTON_HIST_BINS,
                         sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
@@ -1704,11 +1858,9 @@ int misdc_get_newton_histogram(misdc_integ_t I, int sweep, int64_t* counts) {
 
 int misdc_reset_profile(misdc_integ_t I) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
-    MISDC_HIP(hipStreamSynchronize(I->sD));
-    if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
-    MISDC_HIP(hipStreamSynchronize(I->sR2));
-    int rc = drain_timing(I);
-    if (rc) return rc;
+    int rc;
+    if ((rc = sync_streams(I))) return rc;
+    if ((rc = drain_timing(I))) return rc;
     I->t_ms[0] = I->t_ms[1] = 0.0;
     I->t_cnt[0] = I->t_cnt[1] = 0;
     return MISDC_OK;

@@ -68,7 +68,28 @@ struct Mech {
     int device = 0;
     void* block = nullptr;        // one device allocation holding every table
     std::vector<double> W, cp, hf, kappa0;   // host copies (for host-side checks)
+    // reaction solve generated for this mechanism (hipFunction_t, owned by a
+    // process-wide cache), or null with the reason in spec_status
+    void* spec_fn = nullptr;
+    std::string spec_status;
 };
+
+// host copies of the tables from which a mechanism's kernels are generated
+struct MechTables {
+    int N = 0, R = 0, bath = 0;
+    std::vector<int> slots;                         // R x 4 (reactants, products; -1 empty)
+    std::vector<double> A, beta, Ta, dn, uW, W, invW, cp, hf, s0;
+    double rho0 = 0, R_u = 0, newton_scale = 0, ln_patm_over_Ru = 0;
+};
+// largest species count of the generated one-thread-per-cell reaction solve
+constexpr int NEWTON_SPEC_MAX_SPECIES = 12;
+// generates, compiles (hiprtc, once per process, device and mechanism) and
+// loads the specialised reaction solve; leaves m.spec_fn null (and says why
+// in m.spec_status) where it cannot, so the generic kernels serve
+int newton_spec_prepare(Mech& m, const MechTables& t);
+std::string newton_spec_source(const MechTables& t);
+// compiles a generated source for the device without loading it (no GPU needed)
+int newton_spec_compile_check(const std::string& src, std::string& msg);
 
 // ---- grid ------------------------------------------------------------------
 struct Grid {
@@ -127,6 +148,8 @@ struct NewtonArgs {
 constexpr int NEWTON_BUCKETS = 32, NEWTON_BUCKET_STRIDE = 16;   // 128-byte apart
 constexpr int NEWTON_HIST_BINS = 64, NEWTON_HIST_SETS = 8;
 int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s);
+// the generated kernel (statistics into a.buckets / a.hist when a.buckets is set)
+int launch_newton_spec(const Mech& m, const NewtonArgs& a, hipStream_t s);
 // one wavefront per cell (any species count up to 63): FP64 LU, or an FP32
 // LU on the matrix cores refined against the FP64 matrix
 enum { NEWTON_LU_FP64 = 0, NEWTON_LU_FP32_MFMA = 1 };
@@ -196,6 +219,12 @@ struct DiffusionWork {
     int cyclic = 1;               // 1-D systems: 0 one thread per system, 1 one wavefront per system
 };
 int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g);
+// the same workspace carved out of one device block of ``bytes`` (no
+// allocation; the zeroed parts are cleared by kernels on s), and the bytes it
+// needs (each part 256-byte aligned)
+size_t diffusion_work_bytes(const Mech& m, const Grid& g);
+int diffusion_work_carve(DiffusionWork& w, const Mech& m, const Grid& g, void* block, size_t bytes,
+                         hipStream_t s);
 // selects the 2-D CG variant (0 global memory, 1/2/4 cells per thread in
 // registers) and its block count, after checking that it fits
 int diffusion_work_set(DiffusionWork& w, const Mech& m, const Grid& g, int variant, int blocks);
@@ -246,6 +275,9 @@ int mlp_features(const Mech& m, MlpImpl* p, int64_t n, const double* bY, const d
                  const double* c, double c_scalar, float* x, hipStream_t s);
 int mlp_targets(const Mech& m, MlpImpl* p, int64_t n, const double* bY, const double* h,
                 const double* Ys, float* t, hipStream_t s);
+int mlp_prepare(const Mech& m, MlpImpl* p, int64_t n, const double* bY, const double* h,
+                const double* c, const double* Ys, uint64_t seed, float* x, float* t,
+                hipStream_t s);
 int mlp_guess(const Mech& m, MlpImpl* p, int64_t n, const double* bY, const double* h,
               const double* c, double c_scalar, double* Y, int64_t ldy, int32_t* choice,
               hipStream_t s);

@@ -291,35 +291,114 @@ __device__ __forceinline__ double cell_temperature(const MechDev& m, const doubl
     return T_REF + (h - hform) / cpm;
 }
 
-// x[i] = ((b_Y - mu) / sd, (T_b - mu) / sd, (ln c - mu) / sd)
+// Output row of problem i: (pa i + pb) mod n, a bijection of [0, n) when
+// gcd(pa, n) = 1 (pa = 1, pb = 0: the identity).
+__device__ __forceinline__ int64_t out_row(int64_t i, int64_t n, uint64_t pa, uint64_t pb) {
+    return (int64_t)(((uint64_t)i * pa + pb) % (uint64_t)n);
+}
+
+// x[row(i)] = ((b_Y - mu) / sd, (T_b - mu) / sd, (ln c - mu) / sd)
 __global__ void __launch_bounds__(256) features_kernel(MechDev m, NormDev nd, int64_t n,
                                                        const double* bY, const double* h,
                                                        const double* c, double c_scalar,
-                                                       float* x) {
+                                                       float* x, uint64_t pa, uint64_t pb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int N = m.N, nin = N + 2;
     const double Tb = cell_temperature(m, bY, n, i, h[i]);
     const double cc = c ? c[i] * c_scalar : c_scalar;
-    float* xi = x + i * nin;
+    float* xi = x + out_row(i, n, pa, pb) * nin;
     for (int k = 0; k < N; ++k) xi[k] = (float)((bY[(int64_t)k * n + i] - nd.in_mu[k]) / nd.in_sd[k]);
     xi[N] = (float)((Tb - nd.in_mu[N]) / nd.in_sd[N]);
     xi[N + 1] = (float)((log(cc) - nd.in_mu[N + 1]) / nd.in_sd[N + 1]);
 }
 
-// t[i] = ((Y* - b_Y) / sd, (T* - T_b) / sd)
+// t[row(i)] = ((Y* - b_Y) / sd, (T* - T_b) / sd)
 __global__ void __launch_bounds__(256) targets_kernel(MechDev m, NormDev nd, int64_t n,
                                                       const double* bY, const double* h,
-                                                      const double* Ys, float* t) {
+                                                      const double* Ys, float* t, uint64_t pa,
+                                                      uint64_t pb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int N = m.N, nout = N + 1;
     const double Tb = cell_temperature(m, bY, n, i, h[i]);
     const double Ts = cell_temperature(m, Ys, n, i, h[i]);
-    float* ti = t + i * nout;
+    float* ti = t + out_row(i, n, pa, pb) * nout;
     for (int k = 0; k < N; ++k)
         ti[k] = (float)((Ys[(int64_t)k * n + i] - bY[(int64_t)k * n + i]) / nd.out_sd[k]);
     ti[N] = (float)((Ts - Tb) / nd.out_sd[N]);
+}
+
+// ---- statistics of a training set ------------------------------------------
+// Raw (unnormalised) values of problem i in columns of R (Q = 2N + 3 columns
+// of n): b_Y, T_b, ln c (the features), then Y* - b_Y, T* - T_b (the targets).
+__global__ void __launch_bounds__(256) raw_pairs_kernel(MechDev m, int64_t n, const double* bY,
+                                                        const double* h, const double* c,
+                                                        const double* Ys, double* R) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int N = m.N;
+    const double Tb = cell_temperature(m, bY, n, i, h[i]);
+    const double Ts = cell_temperature(m, Ys, n, i, h[i]);
+    for (int k = 0; k < N; ++k) {
+        const double b = bY[(int64_t)k * n + i];
+        R[(int64_t)k * n + i] = b;
+        R[(int64_t)(N + 2 + k) * n + i] = Ys[(int64_t)k * n + i] - b;
+    }
+    R[(int64_t)N * n + i] = Tb;
+    R[(int64_t)(N + 1) * n + i] = log(c[i]);
+    R[(int64_t)(2 * N + 2) * n + i] = Ts - Tb;
+}
+
+constexpr int STAT_BLOCKS = 128;
+
+// Partial column sums in a fixed order: block (b, q) sums v (mean == null) or
+// (v - mean[q])^2 of column q over rows b*256 + t + k*STAT_BLOCKS*256 into
+// part[q * STAT_BLOCKS + b].
+__global__ void __launch_bounds__(256) column_sums_kernel(int64_t n, const double* R,
+                                                          const double* mean, double* part) {
+    __shared__ double red[256];
+    const int q = blockIdx.y;
+    const double mu = mean ? mean[q] : 0.0;
+    const double* col = R + (int64_t)q * n;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)STAT_BLOCKS * 256) {
+        const double v = col[i];
+        acc += mean ? (v - mu) * (v - mu) : v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)q * STAT_BLOCKS + blockIdx.x] = red[0];
+}
+
+// Thread q totals its column's partials in block order.  Pass 0: mean[q].
+// Pass 1: the normalisation: feature q < nin gets mu = mean and sd = the
+// sample standard deviation (n - 1) floored at max(1e-3 |mu|, 1e-6), so that
+// a constant feature stays O(1); target q gets sd floored at 1e-30.
+__global__ void column_totals_kernel(int Q, int nin, int64_t n, const double* part, double* mean,
+                                     int pass, float* norm) {
+    const int q = threadIdx.x;
+    if (q >= Q) return;
+    double tot = 0.0;
+    for (int b = 0; b < STAT_BLOCKS; ++b) tot += part[(int64_t)q * STAT_BLOCKS + b];
+    if (pass == 0) {
+        mean[q] = tot / (double)n;
+        return;
+    }
+    const double sd = sqrt(tot / (double)(n - 1));
+    const int nout = Q - nin;
+    if (q < nin) {
+        const double mu = mean[q];
+        norm[q] = (float)mu;
+        norm[nin + q] = (float)fmax(sd, fmax(1e-3 * fabs(mu), 1e-6));
+    } else {
+        norm[2 * nin + (q - nin)] = (float)fmax(sd, 1e-30);
+    }
+    (void)nout;
 }
 
 // learned candidate Y = b_Y + y sd, raised to min(b_Y, 0) where it falls
@@ -810,7 +889,7 @@ int mlp_features(const Mech& m, MlpImpl* p, int64_t n, const double* bY, const d
                     p->dims[3], m.dev.N);
     if (n == 0) return MISDC_OK;
     hipLaunchKernelGGL(features_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, norm_dev(*p),
-                       n, bY, h, c, c_scalar, x);
+                       n, bY, h, c, c_scalar, x, (uint64_t)1, (uint64_t)0);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;
 }
@@ -821,8 +900,69 @@ int mlp_targets(const Mech& m, MlpImpl* p, int64_t n, const double* bY, const do
         return fail(MISDC_EINVAL, "network widths do not match the mechanism");
     if (n == 0) return MISDC_OK;
     hipLaunchKernelGGL(targets_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, norm_dev(*p),
-                       n, bY, h, Ys, t);
+                       n, bY, h, Ys, t, (uint64_t)1, (uint64_t)0);
     MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+namespace {
+uint64_t splitmix64(uint64_t& z) {
+    uint64_t r = (z += 0x9E3779B97F4A7C15ull);
+    r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ull;
+    r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
+    return r ^ (r >> 31);
+}
+uint64_t gcd64(uint64_t a, uint64_t b) {
+    while (b) {
+        const uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+}  // namespace
+
+int mlp_prepare(const Mech& m, MlpImpl* p, int64_t n, const double* bY, const double* h,
+                const double* c, const double* Ys, uint64_t seed, float* x, float* t,
+                hipStream_t s) {
+    const int N = m.dev.N, nin = N + 2, Q = 2 * N + 3;
+    if (p->dims[0] != nin || p->dims[3] != N + 1)
+        return fail(MISDC_EINVAL, "network widths do not match the mechanism");
+    if (n < 2) return fail(MISDC_EINVAL, "at least two training problems are needed");
+    if (Q > 1024) return fail(MISDC_EUNSUPPORTED, "too many species for the statistics kernel");
+    // the shuffle: row i -> (pa i + pb) mod n with pa coprime to n
+    uint64_t z = seed;
+    uint64_t pa = 1 + splitmix64(z) % (uint64_t)(n - 1);
+    while (gcd64(pa, (uint64_t)n) != 1) pa = pa % (uint64_t)(n - 1) + 1;
+    const uint64_t pb = splitmix64(z) % (uint64_t)n;
+    double* R = nullptr;
+    double* work = nullptr;
+    MISDC_HIP(hipMallocAsync((void**)&R, sizeof(double) * (size_t)Q * n, s));
+    hipError_t e = hipMallocAsync((void**)&work, sizeof(double) * ((size_t)Q * STAT_BLOCKS + Q), s);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(R, s);
+        return fail(MISDC_ENOMEM, "training statistics: %s", hipGetErrorString(e));
+    }
+    double* part = work;
+    double* mean = work + (size_t)Q * STAT_BLOCKS;
+    hipLaunchKernelGGL(raw_pairs_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, n, bY, h, c,
+                       Ys, R);
+    hipLaunchKernelGGL(column_sums_kernel, dim3(STAT_BLOCKS, Q), dim3(256), 0, s, n, R,
+                       (const double*)nullptr, part);
+    hipLaunchKernelGGL(column_totals_kernel, dim3(1), dim3(1024), 0, s, Q, nin, n, part, mean, 0,
+                       p->norm);
+    hipLaunchKernelGGL(column_sums_kernel, dim3(STAT_BLOCKS, Q), dim3(256), 0, s, n, R, mean, part);
+    hipLaunchKernelGGL(column_totals_kernel, dim3(1), dim3(1024), 0, s, Q, nin, n, part, mean, 1,
+                       p->norm);
+    hipLaunchKernelGGL(features_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, norm_dev(*p),
+                       n, bY, h, c, 1.0, x, pa, pb);
+    hipLaunchKernelGGL(targets_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, norm_dev(*p),
+                       n, bY, h, Ys, t, pa, pb);
+    e = hipGetLastError();
+    (void)hipFreeAsync(work, s);
+    (void)hipFreeAsync(R, s);
+    if (e != hipSuccess) return fail(MISDC_EDEVICE, "training set: %s", hipGetErrorString(e));
+    p->has_norm = true;
     return MISDC_OK;
 }
 
@@ -950,6 +1090,17 @@ int misdc_mlp_targets(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, const doubl
     if (n < 0) return fail(MISDC_EINVAL, "n < 0");
     if (n > 0 && (!dev_bY || !dev_h || !dev_Y || !dev_t)) return fail(MISDC_EINVAL, "NULL array");
     return misdc::mlp_targets(mech->m, mlp->p, n, dev_bY, dev_h, dev_Y, dev_t, (hipStream_t)stream);
+}
+
+int misdc_mlp_prepare_training(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, const double* dev_bY,
+                               const double* dev_h, const double* dev_c, const double* dev_Y,
+                               uint64_t seed, float* dev_x, float* dev_t, void* stream) {
+    if (!mech || !mlp) return fail(MISDC_EINVAL, "NULL handle");
+    if (n < 2 || n > ((int64_t)1 << 31)) return fail(MISDC_EINVAL, "n must be in [2, 2^31]");
+    if (!dev_bY || !dev_h || !dev_c || !dev_Y || !dev_x || !dev_t)
+        return fail(MISDC_EINVAL, "NULL array");
+    return misdc::mlp_prepare(mech->m, mlp->p, n, dev_bY, dev_h, dev_c, dev_Y, seed, dev_x, dev_t,
+                              (hipStream_t)stream);
 }
 
 int misdc_reaction_guess_mlp(misdc_mech_t mech, misdc_mlp_t mlp, int64_t n, const double* dev_bY,

@@ -658,23 +658,13 @@ int launch_transport(const Mech& m, const Grid& g, const double* state, const do
     return MISDC_OK;
 }
 
-int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
+namespace {
+
+// Launch configuration of a diffusion workspace whose buffers are in place
+// (the tiled variants need w.edge).
+int diffusion_work_choose(DiffusionWork& w, const Mech& m, const Grid& g) {
     const int64_t n = g.cells();
     const int NF = m.dev.N + 1;
-    if (NF - 1 > CG_MAX_FIELDS)
-        return fail(MISDC_EUNSUPPORTED, "at most %d diffused fields, got %d", CG_MAX_FIELDS, NF - 1);
-    size_t cells_bytes = (size_t)n * sizeof(double);
-    MISDC_HIP(hipMalloc(&w.theta, cells_bytes));
-    MISDC_HIP(hipMalloc(&w.Kx, cells_bytes));
-    MISDC_HIP(hipMalloc(&w.Ky, cells_bytes));
-    MISDC_HIP(hipMemset(w.Ky, 0, cells_bytes));
-    MISDC_HIP(hipMalloc(&w.x, cells_bytes * NF));
-    MISDC_HIP(hipMalloc(&w.r, cells_bytes * NF));
-    MISDC_HIP(hipMalloc(&w.z, cells_bytes * NF));
-    MISDC_HIP(hipMalloc(&w.p, cells_bytes * NF));
-    MISDC_HIP(hipMalloc(&w.q, cells_bytes * NF));
-    if (g.dim == 2 && g.n_flames == 0 && NF - 1 == 9)
-        MISDC_HIP(hipMalloc(&w.edge, TILE_EDGE_DOUBLES * sizeof(double)));
     int cus = 0;
     int rc = device_cus(cus);
     if (rc) return rc;
@@ -683,15 +673,13 @@ int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
     // completes.  The register-resident kernel is used when every cell fits
     // in CPT <= 4 registers slots per thread of such a grid.
     w.variant = -1;
-    const char* force = std::getenv("MISDC_FORCE_CG_GLOBAL");   // test switch
-    const bool allow_regs = !(force && force[0] == '1');
     // the tiled variant (one 32x16 tile per workgroup, one local
     // preconditioner sweep) where the grid has at most 128 tiles: fewer
     // iterations than the diagonal preconditioner at a small cost each
     const int64_t tiles = cg_tile_blocks(g);
-    if (allow_regs && NF - 1 == 9 && tiles >= 1 && tiles <= cus && tiles <= TILE_NB)
+    if (NF - 1 == 9 && tiles >= 1 && tiles <= cus && tiles <= TILE_NB)
         (void)diffusion_work_set(w, m, g, 101, (int)tiles);
-    if (allow_regs && w.variant < 0 && NF - 1 == 9 && g.dim == 2 && g.n_flames == 0) {
+    if (w.variant < 0 && NF - 1 == 9 && g.dim == 2 && g.n_flames == 0) {
         // grid barriers cost less with fewer blocks, so take the fewest cells
         // per thread that keeps the grid at most half the CUs, else at most
         // all of them
@@ -714,14 +702,101 @@ int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
         if (rc) return rc;
     }
     w.threads = CG_THREADS;
-    MISDC_HIP(hipMalloc(&w.partial, sizeof(double) * 2 * (size_t)CG_MAX_BLOCKS * CG_MAX_FIELDS * 4));
-    MISDC_HIP(hipMalloc(&w.totals, sizeof(double) * CG_MAX_FIELDS * 4));
-    MISDC_HIP(hipMalloc(&w.barrier, sizeof(unsigned) * BAR_WORDS));
-    MISDC_HIP(hipMemset(w.barrier, 0, sizeof(unsigned) * BAR_WORDS));
-    MISDC_HIP(hipMalloc(&w.info, sizeof(int32_t) * 4));
-    MISDC_HIP(hipMemset(w.info, 0, sizeof(int32_t) * 4));
     w.fields_cap = NF;
     return MISDC_OK;
+}
+
+// Sizes in bytes of the workspace buffers, in carving order: theta, Kx, Ky,
+// x, r, z, p, q, edge, partial, totals, barrier, info.
+constexpr int WORK_PARTS = 13;
+void diffusion_work_sizes(const Mech& m, const Grid& g, size_t (&sz)[WORK_PARTS]) {
+    const size_t cells = (size_t)g.cells() * sizeof(double);
+    const int NF = m.dev.N + 1;
+    const bool tiled = g.dim == 2 && g.n_flames == 0 && NF - 1 == 9;
+    const size_t parts[WORK_PARTS] = {
+        cells, cells, cells, cells * NF, cells * NF, cells * NF, cells * NF, cells * NF,
+        tiled ? TILE_EDGE_DOUBLES * sizeof(double) : 0,
+        sizeof(double) * 2 * (size_t)CG_MAX_BLOCKS * CG_MAX_FIELDS * 4,
+        sizeof(double) * CG_MAX_FIELDS * 4, sizeof(unsigned) * BAR_WORDS, sizeof(int32_t) * 4};
+    for (int k = 0; k < WORK_PARTS; ++k) sz[k] = parts[k];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+void diffusion_work_assign(DiffusionWork& w, void* const (&ptr)[WORK_PARTS]) {
+    w.theta = (double*)ptr[0];
+    w.Kx = (double*)ptr[1];
+    w.Ky = (double*)ptr[2];
+    w.x = (double*)ptr[3];
+    w.r = (double*)ptr[4];
+    w.z = (double*)ptr[5];
+    w.p = (double*)ptr[6];
+    w.q = (double*)ptr[7];
+    w.edge = (double*)ptr[8];
+    w.partial = (double*)ptr[9];
+    w.totals = (double*)ptr[10];
+    w.barrier = (unsigned*)ptr[11];
+    w.info = (int32_t*)ptr[12];
+}
+
+}  // namespace
+
+int diffusion_work_alloc(DiffusionWork& w, const Mech& m, const Grid& g) {
+    const int NF = m.dev.N + 1;
+    if (NF - 1 > CG_MAX_FIELDS)
+        return fail(MISDC_EUNSUPPORTED, "at most %d diffused fields, got %d", CG_MAX_FIELDS, NF - 1);
+    size_t sz[WORK_PARTS];
+    diffusion_work_sizes(m, g, sz);
+    void* ptr[WORK_PARTS] = {};
+    for (int k = 0; k < WORK_PARTS; ++k) {
+        if (sz[k] == 0) continue;
+        hipError_t e = hipMalloc(&ptr[k], sz[k]);
+        if (e != hipSuccess) {
+            diffusion_work_assign(w, ptr);
+            return fail(MISDC_ENOMEM, "diffusion workspace: %s", hipGetErrorString(e));
+        }
+    }
+    diffusion_work_assign(w, ptr);
+    MISDC_HIP(hipMemset(w.Ky, 0, sz[2]));
+    MISDC_HIP(hipMemset(w.barrier, 0, sz[11]));
+    MISDC_HIP(hipMemset(w.info, 0, sz[12]));
+    return diffusion_work_choose(w, m, g);
+}
+
+size_t diffusion_work_bytes(const Mech& m, const Grid& g) {
+    size_t sz[WORK_PARTS];
+    diffusion_work_sizes(m, g, sz);
+    size_t total = 0;
+    for (int k = 0; k < WORK_PARTS; ++k) total += align256(sz[k]);
+    return total;
+}
+
+int diffusion_work_carve(DiffusionWork& w, const Mech& m, const Grid& g, void* block, size_t bytes,
+                         hipStream_t s) {
+    const int NF = m.dev.N + 1;
+    if (NF - 1 > CG_MAX_FIELDS)
+        return fail(MISDC_EUNSUPPORTED, "at most %d diffused fields, got %d", CG_MAX_FIELDS, NF - 1);
+    if (diffusion_work_bytes(m, g) > bytes)
+        return fail(MISDC_EINVAL, "diffusion workspace of %zu bytes does not fit in %zu",
+                    diffusion_work_bytes(m, g), bytes);
+    size_t sz[WORK_PARTS];
+    diffusion_work_sizes(m, g, sz);
+    void* ptr[WORK_PARTS] = {};
+    char* at = (char*)block;
+    for (int k = 0; k < WORK_PARTS; ++k) {
+        ptr[k] = sz[k] ? at : nullptr;
+        at += align256(sz[k]);
+    }
+    w = DiffusionWork();
+    diffusion_work_assign(w, ptr);
+    // what must start at zero: the y-face coefficients that a 1-D grid never
+    // writes, the barrier counters and the iteration record (kernels, so the
+    // calls may be captured into a graph)
+    int rc = launch_zero(w.Ky, (int64_t)sz[2], s);
+    if (!rc) rc = launch_zero(w.barrier, (int64_t)sz[11], s);
+    if (!rc) rc = launch_zero(w.info, (int64_t)sz[12], s);
+    if (rc) return rc;
+    return diffusion_work_choose(w, m, g);
 }
 
 void diffusion_work_free(DiffusionWork& w) {

@@ -110,6 +110,11 @@ class Integrator:
     def recorded(self):
         return nat.misdc_integ_recorded(self.handle)
 
+    def set_streams(self, diffusion_stream=None, reaction_stream=None):
+        """Issue the diffusion and reaction tasks on the caller's streams
+        (None: the integrator's own)."""
+        nat.misdc_set_streams(self.handle, diffusion_stream, reaction_stream)
+
     def tune(self):
         return nat.misdc_get_tune(self.handle)
 

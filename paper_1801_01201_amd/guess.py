@@ -9,8 +9,6 @@ Typical use::
     train(mech, net, *data, epochs=5)
     integ.set_guess(net)
 """
-import numpy as np
-
 from . import native as nat
 from .flame import Integrator
 
@@ -43,28 +41,16 @@ def record_problems(mech, grid, states, dt, **integ_opts):
 
 
 def train(mech, net, bY, h, c, Ys, epochs=5, batch=4096, lr=2e-3, seed=0):
-    """Sets the network's normalisation from the data (means and standard
-    deviations of the features and targets; each input scale floored at
-    1e-3 of its mean's magnitude so that constant inputs stay O(1)), then
-    trains on the shuffled pairs.  Returns the per-epoch loss (host)."""
+    """The library sets the network's normalisation from the data (means and
+    standard deviations of the features and targets) and writes the
+    normalised pairs in shuffled order, then trains on them.  Returns the
+    per-epoch loss (host)."""
     import torch
     n = h.numel()
     N = net.N
-    net.set_normalization(np.zeros(N + 2, np.float32), np.ones(N + 2, np.float32),
-                          np.ones(N + 1, np.float32))
     x = torch.empty((n, N + 2), dtype=torch.float32, device=h.device)
     t = torch.empty((n, N + 1), dtype=torch.float32, device=h.device)
-    nat.misdc_mlp_features(mech.handle, net.handle, n, bY, h, c, x)
-    nat.misdc_mlp_targets(mech.handle, net.handle, n, bY, h, Ys, t)
-    mu = x.double().mean(0).cpu().numpy()
-    sd = np.maximum(x.double().std(0).cpu().numpy(), np.maximum(1e-3 * np.abs(mu), 1e-6))
-    osd = np.maximum(t.double().std(0).cpu().numpy(), 1e-30)
-    net.set_normalization(mu.astype(np.float32), sd.astype(np.float32), osd.astype(np.float32))
-    nat.misdc_mlp_features(mech.handle, net.handle, n, bY, h, c, x)
-    nat.misdc_mlp_targets(mech.handle, net.handle, n, bY, h, Ys, t)
-    gen = torch.Generator(device="cpu").manual_seed(seed)
-    perm = torch.randperm(n, generator=gen).to(h.device)
-    x, t = x[perm].contiguous(), t[perm].contiguous()
+    nat.misdc_mlp_prepare_training(mech.handle, net.handle, n, bY, h, c, Ys, seed, x, t)
     hist = torch.empty(epochs, dtype=torch.float32, device=h.device)
     nat.misdc_mlp_train(net.handle, n, x, t, batch, epochs, lr, hist)
     return hist.cpu().numpy()

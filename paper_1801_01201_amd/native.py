@@ -38,9 +38,11 @@ EXPORTED = [
     "misdc_mlp_get_params", "misdc_mlp_set_normalization", "misdc_mlp_forward",
     "misdc_mlp_gradients", "misdc_mlp_adam_step", "misdc_mlp_train", "misdc_mlp_features",
     "misdc_mlp_targets", "misdc_reaction_guess_mlp", "misdc_integ_set_guess",
-    "misdc_integ_record", "misdc_integ_recorded",
+    "misdc_integ_record", "misdc_integ_recorded", "misdc_set_streams", "misdc_mlp_prepare_training",
+    "misdc_mech_specialized", "misdc_mech_generate",
 ]
 MLP_PRECISION = {"bf16": 0, "fp32": 1}
+NEWTON_KERNEL = {"auto": 0, "thread": 1, "wave": 2, "specialized": 3}
 
 
 class MisdcError(RuntimeError):
@@ -111,6 +113,9 @@ def load(path=LIB_PATH):
         "misdc_mech_create": (C.c_int, [C.POINTER(misdc_mech_desc), C.POINTER(vp)]),
         "misdc_mech_destroy": (C.c_int, [vp]),
         "misdc_mech_species": (C.c_int, [vp, C.POINTER(i32)]),
+        "misdc_mech_specialized": (C.c_int, [vp, C.POINTER(i32), C.POINTER(C.c_char_p)]),
+        "misdc_mech_generate": (C.c_int, [C.POINTER(misdc_mech_desc), C.c_int, C.c_char_p,
+                                          C.POINTER(C.c_size_t)]),
         "misdc_enthalpy": (C.c_int, [vp, i64, vp, vp, vp, vp]),
         "misdc_temperature": (C.c_int, [vp, i64, vp, vp, vp, vp]),
         "misdc_reaction_source": (C.c_int, [vp, i64, vp, vp, vp, vp]),
@@ -152,6 +157,9 @@ def load(path=LIB_PATH):
         "misdc_integ_set_guess": (C.c_int, [vp, vp, C.c_int]),
         "misdc_integ_record": (C.c_int, [vp, vp, i64]),
         "misdc_integ_recorded": (C.c_int, [vp, C.POINTER(i64)]),
+        "misdc_set_streams": (C.c_int, [vp, vp, vp]),
+        "misdc_mlp_prepare_training": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, C.c_uint64, vp, vp,
+                                                 vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -210,9 +218,9 @@ def misdc_sdc_tables(n_nodes, qi="lu", qe="cumulative"):
     return out
 
 
-def misdc_mech_create(mech):
-    """mech: dict in the generator's format (host arrays)."""
-    keep = {}
+def _mech_desc(mech, keep):
+    """misdc_mech_desc of a mechanism dict in the generator's format (host
+    arrays kept alive in ``keep``)."""
 
     def arr(key, dtype):
         a = np.ascontiguousarray(np.asarray(mech[key], dtype=dtype))
@@ -233,9 +241,37 @@ def misdc_mech_create(mech):
     d.p_atm = float(mech["p_atm"])
     d.R_u = float(mech["R_u"])
     d.R_c = float(mech["R_c"])
+    return d
+
+
+def misdc_mech_create(mech):
+    """mech: dict in the generator's format (host arrays)."""
+    keep = {}
+    d = _mech_desc(mech, keep)
     h = C.c_void_p()
     check(lib().misdc_mech_create(C.byref(d), C.byref(h)))
     return h.value
+
+
+def misdc_mech_specialized(h):
+    """(available, status message) of the reaction solve generated for a
+    mechanism."""
+    av = C.c_int32()
+    msg = C.c_char_p()
+    check(lib().misdc_mech_specialized(h, C.byref(av), C.byref(msg)))
+    return bool(av.value), msg.value.decode()
+
+
+def misdc_mech_generate(mech, compile=False):
+    """Source text generated for a mechanism (host only); with compile, also
+    compiled for the device by hiprtc."""
+    keep = {}
+    d = _mech_desc(mech, keep)
+    n = C.c_size_t(0)
+    check(lib().misdc_mech_generate(C.byref(d), int(bool(compile)), None, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    check(lib().misdc_mech_generate(C.byref(d), 0, buf, C.byref(n)))
+    return buf.value.decode()
 
 
 def misdc_mech_destroy(h):
@@ -254,7 +290,6 @@ def misdc_reaction_source(mech, n, Y, h, FR, stream=None):
     check(lib().misdc_reaction_source(mech, n, _ptr(Y), _ptr(h), _ptr(FR), _stream(stream)))
 
 
-NEWTON_KERNEL = {"auto": 0, "thread": 1, "wave": 2}
 LU = {"fp64": 0, "fp32_mfma": 1}
 
 
@@ -339,10 +374,26 @@ def misdc_step_end(integ, stream=None):
     check(lib().misdc_step_end(integ, _stream(stream)))
 
 
+def misdc_set_streams(integ, diffusion_stream=None, reaction_stream=None):
+    """Run the diffusion and reaction tasks on the caller's streams (torch
+    streams or raw hipStream_t ints); None selects the integrator's own."""
+    def raw(s):
+        if s is None:
+            return None
+        return s if isinstance(s, int) else s.cuda_stream
+    check(lib().misdc_set_streams(integ, raw(diffusion_stream), raw(reaction_stream)))
+
+
 def misdc_get_stats(integ):
+    """Statistics of the last step; "converged" is False where the library
+    returned MISDC_ENOTCONV (the counts are filled either way)."""
     s = misdc_stats()
-    check(lib().misdc_get_stats(integ, C.byref(s)))
-    return s.as_dict()
+    code = lib().misdc_get_stats(integ, C.byref(s))
+    if code not in (MISDC_OK, MISDC_ENOTCONV):
+        check(code)
+    d = s.as_dict()
+    d["converged"] = code == MISDC_OK
+    return d
 
 
 NEWTON_HIST_BINS = 64
@@ -439,6 +490,12 @@ def misdc_mlp_features(mech, h, n, bY, hh, c, x, stream=None):
 def misdc_mlp_targets(mech, h, n, bY, hh, Y, t, stream=None):
     check(lib().misdc_mlp_targets(mech, h, int(n), _ptr(bY), _ptr(hh), _ptr(Y), _ptr(t),
                                   _stream(stream)))
+
+
+def misdc_mlp_prepare_training(mech, h, n, bY, hh, c, Y, seed, x, t, stream=None):
+    check(lib().misdc_mlp_prepare_training(mech, h, int(n), _ptr(bY), _ptr(hh), _ptr(c), _ptr(Y),
+                                           int(seed) & (2**64 - 1), _ptr(x), _ptr(t),
+                                           _stream(stream)))
 
 
 def misdc_reaction_guess_mlp(mech, h, n, bY, hh, c, Y, choice=None, stream=None):

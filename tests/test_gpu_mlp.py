@@ -210,27 +210,13 @@ def _record_problems(nat, mh, mech9, seeds, nx, ny, dt):
 
 
 def train_guess_net(nat, mh, net, bY, hh, cc, Ys, epochs=30, batch=4096, lr=2e-3, seed=0):
-    """Normalisation from the data, then GPU training on shuffled pairs."""
+    """Normalisation from the data and shuffled, normalised pairs (one
+    library call), then GPU training on them."""
     n = hh.numel()
     N = net.N
-    ones_in = np.ones(N + 2, np.float32)
-    net.set_normalization(np.zeros(N + 2, np.float32), ones_in, np.ones(N + 1, np.float32))
     x = torch.empty((n, N + 2), dtype=torch.float32, device="cuda")
     t = torch.empty((n, N + 1), dtype=torch.float32, device="cuda")
-    nat.misdc_mlp_features(mh.handle, net.handle, n, bY, hh, cc, x)
-    nat.misdc_mlp_targets(mh.handle, net.handle, n, bY, hh, Ys, t)
-    # scales floored relative to each feature's magnitude: a constant
-    # feature (the inert bath, ln c of a fixed c) must not turn the float32
-    # rounding of its mean into an O(1) input
-    mu = x.double().mean(0).cpu().numpy()
-    sd = np.maximum(x.double().std(0).cpu().numpy(), np.maximum(1e-3 * np.abs(mu), 1e-6))
-    osd = np.maximum(t.double().std(0).cpu().numpy(), 1e-30)
-    net.set_normalization(mu.astype(np.float32), sd.astype(np.float32), osd.astype(np.float32))
-    nat.misdc_mlp_features(mh.handle, net.handle, n, bY, hh, cc, x)
-    nat.misdc_mlp_targets(mh.handle, net.handle, n, bY, hh, Ys, t)
-    gen = torch.Generator(device="cpu").manual_seed(seed)
-    perm = torch.randperm(n, generator=gen).cuda()
-    x, t = x[perm].contiguous(), t[perm].contiguous()
+    nat.misdc_mlp_prepare_training(mh.handle, net.handle, n, bY, hh, cc, Ys, seed, x, t)
     hist = torch.empty(epochs, dtype=torch.float32, device="cuda")
     nat.misdc_mlp_train(net.handle, n, x, t, batch, epochs, lr, hist)
     return host(hist)

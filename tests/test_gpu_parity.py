@@ -208,10 +208,16 @@ def test_initial_state_parity(nat, mech9, mh):
     assert field_err(st, ref) <= 1e-11
 
 
-def _run_gpu(nat, mh, grid_args, st, dt, steps, **opts):
+def _run_gpu(nat, mh, grid_args, st, dt, steps, tune=None, **opts):
     from paper_1801_01201_amd.flame import Grid, Integrator
     g = Grid(*grid_args)
     integ = Integrator(mh, g, **opts)
+    if tune is not None:
+        t = integ.tune()
+        t.update(tune)
+        integ.set_tune(t["cg_variant"], t["cg_blocks"], t["cyclic"], t["serialize"],
+                       t["cu_split"], t["stagger"])
+        assert all(integ.tune()[k] == v for k, v in tune.items())
     for _ in range(steps):
         integ.step(st, dt)
     stats = integ.stats()
@@ -233,7 +239,7 @@ STEP_CASES = [
 
 
 @pytest.mark.parametrize("case", STEP_CASES, ids=[c[0] for c in STEP_CASES])
-def test_step_parity(nat, mech9, mh, case):
+def test_step_parity(nat, mech9, mh, case, tune=None):
     name, dim, shape, dx, u, n_nodes, sweeps, steps, scheme, nu = case
     if dim == 1:
         Y, T = synth.flame_1d(mech9, shape[0], dx[0])
@@ -246,9 +252,9 @@ def test_step_parity(nat, mech9, mh, case):
         phi, _ = sdc_step(prob, phi, dt, n_nodes, sweeps, scheme, nu=nu)
     st = _gpu_initial(nat, mh, Y, T)
     n = [shape[1], shape[0]] if dim == 2 else [shape[0]]
-    out, stats = _run_gpu(nat, mh, (dim, n, list(dx), list(u)), st, dt, steps, n_nodes=n_nodes,
-                          sweeps=sweeps, nu=nu, scheme=scheme)
-    assert stats["newton_failed"] == 0 and stats["cg_failed"] == 0
+    out, stats = _run_gpu(nat, mh, (dim, n, list(dx), list(u)), st, dt, steps, tune=tune,
+                          n_nodes=n_nodes, sweeps=sweeps, nu=nu, scheme=scheme)
+    assert stats["newton_failed"] == 0 and stats["cg_failed"] == 0 and stats["converged"]
     err = field_err(out, phi.reshape(10, -1))
     assert err <= TOL, err
 
@@ -431,11 +437,12 @@ def test_uniform_state_is_pure_reaction(nat, mech9, mh):
     assert err <= TOL, err
 
 
-def test_step_parity_global_memory_cg(nat, mech9, mh, monkeypatch):
+@pytest.mark.parametrize("blocks", [1, 7, 64])
+def test_step_parity_global_memory_cg(nat, mech9, mh, blocks):
     """The CG variant that keeps its vectors in global memory (used when the
-    register-resident one does not fit) gives the same step."""
-    monkeypatch.setenv("MISDC_FORCE_CG_GLOBAL", "1")
-    test_step_parity(nat, mech9, mh, STEP_CASES[3])
+    register-resident one does not fit), selected through misdc_set_tune,
+    gives the same step, with one workgroup and with several."""
+    test_step_parity(nat, mech9, mh, STEP_CASES[3], tune={"cg_variant": 0, "cg_blocks": blocks})
 
 
 def test_concurrent_equals_serialized_bitwise(nat, mech9, mh):
@@ -549,6 +556,48 @@ def test_full_size_step_properties(nat, mech9, mh):
     np.testing.assert_allclose(out[9].sum(), s0[9].sum(), rtol=1e-12)
     inc = stats["sweep_increment"]
     assert inc[-1] < 1e-3 * inc[0]
+
+
+def test_full_size_step_parity(nat, mech9, mh):
+    """The benchmark's workload at its full size and in the launch
+    configuration the benchmark times (chosen by the autotuner): one step of
+    the 256x256 flame (CISDCQ-1, 5 Gauss-Lobatto nodes, 6 sweeps) against
+    the oracle's step, element by element, and every sweep's increment
+    against the oracle's in the same field-normalised norm (1e-10 absolute in
+    that norm).  The oracle's step takes a minute or two on the host."""
+    import sys
+    from paper_1801_01201_amd.flame import Grid, Integrator
+    cfg = synth.config("flame2d_256")
+    nx, ny = cfg["n"]
+    dt, K = cfg["dt"], cfg["sweeps"]
+    Y, T = synth.flame_2d(mech9, nx, ny, *cfg["dx"])
+    st = _gpu_initial(nat, mh, Y, T)
+    g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
+    integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=K, nu=cfg["nu"], scheme=cfg["scheme"])
+    tune = integ.autotune(st, dt, reps=2)
+    integ.step(st, dt)
+    stats = integ.stats()
+    out = host(st)
+    integ.close()
+    g.close()
+    assert stats["converged"], stats
+    print(f"[full-size parity] GPU step done with {tune}; oracle step follows",
+          file=sys.__stderr__, flush=True)
+    prob = FlameProblem(mech9, cfg["dx"], cfg["u"])
+    fi = []
+
+    def progress(k, inc):
+        print(f"[full-size parity] oracle sweep {k} done (increment {inc:.3e})",
+              file=sys.__stderr__, flush=True)
+
+    ref, _ = sdc_step(prob, relaxed_initial_state(prob, Y, T), dt, cfg["n_nodes"], K,
+                      cfg["scheme"], nu=cfg["nu"], field_increments=fi, progress=progress)
+    err = field_err(out, ref.reshape(10, -1))
+    assert err <= TOL, err
+    inc_ref = [float((f[:, 0] / f[:, 1]).max()) for f in fi]
+    inc_gpu = stats["sweep_increment"]
+    assert len(inc_gpu) == K
+    assert max(abs(a - b) for a, b in zip(inc_gpu, inc_ref)) <= 1e-10, (inc_gpu, inc_ref)
 
 
 @pytest.mark.parametrize("variant", [101, 102, 103])

@@ -115,6 +115,11 @@ def test_null_handles_rejected(nat):
     assert lib.misdc_step_begin(None, None, 1.0, None, None) == nat.MISDC_EINVAL
     assert lib.misdc_sweep(None, None) == nat.MISDC_EINVAL
     assert lib.misdc_step_end(None, None) == nat.MISDC_EINVAL
+    assert lib.misdc_set_streams(None, None, None) == nat.MISDC_EINVAL
+    assert lib.misdc_mlp_prepare_training(None, None, 4, None, None, None, None, 0, None, None,
+                                          None) == nat.MISDC_EINVAL
+    assert lib.misdc_integ_set_guess(None, None, 0) == nat.MISDC_EINVAL
+    assert lib.misdc_integ_record(None, None, 0) == nat.MISDC_EINVAL
     o = nat.misdc_opts_default()
     assert (o.n_nodes, o.n_sweeps, o.nu, o.scheme) == (5, 6, 1, 2)
     assert o.use_graph == 0
@@ -152,3 +157,19 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_generated_reaction_solve_compiles_on_the_host(nat):
+    """The source of the reaction solve generated for the 9-species
+    mechanism (every reaction written out with its constants) compiles for
+    gfx950 with hiprtc, without a GPU; a mechanism beyond the generated
+    kernel's species limit is refused."""
+    mech = synth.make_mechanism(9, 21, 0)
+    src = nat.misdc_mech_generate(mech, compile=True)
+    assert 'extern "C" __global__' in src and "newton_spec" in src
+    for j in range(mech["R"]):
+        assert f"// reaction {j}\n" in src
+    big = synth.make_mechanism(53, 325, 1)
+    with pytest.raises(nat.MisdcError) as e:
+        nat.misdc_mech_generate(big)
+    assert e.value.code == nat.MISDC_EUNSUPPORTED
