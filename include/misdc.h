@@ -264,6 +264,27 @@ int misdc_diffusion_solve(misdc_mech_t mech, misdc_grid_t grid, double c,
                           double* dev_y, int guess_in_y, double rtol, int maxit,
                           int32_t* dev_iters_out, void* stream);
 
+/* misdc_diffusion_solve without any allocation, for callers that cannot
+ * allocate device memory: code being captured into a HIP graph, serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, kernels and
+ * results (bit for bit) as misdc_diffusion_solve, but its work buffers (CG
+ * vectors, face coefficients, partial sums, barrier counters) live in one
+ * fixed device array of MISDC_NOALLOC_SCRATCH_MIB MiB that the library holds
+ * on each device it runs on until the process ends, and the call returns
+ * without synchronising (misdc_diffusion_solve waits for its solve to free
+ * its buffers).  No hipMalloc, hipFree or other allocating call is made;
+ * the parts that must start at zero are cleared by kernels on ``stream``.
+ * Every call on a device shares that device's array: calls that may overlap
+ * on one device (on different streams, or from several threads) race and
+ * must be ordered by the caller.  A grid whose workspace exceeds the array
+ * (about 150,000 cells at 9 species) returns MISDC_EINVAL before any work
+ * is enqueued. */
+#define MISDC_NOALLOC_SCRATCH_MIB 32
+int misdc_diffusion_solve_noalloc(misdc_mech_t mech, misdc_grid_t grid, double c,
+                                  const double* dev_T_lag, const double* dev_rhs,
+                                  double* dev_y, int guess_in_y, double rtol, int maxit,
+                                  int32_t* dev_iters_out, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Integrator                                                              */
 /* ---------------------------------------------------------------------- */

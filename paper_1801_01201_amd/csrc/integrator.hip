@@ -23,6 +23,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "misdc_impl.h"
@@ -1271,6 +1272,80 @@ int misdc_diffusion_solve(misdc_mech_t mech, misdc_grid_t grid, double c, const 
     diffusion_work_free(w);
     if (!rc && e != hipSuccess) rc = fail(MISDC_EDEVICE, "synchronise: %s", hipGetErrorString(e));
     return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device scratch of the diffusion solve that allocates nothing: the CG
+// vectors, face coefficients, block partials, halo edges, barrier counters
+// and iteration record of one call (each GPU the library runs on holds its
+// own copy until the process ends).  Host code never uses the array's name
+// as an address: each device's address comes from hipGetSymbolAddress.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)MISDC_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Address of the current device's scratch, looked up on the first call on
+// that device (with it current) and kept.
+int scratch_address(void** out) {
+    int dev = 0;
+    MISDC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(MISDC_EUNSUPPORTED, "device %d beyond the %d the scratch table holds", dev,
+                    NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MISDC_EDEVICE, "address of the diffusion scratch on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MISDC_OK;
+}
+
+__global__ void copy_word_kernel(int32_t* dst, const int32_t* src) { *dst = *src; }
+
+}  // namespace
+
+extern "C" {
+
+int misdc_diffusion_solve_noalloc(misdc_mech_t mech, misdc_grid_t grid, double c,
+                                  const double* T_lag, const double* rhs, double* y,
+                                  int guess_in_y, double rtol, int maxit, int32_t* iters_out,
+                                  void* stream) {
+    if (!mech || !grid) return fail(MISDC_EINVAL, "NULL handle");
+    if (!T_lag || !rhs || !y) return fail(MISDC_EINVAL, "NULL array");
+    if (rhs == y) return fail(MISDC_EINVAL, "rhs and y must not alias");
+    if (!(c >= 0) || !std::isfinite(c)) return fail(MISDC_EINVAL, "c must be >= 0 and finite");
+    const size_t need = diffusion_work_bytes(mech->m, grid->g);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(MISDC_EINVAL,
+                    "the solve needs %zu bytes of scratch; the no-allocation entry point holds "
+                    "%zu (%d MiB): use misdc_diffusion_solve for this grid",
+                    need, NOALLOC_SCRATCH_BYTES, MISDC_NOALLOC_SCRATCH_MIB);
+    void* block = nullptr;
+    int rc = scratch_address(&block);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    DiffusionWork w;
+    if ((rc = diffusion_work_carve(w, mech->m, grid->g, block, NOALLOC_SCRATCH_BYTES, s))) return rc;
+    rc = launch_diffusion_solve(mech->m, grid->g, w, c, nullptr, 0.0, T_lag, rhs, y, guess_in_y,
+                                rtol, maxit, s);
+    if (rc) return rc;
+    if (iters_out) {
+        hipLaunchKernelGGL(copy_word_kernel, dim3(1), dim3(1), 0, s, iters_out,
+                           (const int32_t*)w.info);
+        MISDC_HIP(hipGetLastError());
+    }
+    return MISDC_OK;
 }
 
 void misdc_opts_default(misdc_opts* o) {

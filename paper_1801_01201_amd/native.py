@@ -39,7 +39,7 @@ EXPORTED = [
     "misdc_mlp_gradients", "misdc_mlp_adam_step", "misdc_mlp_train", "misdc_mlp_features",
     "misdc_mlp_targets", "misdc_reaction_guess_mlp", "misdc_integ_set_guess",
     "misdc_integ_record", "misdc_integ_recorded", "misdc_set_streams", "misdc_mlp_prepare_training",
-    "misdc_mech_specialized", "misdc_mech_generate",
+    "misdc_diffusion_solve_noalloc", "misdc_mech_specialized", "misdc_mech_generate",
 ]
 MLP_PRECISION = {"bf16": 0, "fp32": 1}
 NEWTON_KERNEL = {"auto": 0, "thread": 1, "wave": 2, "specialized": 3}
@@ -128,6 +128,8 @@ def load(path=LIB_PATH):
         "misdc_transport_operators": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "misdc_diffusion_solve": (C.c_int, [vp, vp, dbl, vp, vp, vp, C.c_int, dbl, C.c_int,
                                             vp, vp]),
+        "misdc_diffusion_solve_noalloc": (C.c_int, [vp, vp, dbl, vp, vp, vp, C.c_int, dbl,
+                                                    C.c_int, vp, vp]),
         "misdc_opts_default": (None, [C.POINTER(misdc_opts)]),
         "misdc_integ_create": (C.c_int, [vp, vp, C.POINTER(misdc_opts), C.POINTER(vp)]),
         "misdc_integ_destroy": (C.c_int, [vp]),
