@@ -204,7 +204,8 @@ def accuracy_gate(cfg, mech, mh, state0, tune):
     st = state0.clone()
     g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
     integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
-                       scheme=cfg["scheme"], nu_tol=nu_tol, cg_rtol=cfg.get("cg_rtol", 1e-13))
+                       scheme=cfg["scheme"], nu_tol=nu_tol, cg_rtol=cfg.get("cg_rtol", 1e-13),
+                       pipeline=cfg.get("pipeline", False))
     if tune:
         integ.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"],
                        tune["cu_split"], tune["stagger"])
@@ -247,7 +248,8 @@ def graph_leg(integ, mh, g, cfg, state, args, tune):
     import torch
     from paper_1801_01201_amd.flame import Integrator
     gi = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
-                    scheme=cfg["scheme"], use_graph=True, cg_rtol=cfg.get("cg_rtol", 1e-13))
+                    scheme=cfg["scheme"], use_graph=True, cg_rtol=cfg.get("cg_rtol", 1e-13),
+                    pipeline=cfg.get("pipeline", False))
     if tune:
         gi.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"],
                     tune["cu_split"], tune["stagger"])
@@ -699,6 +701,9 @@ def main():
                          "sweep stops after pass l >= 2 once that pass changed the state by at "
                          "most nu_tol times the first pass's change")
     ap.add_argument("--serialize", action="store_true")
+    ap.add_argument("--pipeline", action="store_true",
+                    help="pipelined nested iterations (CISDCQ, --nu >= 2): the tasks of each "
+                         "pass on streams of their own")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune", default=None,
                     help="launch configuration instead of autotuning: cg_variant,cg_blocks,"
@@ -748,6 +753,7 @@ def main():
         cfg["sweeps"] = args.sweeps
     cfg["nu_tol"] = args.nu_tol
     cfg["cg_rtol"] = args.cg_rtol
+    cfg["pipeline"] = args.pipeline
     # the CPU leg runs first, before anything touches the GPU
     cpu = None if args.no_cpu_baseline else cpu_baseline_leg(cfg)
     if cpu:
@@ -771,7 +777,7 @@ def main():
                              torch.tensor(T.ravel(), device="cuda"))
     integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
                        scheme=cfg["scheme"], serialize=args.serialize, profile=True,
-                       nu_tol=args.nu_tol, cg_rtol=args.cg_rtol)
+                       nu_tol=args.nu_tol, cg_rtol=args.cg_rtol, pipeline=args.pipeline)
     tune = None
     if args.tune:
         integ.set_tune(*[int(v) for v in args.tune.split(",")])
@@ -873,11 +879,13 @@ def main():
                                f"nodes, {cfg['sweeps']} sweeps, dt {cfg['dt']} s",
                    "cells": n, "nodes": cfg["n_nodes"], "sweeps": cfg["sweeps"],
                    "nu": cfg["nu"], "scheme": cfg["scheme"], "serialize": args.serialize,
+                   "pipeline": args.pipeline,
                    "nu_tol": args.nu_tol, "cg_rtol": args.cg_rtol},
         "nested_passes_per_step": passes,
         "sweep_increment_last_step": stats["sweep_increment"],
         "newton_iters_per_cell": newton_per_cell,
         "newton_iters_per_sweep": newton_sweeps,
+        "newton_pivot_retries_last_step": stats.get("newton_pivot_retries"),
         "cg_iters_per_solve": cg_per_solve,
         "cell_node_updates_per_step_incl_node0": n * (M + 1) * cfg["nu"] * cfg["sweeps"],
         "roofline": roof,

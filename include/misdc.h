@@ -316,6 +316,23 @@ typedef struct {
                             delta_1.  The host waits for each delta_l, so
                             use_graph must be 0 (MISDC_EINVAL otherwise).
                             <= 0: nu passes in every sweep */
+    int32_t pipeline;    /* 1: pipelined nested iterations (section 3.2.2 and
+                            Fig. 2; CISDCQ with nu >= 2, no nu_tol, two
+                            streams): the tasks of pass l start as soon as
+                            the equations allow instead of after pass l-1,
+                            so up to 2 diffusion and nu reaction tasks run
+                            at once.  The diffusion tasks of pass l run on
+                            one of two streams confined to the two halves of
+                            every XCD's CUs (l mod 2), so two persistent
+                            diffusion solves never wait for each other's
+                            CUs; the reaction tasks of pass l on a stream of
+                            their own; each stream has its own work buffers.
+                            Results are meant to be bitwise those of
+                            pipeline = 0.  Not combined with use_graph (a
+                            captured graph drops the lanes' CU masks),
+                            misdc_set_streams, a CU split, the stagger or a
+                            learned guess (MISDC_EINVAL / MISDC_EUNSUPPORTED);
+                            the diffusion solve must fit half the CUs */
 } misdc_opts;
 
 /* Fills the defaults: 5 nodes, 6 sweeps, nu 1, CISDCQ, cumulative QE. */
@@ -465,6 +482,10 @@ typedef struct {
     /* nested iterations done in each sweep of the last step (nu, or fewer
      * with opts.nu_tol) */
     int32_t nested_passes[64];
+    /* generated reaction solve (MISDC_NEWTON_SPECIALIZED, last step): Newton
+     * iterations whose diagonal pivots failed the threshold test and were
+     * factored again with partial pivoting */
+    int64_t newton_pivot_retries;
 } misdc_stats;
 
 /* Outcomes of the last step's cell-node Newton solves in sweep k (0 <= k <

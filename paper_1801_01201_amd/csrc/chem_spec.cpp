@@ -15,9 +15,10 @@
 //    whose species indices are runtime values, updates all N x (N+1) entries
 //    through selects;
 //  - the LU of the Newton matrix pivots on the diagonal when the diagonal
-//    entry is at least a tenth of the largest magnitude below it in its
-//    column (threshold pivoting); a cell that fails the test anywhere
-//    assembles its matrix again and factors it with partial pivoting.
+//    entry is at least a tenth of the largest magnitude among the species
+//    rows below it in its column (threshold pivoting; the enthalpy row is
+//    eliminated last); a cell that fails the test anywhere assembles its
+//    matrix again and factors it with partial pivoting.
 // The arithmetic is otherwise that of the generic kernel (chem.hip): the same
 // residual, pseudo-transient continuation, trial acceptance and convergence
 // test, so both agree to the Newton tolerance.
@@ -138,7 +139,11 @@ __device__ __forceinline__ void lu_pivoted(double (&A)[n][n + 1]) {
 }
 
 // LU on the diagonal pivots, refused (returns false) when a pivot is below a
-// tenth of the largest magnitude in its column at or below the diagonal
+// tenth of the largest magnitude among the species rows below it in its
+// column, or is not finite and non-zero.  The last row (the enthalpy
+// equation, whose entries h_k / cp are thousands of kelvin against the O(1)
+// species diagonals) is never a candidate: it is eliminated last, and its
+// own final pivot is the Schur complement of the species block.
 template <int n>
 __device__ __forceinline__ bool lu_threshold(double (&A)[n][n + 1]) {
     bool ok = true;
@@ -146,8 +151,8 @@ __device__ __forceinline__ bool lu_threshold(double (&A)[n][n + 1]) {
     for (int c = 0; c < n; ++c) {
         double amax = 0.0;
 #pragma unroll
-        for (int r = c + 1; r < n; ++r) amax = fmax(amax, fabs(A[r][c]));
-        ok = ok && (fabs(A[c][c]) >= 0.1 * amax) && (A[c][c] != 0.0);
+        for (int r = c + 1; r < n - 1; ++r) amax = fmax(amax, fabs(A[r][c]));
+        ok = ok && (fabs(A[c][c]) >= 0.1 * amax) && (A[c][c] != 0.0) && isfinite(A[c][c]);
         const double inv = 1.0 / A[c][c];
 #pragma unroll
         for (int r = c + 1; r < n; ++r) {
@@ -390,7 +395,7 @@ newton_spec(
     } else {
         i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     }
-    int code = 0;
+    int code = 0, retries = 0;
     if (i < n) {
         const double c = cp ? cp[i] * c_scalar : c_scalar;
         const double h = hp[i];
@@ -400,6 +405,7 @@ newton_spec(
         double T = temperature_of(Y, h);
         double inv_dtau = 0.0, gnorm_old = -1.0;
         int it = 0;
+        retries = 0;
         bool conv = false;
         while (!conv && it < maxit) {
             double M[NX][NX + 1];
@@ -414,6 +420,7 @@ newton_spec(
                     if (lu_threshold<NX>(M)) break;
                 } else {
                     lu_pivoted<NX>(M);
+                    ++retries;
                 }
             }
             double D[NS];
@@ -471,6 +478,7 @@ newton_spec(
             solves += __shfl_xor(solves, off);
             sum += __shfl_xor(sum, off);
             bad += __shfl_xor(bad, off);
+            retries += __shfl_xor(retries, off);
             const int o = __shfl_xor(mx, off);
             mx = o > mx ? o : mx;
         }
@@ -481,6 +489,7 @@ newton_spec(
             atomicAdd(&bk[1], (u64)sum);
             if (bad) atomicAdd(&bk[2], (u64)bad);
             atomicMax(&bk[3], (u64)mx);
+            if (retries) atomicAdd(&bk[4], (u64)retries);
         }
         if (hist) wave_hist(hist + (size_t)(w % HIST_SETS) * HIST_BINS, i < n, code);
     }

@@ -140,6 +140,54 @@ struct misdc_integ_s {
     const double* g_dtf = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
+    // pipelined passes (opts.pipeline): the diffusion tasks of pass l run on
+    // diffusion lane l % 2 (CU-masked streams on the two halves of every
+    // XCD's CUs, so two persistent diffusion solves never compete for CUs),
+    // the reaction tasks of pass l on reaction lane l; each lane has its own
+    // work buffers
+    struct DLane {
+        hipStream_t s = nullptr;
+        double* rD = nullptr;
+        double* th = nullptr;
+        DiffusionWork* dw = nullptr;
+        int32_t* cgstats = nullptr;
+        hipEvent_t end = nullptr;       // the lane's last work of a sweep
+    };
+    struct RLane {
+        hipStream_t s = nullptr;
+        double* bR = nullptr;
+        double* th = nullptr;
+        int32_t* iters = nullptr;
+        int32_t* lu_info = nullptr;
+        hipEvent_t end = nullptr;
+    };
+    bool pipe = false;
+    hipStream_t s_last = nullptr;              // stream of the last sweep's last reaction task
+    DLane pd_lane[2];
+    std::vector<RLane> pr_lane;
+    DiffusionWork pdw[2];
+    std::vector<hipStream_t> lane_streams;     // created by the library for the lanes
+    DLane dlane(int l) {
+        if (pipe) return pd_lane[l % 2];
+        DLane d;
+        d.s = sD;
+        d.rD = rD;
+        d.th = thD;
+        d.dw = &dw;
+        d.cgstats = cgstats;
+        return d;
+    }
+    RLane rlane(int l) {
+        if (pipe) return pr_lane[(size_t)l];
+        RLane r;
+        r.s = sR;
+        r.bR = bR;
+        r.th = thR;
+        r.iters = iters;
+        r.lu_info = lu_info;
+        return r;
+    }
+
     hipEvent_t& D_ev(int l, int p) { return evD[(size_t)l * (M + 1) + p]; }
     hipEvent_t& R_ev(int l, int p) { return evR[(size_t)l * (M + 1) + p]; }
     hipEvent_t& C_ev(int l, int p) { return evC[(size_t)l * (M + 1) + p]; }
@@ -219,6 +267,17 @@ int check_opts(const misdc_opts* o) {
         return fail(MISDC_EINVAL, "adaptive nested iterations need the concurrent scheme");
     if (o->nu_tol > 0 && o->use_graph)
         return fail(MISDC_EINVAL, "adaptive nested iterations cannot be replayed as a graph");
+    if (o->pipeline != 0 && o->pipeline != 1) return fail(MISDC_EINVAL, "pipeline must be 0 or 1");
+    if (o->pipeline && (o->scheme != MISDC_SCHEME_CISDCQ || o->nu < 2 || o->nu_tol > 0 ||
+                        o->serialize))
+        return fail(MISDC_EINVAL, "pipelined passes need CISDCQ with nu >= 2 fixed passes on "
+                                  "separate streams (no nu_tol, no serialize)");
+    // a captured graph does not keep the diffusion lanes' CU masks, and two
+    // persistent diffusion solves sharing CUs could each wait for CUs the
+    // other holds
+    if (o->pipeline && o->use_graph)
+        return fail(MISDC_EINVAL, "pipelined passes are not replayed as a graph (the diffusion "
+                                  "lanes' CU masks do not survive capture)");
     return MISDC_OK;
 }
 
@@ -374,7 +433,7 @@ void diffusion_rhs(misdc_integ_s* I, int ell, int p, LC& b, double& cf_out,
     auto& L0 = I->lev[0];
     auto& Lc = I->lev[ell + 1];       // iteration ell+1 (serial schemes: the new sweep)
     auto& Lp = I->lev[ell];           // iteration ell (lagged); ell = 0: sweep k
-    const int o = b.out(I->rD);
+    const int o = b.out(I->dlane(ell).rD);
     double cf = 0.0;                  // implicit factor c = dt * cf
     const double* T_lag = nullptr;
     if (I->opt.scheme == MISDC_SCHEME_MISDC) {
@@ -424,6 +483,7 @@ void diffusion_rhs(misdc_integ_s* I, int ell, int p, LC& b, double& cf_out,
 int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     const int NF = I->NF;
     const int64_t n = I->n;
+    const misdc_integ_s::DLane L = I->dlane(ell);
     double cf = 0.0;
     const double* T_lag = nullptr;
     LC b(NF, n, dt, I->dtc);
@@ -433,18 +493,18 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
         I->d1_ready = false;          // formed by the sweep constants' pass
     } else {
         // the same pass computes the face coefficients of the lagged operator
-        if ((rc = launch_lincomb_faces(b.lc, *I->grid, T_lag, I->dw, I->sD))) return rc;
+        if ((rc = launch_lincomb_faces(b.lc, *I->grid, T_lag, *L.dw, L.s))) return rc;
     }
     // the solve is next on this stream: a staggered reaction task waits for this
-    if (I->stagger && I->sR != I->sD) MISDC_HIP(hipEventRecord(I->C_ev(ell + 1, p), I->sD));
+    if (I->stagger && I->sR != I->sD) MISDC_HIP(hipEventRecord(I->C_ev(ell + 1, p), L.s));
     // with profiling, the events bracket the solve kernel itself (CG or cyclic)
     const bool timed = I->opt.profile && !I->capturing;
     hipEvent_t t0 = timed ? pool_event(I) : nullptr;
     hipEvent_t t1 = timed ? pool_event(I) : nullptr;
     const bool lag_init = (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell == 0 && p < I->M);
-    rc = launch_diffusion_solve(*I->mech, *I->grid, I->dw, dt * cf, I->dtf, cf, T_lag, I->rD,
-                                I->phiAD[p], 1, I->opt.cg_rtol, I->opt.cg_maxit, I->sD, t0, t1,
-                                I->TAD[p], I->cgstats, lag_init ? I->thD : nullptr, true);
+    rc = launch_diffusion_solve(*I->mech, *I->grid, *L.dw, dt * cf, I->dtf, cf, T_lag, L.rD,
+                                I->phiAD[p], 1, I->opt.cg_rtol, I->opt.cg_maxit, L.s, t0, t1,
+                                I->TAD[p], L.cgstats, lag_init ? L.th : nullptr, true);
     if (rc) return rc;
     if (t0 && t1) I->timed.push_back({t0, t1, 0});
     return MISDC_OK;
@@ -457,8 +517,9 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
 // reaction task of node p, which does not read them.
 int lag_transport(misdc_integ_s* I, int ell, int p) {
     if (I->opt.scheme != MISDC_SCHEME_CISDCQ || ell != 0 || p >= I->M) return MISDC_OK;
+    const misdc_integ_s::DLane L = I->dlane(ell);
     return launch_transport(*I->mech, *I->grid, I->phiAD[p], I->TAD[p], I->hatA[p], I->hatD[p],
-                            I->thD, I->sD, true);
+                            L.th, L.s, true);
 }
 
 // ---- reaction task at node p of nested iteration ell (writes lev[ell+1][p]) ----
@@ -470,8 +531,9 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     auto& L0 = I->lev[0];
     auto& Lc = I->lev[ell + 1];
     auto& Lp = I->lev[ell];
+    const misdc_integ_s::RLane L = I->rlane(ell);
     LC b(N, n, dt, I->dtc);
-    const int o = b.out(I->bR);
+    const int o = b.out(L.bR);
     double cf = 0.0;                  // implicit factor c = dt * cf
     b.add(o, 1.0, I->phiAD[p], N);
     if (I->opt.scheme == MISDC_SCHEME_MISDC) {
@@ -489,27 +551,27 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
         }
         b.addS(o, -cf, Lp[p].FR, N);
     }
-    int rc = launch_lincomb(b.lc, I->sR);
+    int rc = launch_lincomb(b.lc, L.s);
     if (rc) return rc;
     NodeBuf& out = Lc[p];
     // enthalpy is not changed by the reaction step
-    rc = launch_copy(out.phi + (size_t)N * n, I->phiAD[p] + (size_t)N * n, n, I->sR);
+    rc = launch_copy(out.phi + (size_t)N * n, I->phiAD[p] + (size_t)N * n, n, L.s);
     if (rc) return rc;
     const double c_scalar = I->dtc ? cf : dt * cf;
     const double* guess = Lp[p].phi;
     if (I->mlp && (I->guess_sweeps <= 0 || I->sweep_index < I->guess_sweeps)) {
         // the plain guess, replaced cell by cell by the learned one where
         // that has the smaller residual
-        if ((rc = launch_copy(out.phi, Lp[p].phi, (int64_t)N * n, I->sR))) return rc;
-        if ((rc = mlp_guess(*I->mech, I->mlp, n, I->bR, I->phiAD[p] + (size_t)N * n, I->dtc,
-                            c_scalar, out.phi, n, I->choice, I->sR)))
+        if ((rc = launch_copy(out.phi, Lp[p].phi, (int64_t)N * n, L.s))) return rc;
+        if ((rc = mlp_guess(*I->mech, I->mlp, n, L.bR, I->phiAD[p] + (size_t)N * n, I->dtc,
+                            c_scalar, out.phi, n, I->choice, L.s)))
             return rc;
-        if ((rc = launch_count_flags(I->choice, n, I->nstats + 6, I->sR))) return rc;
+        if ((rc = launch_count_flags(I->choice, n, I->nstats + 6, L.s))) return rc;
         guess = out.phi;
     }
     NewtonArgs a;
     a.n = n;
-    a.bY = I->bR;
+    a.bY = L.bR;
     a.ldb = n;
     a.h = I->phiAD[p] + (size_t)N * n;
     // c = dt * cf: per cell for ensembles with per-flame step sizes
@@ -522,8 +584,8 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     a.T = out.T;
     a.FR = out.FR;
     a.ldf = n;
-    a.iters = I->iters;
-    a.lu_info = (I->opt.newton.lu == MISDC_LU_FP32_MFMA) ? I->lu_info : nullptr;
+    a.iters = L.iters;
+    a.lu_info = (I->opt.newton.lu == MISDC_LU_FP32_MFMA) ? L.lu_info : nullptr;
     a.stats = I->nstats;
     a.buckets = I->nbuckets;
     a.hist = I->nhist + (size_t)I->sweep_index * NEWTON_HIST_SETS * NEWTON_HIST_BINS;
@@ -537,21 +599,21 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     // the persistent solve's workgroups take their CUs before the Newton
     // waves fill the device
     if (I->stagger && I->sR != I->sD && I->opt.scheme == MISDC_SCHEME_CISDCQ && p < I->M)
-        MISDC_HIP(hipStreamWaitEvent(I->sR, I->C_ev(ell + 1, p + 1), 0));
-    hipEvent_t t0 = timing_begin(I, I->sR);
-    rc = launch_reaction_newton(*I->mech, a, I->sR);
+        MISDC_HIP(hipStreamWaitEvent(L.s, I->C_ev(ell + 1, p + 1), 0));
+    hipEvent_t t0 = timing_begin(I, L.s);
+    rc = launch_reaction_newton(*I->mech, a, L.s);
     if (rc) return rc;
-    timing_end(I, t0, I->sR, 1);
+    timing_end(I, t0, L.s, 1);
     if (I->rec_buf && I->rec_count < I->rec_cap) {
         // record (b_Y, h, c, Y) of this reaction task
         double* slot = I->rec_buf + (size_t)I->rec_count * (2 * N + 2) * n;
-        if ((rc = launch_copy(slot, I->bR, (int64_t)N * n, I->sR))) return rc;
-        if ((rc = launch_copy(slot + (size_t)N * n, I->phiAD[p] + (size_t)N * n, n, I->sR))) return rc;
-        if ((rc = launch_fill_c(n, I->dtc, c_scalar, slot + (size_t)(N + 1) * n, I->sR))) return rc;
-        if ((rc = launch_copy(slot + (size_t)(N + 2) * n, out.phi, (int64_t)N * n, I->sR))) return rc;
+        if ((rc = launch_copy(slot, L.bR, (int64_t)N * n, L.s))) return rc;
+        if ((rc = launch_copy(slot + (size_t)N * n, I->phiAD[p] + (size_t)N * n, n, L.s))) return rc;
+        if ((rc = launch_fill_c(n, I->dtc, c_scalar, slot + (size_t)(N + 1) * n, L.s))) return rc;
+        if ((rc = launch_copy(slot + (size_t)(N + 2) * n, out.phi, (int64_t)N * n, L.s))) return rc;
         ++I->rec_count;
     }
-    rc = eval_ops(I, out, I->thR, I->sR, false);
+    rc = eval_ops(I, out, L.th, L.s, false);
     (void)NF;
     return rc;
 }
@@ -597,7 +659,7 @@ int sweep_constants(misdc_integ_s* I, double dt) {
             const int o = r.out(I->CR[p]);
             for (int j = 1; j <= p; ++j) r.addS(o, -t.QI[p - 1][j - 1], L0[j].FR, N);
         }
-        if ((rc = launch_lincomb(r.lc, I->sD))) return rc;
+        if ((rc = launch_lincomb(r.lc, I->dlane(0).s))) return rc;
     }
     // the first diffusion task's right-hand side (which contains C^1, folded
     // in as its weights), initial guess and face coefficients in the same
@@ -610,12 +672,13 @@ int sweep_constants(misdc_integ_s* I, double dt) {
         const double* T_lag = nullptr;
         diffusion_rhs(I, 0, 1, f, cf, T_lag);
         if (f.lc.nterms <= LC_MAX_TERMS && f.lc.nout <= LC_MAX_OUT) {
-            if ((rc = launch_lincomb_faces(f.lc, *I->grid, T_lag, I->dw, I->sD))) return rc;
+            if ((rc = launch_lincomb_faces(f.lc, *I->grid, T_lag, *I->dlane(0).dw, I->dlane(0).s)))
+                return rc;
             I->d1_ready = true;
             return MISDC_OK;
         }
     }
-    return launch_lincomb(b.lc, I->sD);
+    return launch_lincomb(b.lc, I->dlane(0).s);
 }
 
 // max over fields of max_i |new - old| / max_i |new| from the (difference,
@@ -636,8 +699,15 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
     const int nu = (I->opt.scheme == MISDC_SCHEME_CISDCQ) ? I->nu : 1;
     int done = nu;                    // nested iterations done in this sweep
     int rc;
-    // the constants read every reaction output of the previous sweep
-    MISDC_HIP(hipStreamWaitEvent(I->sD, I->R_ev(0, M), 0));
+    // the constants read every reaction output of the previous sweep; with
+    // pipelined passes they also wait for every lane's last work of it,
+    // since this sweep's tasks overwrite buffers those lanes read
+    const hipStream_t s0 = I->dlane(0).s;
+    MISDC_HIP(hipStreamWaitEvent(s0, I->R_ev(0, M), 0));
+    if (I->pipe && k > 0) {
+        MISDC_HIP(hipStreamWaitEvent(s0, I->pd_lane[1].end, 0));
+        for (auto& r : I->pr_lane) MISDC_HIP(hipStreamWaitEvent(s0, r.end, 0));
+    }
     rc = sweep_constants(I, dt);
     if (rc) return rc;
     if (I->opt.scheme != MISDC_SCHEME_CISDCQ) {
@@ -654,22 +724,25 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
     } else {
         const bool adapt = I->opt.nu_tol > 0 && nu >= 3;
         for (int ell = 0; ell < nu; ++ell) {
+            // the streams of this pass's tasks (the same two for every pass
+            // unless the passes are pipelined)
+            const hipStream_t sd = I->dlane(ell).s, sr = I->rlane(ell).s;
             for (int s = 0; s <= M; ++s) {
                 const int pd = s + 1;     // diffusion node
                 const int pr = s;         // reaction node
                 if (pd <= M) {
-                    if (pd >= 3) MISDC_HIP(hipStreamWaitEvent(I->sD, I->R_ev(ell + 1, pd - 2), 0));
-                    if (ell >= 1) MISDC_HIP(hipStreamWaitEvent(I->sD, I->R_ev(ell, pd), 0));
+                    if (pd >= 3) MISDC_HIP(hipStreamWaitEvent(sd, I->R_ev(ell + 1, pd - 2), 0));
+                    if (ell >= 1) MISDC_HIP(hipStreamWaitEvent(sd, I->R_ev(ell, pd), 0));
                     rc = diffusion_task(I, ell, pd, dt);
                     if (rc) return rc;
-                    MISDC_HIP(hipEventRecord(I->D_ev(ell + 1, pd), I->sD));
+                    MISDC_HIP(hipEventRecord(I->D_ev(ell + 1, pd), sd));
                     if ((rc = lag_transport(I, ell, pd))) return rc;
                 }
                 if (pr >= 1) {
-                    MISDC_HIP(hipStreamWaitEvent(I->sR, I->D_ev(ell + 1, pr), 0));
+                    MISDC_HIP(hipStreamWaitEvent(sr, I->D_ev(ell + 1, pr), 0));
                     rc = reaction_task(I, ell, pr, dt);
                     if (rc) return rc;
-                    MISDC_HIP(hipEventRecord(I->R_ev(ell + 1, pr), I->sR));
+                    MISDC_HIP(hipEventRecord(I->R_ev(ell + 1, pr), sr));
                 }
             }
             if (adapt && ell + 1 < nu) {
@@ -696,14 +769,21 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
     }
     I->passes[k] = done;
     const int lv = done;
+    // the stream of the sweep's last reaction task
+    const hipStream_t se = I->rlane(lv - 1).s;
+    I->s_last = se;
     // the next sweep's constants need the reaction outputs only, so they are
     // released before the increment below (which reads buffers that only
     // later work of this same stream overwrites)
-    MISDC_HIP(hipEventRecord(I->R_ev(0, M), I->sR));
+    MISDC_HIP(hipEventRecord(I->R_ev(0, M), se));
     // sweep increment at node M (reaction stream, after the last reaction task)
     rc = launch_field_diff_max(I->NF, I->n, I->lev[lv][M].phi, I->lev[0][M].phi, I->inc_partial,
-                               I->inc_blocks, I->inc + (size_t)k * I->NF * 2, I->sR);
+                               I->inc_blocks, I->inc + (size_t)k * I->NF * 2, se);
     if (rc) return rc;
+    if (I->pipe) {
+        for (auto& d : I->pd_lane) MISDC_HIP(hipEventRecord(d.end, d.s));
+        for (auto& r : I->pr_lane) MISDC_HIP(hipEventRecord(r.end, r.s));
+    }
     // S7: the last nested iteration becomes sweep k+1 (swap buffer sets)
     for (int p = 1; p <= M; ++p) std::swap(I->lev[0][p], I->lev[lv][p]);
     return MISDC_OK;
@@ -714,8 +794,27 @@ int sync_streams(misdc_integ_s* I) {
     MISDC_HIP(hipStreamSynchronize(I->sD));
     if (I->sRm) MISDC_HIP(hipStreamSynchronize(I->sRm));
     MISDC_HIP(hipStreamSynchronize(I->sR2));
+    for (hipStream_t s : I->lane_streams) MISDC_HIP(hipStreamSynchronize(s));
     return MISDC_OK;
 }
+
+// CG counters of the last step over every diffusion lane: [0] iterations,
+// [1] max, [2] failed, [3] solves, [4] barrier timeouts
+int read_cgstats(misdc_integ_s* I, int32_t (&cg)[8]) {
+    MISDC_HIP(hipMemcpy(cg, I->cgstats, sizeof(cg), hipMemcpyDeviceToHost));
+    if (I->pipe)
+        for (auto& d : I->pd_lane) {
+            int32_t l[8];
+            MISDC_HIP(hipMemcpy(l, d.cgstats, sizeof(l), hipMemcpyDeviceToHost));
+            cg[0] += l[0];
+            cg[1] = l[1] > cg[1] ? l[1] : cg[1];
+            cg[2] += l[2];
+            cg[3] += l[3];
+            cg[4] += l[4];
+        }
+    return MISDC_OK;
+}
+
 
 // MISDC_ENOTCONV (with a message naming the counters) if the step whose
 // counters are on the device left a Newton solve or a diffusion solve
@@ -729,7 +828,7 @@ int convergence_status(misdc_integ_s* I) {
     MISDC_HIP(hipMemcpy(b.data(), I->nbuckets, sizeof(unsigned long long) * b.size(),
                         hipMemcpyDeviceToHost));
     for (int k = 0; k < NEWTON_BUCKETS; ++k) failed += b[(size_t)k * NEWTON_BUCKET_STRIDE + 2];
-    MISDC_HIP(hipMemcpy(cg, I->cgstats, sizeof(cg), hipMemcpyDeviceToHost));
+    if (int rc = read_cgstats(I, cg)) return rc;
     if (failed > 0 || cg[2] > 0 || cg[4] > 0)
         return fail(MISDC_ENOTCONV,
                     "unconverged solves in the last step: %llu cell-node Newton solves, "
@@ -772,10 +871,12 @@ int issue_begin(misdc_integ_s* I, double* state, double dt, const double* dtf, i
     const int M = I->M, N = I->N, NF = I->NF;
     const int64_t n = I->n;
     int rc;
-    if (I->sR != I->sD) {
+    if (I->sR != I->sD || I->pipe) {
         MISDC_HIP(hipEventRecord(I->ev_fork, I->sD));
-        MISDC_HIP(hipStreamWaitEvent(I->sR, I->ev_fork, 0));
+        if (I->sR != I->sD) MISDC_HIP(hipStreamWaitEvent(I->sR, I->ev_fork, 0));
+        for (hipStream_t s : I->lane_streams) MISDC_HIP(hipStreamWaitEvent(s, I->ev_fork, 0));
     }
+    I->s_last = I->sR;
     I->dtf = dtf;
     I->dtc = nullptr;
     if (dtf) {
@@ -791,6 +892,9 @@ int issue_begin(misdc_integ_s* I, double* state, double dt, const double* dtf, i
                                         NEWTON_HIST_SETS * NEWTON_HIST_BINS, I->sD)))
         return rc;
     if ((rc = launch_zero(I->cgstats, 8 * sizeof(int32_t), I->sD))) return rc;
+    if (I->pipe)
+        for (auto& d : I->pd_lane)
+            if ((rc = launch_zero(d.cgstats, 8 * sizeof(int32_t), I->sD))) return rc;
     // I1, I2, I4: every node of sweep 0 holds phi^n and F(phi^n)
     NodeBuf& b0 = I->lev[0][0];
     if ((rc = launch_copy(b0.phi, state, (int64_t)NF * n, I->sD))) return rc;
@@ -825,10 +929,20 @@ int issue_begin(misdc_integ_s* I, double* state, double dt, const double* dtf, i
 // reaction stream joins sD.
 int issue_end(misdc_integ_s* I, double* state) {
     int rc;
-    if ((rc = launch_copy(state, I->lev[0][I->M].phi, (int64_t)I->NF * I->n, I->sR))) return rc;
-    if (I->sR != I->sD) {
-        MISDC_HIP(hipEventRecord(I->ev_join, I->sR));
+    const hipStream_t se = I->s_last;         // after the last reaction task
+    if ((rc = launch_copy(state, I->lev[0][I->M].phi, (int64_t)I->NF * I->n, se))) return rc;
+    if (se != I->sD) {
+        MISDC_HIP(hipEventRecord(I->ev_join, se));
         MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_join, 0));
+    }
+    if (I->sR != I->sD && I->sR != se) {
+        MISDC_HIP(hipEventRecord(I->ev_outR, I->sR));
+        MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_outR, 0));
+    }
+    if (I->pipe) {
+        // every lane joins the origin stream (their end events of the last sweep)
+        for (auto& d : I->pd_lane) MISDC_HIP(hipStreamWaitEvent(I->sD, d.end, 0));
+        for (auto& r : I->pr_lane) MISDC_HIP(hipStreamWaitEvent(I->sD, r.end, 0));
     }
     return MISDC_OK;
 }
@@ -1367,6 +1481,77 @@ void misdc_opts_default(misdc_opts* o) {
 
 int misdc_integ_destroy(misdc_integ_t I);
 
+}  // extern "C"
+
+namespace {
+
+// CU mask of one half of every XCD's CUs (half 0 or 1): bit i is set when
+// (i / 8) mod 4 falls in that half, as for the reaction stream's CU split
+int half_mask_stream(int half, hipStream_t* out) {
+    int cus = 0;
+    int rc = device_cus(cus);
+    if (rc) return rc;
+    if (cus < 32 || cus % 32)
+        return fail(MISDC_EUNSUPPORTED, "pipelined passes need a multiple of 32 CUs (device has %d)",
+                    cus);
+    const size_t words = (size_t)cus / 32;
+    std::vector<uint32_t> mask(words, 0u), back(words, 0u);
+    for (int i = 0; i < cus; ++i)
+        if (((i / 8) % 4) / 2 == half) mask[(size_t)i / 32] |= 1u << (i % 32);
+    hipStream_t s = nullptr;
+    MISDC_HIP(hipExtStreamCreateWithCUMask(&s, (uint32_t)words, mask.data()));
+    hipError_t e = hipExtStreamGetCUMask(s, (uint32_t)words, back.data());
+    if (e != hipSuccess || back != mask) {
+        (void)hipStreamDestroy(s);
+        return fail(MISDC_EDEVICE, "CU mask of a diffusion lane not applied");
+    }
+    *out = s;
+    return MISDC_OK;
+}
+
+// The lanes of pipelined passes: two diffusion lanes on the two CU halves
+// (their persistent solves must each hold all of their workgroups at once, so
+// each needs CUs the other does not take) and one reaction lane per pass.
+int create_lanes(misdc_integ_s* I) {
+    const int64_t n = I->n;
+    const int NF = I->NF, N = I->N;
+    int cus = 0;
+    int rc = device_cus(cus);
+    if (rc) return rc;
+    I->pipe = true;
+    for (int h = 0; h < 2; ++h) {
+        auto& d = I->pd_lane[h];
+        if ((rc = half_mask_stream(h, &d.s))) return rc;
+        I->lane_streams.push_back(d.s);
+        if ((rc = dalloc(I, &d.rD, (size_t)NF * n))) return rc;
+        if ((rc = dalloc(I, &d.th, (size_t)n))) return rc;
+        if ((rc = dalloc(I, &d.cgstats, 8))) return rc;
+        if ((rc = diffusion_work_alloc(I->pdw[h], *I->mech, *I->grid))) return rc;
+        if (I->pdw[h].blocks > cus / 2)
+            return fail(MISDC_EUNSUPPORTED,
+                        "pipelined passes: the diffusion solve takes %d workgroups, more than "
+                        "the %d CUs of a lane", I->pdw[h].blocks, cus / 2);
+        d.dw = &I->pdw[h];
+        MISDC_HIP(hipEventCreateWithFlags(&d.end, hipEventDisableTiming));
+    }
+    I->pr_lane.assign((size_t)I->nu, misdc_integ_s::RLane());
+    for (auto& r : I->pr_lane) {
+        MISDC_HIP(hipStreamCreateWithFlags(&r.s, hipStreamNonBlocking));
+        I->lane_streams.push_back(r.s);
+        if ((rc = dalloc(I, &r.bR, (size_t)N * n))) return rc;
+        if ((rc = dalloc(I, &r.th, (size_t)n))) return rc;
+        if ((rc = dalloc(I, &r.iters, (size_t)n))) return rc;
+        if ((rc = dalloc(I, &r.lu_info, (size_t)n))) return rc;
+        MISDC_HIP(hipEventCreateWithFlags(&r.end, hipEventDisableTiming));
+    }
+    I->stagger = 0;
+    return MISDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* opts,
                        misdc_integ_t* out) {
     if (!out) return fail(MISDC_EINVAL, "output handle pointer is NULL");
@@ -1481,6 +1666,7 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) return bail(fail(MISDC_EDEVICE, "events: %s", hipGetErrorString(e)));
+    if (opts->pipeline && (rc = create_lanes(I))) return bail(rc);
     *out = I;
     return MISDC_OK;
 }
@@ -1492,7 +1678,14 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (I->sRm) (void)hipStreamSynchronize(I->sRm);
     if (I->sD_own) (void)hipStreamSynchronize(I->sD_own);
     if (I->sR2_own) (void)hipStreamSynchronize(I->sR2_own);
+    for (hipStream_t s : I->lane_streams) (void)hipStreamSynchronize(s);
     if (I->gexec) (void)hipGraphExecDestroy(I->gexec);
+    for (auto& d : I->pd_lane)
+        if (d.end) (void)hipEventDestroy(d.end);
+    for (auto& r : I->pr_lane)
+        if (r.end) (void)hipEventDestroy(r.end);
+    for (hipStream_t s : I->lane_streams) (void)hipStreamDestroy(s);
+    for (auto& w : I->pdw) diffusion_work_free(w);
     for (hipEvent_t ev : I->evD)
         if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : I->evR)
@@ -1620,6 +1813,9 @@ int misdc_integ_set_guess(misdc_integ_t I, misdc_mlp_t mlp, int sweeps) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
     if (sweeps < 0) return fail(MISDC_EINVAL, "sweeps must be >= 0");
     if (I->open) return fail(MISDC_ESTATE, "a step opened by misdc_step_begin is not ended");
+    if (I->pipe && mlp)
+        return fail(MISDC_EUNSUPPORTED, "the learned guess's buffers serve one reaction task at a "
+                                        "time; pipelined passes run several");
     int rc;
     if ((rc = sync_streams(I))) return rc;
     if (mlp) {
@@ -1695,6 +1891,8 @@ int misdc_set_streams(misdc_integ_t I, void* diffusion_stream, void* reaction_st
     if (I->open) return fail(MISDC_ESTATE, "a step opened by misdc_step_begin is not ended");
     if (diffusion_stream && diffusion_stream == reaction_stream)
         return fail(MISDC_EINVAL, "the two streams must differ (one stream: set_tune serialize)");
+    if (I->pipe && (diffusion_stream || reaction_stream))
+        return fail(MISDC_EUNSUPPORTED, "pipelined passes run on the integrator's own lanes");
     int rc;
     if ((rc = sync_streams(I))) return rc;
     const bool serial = I->sR == I->sD;
@@ -1733,6 +1931,9 @@ int misdc_set_tune(misdc_integ_t I, const misdc_tune* t) {
     if (t->cu_split && !t->serialize && I->caller_R)
         return fail(MISDC_EINVAL, "cu_split needs the library's own reaction stream "
                                   "(misdc_set_streams gave one of the caller's)");
+    if (I->pipe && (t->serialize || t->cu_split || t->stagger))
+        return fail(MISDC_EINVAL, "pipelined passes take their own lanes: serialize, cu_split "
+                                  "and stagger must be 0");
     const Grid& g = *I->grid;
     int rc;
     if ((rc = sync_streams(I))) return rc;
@@ -1740,6 +1941,17 @@ int misdc_set_tune(misdc_integ_t I, const misdc_tune* t) {
         DiffusionWork probe = I->dw;
         rc = diffusion_work_set(probe, *I->mech, g, t->cg_variant, t->cg_blocks);
         if (rc) return rc;
+        if (I->pipe) {
+            int cus = 0;
+            if ((rc = device_cus(cus))) return rc;
+            if (probe.blocks > cus / 2)
+                return fail(MISDC_EINVAL, "pipelined passes: at most %d diffusion workgroups",
+                            cus / 2);
+            for (auto& w : I->pdw) {
+                w.variant = probe.variant;
+                w.blocks = probe.blocks;
+            }
+        }
         I->dw.variant = probe.variant;
         I->dw.blocks = probe.blocks;
     }
@@ -1748,6 +1960,7 @@ int misdc_set_tune(misdc_integ_t I, const misdc_tune* t) {
         if (rc) return rc;
     }
     I->dw.cyclic = t->cyclic;
+    for (auto& w : I->pdw) w.cyclic = t->cyclic;
     I->cu_split = t->serialize ? 0 : t->cu_split;
     I->stagger = t->serialize ? 0 : t->stagger;
     I->sR = t->serialize ? I->sD : (I->cu_split ? I->sRm : I->sR2);
@@ -1869,9 +2082,10 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
             ns[1] += s[1];
             ns[2] += s[2];
             ns[3] = s[3] > ns[3] ? s[3] : ns[3];
+            st->newton_pivot_retries += (int64_t)s[4];
         }
     }
-    MISDC_HIP(hipMemcpy(cg, I->cgstats, sizeof(cg), hipMemcpyDeviceToHost));
+    if ((rc = read_cgstats(I, cg))) return rc;
     st->newton_solves = (int64_t)ns[0];
     st->newton_iters = (int64_t)ns[1];
     st->newton_failed = (int64_t)ns[2];

@@ -70,7 +70,8 @@ class misdc_opts(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("n_sweeps", C.c_int32), ("nu", C.c_int32),
                 ("scheme", C.c_int32), ("qe_mode", C.c_int32), ("serialize", C.c_int32),
                 ("newton", misdc_newton_opts), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
-                ("profile", C.c_int32), ("use_graph", C.c_int32), ("nu_tol", C.c_double)]
+                ("profile", C.c_int32), ("use_graph", C.c_int32), ("nu_tol", C.c_double),
+                ("pipeline", C.c_int32)]
 
 
 class misdc_tune(C.Structure):
@@ -91,7 +92,7 @@ class misdc_stats(C.Structure):
                 ("diffusion_kernel_launches", C.c_int64), ("newton_kernel_ms", C.c_double),
                 ("newton_kernel_launches", C.c_int64), ("newton_lu_solves", C.c_int64),
                 ("newton_lu_fallbacks", C.c_int64), ("newton_guess_learned", C.c_int64),
-                ("nested_passes", C.c_int32 * 64)]
+                ("nested_passes", C.c_int32 * 64), ("newton_pivot_retries", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_
@@ -521,7 +522,7 @@ def misdc_integ_recorded(integ):
 
 def make_opts(n_nodes=5, sweeps=6, nu=1, scheme="cisdcq", qe="cumulative", serialize=False,
               cg_rtol=1e-13, cg_maxit=500, newton=None, profile=False, use_graph=False,
-              nu_tol=0.0):
+              nu_tol=0.0, pipeline=False):
     o = misdc_opts_default()
     o.n_nodes = n_nodes
     o.n_sweeps = sweeps
@@ -534,6 +535,7 @@ def make_opts(n_nodes=5, sweeps=6, nu=1, scheme="cisdcq", qe="cumulative", seria
     o.profile = int(bool(profile))
     o.use_graph = int(bool(use_graph))
     o.nu_tol = float(nu_tol)
+    o.pipeline = int(bool(pipeline))
     if newton is not None:
         o.newton = newton
     return o
