@@ -10,9 +10,13 @@ closed-form T(Y, h).
 The implicit diffusion solve uses coefficients from the lagged state passed by
 the SDC driver (eq. lagged_diffusion_flux); explicit evaluations of FD use the
 state's own temperature.  The reaction solve keeps h fixed and solves the
-backward-Euler system for (Y, T) with the guess passed by the driver.
+backward-Euler system for (Y, T) with the guess passed by the driver.  The
+coupled solve of the comparison scheme IMEXQ (section 3.2.2) treats diffusion
+(lagged coefficients) and reaction implicitly together.
 """
 import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from . import chemistry as chem
 from . import transport as tr
@@ -69,6 +73,72 @@ class FlameProblem:
         out[:N] = Y.reshape((N,) + shape)
         out[N] = b[N]                 # no reaction source in the enthalpy
         return out
+
+
+    def solve_DR(self, c, rhs, guess, lag, tol=1e-13, maxit=30):
+        """IMEXQ's implicit step: phi - c (FD_lag(phi) + FR(phi)) = rhs, with
+        FD_lag the diffusion operator whose coefficients come from the lagged
+        state (as in solve_D, dominant species by closure) and FR the reaction
+        source at phi's own temperature T(Y, h).  Newton's method on the whole
+        grid from ``guess``: the Jacobian I - c (D + R) is assembled as a
+        sparse matrix, D the lagged diffusion operator of every field (the
+        dominant species' row is minus the sum of the other species' rows) and
+        R each cell's derivative of FR with respect to (Y, h) through
+        T(Y, h), and solved directly.  Converged when every field's update is
+        at most tol times that field's largest magnitude."""
+        mech, N = self.mech, self.N
+        nf = N + 1
+        shape = rhs.shape[1:]
+        n = int(np.prod(shape))
+        th = tr.theta(self.temperature(lag))
+        L = tr.laplacian_matrix(th, self.dx)
+        k0 = tr.diffusion_coefficients(mech)
+        i0 = mech["bath"]
+        blocks = [[None] * nf for _ in range(nf)]
+        for f in range(nf):
+            if f != i0:
+                blocks[f][f] = k0[f] * L
+        for k in range(N):
+            if k != i0:
+                blocks[i0][k] = -k0[k] * L
+        for f in range(nf):
+            if blocks[f][f] is None:
+                blocks[f][f] = sp.csc_matrix((n, n))
+        D = sp.bmat(blocks, format="csc")
+        x = np.array(guess, dtype=np.float64).reshape(nf, n).copy()
+        b = rhs.reshape(nf, n)
+        idx = np.arange(n)
+        for _ in range(maxit):
+            Y, h = x[:N], x[N]
+            T = chem.temperature(mech, Y, h)
+            FR = np.zeros_like(x)
+            FR[:N] = chem.reaction_source(mech, Y, T)
+            G = x.ravel() - c * (D @ x.ravel() + FR.ravel()) - b.ravel()
+            dY, dT = chem.reaction_source_jacobian(mech, Y, T)
+            cpm = np.sum(Y * (mech["cp"] / mech["W"])[:, None], axis=0)
+            hhat = chem.species_enthalpy(mech, T) / mech["W"][:, None]
+            rows, cols, vals = [], [], []
+            for k in range(N):
+                for l in range(N):
+                    rows.append(k * n + idx)
+                    cols.append(l * n + idx)
+                    vals.append(dY[k, l] - dT[k] * hhat[l] / cpm)
+                rows.append(k * n + idx)
+                cols.append(N * n + idx)
+                vals.append(dT[k] / cpm)
+            R = sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                              shape=(nf * n, nf * n))
+            A = sp.identity(nf * n, format="csc") - c * (D + R)
+            d = spla.spsolve(A, G).reshape(nf, n)
+            if not np.all(np.isfinite(d)):
+                raise FloatingPointError("coupled diffusion-reaction Newton step is not finite")
+            x -= d
+            scale = np.maximum(np.abs(x).max(axis=1), 1e-300)
+            if np.all(np.abs(d).max(axis=1) <= tol * scale):
+                break
+        else:
+            raise RuntimeError("coupled diffusion-reaction solve did not converge")
+        return x.reshape(rhs.shape)
 
 
 RELAX_TIME = 1.0

@@ -32,7 +32,8 @@ def mild_collocation(mild_flame):
     return collocation_solve(prob, phi0, 2e-5, 5)
 
 
-@pytest.mark.parametrize("scheme,nu", [("misdc", 1), ("misdcq", 1), ("cisdcq", 1), ("cisdcq", 3)])
+@pytest.mark.parametrize("scheme,nu", [("misdc", 1), ("misdcq", 1), ("cisdcq", 1), ("cisdcq", 3),
+                                       ("imexq", 1)])
 def test_sweeps_reach_collocation_fixed_point(mild_flame, mild_collocation, scheme, nu):
     prob, phi0 = mild_flame
     out, _ = sdc_step(prob, phi0, 2e-5, 5, 60, scheme, nu=nu)
@@ -133,3 +134,68 @@ def test_field_increments_and_progress_record_the_sweep_changes():
         np.testing.assert_allclose(fi[k][:, 0], d, rtol=1e-12, atol=1e-300)
         np.testing.assert_allclose(fi[k][:, 1], a, rtol=1e-15)
         assert inc[k] == fi[k][:, 0].max()
+
+
+def _coupled_case(mech, nx=10, ny=8, seed=3):
+    """A 2-D state, a right-hand side near it and a lagged state."""
+    Y, T = synth.flame_2d(mech, nx, ny)
+    prob = FlameProblem(mech, (0.01, 0.01), (100.0, 0.0))
+    phi = relaxed_initial_state(prob, Y, T)
+    rng = np.random.default_rng(seed)
+    rhs = phi * (1.0 + 1e-3 * rng.standard_normal(phi.shape))
+    rhs[:9] = np.abs(rhs[:9])
+    lag = phi * (1.0 + 1e-3 * rng.standard_normal(phi.shape))
+    lag[:9] = np.abs(lag[:9])
+    return prob, phi, rhs, lag
+
+
+def test_coupled_solve_without_reactions_is_the_diffusion_solve():
+    """IMEXQ's coupled solve with every rate constant zero has no reaction
+    source: it is the implicit diffusion step S3/S4 of the same lagged
+    coefficients (a direct solve per field and the dominant-species closure),
+    computed independently by solve_D."""
+    mech = synth.make_mechanism(9, 21, 0)
+    mech = dict(mech, A=np.zeros_like(mech["A"]))
+    prob, phi, rhs, lag = _coupled_case(mech)
+    c = 3e-5
+    got = prob.solve_DR(c, rhs, phi, lag)
+    ref = prob.solve_D(c, rhs, lag)
+    scale = np.abs(ref).reshape(10, -1).max(axis=1)[:, None, None]
+    assert (np.abs(got - ref) / scale).max() <= 1e-12
+
+
+def test_coupled_solve_without_diffusion_is_the_reaction_solve():
+    """With every diffusivity zero the coupled solve has no spatial coupling:
+    it is the per-cell backward-Euler reaction step S5 at fixed h, computed
+    independently by solve_R (Newton on (Y, T) with pseudo-transient
+    continuation)."""
+    mech = synth.make_mechanism(9, 21, 0)
+    mech = dict(mech, D0=np.zeros_like(mech["D0"]), alpha0=0.0)
+    prob, phi, rhs, lag = _coupled_case(mech)
+    c = 3e-5
+    got = prob.solve_DR(c, rhs, phi, lag)
+    ref = prob.solve_R(c, rhs, phi)
+    scale = np.abs(ref).reshape(10, -1).max(axis=1)[:, None, None]
+    assert (np.abs(got - ref) / scale).max() <= 1e-11
+
+
+def test_coupled_solve_residual_and_conservation():
+    """The coupled solve's result satisfies its equation, evaluated with the
+    explicit diffusion operator at the lagged temperature and the reaction
+    source; the mass fractions of every cell still sum to that of the
+    right-hand side (neither operator creates mass)."""
+    from oracle import chemistry as ch
+    from oracle import transport as tr
+    mech = synth.make_mechanism(9, 21, 0)
+    prob, phi, rhs, lag = _coupled_case(mech)
+    c = 3e-5
+    x = prob.solve_DR(c, rhs, phi, lag)
+    FD = tr.diffusion(mech, x, prob.temperature(lag), prob.dx)
+    FR = prob.FR(x)
+    res = x - c * (FD + FR) - rhs
+    # mass fractions are O(1) quantities: a species whose largest value is
+    # tiny is still measured against 1e-3
+    scale = np.abs(rhs).reshape(10, -1).max(axis=1)
+    scale[:9] = np.maximum(scale[:9], 1e-3)
+    assert (np.abs(res) / scale[:, None, None]).max() <= 1e-12
+    np.testing.assert_allclose(x[:9].sum(axis=0), rhs[:9].sum(axis=0), atol=1e-12)
