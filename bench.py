@@ -208,7 +208,7 @@ def accuracy_gate(cfg, mech, mh, state0, tune):
                        pipeline=cfg.get("pipeline", False))
     if tune:
         integ.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"],
-                       tune["cu_split"], tune["stagger"])
+                       tune["cu_split"], tune["stagger"], tune.get("fused", 0))
     integ.step(st, cfg["dt"])
     out = st.cpu().numpy()
     s = integ.stats()
@@ -252,7 +252,7 @@ def graph_leg(integ, mh, g, cfg, state, args, tune):
                     pipeline=cfg.get("pipeline", False))
     if tune:
         gi.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"],
-                    tune["cu_split"], tune["stagger"])
+                    tune["cu_split"], tune["stagger"], tune.get("fused", 0))
     st = state.clone()
     for _ in range(max(1, args.warmup)):
         gi.step(st, cfg["dt"])
@@ -309,7 +309,7 @@ def ensemble_main(args):
             tune = integ.autotune(state, 0.0, dt_per_flame=d_dt, reps=3)
         elif tune is not None:
             integ.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"],
-                           tune["cu_split"], tune["stagger"])
+                           tune["cu_split"], tune["stagger"], tune.get("fused", 0))
         st = state.clone()
         for _ in range(max(1, args.warmup)):
             integ.step(st, 0.0, dt_per_flame=d_dt)
@@ -339,6 +339,17 @@ def ensemble_main(args):
                 "unit": "GB/s", "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
                 "avg_launch_ms": avg_s * 1e3, "launches": d_n,
                 "algorithmic_bytes_per_launch": byts}
+    elif tune and tune.get("fused"):
+        # one persistent launch per stage: the flames' tridiagonal systems and
+        # the cells' Newton solves from one work queue; achieved counts the
+        # reaction solve's FP64 work only (the diffusion systems add little)
+        avg_s = r_ms / max(1, r_n) * 1e-3
+        flops = NEWTON_FLOP_PER_ITER_9 * n * newton_per_cell
+        roof = {"kernel": "stage_kernel (fused stage: tridiagonal systems and per-cell Newton "
+                          "solves from one atomic work queue)", "bound": "alu",
+                "achieved": flops / avg_s / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": None, "avg_launch_ms": avg_s * 1e3, "launches": r_n}
     else:
         avg_s = r_ms / max(1, r_n) * 1e-3
         flops = NEWTON_FLOP_PER_ITER_9 * n * newton_per_cell
@@ -852,13 +863,32 @@ def main():
         avg_s = r_ms / max(1, r_n) * 1e-3
         flops = NEWTON_FLOP_PER_ITER_9 * n * newton_per_cell
         achieved = flops / avg_s / 1e12
-        roof = {"kernel": "newton_kernel<9, true> (per-cell reaction solve, inert bath "
-                          "eliminated)", "bound": "alu",
+        roof = {"kernel": ("newton_spec (reaction solve generated for the mechanism)"
+                           if native.misdc_mech_specialized(mh.handle)[0] else
+                           "newton_kernel<9, true> (per-cell reaction solve, inert bath "
+                           "eliminated)"), "bound": "alu",
                 "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                 "traffic": measured_traffic("pmc_newton_kernel_flame2d_256.md",
                                             "paper_1801_01201_amd/csrc/chem.hip"),
                 "avg_launch_ms": avg_s * 1e3, "launches": r_n}
+    # the reaction solve's own roofline, whichever kernel dominates: FP64 work
+    # against the vector peak, and its algorithmic HBM bytes against 8 TB/s
+    r_avg = r_ms / max(1, r_n) * 1e-3
+    spec_ok, _ = native.misdc_mech_specialized(mh.handle)
+    r_flops = NEWTON_FLOP_PER_ITER_9 * n * newton_per_cell
+    r_bytes = NEWTON_BYTES_PER_SOLVE_9 * n
+    roof_r = None if r_n == 0 else {
+        "kernel": ("newton_spec (reaction solve generated for the mechanism, one thread per "
+                   "cell-node)" if spec_ok else "newton_kernel<9, true>"),
+        "bound": "alu", "achieved": r_flops / r_avg / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s", "frac": r_flops / r_avg / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+        "hbm_achieved_GBs": r_bytes / r_avg / 1e9, "hbm_frac": r_bytes / r_avg / 1e9 / HBM_PEAK_GBS,
+        "avg_launch_ms": r_avg * 1e3, "launches": r_n,
+        "algorithmic_flops_per_launch": r_flops, "algorithmic_bytes_per_launch": r_bytes,
+        "traffic": (measured_traffic("pmc_newton_spec_flame2d_256.md",
+                                     "paper_1801_01201_amd/csrc/chem_spec.cpp")
+                    if spec_ok else None)}
     other = {"diffusion_solve_ms_per_launch": d_ms / max(1, d_n),
              "newton_ms_per_launch": r_ms / max(1, r_n),
              "diffusion_solve_share_of_step": d_ms / (elapsed * 1e3),
@@ -889,6 +919,7 @@ def main():
         "cg_iters_per_solve": cg_per_solve,
         "cell_node_updates_per_step_incl_node0": n * (M + 1) * cfg["nu"] * cfg["sweeps"],
         "roofline": roof,
+        "roofline_reaction_solve": roof_r,
         "fp64_counters": fp64_counter_rates(d_ms, d_n, r_ms, r_n),
         "kernel_split": other,
         "autotune": tune,

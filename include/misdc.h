@@ -424,6 +424,19 @@ typedef struct {
                              results are unchanged); the default with two
                              streams */
     double step_ms;       /* measured by misdc_autotune: mean time of one step */
+    int32_t fused;        /* ensembles of 1-D flames, CISDCQ, 9 species: 1 each
+                             stage of a pass (the diffusion solve at node m+1
+                             and the reaction solve at node m) as one
+                             persistent launch whose wavefronts take the
+                             flames' tridiagonal systems (longest flames
+                             first) and 64-cell chunks of Newton solves from
+                             one atomic work queue; the wavefront finishing a
+                             flame's last system or cell does that flame's
+                             closure or explicit operators.  Needs
+                             serialize = 1 (one stream), cu_split = stagger
+                             = 0, the FP64 one-thread-per-cell reaction solve
+                             (newton.kernel AUTO or THREAD), no learned guess
+                             or recording, flames of >= 16 cells */
 } misdc_tune;
 
 /* Times candidate launch configurations on the caller's workload (reps steps

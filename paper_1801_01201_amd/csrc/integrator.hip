@@ -19,6 +19,7 @@
 // iteration), so there is no write-after-read hazard and the result is
 // bitwise independent of the interleaving (option ``serialize`` runs the same
 // DAG on one stream).
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -163,6 +164,13 @@ struct misdc_integ_s {
     };
     bool pipe = false;
     hipStream_t s_last = nullptr;              // stream of the last sweep's last reaction task
+    // ensembles: each stage of a concurrent pass as one persistent launch
+    // (misdc_tune.fused) over the diffusion systems (field << 16 | flame, the
+    // longest flames first) and the cells' reaction problems
+    bool fused = false;
+    int* d_items = nullptr;
+    int nD_items = 0;
+    unsigned* stage_counters = nullptr;
     DLane pd_lane[2];
     std::vector<RLane> pr_lane;
     DiffusionWork pdw[2];
@@ -523,18 +531,19 @@ int lag_transport(misdc_integ_s* I, int ell, int p) {
 }
 
 // ---- reaction task at node p of nested iteration ell (writes lev[ell+1][p]) ----
-int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
-    const int N = I->N, NF = I->NF;
-    const int64_t n = I->n;
+// Right-hand side b of the reaction task at node p of nested iteration ell
+// (eqs. ..._misdc_discrete_form_R, ..._misdcq_discrete_form_R and
+// ..._amisdcq_discrete_form_R_alt) into out; returns the implicit factor cf
+// (c = dt * cf).
+double reaction_rhs(misdc_integ_s* I, int ell, int p, LC& b, double* out) {
+    const int N = I->N;
     const Tables& t = I->tab;
     const int m = p - 1;
     auto& L0 = I->lev[0];
     auto& Lc = I->lev[ell + 1];
     auto& Lp = I->lev[ell];
-    const misdc_integ_s::RLane L = I->rlane(ell);
-    LC b(N, n, dt, I->dtc);
-    const int o = b.out(L.bR);
-    double cf = 0.0;                  // implicit factor c = dt * cf
+    const int o = b.out(out);
+    double cf = 0.0;
     b.add(o, 1.0, I->phiAD[p], N);
     if (I->opt.scheme == MISDC_SCHEME_MISDC) {
         cf = t.tau[p] - t.tau[p - 1];
@@ -551,6 +560,17 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
         }
         b.addS(o, -cf, Lp[p].FR, N);
     }
+    return cf;
+}
+
+int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
+    const int N = I->N, NF = I->NF;
+    const int64_t n = I->n;
+    auto& Lc = I->lev[ell + 1];
+    auto& Lp = I->lev[ell];
+    const misdc_integ_s::RLane L = I->rlane(ell);
+    LC b(N, n, dt, I->dtc);
+    const double cf = reaction_rhs(I, ell, p, b, L.bR);
     int rc = launch_lincomb(b.lc, L.s);
     if (rc) return rc;
     NodeBuf& out = Lc[p];
@@ -694,6 +714,87 @@ double pass_change(const double* pairs, int nf) {
     return worst;
 }
 
+// One stage of a concurrent pass as one persistent launch (ensembles): the
+// right-hand sides of D_{s+1} and R_s are formed by their usual passes, then
+// one stage kernel solves the flames' diffusion systems and the cells'
+// reaction problems from one work queue; everything is on the diffusion
+// stream, whose order stands for the events of the two-stream schedule.
+int fused_stage(misdc_integ_s* I, int ell, int s, double dt) {
+    const int M = I->M, N = I->N, NF = I->NF;
+    const int64_t n = I->n;
+    const int pd = s + 1, pr = s;
+    EnsembleStage st;
+    int rc;
+    if (pd <= M) {
+        double cf = 0.0;
+        const double* T_lag = nullptr;
+        LC b(NF, n, dt, I->dtc);
+        diffusion_rhs(I, ell, pd, b, cf, T_lag);
+        if (ell == 0 && pd == 1 && I->d1_ready)
+            I->d1_ready = false;          // formed by the sweep constants' pass
+        else if ((rc = launch_lincomb_faces(b.lc, *I->grid, T_lag, I->dw, I->sD)))
+            return rc;
+        const bool lag_init = (ell == 0 && pd < M);
+        st.has_d = true;
+        st.nD = I->nD_items;
+        st.d_items = I->d_items;
+        st.c = dt * cf;
+        st.cfac = cf;
+        st.dtf = I->dtf;
+        st.Kx = I->dw.Kx;
+        st.rhs = I->rD;
+        st.y = I->phiAD[pd];
+        st.sc = I->dw.r;
+        st.su = I->dw.z;
+        st.sv = I->dw.p;
+        st.sw = I->dw.q;
+        st.T_out = I->TAD[pd];
+        st.th_out = lag_init ? I->thD : nullptr;
+        if (lag_init) {
+            st.lagFA = I->hatA[pd];
+            st.lagFD = I->hatD[pd];
+        }
+    }
+    if (pr >= 1) {
+        NodeBuf& out = I->lev[ell + 1][pr];
+        LC b(N, n, dt, I->dtc);
+        const double cf = reaction_rhs(I, ell, pr, b, I->bR);
+        if ((rc = launch_lincomb(b.lc, I->sD))) return rc;
+        NewtonArgs& a = st.na;
+        a.n = n;
+        a.bY = I->bR;
+        a.ldb = n;
+        a.h = I->phiAD[pr] + (size_t)N * n;
+        a.c = I->dtc;
+        a.c_scalar = I->dtc ? cf : dt * cf;
+        a.guess = I->lev[ell][pr].phi;
+        a.ldg = n;
+        a.Y = out.phi;
+        a.ldy = n;
+        a.T = out.T;
+        a.FR = out.FR;
+        a.ldf = n;
+        a.iters = I->iters;
+        a.stats = I->nstats;
+        a.buckets = I->nbuckets;
+        a.hist = I->nhist + (size_t)I->sweep_index * NEWTON_HIST_SETS * NEWTON_HIST_BINS;
+        a.opt = I->opt.newton;
+        st.has_r = true;
+        st.h_src = I->phiAD[pr] + (size_t)N * n;
+        st.h_dst = out.phi + (size_t)N * n;
+        st.rstate = out.phi;
+        st.rT = out.T;
+        st.rth = I->thR;
+        st.rFA = out.FA;
+        st.rFD = out.FD;
+    }
+    st.counters = I->stage_counters;
+    hipEvent_t t0 = timing_begin(I, I->sD);
+    if ((rc = launch_ensemble_stage(*I->mech, *I->grid, st, I->sD))) return rc;
+    timing_end(I, t0, I->sD, 1);
+    return MISDC_OK;
+}
+
 int run_sweep(misdc_integ_s* I, int k, double dt) {
     const int M = I->M;
     const int nu = (I->opt.scheme == MISDC_SCHEME_CISDCQ) ? I->nu : 1;
@@ -727,6 +828,11 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
             // the streams of this pass's tasks (the same two for every pass
             // unless the passes are pipelined)
             const hipStream_t sd = I->dlane(ell).s, sr = I->rlane(ell).s;
+            if (I->fused) {
+                for (int s = 0; s <= M; ++s)
+                    if ((rc = fused_stage(I, ell, s, dt))) return rc;
+                continue;
+            }
             for (int s = 0; s <= M; ++s) {
                 const int pd = s + 1;     // diffusion node
                 const int pr = s;         // reaction node
@@ -1667,6 +1773,25 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) return bail(fail(MISDC_EDEVICE, "events: %s", hipGetErrorString(e)));
     if (opts->pipeline && (rc = create_lanes(I))) return bail(rc);
+    if (grid->g.n_flames > 0 && grid->g.n_flames <= 0xffff) {
+        // the fused stages' work list: every diffused field of every flame,
+        // the longest flames first (their systems take longest)
+        const Grid& g = grid->g;
+        std::vector<int> order(g.n_flames);
+        for (int f = 0; f < g.n_flames; ++f) order[f] = f;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return g.len[a] > g.len[b]; });
+        std::vector<int> items;
+        for (int fl : order)
+            for (int f = 0; f <= N; ++f)
+                if (f != mech->m.dev.bath) items.push_back((f << 16) | fl);
+        if ((rc = dalloc(I, &I->d_items, items.size()))) return bail(rc);
+        if (hipMemcpy(I->d_items, items.data(), sizeof(int) * items.size(),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(MISDC_EDEVICE, "upload of the stage work list"));
+        I->nD_items = (int)items.size();
+        if ((rc = dalloc(I, &I->stage_counters, 1 + 2 * (size_t)g.n_flames))) return bail(rc);
+    }
     *out = I;
     return MISDC_OK;
 }
@@ -1816,6 +1941,8 @@ int misdc_integ_set_guess(misdc_integ_t I, misdc_mlp_t mlp, int sweeps) {
     if (I->pipe && mlp)
         return fail(MISDC_EUNSUPPORTED, "the learned guess's buffers serve one reaction task at a "
                                         "time; pipelined passes run several");
+    if (I->fused && mlp)
+        return fail(MISDC_EUNSUPPORTED, "fused stages run the plain Newton guess");
     int rc;
     if ((rc = sync_streams(I))) return rc;
     if (mlp) {
@@ -1834,6 +1961,8 @@ int misdc_integ_record(misdc_integ_t I, double* dev_buf, int64_t max_tasks) {
     if (!I) return fail(MISDC_EINVAL, "integrator is NULL");
     if (max_tasks < 0 || (max_tasks > 0 && !dev_buf)) return fail(MISDC_EINVAL, "invalid buffer");
     if (I->open) return fail(MISDC_ESTATE, "a step opened by misdc_step_begin is not ended");
+    if (I->fused && max_tasks > 0)
+        return fail(MISDC_EUNSUPPORTED, "fused stages do not record reaction problems");
     int rc;
     if ((rc = sync_streams(I))) return rc;
     I->rec_buf = max_tasks > 0 ? dev_buf : nullptr;
@@ -1918,6 +2047,7 @@ int misdc_get_tune(misdc_integ_t I, misdc_tune* t) {
     t->cu_split = I->cu_split;
     t->stagger = I->stagger;
     t->step_ms = I->tuned_ms;
+    t->fused = I->fused ? 1 : 0;
     return MISDC_OK;
 }
 
@@ -1934,6 +2064,23 @@ int misdc_set_tune(misdc_integ_t I, const misdc_tune* t) {
     if (I->pipe && (t->serialize || t->cu_split || t->stagger))
         return fail(MISDC_EINVAL, "pipelined passes take their own lanes: serialize, cu_split "
                                   "and stagger must be 0");
+    if (t->fused != 0 && t->fused != 1) return fail(MISDC_EINVAL, "fused must be 0 or 1");
+    if (t->fused) {
+        const misdc_newton_opts& no = I->opt.newton;
+        if (I->grid->n_flames <= 0 || !I->d_items || I->opt.scheme != MISDC_SCHEME_CISDCQ ||
+            I->N != 9 || I->pipe || I->mlp || I->rec_buf)
+            return fail(MISDC_EINVAL, "fused stages need an ensemble grid, CISDCQ, 9 species, "
+                                      "no pipelined passes, learned guess or recording");
+        if (no.lu != MISDC_LU_FP64 ||
+            (no.kernel != MISDC_NEWTON_AUTO && no.kernel != MISDC_NEWTON_THREAD))
+            return fail(MISDC_EINVAL, "fused stages run the FP64 one-thread-per-cell reaction "
+                                      "solve");
+        if (t->serialize != 1 || t->cu_split || t->stagger)
+            return fail(MISDC_EINVAL, "fused stages run on one stream: serialize 1, cu_split "
+                                      "and stagger 0");
+        for (int64_t L : I->grid->len)
+            if (L < 16) return fail(MISDC_EINVAL, "fused stages need flames of >= 16 cells");
+    }
     const Grid& g = *I->grid;
     int rc;
     if ((rc = sync_streams(I))) return rc;
@@ -1961,6 +2108,7 @@ int misdc_set_tune(misdc_integ_t I, const misdc_tune* t) {
     }
     I->dw.cyclic = t->cyclic;
     for (auto& w : I->pdw) w.cyclic = t->cyclic;
+    I->fused = t->fused != 0;
     I->cu_split = t->serialize ? 0 : t->cu_split;
     I->stagger = t->serialize ? 0 : t->stagger;
     I->sR = t->serialize ? I->sD : (I->cu_split ? I->sRm : I->sR2);
@@ -1990,6 +2138,7 @@ int misdc_autotune(misdc_integ_t I, const double* state, double dt, const double
         t.serialize = SER[k];
         t.cu_split = SPLIT[k];
         t.stagger = STAG[k];
+        t.fused = 0;
         if (g.dim == 2 && g.n_flames == 0) {
             const int cap = cus < 256 ? cus : 256;
             if (I->N == 9)
@@ -2019,6 +2168,16 @@ int misdc_autotune(misdc_integ_t I, const double* state, double dt, const double
                 cand.push_back(t);
             }
         }
+    }
+    if (g.n_flames > 0 && I->d_items) {
+        // each stage as one persistent launch (refused where it does not apply)
+        misdc_tune t = base;
+        t.serialize = 1;
+        t.cu_split = 0;
+        t.stagger = 0;
+        t.cyclic = 1;
+        t.fused = 1;
+        cand.push_back(t);
     }
     const size_t bytes = sizeof(double) * (size_t)I->NF * I->n;
     double* work = nullptr;

@@ -255,6 +255,38 @@ int launch_lincomb_faces(const LinComb& lc, const Grid& g, const double* T_lag, 
 int launch_field_diff_max(int nfields, int64_t n, const double* a, const double* b,
                           double* partial, int partial_blocks, double* out, hipStream_t s);
 
+// One stage of a concurrent sweep over an ensemble of 1-D flames as one
+// persistent launch (ensemble.hip): the diffusion solve at node m+1 (its
+// right-hand side, guess and face coefficients already formed) and the
+// reaction solve at node m (its right-hand side formed), both drawn from one
+// atomic work queue; either part may be absent.
+struct EnsembleStage {
+    bool has_d = false, has_r = false;
+    int nD = 0;                       // (field << 16 | flame) systems, longest first
+    const int* d_items = nullptr;
+    double c = 0.0, cfac = 0.0;       // c, or dtf[flame] * cfac, times kappa0
+    const double* dtf = nullptr;
+    const double* Kx = nullptr;
+    const double* rhs = nullptr;
+    double* y = nullptr;
+    double *sc = nullptr, *su = nullptr, *sv = nullptr, *sw = nullptr;
+    double* T_out = nullptr;
+    double* th_out = nullptr;
+    double* lagFA = nullptr;          // non-null: lag transport at y
+    double* lagFD = nullptr;
+    NewtonArgs na{};
+    const double* h_src = nullptr;
+    double* h_dst = nullptr;
+    const double* rstate = nullptr;
+    const double* rT = nullptr;
+    double* rth = nullptr;
+    double* rFA = nullptr;
+    double* rFD = nullptr;
+    unsigned* counters = nullptr;     // 1 + 2 n_flames words
+    int waves_per_slot = 1;
+};
+int launch_ensemble_stage(const Mech& m, const Grid& g, const EnsembleStage& st, hipStream_t s);
+
 // ---- learned Newton guess (dense network on the matrix cores) ----------------
 struct MlpImpl;
 int mlp_create(int n_in, int n_hidden, int n_out, int prec, MlpImpl** out);

@@ -118,9 +118,9 @@ class Integrator:
     def tune(self):
         return nat.misdc_get_tune(self.handle)
 
-    def set_tune(self, cg_variant, cg_blocks, cyclic, serialize, cu_split=0, stagger=0):
+    def set_tune(self, cg_variant, cg_blocks, cyclic, serialize, cu_split=0, stagger=0, fused=0):
         nat.misdc_set_tune(self.handle, cg_variant, cg_blocks, cyclic, serialize, cu_split,
-                           stagger)
+                           stagger, fused)
 
     def stats(self):
         return nat.misdc_get_stats(self.handle)

@@ -77,7 +77,7 @@ class misdc_opts(C.Structure):
 class misdc_tune(C.Structure):
     _fields_ = [("cg_variant", C.c_int32), ("cg_blocks", C.c_int32), ("cyclic", C.c_int32),
                 ("serialize", C.c_int32), ("cu_split", C.c_int32),
-                ("stagger", C.c_int32), ("step_ms", C.c_double)]
+                ("stagger", C.c_int32), ("step_ms", C.c_double), ("fused", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -428,9 +428,10 @@ def misdc_get_tune(integ):
     return t.as_dict()
 
 
-def misdc_set_tune(integ, cg_variant, cg_blocks, cyclic, serialize, cu_split=0, stagger=0):
+def misdc_set_tune(integ, cg_variant, cg_blocks, cyclic, serialize, cu_split=0, stagger=0,
+                   fused=0):
     t = misdc_tune(int(cg_variant), int(cg_blocks), int(cyclic), int(serialize), int(cu_split),
-                   int(stagger), 0.0)
+                   int(stagger), 0.0, int(fused))
     check(lib().misdc_set_tune(integ, C.byref(t)))
 
 
