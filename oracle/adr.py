@@ -84,8 +84,12 @@ class FlameProblem:
         sparse matrix, D the lagged diffusion operator of every field (the
         dominant species' row is minus the sum of the other species' rows) and
         R each cell's derivative of FR with respect to (Y, h) through
-        T(Y, h), and solved directly.  Converged when every field's update is
-        at most tol times that field's largest magnitude."""
+        T(Y, h), and solved directly.  Converged when every mass fraction's
+        update is at most tol (mass fractions are O(1) quantities, tested
+        absolutely as in the per-cell reaction solve: a trace species' update
+        stalls at the rounding level of the large ones coupled into it, far
+        above tol times its own magnitude) and the enthalpy's update at most
+        tol times its largest magnitude."""
         mech, N = self.mech, self.N
         nf = N + 1
         shape = rhs.shape[1:]
@@ -133,7 +137,8 @@ class FlameProblem:
             if not np.all(np.isfinite(d)):
                 raise FloatingPointError("coupled diffusion-reaction Newton step is not finite")
             x -= d
-            scale = np.maximum(np.abs(x).max(axis=1), 1e-300)
+            scale = np.ones(nf)
+            scale[N] = np.abs(x[N]).max()
             if np.all(np.abs(d).max(axis=1) <= tol * scale):
                 break
         else:
