@@ -99,13 +99,15 @@ def measured_fp64_ops(kernel, source_rel):
     return val if cur == sha else None
 
 
-def fp64_counter_rates(d_ms, d_n, r_ms, r_n):
+def fp64_counter_rates(d_ms, d_n, r_ms, r_n, spec):
     """Counted FP64 lane operations of the two leaves against the FP64 vector
-    peak, with this run's average launch durations."""
+    peak, with this run's average launch durations (``spec``: the reaction
+    solve is the kernel generated for the mechanism)."""
     out = {}
+    reaction = (("newton_spec", "paper_1801_01201_amd/csrc/chem_spec.cpp") if spec else
+                ("newton_kernel<9, true>", "paper_1801_01201_amd/csrc/chem.hip"))
     for kernel, src, ms, cnt in (("cg_tile_kernel<9, 1>", "paper_1801_01201_amd/csrc/cg.hip", d_ms, d_n),
-                                 ("newton_kernel<9, true>", "paper_1801_01201_amd/csrc/chem.hip",
-                                  r_ms, r_n)):
+                                 reaction + (r_ms, r_n)):
         ops = measured_fp64_ops(kernel, src)
         if ops is None or cnt == 0:
             out[kernel] = None
@@ -114,6 +116,93 @@ def fp64_counter_rates(d_ms, d_n, r_ms, r_n):
         out[kernel] = {"ops_per_launch": ops, "tflops": tf,
                        "frac_of_fp64_peak": tf / FP64_VECTOR_PEAK_TFLOPS}
     return out
+
+
+def overlap_probe():
+    """Eager steps, a pause, then graph-replayed steps of the 256x256 workload."""
+    import time
+    import torch
+    import synth
+    from paper_1801_01201_amd import native
+    from paper_1801_01201_amd.flame import Mechanism, Grid, Integrator, initial_state
+    native.lib()
+    cfg = workload()
+    mech = synth.make_mechanism(**cfg["mech"])
+    nx, ny = cfg["n"]
+    mh = Mechanism(mech)
+    g = Grid(2, [nx, ny], list(cfg["dx"]), list(cfg["u"]))
+    Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
+    state, _ = initial_state(mh, torch.tensor(Y.reshape(9, -1), device="cuda"),
+                             torch.tensor(T.ravel(), device="cuda"))
+    for graph in (False, True):
+        integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
+                           scheme=cfg["scheme"], use_graph=graph)
+        s = state.clone()
+        for _ in range(2):
+            integ.step(s, cfg["dt"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            integ.step(s, cfg["dt"])
+        torch.cuda.synchronize()
+        print(json.dumps({"execution": "graph" if graph else "eager",
+                          "ms_per_step": (time.perf_counter() - t0) / 3 * 1e3}), flush=True)
+        integ.close()
+        time.sleep(0.3)
+    g.close()
+
+
+def analyse_trace(directory):
+    """Per phase of a kernel trace (phases split at gaps of more than 100 ms):
+    busy time of the diffusion kernels (cg_*, cyclic_*, tridiagonal and
+    diffusion solves) and of the reaction kernels (newton*), and the time both
+    run at once."""
+    import csv
+    import glob
+    paths = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)
+    if not paths:
+        print(f"no kernel trace under {directory}", file=sys.stderr)
+        sys.exit(1)
+    rows = list(csv.DictReader(open(paths[0])))
+    ks = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in rows)
+
+    def merged(iv):
+        out = []
+        for a, b in sorted(iv):
+            if out and a <= out[-1][1]:
+                out[-1][1] = max(out[-1][1], b)
+            else:
+                out.append([a, b])
+        return out
+
+    def busy(iv):
+        return sum(b - a for a, b in iv)
+
+    def both(x, y):
+        tot = i = j = 0
+        while i < len(x) and j < len(y):
+            lo, hi = max(x[i][0], y[j][0]), min(x[i][1], y[j][1])
+            tot += max(0, hi - lo)
+            if x[i][1] < y[j][1]:
+                i += 1
+            else:
+                j += 1
+        return tot
+
+    phases, cur = [], [ks[0]]
+    for k in ks[1:]:
+        if k[0] - cur[-1][1] > 100_000_000:
+            phases.append(cur)
+            cur = []
+        cur.append(k)
+    phases.append(cur)
+    diff_keys = ("cg_", "cyclic", "tridiag", "diffusion")
+    for n, ph in enumerate(phases):
+        d = merged([(a, b) for a, b, k in ph if any(t in k for t in diff_keys)])
+        r = merged([(a, b) for a, b, k in ph if "newton" in k])
+        print(json.dumps({"phase": n, "kernels": len(ph), "span_ms": (ph[-1][1] - ph[0][0]) / 1e6,
+                          "diffusion_busy_ms": busy(d) / 1e6, "reaction_busy_ms": busy(r) / 1e6,
+                          "overlap_ms": both(d, r) / 1e6}))
 
 
 def workload():
@@ -241,15 +330,16 @@ def accuracy_gate(cfg, mech, mh, state0, tune):
             "nested_passes": s["nested_passes"], "oracle_seconds": wall}
 
 
-def graph_leg(integ, mh, g, cfg, state, args, tune):
-    """The same steps replayed as one captured HIP graph per step (a second
-    integrator with the tuned launch configuration); kernel timing events
-    are not recorded in graphs, so the roofline comes from the eager steps."""
+def timed_leg(mh, g, cfg, state, args, tune, use_graph):
+    """The timed steps from ``state`` (not modified) with a fresh integrator in
+    the tuned launch configuration, issued eagerly or replayed as one captured
+    HIP graph per step, without kernel timing events (those are not recorded
+    in graphs; the roofline comes from the profiled steps)."""
     import torch
     from paper_1801_01201_amd.flame import Integrator
     gi = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
-                    scheme=cfg["scheme"], use_graph=True, cg_rtol=cfg.get("cg_rtol", 1e-13),
-                    pipeline=cfg.get("pipeline", False))
+                    scheme=cfg["scheme"], use_graph=use_graph, cg_rtol=cfg.get("cg_rtol", 1e-13),
+                    serialize=args.serialize, pipeline=cfg.get("pipeline", False))
     if tune:
         gi.set_tune(tune["cg_variant"], tune["cg_blocks"], tune["cyclic"], tune["serialize"],
                     tune["cu_split"], tune["stagger"], tune.get("fused", 0))
@@ -735,7 +825,19 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device-to-device 4 times (calibrates the HBM "
                          "byte counters of rocprofv3 --pmc) and exit")
+    ap.add_argument("--overlap-probe", action="store_true",
+                    help="only run 2 + 3 eager steps, a pause, then 2 + 3 graph-replayed steps "
+                         "of the 256x256 workload (default launch configuration), for a kernel "
+                         "trace that shows the overlap of the two solves in each; then exit")
+    ap.add_argument("--analyse-trace", default=None, metavar="DIR",
+                    help="only read a rocprofv3 kernel trace (CSV) under DIR and print, per "
+                         "phase, the busy time of the diffusion and reaction kernels and "
+                         "their overlap; then exit")
     args = ap.parse_args()
+    if args.analyse_trace:
+        return analyse_trace(args.analyse_trace)
+    if args.overlap_probe:
+        return overlap_probe()
     if args.copy_calibration:
         import torch
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -786,6 +888,7 @@ def main():
     Y, T = synth.flame_2d(mech, nx, ny, *cfg["dx"])
     state, _ = initial_state(mh, torch.tensor(Y.reshape(9, -1), device="cuda"),
                              torch.tensor(T.ravel(), device="cuda"))
+    state_init = state.clone()
     integ = Integrator(mh, g, n_nodes=cfg["n_nodes"], sweeps=cfg["sweeps"], nu=cfg["nu"],
                        scheme=cfg["scheme"], serialize=args.serialize, profile=True,
                        nu_tol=args.nu_tol, cg_rtol=args.cg_rtol, pipeline=args.pipeline)
@@ -829,11 +932,29 @@ def main():
         passes = None
         updates = n * M * cfg["nu"] * cfg["sweeps"] * args.steps
     value = updates / elapsed
+    profiled_ms = elapsed / args.steps * 1e3
     newton_per_cell = stats["newton_iters"] / max(1, stats["newton_solves"])
     newton_sweeps = newton_sweep_stats(integ, cfg["sweeps"])
     cg_per_solve = stats["cg_iters"] / max(1, stats["cg_solves"])
-    graph = None if (args.no_graph or args.nu_tol > 0) else graph_leg(integ, mh, g, cfg, state,
-                                                                      args, tune)
+    variant = integ.tune()["cg_variant"]
+    # the eager integrator is closed before the graph leg and the gate build
+    # their own: its streams would otherwise share the hardware queues with
+    # theirs
+    integ.close()
+    # the same steps without timing events, issued eagerly and replayed as
+    # graphs; the faster of the two is the measurement (fixed passes only:
+    # adaptive passes read the host between passes)
+    legs = {}
+    if args.nu_tol <= 0:
+        legs["eager"] = timed_leg(mh, g, cfg, state_init, args, tune, False)
+        if not args.no_graph:
+            legs["graph"] = timed_leg(mh, g, cfg, state_init, args, tune, True)
+    execution = "eager_profiled"
+    if legs:
+        execution = min(legs, key=lambda k: legs[k]["ms_per_step"])
+        value = legs[execution]["value"]
+        elapsed = legs[execution]["ms_per_step"] * args.steps * 1e-3
+    graph = legs.get("graph")
 
     # roofline of the dominant kernel
     d_ms, d_n = stats["diffusion_kernel_ms"], stats["diffusion_kernel_launches"]
@@ -849,7 +970,6 @@ def main():
                     101: "cg_tile_kernel<9,1> (32x16 tiles, 1 local preconditioner sweep)",
                     102: "cg_tile_kernel<9,2> (32x16 tiles, 2 local preconditioner sweeps)",
                     103: "cg_tile_kernel<9,3> (32x16 tiles, 3 local preconditioner sweeps)"}
-        variant = integ.tune()["cg_variant"]
         roof = {"kernel": cg_names.get(variant, str(variant)) + ": batched pipelined PCG, "
                           "implicit diffusion of 9 fields",
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -869,8 +989,11 @@ def main():
                            "eliminated)"), "bound": "alu",
                 "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                "traffic": measured_traffic("pmc_newton_kernel_flame2d_256.md",
-                                            "paper_1801_01201_amd/csrc/chem.hip"),
+                "traffic": (measured_traffic("pmc_newton_spec_flame2d_256.md",
+                                             "paper_1801_01201_amd/csrc/chem_spec.cpp")
+                            if native.misdc_mech_specialized(mh.handle)[0] else
+                            measured_traffic("pmc_newton_kernel_flame2d_256.md",
+                                             "paper_1801_01201_amd/csrc/chem.hip")),
                 "avg_launch_ms": avg_s * 1e3, "launches": r_n}
     # the reaction solve's own roofline, whichever kernel dominates: FP64 work
     # against the vector peak, and its algorithmic HBM bytes against 8 TB/s
@@ -891,10 +1014,9 @@ def main():
                     if spec_ok else None)}
     other = {"diffusion_solve_ms_per_launch": d_ms / max(1, d_n),
              "newton_ms_per_launch": r_ms / max(1, r_n),
-             "diffusion_solve_share_of_step": d_ms / (elapsed * 1e3),
-             "newton_share_of_step": r_ms / (elapsed * 1e3)}
+             "diffusion_solve_share_of_step": d_ms / (profiled_ms * args.steps),
+             "newton_share_of_step": r_ms / (profiled_ms * args.steps)}
     gate = None if args.no_gate else accuracy_gate(cfg, mech, mh, state0, tune)
-    integ.close()
     g.close()
     line = {
         "metric": METRIC, "value": value, "unit": "cell-node updates/s", "n_gpus": 1,
@@ -920,9 +1042,13 @@ def main():
         "cell_node_updates_per_step_incl_node0": n * (M + 1) * cfg["nu"] * cfg["sweeps"],
         "roofline": roof,
         "roofline_reaction_solve": roof_r,
-        "fp64_counters": fp64_counter_rates(d_ms, d_n, r_ms, r_n),
+        "fp64_counters": fp64_counter_rates(d_ms, d_n, r_ms, r_n, spec_ok),
         "kernel_split": other,
         "autotune": tune,
+        "execution": execution,
+        "eager_profiled_ms_per_step": profiled_ms,
+        "eager_ms_per_step": legs["eager"]["ms_per_step"] if "eager" in legs else None,
+        "graph_ms_per_step": graph["ms_per_step"] if graph else None,
         "graph_replay": graph,
         "cpu_baseline": cpu,
         "accuracy_gate": gate,
@@ -930,7 +1056,7 @@ def main():
     }
     # a run with unconverged solves or a failed gate is not a measurement
     line["valid"] = bool(stats["converged"] and (gate is None or gate["passed"])
-                         and (graph is None or graph["converged"]))
+                         and all(leg["converged"] for leg in legs.values()))
     print(json.dumps(line), flush=True)
     if not line["valid"]:
         print("[bench] INVALID: unconverged solves or failed accuracy gate", file=sys.stderr)

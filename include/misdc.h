@@ -16,7 +16,15 @@
  *                        reaction step at node m runs on another
  *                        (eqs. update_equation_amisdcq_discrete_form_D and
  *                        _R_alt, lag initialisation initial_lagged_values_*,
- *                        nu nested iterations, algorithm steps S1-S7).
+ *                        nu nested iterations, algorithm steps S1-S7);
+ *   MISDC_SCHEME_IMEXQ   the comparison scheme IMEXQ (section 3.2.2, the
+ *                        scheme whose amplification factor R'_nu the
+ *                        concurrent scheme is measured against): advection
+ *                        explicit, diffusion (coefficients lagged at sweep
+ *                        k) and reaction implicit together in one coupled
+ *                        solve of the whole grid per node (Newton's method,
+ *                        BiCGStab with each cell's own block as
+ *                        preconditioner).  Single grids of 9 species only.
  *
  * Conventions
  *  - Every function returns an int status: MISDC_OK (0) or a negative code.
@@ -57,7 +65,8 @@ enum {
     MISDC_ESTATE = -6       /* call out of order (a sweep without an open step, ...) */
 };
 
-enum { MISDC_SCHEME_MISDC = 0, MISDC_SCHEME_MISDCQ = 1, MISDC_SCHEME_CISDCQ = 2 };
+enum { MISDC_SCHEME_MISDC = 0, MISDC_SCHEME_MISDCQ = 1, MISDC_SCHEME_CISDCQ = 2,
+       MISDC_SCHEME_IMEXQ = 3 };
 enum { MISDC_QE_CUMULATIVE = 0, MISDC_QE_LITERAL = 1 };
 enum { MISDC_QI_LU = 0, MISDC_QI_BE = 1 };
 
@@ -333,6 +342,21 @@ typedef struct {
                             misdc_set_streams, a CU split, the stagger or a
                             learned guess (MISDC_EINVAL / MISDC_EUNSUPPORTED);
                             the diffusion solve must fit half the CUs */
+    /* MISDC_SCHEME_IMEXQ's coupled solve of node m+1,
+     *   phi - c (FD_lag(phi) + FR(phi)) = rhs,
+     * from phi^{m+1,(k)}: Newton's method stops once every mass fraction's
+     * update is at most imexq_tol and the enthalpy's at most imexq_tol times
+     * its largest magnitude (<= 0: 1e-13), at most imexq_maxit iterations
+     * (<= 0: 30); each Newton system
+     * is solved by BiCGStab on the field-scaled unknowns to a relative
+     * residual of imexq_krylov_rtol (<= 0: 1e-9), at most
+     * imexq_krylov_maxit iterations (<= 0: 400).  The host reads every
+     * scalar of these iterations, so a step synchronises its streams many
+     * times and use_graph must be 0 (MISDC_EINVAL). */
+    double imexq_tol;
+    int32_t imexq_maxit;
+    double imexq_krylov_rtol;
+    int32_t imexq_krylov_maxit;
 } misdc_opts;
 
 /* Fills the defaults: 5 nodes, 6 sweeps, nu 1, CISDCQ, cumulative QE. */
@@ -499,6 +523,17 @@ typedef struct {
      * iterations whose diagonal pivots failed the threshold test and were
      * factored again with partial pivoting */
     int64_t newton_pivot_retries;
+    /* MISDC_SCHEME_IMEXQ (last step): coupled solves, their Newton
+     * iterations, solves that reached imexq_maxit (counted in newton_failed
+     * too, so that the step reports MISDC_ENOTCONV), BiCGStab iterations
+     * (sum and largest per Newton system) and Newton systems whose
+     * BiCGStab stopped short of imexq_krylov_rtol */
+    int64_t imexq_solves;
+    int64_t imexq_newton_iters;
+    int64_t imexq_failed;
+    int64_t imexq_krylov_iters;
+    int64_t imexq_krylov_max;
+    int64_t imexq_krylov_failed;
 } misdc_stats;
 
 /* Outcomes of the last step's cell-node Newton solves in sweep k (0 <= k <

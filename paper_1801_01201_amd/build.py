@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmisdc.so")
-SOURCES = ["tables.cpp", "chem.hip", "chem_spec.cpp", "chem_wave.hip", "transport.hip", "cg.hip", "mlp.hip", "ensemble.hip", "integrator.hip"]
+SOURCES = ["tables.cpp", "chem.hip", "chem_spec.cpp", "chem_wave.hip", "transport.hip", "cg.hip", "mlp.hip", "ensemble.hip", "coupled.hip", "integrator.hip"]
 ARCH = os.environ.get("MISDC_OFFLOAD_ARCH", "gfx950")
 
 

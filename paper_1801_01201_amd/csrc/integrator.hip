@@ -168,6 +168,10 @@ struct misdc_integ_s {
     // (misdc_tune.fused) over the diffusion systems (field << 16 | flame, the
     // longest flames first) and the cells' reaction problems
     bool fused = false;
+    // MISDC_SCHEME_IMEXQ: the coupled solve's work space and the last step's
+    // counters
+    CoupledWork cw;
+    CoupledStats cst;
     int* d_items = nullptr;
     int nD_items = 0;
     unsigned* stage_counters = nullptr;
@@ -263,8 +267,13 @@ int check_opts(const misdc_opts* o) {
         return fail(MISDC_EINVAL, "n_nodes must be in [2, %d]", MAX_NODES);
     if (o->n_sweeps < 1 || o->n_sweeps > 64)
         return fail(MISDC_EINVAL, "n_sweeps must be in [1, 64]");
-    if (o->scheme < MISDC_SCHEME_MISDC || o->scheme > MISDC_SCHEME_CISDCQ)
+    if (o->scheme < MISDC_SCHEME_MISDC || o->scheme > MISDC_SCHEME_IMEXQ)
         return fail(MISDC_EINVAL, "unknown scheme %d", o->scheme);
+    if (o->scheme == MISDC_SCHEME_IMEXQ && o->use_graph)
+        return fail(MISDC_EINVAL, "IMEXQ's coupled solve is driven by the host and cannot be "
+                                  "replayed as a graph");
+    if (!(o->imexq_tol == o->imexq_tol) || !(o->imexq_krylov_rtol == o->imexq_krylov_rtol))
+        return fail(MISDC_EINVAL, "IMEXQ tolerance is NaN");
     if (o->nu < 1 || o->nu > 16) return fail(MISDC_EINVAL, "nu must be in [1, 16]");
     if (o->scheme != MISDC_SCHEME_CISDCQ && o->nu != 1)
         return fail(MISDC_EINVAL, "nu > 1 needs the concurrent scheme");
@@ -638,6 +647,44 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     return rc;
 }
 
+// ---- IMEXQ's coupled task at node p (writes lev[1][p]) ----
+// Right-hand side C^p + dt sum_{j<=m} [QE_{p,j} FA_j + QI_{p,j} (FD_j + FR_j)]
+// at sweep k+1, the guess phi^{p,(k)}, the coupled solve with diffusion
+// coefficients lagged at phi^{p,(k)}, then FA, FD, FR and T at the result.
+// Everything runs on the diffusion stream.
+int imexq_task(misdc_integ_s* I, int p, double dt) {
+    const int N = I->N, NF = I->NF;
+    const int64_t n = I->n;
+    const Tables& t = I->tab;
+    const int m = p - 1;
+    auto& L0 = I->lev[0];
+    auto& Lc = I->lev[1];
+    LC b(NF, n, dt, I->dtc);
+    const int o = b.out(I->rD);
+    b.add(o, 1.0, I->C[p], NF);
+    for (int j = 1; j <= m; ++j) {
+        b.addS(o, t.QE[p - 1][j - 1], Lc[j].FA, NF);
+        b.addS(o, t.QI[p - 1][j - 1], Lc[j].FD, NF);
+        b.addS(o, t.QI[p - 1][j - 1], Lc[j].FR, N);
+    }
+    const int og = b.out(Lc[p].phi);
+    b.add(og, 1.0, L0[p].phi, NF);
+    int rc = launch_lincomb(b.lc, I->sD);
+    if (rc) return rc;
+    const misdc_opts& op = I->opt;
+    const double tol = op.imexq_tol > 0 ? op.imexq_tol : 1e-13;
+    const int maxit = op.imexq_maxit > 0 ? op.imexq_maxit : 30;
+    const double krtol = op.imexq_krylov_rtol > 0 ? op.imexq_krylov_rtol : 1e-9;
+    const int kmaxit = op.imexq_krylov_maxit > 0 ? op.imexq_krylov_maxit : 400;
+    rc = coupled_solve(*I->mech, *I->grid, I->cw, dt * t.QI[p - 1][p - 1], L0[p].T, I->rD,
+                       Lc[p].phi, tol, maxit, krtol, kmaxit, I->cst, I->sD);
+    if (rc) return rc;
+    NodeBuf& out = Lc[p];
+    if ((rc = launch_temperature(*I->mech, n, out.phi, out.phi + (size_t)N * n, out.T, I->sD)))
+        return rc;
+    return eval_ops(I, out, I->thD, I->sD, true);
+}
+
 // sweep-start constants (all terms of sweep k)
 int sweep_constants(misdc_integ_s* I, double dt) {
     const int M = I->M, N = I->N, NF = I->NF;
@@ -665,7 +712,8 @@ int sweep_constants(misdc_integ_s* I, double dt) {
                 b.addS(o, t.Q[p - 1][j], L0[j].FR, N);
             }
             for (int j = 1; j <= p - 1; ++j) b.addS(o, -t.QE[p - 1][j - 1], L0[j].FA, NF);
-            const bool with_R = (I->opt.scheme == MISDC_SCHEME_CISDCQ);
+            const bool with_R = (I->opt.scheme == MISDC_SCHEME_CISDCQ ||
+                                  I->opt.scheme == MISDC_SCHEME_IMEXQ);
             for (int j = 1; j <= p; ++j) {
                 b.addS(o, -t.QI[p - 1][j - 1], L0[j].FD, NF);
                 if (with_R) b.addS(o, -t.QI[p - 1][j - 1], L0[j].FR, N);
@@ -685,7 +733,7 @@ int sweep_constants(misdc_integ_s* I, double dt) {
     // in as its weights), initial guess and face coefficients in the same
     // pass: one launch fewer between the sweeps on the critical path
     I->d1_ready = false;
-    if (M + 2 <= LC_MAX_OUT) {
+    if (M + 2 <= LC_MAX_OUT && I->opt.scheme != MISDC_SCHEME_IMEXQ) {
         LC f = b;
         f.fold = true;
         double cf = 0.0;
@@ -811,7 +859,13 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
     }
     rc = sweep_constants(I, dt);
     if (rc) return rc;
-    if (I->opt.scheme != MISDC_SCHEME_CISDCQ) {
+    if (I->opt.scheme == MISDC_SCHEME_IMEXQ) {
+        for (int p = 1; p <= M; ++p)
+            if ((rc = imexq_task(I, p, dt))) return rc;
+        // the sweep's end is ordered on the reaction stream
+        MISDC_HIP(hipEventRecord(I->R_ev(1, M), I->sD));
+        MISDC_HIP(hipStreamWaitEvent(I->sR, I->R_ev(1, M), 0));
+    } else if (I->opt.scheme != MISDC_SCHEME_CISDCQ) {
         for (int p = 1; p <= M; ++p) {
             if (p > 1) MISDC_HIP(hipStreamWaitEvent(I->sD, I->R_ev(1, p - 1), 0));
             rc = diffusion_task(I, 0, p, dt);
@@ -940,6 +994,10 @@ int convergence_status(misdc_integ_s* I) {
                     "unconverged solves in the last step: %llu cell-node Newton solves, "
                     "%d diffusion solves at their iteration limit, %d barrier timeouts",
                     failed, cg[2], cg[4]);
+    if (I->cst.newton_failed > 0)
+        return fail(MISDC_ENOTCONV, "unconverged solves in the last step: %lld coupled "
+                                    "diffusion-reaction solves (IMEXQ)",
+                    (long long)I->cst.newton_failed);
     return MISDC_OK;
 }
 
@@ -998,6 +1056,7 @@ int issue_begin(misdc_integ_s* I, double* state, double dt, const double* dtf, i
                                         NEWTON_HIST_SETS * NEWTON_HIST_BINS, I->sD)))
         return rc;
     if ((rc = launch_zero(I->cgstats, 8 * sizeof(int32_t), I->sD))) return rc;
+    I->cst = CoupledStats();
     if (I->pipe)
         for (auto& d : I->pd_lane)
             if ((rc = launch_zero(d.cgstats, 8 * sizeof(int32_t), I->sD))) return rc;
@@ -1773,6 +1832,8 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) return bail(fail(MISDC_EDEVICE, "events: %s", hipGetErrorString(e)));
     if (opts->pipeline && (rc = create_lanes(I))) return bail(rc);
+    if (opts->scheme == MISDC_SCHEME_IMEXQ && (rc = coupled_work_alloc(I->cw, mech->m, grid->g)))
+        return bail(rc);
     if (grid->g.n_flames > 0 && grid->g.n_flames <= 0xffff) {
         // the fused stages' work list: every diffused field of every flame,
         // the longest flames first (their systems take longest)
@@ -1832,6 +1893,7 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (I->sRm) (void)hipStreamDestroy(I->sRm);
     if (I->sD_own) (void)hipStreamDestroy(I->sD_own);
     diffusion_work_free(I->dw);
+    coupled_work_free(I->cw);
     if (I->pinc_host) (void)hipHostFree(I->pinc_host);
     for (void* p : I->allocs) (void)hipFree(p);
     delete I;
@@ -1943,6 +2005,8 @@ int misdc_integ_set_guess(misdc_integ_t I, misdc_mlp_t mlp, int sweeps) {
                                         "time; pipelined passes run several");
     if (I->fused && mlp)
         return fail(MISDC_EUNSUPPORTED, "fused stages run the plain Newton guess");
+    if (I->opt.scheme == MISDC_SCHEME_IMEXQ && mlp)
+        return fail(MISDC_EUNSUPPORTED, "IMEXQ has no per-cell reaction solve to guess for");
     int rc;
     if ((rc = sync_streams(I))) return rc;
     if (mlp) {
@@ -1963,6 +2027,8 @@ int misdc_integ_record(misdc_integ_t I, double* dev_buf, int64_t max_tasks) {
     if (I->open) return fail(MISDC_ESTATE, "a step opened by misdc_step_begin is not ended");
     if (I->fused && max_tasks > 0)
         return fail(MISDC_EUNSUPPORTED, "fused stages do not record reaction problems");
+    if (I->opt.scheme == MISDC_SCHEME_IMEXQ && max_tasks > 0)
+        return fail(MISDC_EUNSUPPORTED, "IMEXQ has no per-cell reaction problems to record");
     int rc;
     if ((rc = sync_streams(I))) return rc;
     I->rec_buf = max_tasks > 0 ? dev_buf : nullptr;
@@ -2112,6 +2178,15 @@ int misdc_set_tune(misdc_integ_t I, const misdc_tune* t) {
     I->cu_split = t->serialize ? 0 : t->cu_split;
     I->stagger = t->serialize ? 0 : t->stagger;
     I->sR = t->serialize ? I->sD : (I->cu_split ? I->sRm : I->sR2);
+    if (!I->cu_split && I->sRm) {
+        // a CU-masked stream holds a hardware queue of its own (the mask is a
+        // queue property) even while idle; with few queues per process an
+        // idle one can make the streams in use, or a replayed graph's, share
+        // a queue and run in order, so it is released when not in use
+        (void)hipStreamDestroy(I->sRm);
+        I->sRm = nullptr;
+        I->sRm_split = 0;
+    }
     drop_graph(I);
     return MISDC_OK;
 }
@@ -2252,6 +2327,13 @@ int misdc_get_stats(misdc_integ_t I, misdc_stats* st) {
     st->newton_lu_solves = (int64_t)ns[4];
     st->newton_lu_fallbacks = (int64_t)ns[5];
     st->newton_guess_learned = (int64_t)ns[6];
+    st->imexq_solves = I->cst.solves;
+    st->imexq_newton_iters = I->cst.newton_iters;
+    st->imexq_failed = I->cst.newton_failed;
+    st->imexq_krylov_iters = I->cst.krylov_iters;
+    st->imexq_krylov_max = I->cst.krylov_max;
+    st->imexq_krylov_failed = I->cst.krylov_failed;
+    st->newton_failed += I->cst.newton_failed;
     for (int k = 0; k < I->last_sweeps && k < 64; ++k) st->nested_passes[k] = I->passes[k];
     st->cg_iters = cg[0];
     st->cg_max = cg[1];

@@ -287,6 +287,28 @@ struct EnsembleStage {
 };
 int launch_ensemble_stage(const Mech& m, const Grid& g, const EnsembleStage& st, hipStream_t s);
 
+// ---- the coupled implicit diffusion-reaction solve of IMEXQ (9 species) -----
+struct CoupledWork {
+    int64_t n = 0;
+    double *G = nullptr, *d = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr,
+           *y = nullptr, *s = nullptr, *t = nullptr, *zz = nullptr;   // NF fields each
+    double* JR = nullptr;        // reaction Jacobian w.r.t. (Y, h): N x NF entries per cell
+    double *th = nullptr, *Kx = nullptr, *Ky = nullptr;
+    double* sigma = nullptr;     // field scales (NF)
+    double* partial = nullptr;   // per-block reduction partials
+};
+struct CoupledStats {
+    int64_t solves = 0, newton_iters = 0, newton_failed = 0;
+    int64_t krylov_iters = 0, krylov_max = 0, krylov_failed = 0;
+};
+int coupled_work_alloc(CoupledWork& w, const Mech& m, const Grid& g);
+void coupled_work_free(CoupledWork& w);
+// x (NF fields, holding the initial guess) <- the solution of
+// x - c (FD_lag(x) + FR(x)) = rhs; synchronises s while it iterates
+int coupled_solve(const Mech& m, const Grid& g, CoupledWork& w, double c, const double* T_lag,
+                  const double* rhs, double* x, double newton_tol, int newton_maxit,
+                  double lin_rtol, int lin_maxit, CoupledStats& st, hipStream_t s);
+
 // ---- learned Newton guess (dense network on the matrix cores) ----------------
 struct MlpImpl;
 int mlp_create(int n_in, int n_hidden, int n_out, int prec, MlpImpl** out);

@@ -21,7 +21,7 @@ MISDC_EDEVICE = -3
 MISDC_ENOTCONV = -4
 MISDC_EUNSUPPORTED = -5
 MISDC_ESTATE = -6
-SCHEME = {"misdc": 0, "misdcq": 1, "cisdcq": 2}
+SCHEME = {"misdc": 0, "misdcq": 1, "cisdcq": 2, "imexq": 3}
 QE = {"cumulative": 0, "literal": 1}
 QI = {"lu": 0, "be": 1}
 
@@ -71,7 +71,8 @@ class misdc_opts(C.Structure):
                 ("scheme", C.c_int32), ("qe_mode", C.c_int32), ("serialize", C.c_int32),
                 ("newton", misdc_newton_opts), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
                 ("profile", C.c_int32), ("use_graph", C.c_int32), ("nu_tol", C.c_double),
-                ("pipeline", C.c_int32)]
+                ("pipeline", C.c_int32), ("imexq_tol", C.c_double), ("imexq_maxit", C.c_int32),
+                ("imexq_krylov_rtol", C.c_double), ("imexq_krylov_maxit", C.c_int32)]
 
 
 class misdc_tune(C.Structure):
@@ -92,7 +93,10 @@ class misdc_stats(C.Structure):
                 ("diffusion_kernel_launches", C.c_int64), ("newton_kernel_ms", C.c_double),
                 ("newton_kernel_launches", C.c_int64), ("newton_lu_solves", C.c_int64),
                 ("newton_lu_fallbacks", C.c_int64), ("newton_guess_learned", C.c_int64),
-                ("nested_passes", C.c_int32 * 64), ("newton_pivot_retries", C.c_int64)]
+                ("nested_passes", C.c_int32 * 64), ("newton_pivot_retries", C.c_int64),
+                ("imexq_solves", C.c_int64), ("imexq_newton_iters", C.c_int64),
+                ("imexq_failed", C.c_int64), ("imexq_krylov_iters", C.c_int64),
+                ("imexq_krylov_max", C.c_int64), ("imexq_krylov_failed", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_
@@ -523,7 +527,8 @@ def misdc_integ_recorded(integ):
 
 def make_opts(n_nodes=5, sweeps=6, nu=1, scheme="cisdcq", qe="cumulative", serialize=False,
               cg_rtol=1e-13, cg_maxit=500, newton=None, profile=False, use_graph=False,
-              nu_tol=0.0, pipeline=False):
+              nu_tol=0.0, pipeline=False, imexq_tol=0.0, imexq_maxit=0, imexq_krylov_rtol=0.0,
+              imexq_krylov_maxit=0):
     o = misdc_opts_default()
     o.n_nodes = n_nodes
     o.n_sweeps = sweeps
@@ -537,6 +542,10 @@ def make_opts(n_nodes=5, sweeps=6, nu=1, scheme="cisdcq", qe="cumulative", seria
     o.use_graph = int(bool(use_graph))
     o.nu_tol = float(nu_tol)
     o.pipeline = int(bool(pipeline))
+    o.imexq_tol = float(imexq_tol)
+    o.imexq_maxit = int(imexq_maxit)
+    o.imexq_krylov_rtol = float(imexq_krylov_rtol)
+    o.imexq_krylov_maxit = int(imexq_krylov_maxit)
     if newton is not None:
         o.newton = newton
     return o

@@ -235,6 +235,9 @@ STEP_CASES = [
     ("flame2d_cisdcq1", 2, (20, 24), (0.01, 0.01), (100.0, 0.0), 5, 6, 1, "cisdcq", 1),
     ("flame2d_cisdcq2", 2, (29, 37), (0.01, 0.01), (100.0, -30.0), 5, 4, 1, "cisdcq", 2),
     ("flame2d_cisdcq1_3nodes", 2, (20, 24), (0.01, 0.01), (100.0, 0.0), 3, 4, 2, "cisdcq", 1),
+    # the comparison scheme IMEXQ: one coupled diffusion-reaction solve per node
+    ("flame1d_64_imexq", 1, (64,), (0.01,), (100.0,), 3, 4, 3, "imexq", 1),
+    ("flame2d_imexq", 2, (20, 24), (0.01, 0.01), (100.0, -30.0), 5, 4, 1, "imexq", 1),
 ]
 
 
@@ -255,8 +258,44 @@ def test_step_parity(nat, mech9, mh, case, tune=None):
     out, stats = _run_gpu(nat, mh, (dim, n, list(dx), list(u)), st, dt, steps, tune=tune,
                           n_nodes=n_nodes, sweeps=sweeps, nu=nu, scheme=scheme)
     assert stats["newton_failed"] == 0 and stats["cg_failed"] == 0 and stats["converged"]
+    if scheme == "imexq":
+        # one coupled solve per node and sweep, each converged; the last step's
+        # counters
+        assert stats["imexq_solves"] == (n_nodes - 1) * sweeps
+        assert stats["imexq_failed"] == 0 and stats["imexq_krylov_failed"] == 0
+        assert stats["imexq_newton_iters"] >= stats["imexq_solves"]
+        assert stats["newton_solves"] == 0 and stats["cg_solves"] == 0
     err = field_err(out, phi.reshape(10, -1))
     assert err <= TOL, err
+
+
+def test_imexq_refusals(nat, mech9, mh):
+    """IMEXQ is driven by the host (no graph), built for single grids of 9
+    species, and has no per-cell reaction problems for a learned guess or
+    the recorder."""
+    from paper_1801_01201_amd.flame import Grid, Integrator, GuessNet
+    g = Grid(1, [32], [0.01], [100.0])
+    with pytest.raises(nat.MisdcError):
+        Integrator(mh, g, scheme="imexq", use_graph=True)
+    with pytest.raises(nat.MisdcError):
+        Integrator(mh, g, scheme="imexq", nu=2)
+    ge = Grid(ensemble=([32, 40], [0.01, 0.01], [100.0, 50.0]))
+    with pytest.raises(nat.MisdcError) as e:
+        Integrator(mh, ge, scheme="imexq")
+    assert e.value.code == nat.MISDC_EUNSUPPORTED
+    ge.close()
+    integ = Integrator(mh, g, scheme="imexq", n_nodes=3, sweeps=1)
+    buf = torch.zeros(4 * 20 * 32, dtype=torch.float64, device="cuda")
+    with pytest.raises(nat.MisdcError) as e:
+        nat.misdc_integ_record(integ.handle, buf, 4)
+    assert e.value.code == nat.MISDC_EUNSUPPORTED
+    net = GuessNet(9)
+    with pytest.raises(nat.MisdcError) as e:
+        nat.misdc_integ_set_guess(integ.handle, net.handle, 0)
+    assert e.value.code == nat.MISDC_EUNSUPPORTED
+    net.close()
+    integ.close()
+    g.close()
 
 
 def _histogram(it):
