@@ -307,6 +307,15 @@ __device__ __forceinline__ void wave_put(double v, double* red, int slot) {
     if ((threadIdx.x & 63) == 0) red[slot * (BS / 64) + (threadIdx.x >> 6)] = v;
 }
 
+// wave_put of K slots at once (value(s): this lane's value of slot s), by
+// one batched reduction whose slot-s total lands in lanes 2s and 2s+1
+template <int BS, int K, class F>
+__device__ __forceinline__ void wave_put_slots(F value, double* red) {
+    const double v = wave_sum_slots<K>(value);
+    const int lane = threadIdx.x & 63;
+    if ((lane & 1) == 0 && (lane >> 1) < K) red[(lane >> 1) * (BS / 64) + (threadIdx.x >> 6)] = v;
+}
+
 // Register-resident pipelined preconditioned CG (the single-reduction
 // recurrences of Ghysels & Vanroose).  Every thread owns CPT cells for the
 // whole solve and keeps all vectors of the NFD fields in registers; the only
@@ -894,14 +903,21 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
 #pragma unroll
         for (int d = 0; d < NFD; ++d) m[d] = 0.0;
         tile_precond<NFD, KSW>(w, m, dinv, cf, ke, kw, kn, ks, he, hw, hn, hs, zt, s_active);
+        unsigned live = 0u;                           // converged fields: nothing to reduce
 #pragma unroll
         for (int d = 0; d < NFD; ++d) {
-            if (!s_active[d]) continue;               // converged: nothing to reduce
+            if (!s_active[d]) continue;
+            live |= 1u << d;
             mt[d * BS + threadIdx.x] = m[d];
-            wave_put<BS>(own ? r[d] * u[d] : 0.0, red, 3 * d + 0);
-            wave_put<BS>(own ? w[d] * u[d] : 0.0, red, 3 * d + 1);
-            wave_put<BS>(own ? r[d] * r[d] : 0.0, red, 3 * d + 2);
         }
+        // the 3 NFD partial sums of the wavefront in one batched reduction
+        wave_put_slots<BS, NS>(
+            [&](int sl) {
+                const int d = sl / 3, j = sl - 3 * d;
+                if (!own || !(live & (1u << d))) return 0.0;
+                return (j == 1 ? w[d] : r[d]) * (j == 2 ? r[d] : u[d]);
+            },
+            red);
         grid_allreduce_coeffs<BS, NFD, HPT>(a, kb++, it, red, stage, mt, elds, eb, hsrc, halo, s_bb,
                                             s_gprev, s_aprev, s_alpha, s_beta, s_active);
         int any = 0;
