@@ -569,18 +569,37 @@ __device__ __forceinline__ void grid_sync_direct(unsigned* bar, unsigned nb, uns
     __syncthreads();
 }
 
-// Reduction of the partial sums (r,u), (w,u), (r,r) of every field over
-// the blocks, fused with the recurrence coefficients: the wavefront that
-// reduces a field's three sums computes its coefficients.  A field whose
-// residual has met the tolerance stays inactive (its sums are no longer
-// formed).  The partials and the tile's edges of m (copied from the tile
-// ``mt`` in LDS: elds holds the LDS index of each of this thread's edge
-// slots, -1 for none) travel through agent-scope atomic stores and loads, so
-// the barrier needs no cache write-back or invalidation.  After it every
-// thread issues all of its loads at once -- its share of the blocks'
-// partials (into ``stage``) and of the tile's halo of m (hsrc: offsets into
-// the edge half ``eb``, -1 for none; into ``halo``) -- so the exchange costs
-// one memory latency.
+// The blocks' partial sums of one exchange, slot-major: thread (slot t =
+// tid mod 32, group g = tid / 32) loads slot t of blocks g, g + G, g + 2G,
+// ... (G = 16 groups of the workgroup) and adds them in that order; the
+// group sums go to stage[g * 32 + t] (4 KB of LDS for every block count),
+// which slot_total adds in group order.  Loads are issued together with the
+// caller's halo loads, so the exchange costs one memory latency.
+constexpr int TILE_GROUPS = TILE_BS / 32;
+constexpr int TILE_BPG = (TILE_NB + TILE_GROUPS - 1) / TILE_GROUPS;
+__device__ __forceinline__ double group_partial(const double* part, unsigned nb, int nslots) {
+    const int t = threadIdx.x & 31, g = threadIdx.x >> 5;
+    double pv[TILE_BPG];
+#pragma unroll
+    for (int j = 0; j < TILE_BPG; ++j) {
+        const unsigned b = (unsigned)(g + TILE_GROUPS * j);
+        pv[j] = (t < nslots && b < nb)
+                    ? __hip_atomic_load(&part[b * (CG_MAX_FIELDS * 4) + (unsigned)t],
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    : 0.0;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < TILE_BPG; ++j) acc += pv[j];
+    return acc;
+}
+__device__ __forceinline__ double slot_total(const double* stage, int t) {
+    double v = 0.0;
+#pragma unroll
+    for (int g = 0; g < TILE_GROUPS; ++g) v += stage[g * 32 + t];
+    return v;
+}
+
 // Exchange 0 of the tiled kernel (its prologue): the blocks' partial sums of
 // NFD fields and the tile's edges of mt (u of every field) travel through
 // agent-scope atomic stores and loads around the barrier without cache
@@ -591,8 +610,8 @@ __device__ __forceinline__ void grid_exchange_first(const CGArgs& a, const doubl
                                                     double* stage, double* tot, const double* mt,
                                                     const int (&elds)[HPT], const int (&hsrc)[HPT],
                                                     double* halo) {
+    static_assert(BS == TILE_BS, "slot-major partials: 16 groups of 32 threads");
     constexpr int NW = BS / 64;
-    constexpr int PPT = (TILE_NB * NFD + BS - 1) / BS;
     const unsigned nb = gridDim.x;
     double* part = a.partial;                                // parity of exchange 0
     double* eb = a.edge;                                     // edge half of exchange 0
@@ -611,43 +630,36 @@ __device__ __forceinline__ void grid_exchange_first(const CGArgs& a, const doubl
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     grid_sync_direct(a.bar, nb, 0u, a.info);
-    const int total = (int)nb * NFD;
-    double pv[PPT], hv[HPT];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const int e = threadIdx.x + j * BS;
-        const int b = e / NFD, t = e - b * NFD;
-        pv[j] = e < total ? __hip_atomic_load(&part[(unsigned)(b * (CG_MAX_FIELDS * 4) + t)],
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                          : 0.0;
-    }
+    double hv[HPT];
 #pragma unroll
     for (int j = 0; j < HPT; ++j)
         hv[j] = hsrc[j] >= 0
                     ? __hip_atomic_load(&eb[(unsigned)hsrc[j]], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT)
                     : 0.0;
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const int e = threadIdx.x + j * BS;
-        if (e < total) stage[e] = pv[j];
-    }
+    stage[threadIdx.x] = group_partial(part, nb, NFD);
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
         const int e = threadIdx.x + j * BS;
         if (e < NFD * TILE_HALO) halo[e] = hv[j];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int t = wave; t < NFD; t += NW) {
-        double v = 0.0;
-        for (unsigned b = lane; b < nb; b += 64) v += stage[b * NFD + t];
-        v = wave_sum(v);
-        if (lane == 0) tot[t] = v;
-    }
+    if (threadIdx.x < NFD) tot[threadIdx.x] = slot_total(stage, threadIdx.x);
     __syncthreads();
 }
 
+// Reduction of the partial sums (r,u), (w,u), (r,r) of every field over
+// the blocks, fused with the recurrence coefficients: the wavefront that
+// reduces a field's three sums computes its coefficients.  A field whose
+// residual has met the tolerance stays inactive (its sums are no longer
+// formed).  The partials and the tile's edges of m (copied from the tile
+// ``mt`` in LDS: elds holds the LDS index of each of this thread's edge
+// slots, -1 for none) travel through agent-scope atomic stores and loads, so
+// the barrier needs no cache write-back or invalidation.  After it every
+// thread issues all of its loads at once -- its share of the blocks'
+// partials (group sums into ``stage``) and of the tile's halo of m (hsrc:
+// offsets into the edge half ``eb``, -1 for none; into ``halo``) -- so the
+// exchange costs one memory latency.
 template <int BS, int NFD, int HPT>
 __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned k, int it,
                                                       const double* red, double* stage,
@@ -657,8 +669,8 @@ __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned 
                                                       const double* s_bb, double* s_gprev,
                                                       double* s_aprev, double* s_alpha,
                                                       double* s_beta, int* s_active) {
+    static_assert(BS == TILE_BS && 3 * NFD <= 32, "slot-major partials: 32 slots per group");
     constexpr int NW = BS / 64, NS = 3 * NFD;
-    constexpr int PPT = (TILE_NB * NS + BS - 1) / BS;
     const unsigned nb = gridDim.x;
     double* part = a.partial + (size_t)(k & 1u) * CG_MAX_BLOCKS * (CG_MAX_FIELDS * 4);
     __syncthreads();
@@ -676,27 +688,14 @@ __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned 
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     grid_sync_direct(a.bar, nb, k, a.info);
-    const int total = (int)nb * NS;
-    double pv[PPT], hv[HPT];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const int e = threadIdx.x + j * BS;
-        const int b = e / NS, t = e - b * NS;
-        pv[j] = e < total ? __hip_atomic_load(&part[(unsigned)(b * (CG_MAX_FIELDS * 4) + t)],
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                          : 0.0;
-    }
+    double hv[HPT];
 #pragma unroll
     for (int j = 0; j < HPT; ++j)
         hv[j] = hsrc[j] >= 0
                     ? __hip_atomic_load(&eb[(unsigned)hsrc[j]], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT)
                     : 0.0;
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const int e = threadIdx.x + j * BS;
-        if (e < total) stage[e] = pv[j];
-    }
+    stage[threadIdx.x] = group_partial(part, nb, NS);
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
         const int e = threadIdx.x + j * BS;
@@ -705,13 +704,10 @@ __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned 
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int d = wave; d < NFD; d += NW) {
-        if (!s_active[d]) continue;                   // uniform over the wavefront
-        double g = 0.0, de = 0.0, rr = 0.0;
-        for (unsigned b = lane; b < nb; b += 64) {
-            g += stage[b * NS + 3 * d];
-            de += stage[b * NS + 3 * d + 1];
-            rr += stage[b * NS + 3 * d + 2];
-        }
+        if (!s_active[d]) continue;
+        double g = lane < TILE_GROUPS ? stage[lane * 32 + 3 * d] : 0.0;
+        double de = lane < TILE_GROUPS ? stage[lane * 32 + 3 * d + 1] : 0.0;
+        double rr = lane < TILE_GROUPS ? stage[lane * 32 + 3 * d + 2] : 0.0;
         g = wave_sum(g);
         de = wave_sum(de);
         rr = wave_sum(rr);
@@ -737,17 +733,19 @@ __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned 
 }
 
 // z = M^-1 v for the fields marked in ``live`` (others untouched); dinv
-// holds D^-1 per field and cell of the tile (LDS); every thread of the
-// workgroup must call it (it synchronises, first so that earlier readers of
-// zt are done)
+// holds D^-1 per field and cell of the tile (LDS, rounded to single
+// precision: any fixed symmetric positive definite preconditioner will do,
+// and the rounded diagonal is one); zt is the sweeps' work tile, which
+// nothing else reads, so only the sweeps synchronise (the workgroup
+// barriers of the exchange separate one call's reads of zt from the next
+// call's writes); every thread of the workgroup must call it
 template <int NFD, int KSW>
 __device__ __forceinline__ void tile_precond(const double (&v)[NFD], double (&z)[NFD],
-                                             const double* dinv, const double (&cf)[NFD],
+                                             const float* dinv, const double (&cf)[NFD],
                                              double ke, double kw, double kn, double ks,
                                              bool he, bool hw, bool hn, bool hs, double* zt,
                                              const int* live) {
     const int t = threadIdx.x;
-    __syncthreads();
 #pragma unroll
     for (int d = 0; d < NFD; ++d)
         if (live[d]) z[d] = dinv[d * TILE_BS + t] * v[d];
@@ -768,7 +766,7 @@ __device__ __forceinline__ void tile_precond(const double (&v)[NFD], double (&z)
             if (hs) nb += ks * Z[t - TILE_X];
             z[d] = dinv[d * TILE_BS + t] * (v[d] + cf[d] * nb);
         }
-        __syncthreads();
+        if (sw + 1 < KSW) __syncthreads();
     }
 }
 
@@ -779,16 +777,16 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
     constexpr int NS = 3 * NFD;
     constexpr int HPT = (NFD * TILE_HALO + BS - 1) / BS;   // halo slots per thread
     // one workgroup per CU (register bound), so LDS is plentiful: the
-    // preconditioner's work tile, which then holds m of this tile (the
-    // stencil's neighbours inside the tile) until the next preconditioner
-    // call; D^-1 and the iterate x (kept out of registers); the halo of m
-    // and the partials of all blocks
+    // preconditioner's work tile; m of this tile (the stencil's neighbours
+    // inside the tile, and the edges it publishes); D^-1 and the iterate x
+    // (kept out of registers); the halo of m and the groups' sums of the
+    // blocks' partials
     __shared__ double zt[NFD * BS];
-    double* const mt = zt;
-    __shared__ double dinv[NFD * BS];
+    __shared__ double mt[NFD * BS];
+    __shared__ float dinv[NFD * BS];
     __shared__ double xt[NFD * BS];
     __shared__ double halo[NFD * TILE_HALO];
-    __shared__ double stage[TILE_NB * NS];
+    __shared__ double stage[TILE_BS];
     __shared__ double red[NS * (BS / 64)];
     __shared__ double tot[NS];
     __shared__ double s_bb[NFD], s_gprev[NFD], s_aprev[NFD], s_alpha[NFD], s_beta[NFD];
@@ -845,7 +843,7 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
 #pragma unroll
     for (int d = 0; d < NFD; ++d) {
         cf[d] = a.cf[d];
-        dinv[d * BS + threadIdx.x] = own ? 1.0 / (1.0 + cf[d] * (ke + kw + kn + ks)) : 0.0;
+        dinv[d * BS + threadIdx.x] = own ? (float)(1.0 / (1.0 + cf[d] * (ke + kw + kn + ks))) : 0.0f;
     }
     double r[NFD], u[NFD], w[NFD], zz[NFD], qq[NFD], ss[NFD], pp[NFD];
     unsigned kb = 0;
