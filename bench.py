@@ -590,11 +590,10 @@ def mlp_main(args):
     import numpy as np
     import torch
     import synth
-    from oracle import mlp as om
     from paper_1801_01201_amd import native
     from paper_1801_01201_amd.flame import (Mechanism, Grid, Integrator, initial_state, GuessNet,
                                             RELAX_TIME)
-    from paper_1801_01201_amd.guess import record_problems, train
+    from paper_1801_01201_amd.guess import pack_params, record_problems, train
     native.lib()
     cfg = synth.config("flame2d_256")
     mech = synth.make_mechanism(**cfg["mech"])
@@ -633,7 +632,7 @@ def mlp_main(args):
     n_train = hh.numel()
     print(f"[bench] mlp: {n_train} training problems in {t_data:.1f} s", file=sys.stderr, flush=True)
     net = GuessNet(9, 256, "bf16")
-    net.set_params(om.pack(synth.mlp_init(net.sizes, 7)).astype(np.float32))
+    net.set_params(pack_params(synth.mlp_init(net.sizes, 7)))
     epochs, batch = 4, 65536
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -648,6 +648,41 @@ __device__ __forceinline__ void grid_exchange_first(const CGArgs& a, const doubl
     __syncthreads();
 }
 
+// grid_sync_direct in two halves, so that a workgroup can work while the
+// other workgroups arrive: grid_arrive waits for this workgroup's stores and
+// counts it into its group and, if it completes the group, the group into
+// the barrier (at once, since the other workgroups wait on that count);
+// grid_wait waits for barrier k and synchronises the workgroup.
+__device__ __forceinline__ void grid_arrive(unsigned* bar, unsigned nb, unsigned k) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned g = blockIdx.x % BAR_GROUPS;
+        const unsigned gsize = (nb - 1u - g) / BAR_GROUPS + 1u;      // workgroups of group g
+        const unsigned before = __hip_atomic_fetch_add(&bar[BAR_STRIDE * (1 + g)], 1u,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (before + 1u == (k + 1u) * gsize)
+            __hip_atomic_fetch_add(bar + BAR_GLOBAL, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+__device__ __forceinline__ void grid_wait(unsigned* bar, unsigned nb, unsigned k, int32_t* info) {
+    if (threadIdx.x == 0) {
+        const unsigned ngroups = nb < (unsigned)BAR_GROUPS ? nb : (unsigned)BAR_GROUPS;
+        const unsigned target = (k + 1u) * ngroups;
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar + BAR_GLOBAL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1u << 27)) {
+                __hip_atomic_store(&info[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // Reduction of the partial sums (r,u), (w,u), (r,r) of every field over
 // the blocks, fused with the recurrence coefficients: the wavefront that
 // reduces a field's three sums computes its coefficients.  A field whose
@@ -661,17 +696,11 @@ __device__ __forceinline__ void grid_exchange_first(const CGArgs& a, const doubl
 // offsets into the edge half ``eb``, -1 for none; into ``halo``) -- so the
 // exchange costs one memory latency.
 template <int BS, int NFD, int HPT>
-__device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned k, int it,
-                                                      const double* red, double* stage,
-                                                      const double* mt, const int (&elds)[HPT],
-                                                      double* eb,
-                                                      const int (&hsrc)[HPT], double* halo,
-                                                      const double* s_bb, double* s_gprev,
-                                                      double* s_aprev, double* s_alpha,
-                                                      double* s_beta, int* s_active) {
-    static_assert(BS == TILE_BS && 3 * NFD <= 32, "slot-major partials: 32 slots per group");
+__device__ __forceinline__ void grid_publish_arrive(const CGArgs& a, unsigned k,
+                                                        const double* red, const double* mt,
+                                                        const int (&elds)[HPT], double* eb,
+                                                        const int* s_active) {
     constexpr int NW = BS / 64, NS = 3 * NFD;
-    const unsigned nb = gridDim.x;
     double* part = a.partial + (size_t)(k & 1u) * CG_MAX_BLOCKS * (CG_MAX_FIELDS * 4);
     __syncthreads();
     for (int t = threadIdx.x; t < NS; t += BS) {
@@ -687,7 +716,22 @@ __device__ __forceinline__ void grid_allreduce_coeffs(const CGArgs& a, unsigned 
             __hip_atomic_store(&eb[(size_t)blockIdx.x * (NFD * TILE_HALO) + e], mt[elds[j]],
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    grid_sync_direct(a.bar, nb, k, a.info);
+    grid_arrive(a.bar, gridDim.x, k);
+}
+
+template <int BS, int NFD, int HPT>
+__device__ __forceinline__ void grid_finish_coeffs(const CGArgs& a, unsigned k, int it,
+                                                   double* stage,
+                                                   double* eb, const int (&hsrc)[HPT],
+                                                   double* halo, const double* s_bb,
+                                                   double* s_gprev, double* s_aprev,
+                                                   double* s_alpha, double* s_beta,
+                                                   int* s_active) {
+    static_assert(BS == TILE_BS && 3 * NFD <= 32, "slot-major partials: 32 slots per group");
+    constexpr int NW = BS / 64, NS = 3 * NFD;
+    const unsigned nb = gridDim.x;
+    double* part = a.partial + (size_t)(k & 1u) * CG_MAX_BLOCKS * (CG_MAX_FIELDS * 4);
+    grid_wait(a.bar, nb, k, a.info);
     double hv[HPT];
 #pragma unroll
     for (int j = 0; j < HPT; ++j)
@@ -916,13 +960,30 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
                 return (j == 1 ? w[d] : r[d]) * (j == 2 ? r[d] : u[d]);
             },
             red);
-        grid_allreduce_coeffs<BS, NFD, HPT>(a, kb++, it, red, stage, mt, elds, eb, hsrc, halo, s_bb,
-                                            s_gprev, s_aprev, s_alpha, s_beta, s_active);
+        grid_publish_arrive<BS, NFD, HPT>(a, kb, red, mt, elds, eb, s_active);
+        // n = A m of the cells whose four neighbours lie in the tile, into the
+        // preconditioner's (now free) tile, while the other workgroups
+        // arrive; cells on the tile's edges take theirs after the exchange
+        const bool inner = own && he && hw && hn && hs;
+        if (inner) {
+            const int t = threadIdx.x;
+#pragma unroll
+            for (int d = 0; d < NFD; ++d) {
+                if (!(live & (1u << d))) continue;
+                const double* Mt = mt + d * BS;
+                const double mi = Mt[t];
+                zt[d * BS + t] = mi - cf[d] * (ke * (Mt[t + 1] - mi) - kw * (mi - Mt[t - 1]) +
+                                               kn * (Mt[t + TILE_X] - mi) -
+                                               ks * (mi - Mt[t - TILE_X]));
+            }
+        }
+        grid_finish_coeffs<BS, NFD, HPT>(a, kb++, it, stage, eb, hsrc, halo, s_bb, s_gprev, s_aprev,
+                                         s_alpha, s_beta, s_active);
         int any = 0;
 #pragma unroll
         for (int d = 0; d < NFD; ++d) any |= s_active[d];
         if (!any) break;
-        // ---- n = A m (neighbours from the tile and its halo in LDS) ; recurrences ----
+        // ---- n = A m (edge cells: neighbours from the tile and its halo in LDS) ; recurrences ----
 #pragma unroll
         for (int d = 0; d < NFD; ++d) {
             const double* Mt = mt + d * BS;
@@ -932,12 +993,17 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
             if (!own || !act) continue;
             const int t = threadIdx.x;
             const double mi = Mt[t];      // m of this cell, kept in LDS across the barrier
-            const double mE = he ? Mt[t + 1] : H[2 * TILE_X + ty];
-            const double mW = hw ? Mt[t - 1] : H[2 * TILE_X + TILE_Y + ty];
-            const double mN = hn ? Mt[t + TILE_X] : H[tx];
-            const double mS = hs ? Mt[t - TILE_X] : H[TILE_X + tx];
-            const double ni = mi - cf[d] * (ke * (mE - mi) - kw * (mi - mW) +
-                                            kn * (mN - mi) - ks * (mi - mS));
+            double ni;
+            if (inner) {
+                ni = zt[d * BS + t];
+            } else {
+                const double mE = he ? Mt[t + 1] : H[2 * TILE_X + ty];
+                const double mW = hw ? Mt[t - 1] : H[2 * TILE_X + TILE_Y + ty];
+                const double mN = hn ? Mt[t + TILE_X] : H[tx];
+                const double mS = hs ? Mt[t - TILE_X] : H[TILE_X + tx];
+                ni = mi - cf[d] * (ke * (mE - mi) - kw * (mi - mW) + kn * (mN - mi) -
+                                   ks * (mi - mS));
+            }
             const double z1 = ni + be * zz[d];
             const double q1 = mi + be * qq[d];
             const double s1 = w[d] + be * ss[d];

@@ -9,8 +9,18 @@ Typical use::
     train(mech, net, *data, epochs=5)
     integ.set_guess(net)
 """
+import numpy as np
+
 from . import native as nat
 from .flame import Integrator
+
+
+def pack_params(layers):
+    """Flat FP32 parameter vector in the library's layer order (W1, b1, W2,
+    b2, ...; each W row-major, inputs by outputs) from a list of (W, b)."""
+    return np.concatenate([np.concatenate([np.asarray(W, dtype=np.float32).ravel(),
+                                           np.asarray(b, dtype=np.float32).ravel()])
+                           for W, b in layers])
 
 
 def record_problems(mech, grid, states, dt, **integ_opts):
