@@ -488,8 +488,12 @@ int misdc_set_tune(misdc_integ_t integ, const misdc_tune* tune);
  * misdc_step is asynchronous and returns before its solves finish, so this
  * call reports their outcome: it fills *stats and returns MISDC_ENOTCONV if
  * newton_failed or cg_failed is above zero (cells whose Newton iteration
- * reached newton.maxit or stalled; diffusion solves that reached cg_maxit or
- * whose workgroups timed out waiting for each other), else MISDC_OK. */
+ * reached newton.maxit or stalled; diffusion solves that reached cg_maxit,
+ * whose workgroups timed out waiting for each other, or, with the tiled 2-D
+ * CG, whose result's own residual |b - A y|, taken over the cells whose four
+ * neighbours lie in the same 32 x 16 tile, exceeded 10 cg_rtol |b| in some
+ * field although the iteration's recurrence residual met the tolerance),
+ * else MISDC_OK. */
 typedef struct {
     int64_t newton_solves;      /* cell-node Newton solves */
     int64_t newton_iters;       /* total linear solves */

@@ -15,9 +15,11 @@ constexpr int CG_MAX_BLOCKS = 256;
 constexpr int TILE_X = 32, TILE_Y = 16, TILE_BS = TILE_X * TILE_Y, TILE_NB = 128;
 // grid-barrier words: [0] arrivals, [1] generation; the two-level barrier
 // of the tiled kernel: BAR_GROUPS group counters at word BAR_STRIDE * (1 + g)
-// and its count of arrived groups at BAR_GLOBAL, each on its own 128-byte line
+// and its count of arrived groups at BAR_GLOBAL, each on its own 128-byte
+// line; BAR_EXIT counts the workgroups that have published the partial sums
+// of the result's residual (the last one adds them up and zeroes it)
 constexpr int BAR_GROUPS = 8, BAR_STRIDE = 32, BAR_GLOBAL = BAR_STRIDE * (1 + BAR_GROUPS),
-              BAR_WORDS = BAR_GLOBAL + BAR_STRIDE;
+              BAR_EXIT = BAR_GLOBAL + BAR_STRIDE, BAR_WORDS = BAR_EXIT + BAR_STRIDE;
 // cells on the four sides of a tile (its edges, and the halo around it)
 constexpr int TILE_HALO = 2 * TILE_X + 2 * TILE_Y;
 // edge buffer of the tiled kernels: 2 (iteration parity) x tiles x 9 fields x TILE_HALO
@@ -58,7 +60,8 @@ struct CGArgs {
     const double* invW;
     double* T_out;
     double* th_out;
-    int32_t* cgstats;       // [0] iterations, [1] max, [2] failures, [3] solves, [4] timeouts
+    int32_t* cgstats;       // [0] iterations, [1] max, [2] failures, [3] solves, [4] timeouts,
+                            // [5] tiled variants: results whose true residual failed the check
 };
 
 // launches the CG kernel of a variant (0 global memory, 1/2/4 register

@@ -834,6 +834,7 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
     __shared__ double red[NS * (BS / 64)];
     __shared__ double tot[NS];
     __shared__ double s_bb[NFD], s_gprev[NFD], s_aprev[NFD], s_alpha[NFD], s_beta[NFD];
+    __shared__ int s_last;
     __shared__ int s_active[NFD];
     if (threadIdx.x < NFD) s_active[threadIdx.x] = 1;
     __syncthreads();
@@ -1016,6 +1017,58 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
             r[d] = act ? r[d] - al * s1 : r[d];
             u[d] = act ? u[d] - al * q1 : u[d];
             w[d] = act ? w[d] - al * z1 : w[d];
+        }
+    }
+    if (a.cgstats) {
+        // ---- the true residual |b - A x| of the result, against 10 rtol |b|
+        // per field: the recurrences' residual can drift away from it, so a
+        // result whose own residual fails is counted as a failed solve.  It is
+        // taken over the cells whose four neighbours lie in the same tile (no
+        // further exchange of x: 82 % of the cells at 32 x 16), a lower bound
+        // of the whole residual, so a flagged result has failed.  Each
+        // workgroup publishes its partial sums and counts itself out; the
+        // last one out adds them up, so nothing is waited for ----
+        const int t = threadIdx.x;
+        const bool inner = own && he && hw && hn && hs;
+        wave_put_slots<BS, NFD>(
+            [&](int d) {
+                if (!inner) return 0.0;
+                const double* Xt = xt + d * BS;
+                const double xi = Xt[t];
+                const double Ax = xi - cf[d] * (ke * (Xt[t + 1] - xi) - kw * (xi - Xt[t - 1]) +
+                                                kn * (Xt[t + TILE_X] - xi) -
+                                                ks * (xi - Xt[t - TILE_X]));
+                const double res = a.b[(size_t)a.fmap[d] * a.n + cell] - Ax;
+                return res * res;
+            },
+            red);
+        double* part = a.partial + (size_t)(kb & 1u) * CG_MAX_BLOCKS * (CG_MAX_FIELDS * 4);
+        __syncthreads();
+        for (int q = threadIdx.x; q < NFD; q += BS) {
+            double v = 0.0;
+            for (int w2 = 0; w2 < BS / 64; ++w2) v += red[q * (BS / 64) + w2];
+            __hip_atomic_store(&part[(size_t)blockIdx.x * (CG_MAX_FIELDS * 4) + q], v,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_last = __hip_atomic_fetch_add(&a.bar[BAR_EXIT], 1u, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT) + 1u == gridDim.x;
+        __syncthreads();
+        if (s_last) {                                 // uniform over the workgroup
+            stage[threadIdx.x] = group_partial(part, gridDim.x, NFD);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                // a solve already failed at maxit is not counted twice; NaN fails
+                int bad = 0, open_fields = 0;
+                for (int d = 0; d < NFD; ++d) {
+                    bad |= !(slot_total(stage, d) <= 100.0 * a.rtol2 * s_bb[d]);
+                    open_fields |= s_active[d];
+                }
+                a.cgstats[5] += (it == a.maxit && open_fields) ? 0 : bad;
+                __hip_atomic_store(&a.bar[BAR_EXIT], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
 #pragma unroll

@@ -960,15 +960,18 @@ int sync_streams(misdc_integ_s* I) {
 
 // CG counters of the last step over every diffusion lane: [0] iterations,
 // [1] max, [2] failed, [3] solves, [4] barrier timeouts
+// (results of the tiled CG whose true residual failed its check count as
+// failed solves)
 int read_cgstats(misdc_integ_s* I, int32_t (&cg)[8]) {
     MISDC_HIP(hipMemcpy(cg, I->cgstats, sizeof(cg), hipMemcpyDeviceToHost));
+    cg[2] += cg[5];
     if (I->pipe)
         for (auto& d : I->pd_lane) {
             int32_t l[8];
             MISDC_HIP(hipMemcpy(l, d.cgstats, sizeof(l), hipMemcpyDeviceToHost));
             cg[0] += l[0];
             cg[1] = l[1] > cg[1] ? l[1] : cg[1];
-            cg[2] += l[2];
+            cg[2] += l[2] + l[5];
             cg[3] += l[3];
             cg[4] += l[4];
         }

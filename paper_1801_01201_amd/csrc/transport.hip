@@ -109,6 +109,7 @@ __device__ __forceinline__ void zero_barrier(unsigned* bar) {
     bar[1] = 0u;
     for (int g = 0; g < BAR_GROUPS; ++g) bar[BAR_STRIDE * (1 + g)] = 0u;
     bar[BAR_GLOBAL] = 0u;
+    bar[BAR_EXIT] = 0u;
 }
 
 __global__ void __launch_bounds__(256) faces_kernel(GridDev g, int64_t n, const double* T,
