@@ -24,18 +24,17 @@ namespace {
 template <int NS, bool INERT_LAST>
 __global__ void __launch_bounds__(64) newton_kernel(MechDev m, NewtonArgs a) {
     // A wavefront iterates until its slowest cell has converged.  On a 2-D
-    // grid an 8 x 8 tile of cells keeps cells at similar distances from a
-    // flame front together, whichever way the front runs, so its iteration
-    // counts differ less than along 64 cells of a row (256 x 256 flame: the
-    // mean per-wavefront maximum falls from 2.8 to 2.3 iterations, against a
-    // mean of 2.2).  The launch time follows the slowest wavefronts of its
-    // one or two rounds rather than the mean, so it gains only ~1 %.  Lanes
-    // outside the grid take i = n.
+    // grid a compact tile of cells keeps cells at similar distances from a
+    // flame front together, so its iteration counts differ less than along
+    // 64 cells of a row (256 x 256 flame, 8 x 8 tiles: the mean per-wavefront
+    // maximum falls from 2.8 to 2.3 iterations, against a mean of 2.2).  A
+    // 16 x 4 tile keeps most of that and reads whole 128-byte lines: no line
+    // is fetched by two workgroups.  Lanes outside the grid take i = n.
     int64_t i;
     if (a.tile_nx > 0) {
-        const int ntx = (a.tile_nx + 7) / 8;
-        const int x = (int)(blockIdx.x % ntx) * 8 + (int)(threadIdx.x & 7);
-        const int y = (int)(blockIdx.x / ntx) * 8 + (int)(threadIdx.x >> 3);
+        const int ntx = (a.tile_nx + NEWTON_TILE_X - 1) / NEWTON_TILE_X;
+        const int x = (int)(blockIdx.x % ntx) * NEWTON_TILE_X + (int)(threadIdx.x % NEWTON_TILE_X);
+        const int y = (int)(blockIdx.x / ntx) * NEWTON_TILE_Y + (int)(threadIdx.x / NEWTON_TILE_X);
         i = (x < a.tile_nx && y < a.tile_ny) ? (int64_t)y * a.tile_nx + x : a.n;
     } else {
         i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -199,7 +198,14 @@ int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s) {
         }
         return MISDC_OK;
     }
-    if (!thread) return launch_reaction_newton_wave(m, a, a.opt.lu, s);
+    if (!thread) {
+        // the wavefront kernels leave the copy of h to a pass of its own
+        if (a.h_out) {
+            const int rc = launch_copy(a.h_out, a.h, a.n, s);
+            if (rc) return rc;
+        }
+        return launch_reaction_newton_wave(m, a, a.opt.lu, s);
+    }
     if (m.dev.N != 9)
         return fail(MISDC_EUNSUPPORTED, "per-thread reaction solve: %d species not built", m.dev.N);
     int64_t blocks = grid_for(a.n, 64);
@@ -207,7 +213,8 @@ int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s) {
         if (a.tile_ny <= 0 || (int64_t)a.tile_nx * a.tile_ny != a.n)
             return fail(MISDC_EINVAL, "tiled reaction solve: %d x %d cells for n = %lld", a.tile_nx,
                         a.tile_ny, (long long)a.n);
-        blocks = (int64_t)((a.tile_nx + 7) / 8) * ((a.tile_ny + 7) / 8);
+        blocks = (int64_t)((a.tile_nx + NEWTON_TILE_X - 1) / NEWTON_TILE_X) *
+                 ((a.tile_ny + NEWTON_TILE_Y - 1) / NEWTON_TILE_Y);
     }
     if (m.dev.bath == 8)
         hipLaunchKernelGGL((newton_kernel<9, true>), dim3((unsigned)blocks), dim3(64), 0, s, m.dev, a);

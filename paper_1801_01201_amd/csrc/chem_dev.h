@@ -306,6 +306,7 @@ __device__ __forceinline__ int newton_cell(const MechDev& m, const NewtonArgs& a
     for (int k = 0; k < NS; ++k) a.Y[k * a.ldy + i] = Y[k];
     const double Tc = temperature_of<NS>(m, Y, h);
     if (a.T) a.T[i] = Tc;
+    if (a.h_out) a.h_out[i] = h;
     if (a.FR) {
         double FR[NS], J[1][NS + 1];
         reaction_terms<NS, false>(m, Y, Tc, FR, J);

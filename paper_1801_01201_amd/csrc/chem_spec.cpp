@@ -376,6 +376,7 @@ std::string generate(const MechHost& m) {
     for (int q = 0; q < NR; ++q) emit(s, "    D[%d] = M[%d][NX];\n", rs[q], q);
     emit(s, "    D[%d] = db;\n}\n", b);
     emit(s, "#define WAVES_PER_EU %d\n", NEWTON_SPEC_WAVES_PER_EU);
+    emit(s, "constexpr int TILE_X = %d, TILE_Y = %d;\n", NEWTON_TILE_X, NEWTON_TILE_Y);
     emit(s, "constexpr int BUCKETS = %d, BUCKET_STRIDE = %d, HIST_SETS = %d, HIST_BINS = %d;\n",
          NEWTON_BUCKETS, NEWTON_BUCKET_STRIDE, NEWTON_HIST_SETS, NEWTON_HIST_BINS);
     // the kernel: the loop of the generic per-thread kernel
@@ -383,14 +384,14 @@ std::string generate(const MechHost& m) {
 extern "C" __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
 newton_spec(
         i64 n, const double* bY, i64 ldb, const double* hp, const double* cp, double c_scalar,
-        const double* guess, i64 ldg, double* Yo, i64 ldy, double* To, double* FRo, i64 ldf,
+        const double* guess, i64 ldg, double* Yo, i64 ldy, double* To, double* Ho, double* FRo, i64 ldf,
         int* iters, u64* buckets, u64* hist, int tile_nx, int tile_ny, double tol, int maxit,
         double dtau0, double dtau_max, double neg_slack) {
     i64 i;
     if (tile_nx > 0) {
-        const int ntx = (tile_nx + 7) / 8;
-        const int x = (int)(blockIdx.x % ntx) * 8 + (int)(threadIdx.x & 7);
-        const int y = (int)(blockIdx.x / ntx) * 8 + (int)(threadIdx.x >> 3);
+        const int ntx = (tile_nx + TILE_X - 1) / TILE_X;
+        const int x = (int)(blockIdx.x % ntx) * TILE_X + (int)(threadIdx.x % TILE_X);
+        const int y = (int)(blockIdx.x / ntx) * TILE_Y + (int)(threadIdx.x / TILE_X);
         i = (x < tile_nx && y < tile_ny) ? (i64)y * tile_nx + x : n;
     } else {
         i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -460,6 +461,7 @@ newton_spec(
         for (int k = 0; k < NS; ++k) Yo[(i64)k * ldy + i] = Y[k];
         const double Tc = temperature_of(Y, h);
         if (To) To[i] = Tc;
+        if (Ho) Ho[i] = h;
         if (FRo) {
             double F[NS];
             int kz;
@@ -607,7 +609,8 @@ int launch_newton_spec(const Mech& m, const NewtonArgs& a, hipStream_t s) {
         if (a.tile_ny <= 0 || (int64_t)a.tile_nx * a.tile_ny != a.n)
             return fail(MISDC_EINVAL, "tiled reaction solve: %d x %d cells for n = %lld", a.tile_nx,
                         a.tile_ny, (long long)a.n);
-        blocks = (int64_t)((a.tile_nx + 7) / 8) * ((a.tile_ny + 7) / 8);
+        blocks = (int64_t)((a.tile_nx + NEWTON_TILE_X - 1) / NEWTON_TILE_X) *
+                 ((a.tile_ny + NEWTON_TILE_Y - 1) / NEWTON_TILE_Y);
     }
     if (blocks > 0x7fffffffll) return fail(MISDC_EINVAL, "too many cells for one launch");
     int64_t n = a.n, ldb = a.ldb, ldg = a.ldg, ldy = a.ldy, ldf = a.ldf;
@@ -618,6 +621,7 @@ int launch_newton_spec(const Mech& m, const NewtonArgs& a, hipStream_t s) {
     const double* guess = a.guess;
     double* Yo = a.Y;
     double* To = a.T;
+    double* Ho = a.h_out;
     double* FRo = a.FR;
     int* iters = a.iters;
     unsigned long long* buckets = a.buckets;
@@ -625,7 +629,7 @@ int launch_newton_spec(const Mech& m, const NewtonArgs& a, hipStream_t s) {
     int tnx = a.tile_nx, tny = a.tile_ny;
     double tol = a.opt.tol, dtau0 = a.opt.dtau0, dtau_max = a.opt.dtau_max, slack = a.opt.neg_slack;
     int maxit = a.opt.maxit;
-    void* args[] = {&n, &bY, &ldb, &hp, &cp, &c_scalar, &guess, &ldg, &Yo, &ldy, &To, &FRo, &ldf,
+    void* args[] = {&n, &bY, &ldb, &hp, &cp, &c_scalar, &guess, &ldg, &Yo, &ldy, &To, &Ho, &FRo, &ldf,
                     &iters, &buckets, &hist, &tnx, &tny, &tol, &maxit, &dtau0, &dtau_max, &slack};
     MISDC_HIP(hipModuleLaunchKernel((hipFunction_t)m.spec_fn, (unsigned)blocks, 1, 1, 64, 1, 1, 0,
                                     s, args, nullptr));

@@ -24,6 +24,9 @@ struct Row {
 };
 
 __device__ __forceinline__ int64_t wrap(int64_t k, int64_t len) {
+    // the neighbours of a position in [0, len) lie within one period: no
+    // 64-bit remainder (a long instruction sequence) unless len < 2
+    if (k >= -len && k < 2 * len) return k < 0 ? k + len : (k >= len ? k - len : k);
     k %= len;
     return k < 0 ? k + len : k;
 }
@@ -51,66 +54,141 @@ __device__ __forceinline__ Row row_of(const GridDev& g, int64_t i) {
     return r;
 }
 
-// FA and FD for every field of one cell.  FD of the bath species is minus the
-// sum of the other species' FD.  FROM_T: theta = (T/300)^1.7 of the cell and
-// its neighbours is computed here from T (and the cell's own value stored in
-// th) instead of being read from th.
-template <bool FROM_T>
+// The explicit operators' stencil at one cell: the four neighbours along x
+// (periodic in the row or flame) and along y (2-D grids), the advection
+// factors u/dx, and the face coefficients theta_face / dx^2 (mean of the two
+// cells' theta) of the diffusion operator of eqs. `species_equation` and
+// `enthalpy_equation`.
+struct Stencil {
+    int64_t xm2, xm1, xp1, xp2, ym2, ym1, yp1, yp2;
+    bool two_d;
+    double ax, ay, kxe, kxw, kyn, kys;
+};
+
+template <class Theta>
+__device__ __forceinline__ Stencil stencil_at(const GridDev& g, int64_t i, double t0, Theta theta) {
+    Stencil s;
+    const Row r = row_of(g, i);
+    s.xm2 = r.base + wrap(r.pos - 2, r.len);
+    s.xm1 = r.base + wrap(r.pos - 1, r.len);
+    s.xp1 = r.base + wrap(r.pos + 1, r.len);
+    s.xp2 = r.base + wrap(r.pos + 2, r.len);
+    s.ym2 = s.ym1 = s.yp1 = s.yp2 = 0;
+    s.two_d = (g.dim == 2 && g.n_flames == 0);
+    if (s.two_d) {
+        const int64_t iy = i / g.nx, ix = i - iy * g.nx;
+        s.ym2 = wrap(iy - 2, g.ny) * g.nx + ix;
+        s.ym1 = wrap(iy - 1, g.ny) * g.nx + ix;
+        s.yp1 = wrap(iy + 1, g.ny) * g.nx + ix;
+        s.yp2 = wrap(iy + 2, g.ny) * g.nx + ix;
+    }
+    const double idx2 = 1.0 / (r.dx * r.dx);
+    s.kxe = 0.5 * (t0 + theta(s.xp1)) * idx2;
+    s.kxw = 0.5 * (t0 + theta(s.xm1)) * idx2;
+    s.kyn = s.kys = 0.0;
+    if (s.two_d) {
+        const double idy2 = 1.0 / (g.dy * g.dy);
+        s.kyn = 0.5 * (t0 + theta(s.yp1)) * idy2;
+        s.kys = 0.5 * (t0 + theta(s.ym1)) * idy2;
+    }
+    s.ax = r.u / r.dx;
+    s.ay = s.two_d ? g.uy / g.dy : 0.0;
+    return s;
+}
+
+// the stencil values of one field p at cell i: c0, then x-1, x-2, x+1, x+2,
+// then (TWO_D) y-1, y-2, y+1, y+2
+template <bool TWO_D>
+__device__ __forceinline__ void load_stencil(const Stencil& s, const double* p, int64_t i,
+                                             double (&v)[9]) {
+    v[0] = p[i];
+    v[1] = p[s.xm1];
+    v[2] = p[s.xm2];
+    v[3] = p[s.xp1];
+    v[4] = p[s.xp2];
+    if (TWO_D) {
+        v[5] = p[s.ym1];
+        v[6] = p[s.ym2];
+        v[7] = p[s.yp1];
+        v[8] = p[s.yp2];
+    }
+}
+
+// advection -div(u phi) with fourth-order face values, and div(theta grad phi)
+// (the diffusion operator without kappa0), from one field's stencil values
+template <bool TWO_D>
+__device__ __forceinline__ void field_ops(const Stencil& s, const double (&v)[9], double& fa,
+                                          double& lap) {
+    const double c0 = v[0], w1 = v[1], w2 = v[2], e1 = v[3], e2 = v[4];
+    // fourth-order face values at i+1/2 and i-1/2
+    const double fe = (7.0 * (c0 + e1) - (w1 + e2)) / 12.0;
+    const double fw = (7.0 * (w1 + c0) - (w2 + e1)) / 12.0;
+    fa = -s.ax * (fe - fw);
+    lap = s.kxe * (e1 - c0) - s.kxw * (c0 - w1);
+    if (TWO_D) {
+        const double s1 = v[5], s2 = v[6], n1 = v[7], n2 = v[8];
+        const double fn = (7.0 * (c0 + n1) - (s1 + n2)) / 12.0;
+        const double fs = (7.0 * (s1 + c0) - (s2 + n1)) / 12.0;
+        if (s.ay != 0.0) fa -= s.ay * (fn - fs);
+        lap += s.kyn * (n1 - c0) - s.kys * (c0 - s1);
+    }
+}
+
+// FA and FD of every field at cell i from the stencil s, CH fields at a time:
+// a chunk's stencil values are all loaded before any of its results is
+// stored, so that a chunk waits for memory once rather than once per field
+// (the kernel is bound by that latency: one thread per cell, one wavefront
+// per SIMD).  FD of the bath species is minus the sum of the other species'.
+template <int CH, bool TWO_D>
+__device__ __forceinline__ void transport_fields(const Stencil& s, const MechDev& m, int64_t n,
+                                                 const double* st, double* FA, double* FD,
+                                                 int64_t i) {
+    const int NF = m.N + 1;
+    double fd_sum = 0.0;
+    for (int f0 = 0; f0 < NF; f0 += CH) {
+        double v[CH][9];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            // past the last field a chunk reloads that field, so every load
+            // stays in bounds and none sits behind a branch
+            const int f = f0 + c < NF ? f0 + c : NF - 1;
+            load_stencil<TWO_D>(s, st + (size_t)f * n, i, v[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int f = f0 + c;
+            if (f >= NF) continue;
+            double fa, lap;
+            field_ops<TWO_D>(s, v[c], fa, lap);
+            if (FA) FA[(size_t)f * n + i] = fa;
+            if (FD && f != m.bath) {
+                const double fd = m.kappa0[f] * lap;
+                FD[(size_t)f * n + i] = fd;
+                if (f < m.N) fd_sum += fd;
+            }
+        }
+    }
+    if (FD) FD[(size_t)m.bath * n + i] = -fd_sum;
+}
+
+// FA and FD for every field of one cell.  FROM_T: theta = (T/300)^1.7 of the
+// cell and its neighbours is computed here from T (and the cell's own value
+// stored in th) instead of being read from th.  CH: fields per chunk of
+// loads (see transport_fields).
+template <bool FROM_T, int CH = 1>
 __device__ __forceinline__ void transport_cell(const GridDev& g, const MechDev& m, int64_t n,
                                                const double* st, const double* T, double* th,
                                                double* FA, double* FD, int64_t i) {
     auto theta = [&](int64_t j) {
         return FROM_T ? pow(T[j] / T_DIFF_REF, THETA_EXP) : th[j];
     };
-    const Row r = row_of(g, i);
-    const int64_t xm2 = r.base + wrap(r.pos - 2, r.len), xm1 = r.base + wrap(r.pos - 1, r.len);
-    const int64_t xp1 = r.base + wrap(r.pos + 1, r.len), xp2 = r.base + wrap(r.pos + 2, r.len);
-    int64_t ym2 = 0, ym1 = 0, yp1 = 0, yp2 = 0;
-    const bool two_d = (g.dim == 2 && g.n_flames == 0);
-    if (two_d) {
-        const int64_t iy = i / g.nx, ix = i - iy * g.nx;
-        ym2 = wrap(iy - 2, g.ny) * g.nx + ix;
-        ym1 = wrap(iy - 1, g.ny) * g.nx + ix;
-        yp1 = wrap(iy + 1, g.ny) * g.nx + ix;
-        yp2 = wrap(iy + 2, g.ny) * g.nx + ix;
-    }
     const double t0 = theta(i);
     if (FROM_T) th[i] = t0;
-    const double idx2 = 1.0 / (r.dx * r.dx);
-    const double kxe = 0.5 * (t0 + theta(xp1)) * idx2, kxw = 0.5 * (t0 + theta(xm1)) * idx2;
-    double kyn = 0.0, kys = 0.0;
-    if (two_d) {
-        const double idy2 = 1.0 / (g.dy * g.dy);
-        kyn = 0.5 * (t0 + theta(yp1)) * idy2;
-        kys = 0.5 * (t0 + theta(ym1)) * idy2;
-    }
-    const double ax = r.u / r.dx;
-    const double ay = two_d ? g.uy / g.dy : 0.0;
-    double fd_sum = 0.0;
-    const int NF = m.N + 1;
-    for (int f = 0; f < NF; ++f) {
-        const double* p = st + (size_t)f * n;
-        const double c0 = p[i], w1 = p[xm1], w2 = p[xm2], e1 = p[xp1], e2 = p[xp2];
-        // fourth-order face values at i+1/2 and i-1/2
-        const double fe = (7.0 * (c0 + e1) - (w1 + e2)) / 12.0;
-        const double fw = (7.0 * (w1 + c0) - (w2 + e1)) / 12.0;
-        double fa = -ax * (fe - fw);
-        double lap = kxe * (e1 - c0) - kxw * (c0 - w1);
-        if (two_d) {
-            const double s1 = p[ym1], s2 = p[ym2], n1 = p[yp1], n2 = p[yp2];
-            const double fn = (7.0 * (c0 + n1) - (s1 + n2)) / 12.0;
-            const double fs = (7.0 * (s1 + c0) - (s2 + n1)) / 12.0;
-            if (ay != 0.0) fa -= ay * (fn - fs);
-            lap += kyn * (n1 - c0) - kys * (c0 - s1);
-        }
-        if (FA) FA[(size_t)f * n + i] = fa;
-        if (FD && f != m.bath) {
-            const double fd = m.kappa0[f] * lap;
-            FD[(size_t)f * n + i] = fd;
-            if (f < m.N) fd_sum += fd;
-        }
-    }
-    if (FD) FD[(size_t)m.bath * n + i] = -fd_sum;
+    const Stencil s = stencil_at(g, i, t0, theta);
+    if (s.two_d)
+        transport_fields<CH, true>(s, m, n, st, FA, FD, i);
+    else
+        transport_fields<CH, false>(s, m, n, st, FA, FD, i);
 }
 
 // face coefficients of the lagged operator: Kx[i] = east face / dx^2, Ky[i] =

@@ -583,9 +583,6 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     int rc = launch_lincomb(b.lc, L.s);
     if (rc) return rc;
     NodeBuf& out = Lc[p];
-    // enthalpy is not changed by the reaction step
-    rc = launch_copy(out.phi + (size_t)N * n, I->phiAD[p] + (size_t)N * n, n, L.s);
-    if (rc) return rc;
     const double c_scalar = I->dtc ? cf : dt * cf;
     const double* guess = Lp[p].phi;
     if (I->mlp && (I->guess_sweeps <= 0 || I->sweep_index < I->guess_sweeps)) {
@@ -611,6 +608,8 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     a.Y = out.phi;
     a.ldy = n;
     a.T = out.T;
+    // enthalpy is not changed by the reaction step: the solve copies it
+    a.h_out = out.phi + (size_t)N * n;
     a.FR = out.FR;
     a.ldf = n;
     a.iters = L.iters;

@@ -125,6 +125,8 @@ struct NewtonArgs {
     const double* guess; int64_t ldg;       // N fields
     double* Y; int64_t ldy;                 // N fields out
     double* T;                              // n out (closed form of (Y, h)), may be null
+    double* h_out = nullptr;                // n out, may be null: a copy of h (the reaction
+                                            // step leaves the enthalpy unchanged)
     double* FR; int64_t ldf;                // N fields out, may be null
     int32_t* iters;                         // n out, may be null
     int32_t* lu_info = nullptr;             // n out, may be null: FP32 solves | FP64 fallbacks << 16
@@ -141,12 +143,18 @@ struct NewtonArgs {
     unsigned long long* hist = nullptr;
     // per-thread kernel only: > 0 for the cells of a 2-D grid of tile_nx x
     // tile_ny cells (x fastest, tile_nx * tile_ny = n); each 64-thread block
-    // then takes one 8 x 8 tile of cells instead of 64 consecutive cells
+    // then takes one NEWTON_TILE_X x NEWTON_TILE_Y tile of cells instead of
+    // 64 consecutive cells
     int tile_nx = 0, tile_ny = 0;
     misdc_newton_opts opt;
 };
 constexpr int NEWTON_BUCKETS = 32, NEWTON_BUCKET_STRIDE = 16;   // 128-byte apart
 constexpr int NEWTON_HIST_BINS = 64, NEWTON_HIST_SETS = 8;
+// the cell tile of the tiled per-thread Newton launches: a row of 16 FP64
+// values is one whole 128-byte line, so no line is split between two
+// workgroups (which may sit on different XCDs and their L2s)
+constexpr int NEWTON_TILE_X = 16, NEWTON_TILE_Y = 4;
+static_assert(NEWTON_TILE_X * NEWTON_TILE_Y == 64, "one wavefront per cell tile");
 int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s);
 // the generated kernel (statistics into a.buckets / a.hist when a.buckets is set)
 int launch_newton_spec(const Mech& m, const NewtonArgs& a, hipStream_t s);

@@ -26,23 +26,47 @@ inline unsigned grid_for(int64_t n, int threads) {
 // ---------------------------------------------------------------------------
 // linear combinations
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) lincomb_kernel(LinComb lc) {
-    const int64_t total = (int64_t)lc.nfields * lc.ncells;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int f = (int)(e / lc.ncells);
-        double acc[LC_MAX_OUT];
+// acc[p] = sum over the terms t, in ascending order, of W[p][t] X[t][e] (the
+// terms in smask times the cell's scale) for element e = f * ncells + cell.
+// A batch of LC_BATCH terms is loaded before any of them is used, so that
+// the batch waits for memory once (the kernels below are bound by that
+// latency, not by bandwidth, when every term waits in turn).
+constexpr int LC_BATCH = 8;
+
+__device__ __forceinline__ void lincomb_element(const LinComb& lc, int f, int64_t cell,
+                                                double (&acc)[LC_MAX_OUT]) {
+    const int64_t e = (int64_t)f * lc.ncells + cell;
+    const double sc = lc.smask ? lc.scale[cell] : 1.0;
 #pragma unroll
-        for (int p = 0; p < LC_MAX_OUT; ++p) acc[p] = 0.0;
-        const double sc = lc.smask ? lc.scale[e - (int64_t)f * lc.ncells] : 1.0;
-        for (int t = 0; t < lc.nterms; ++t) {
-            if (f >= lc.nf[t]) continue;
-            double v = lc.X[t][e];
-            if ((lc.smask >> t) & 1u) v *= sc;
+    for (int p = 0; p < LC_MAX_OUT; ++p) acc[p] = 0.0;
+    for (int t0 = 0; t0 < lc.nterms; t0 += LC_BATCH) {
+        double v[LC_BATCH];
+#pragma unroll
+        for (int c = 0; c < LC_BATCH; ++c) {
+            const int t = t0 + c;
+            v[c] = (t < lc.nterms && f < lc.nf[t]) ? lc.X[t][e] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < LC_BATCH; ++c) {
+            const int t = t0 + c;
+            if (t >= lc.nterms || f >= lc.nf[t]) continue;
+            double x = v[c];
+            if ((lc.smask >> t) & 1u) x *= sc;
 #pragma unroll
             for (int p = 0; p < LC_MAX_OUT; ++p)
-                if (p < lc.nout) acc[p] += lc.W[p][t] * v;
+                if (p < lc.nout) acc[p] += lc.W[p][t] * x;
         }
+    }
+}
+
+// one field per blockIdx.y, cells over blockIdx.x (grid-stride)
+__global__ void __launch_bounds__(256) lincomb_kernel(LinComb lc) {
+    const int f = (int)blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < lc.ncells;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double acc[LC_MAX_OUT];
+        lincomb_element(lc, f, i, acc);
+        const int64_t e = (int64_t)f * lc.ncells + i;
 #pragma unroll
         for (int p = 0; p < LC_MAX_OUT; ++p)
             if (p < lc.nout) lc.out[p][e] = acc[p];
@@ -90,13 +114,17 @@ __global__ void __launch_bounds__(256) expand_kernel(int n_flames, const int64_t
 // ---------------------------------------------------------------------------
 // explicit operators
 // ---------------------------------------------------------------------------
+// one thread per cell; the stencil values of ten fields (every field of a
+// 9-species mechanism) are loaded before any result is stored
+constexpr int TRANSPORT_CHUNK = 10;
+
 template <bool FROM_T>
 __global__ void __launch_bounds__(256) transport_kernel(GridDev g, MechDev m, int64_t n,
                                                         const double* st, const double* T,
                                                         double* th, double* FA, double* FD) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    transport_cell<FROM_T>(g, m, n, st, T, th, FA, FD, i);
+    transport_cell<FROM_T, TRANSPORT_CHUNK>(g, m, n, st, T, th, FA, FD, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -124,28 +152,18 @@ __global__ void __launch_bounds__(256) faces_kernel(GridDev g, int64_t n, const 
 }
 
 // The right-hand side of a diffusion solve and, in the same pass, the face
-// coefficients of its lagged operator (cells are the elements of field 0).
+// coefficients of its lagged operator (by the blocks of field 0).
 __global__ void __launch_bounds__(256) lincomb_faces_kernel(LinComb lc, GridDev g, const double* T,
                                                             double* th, double* Kx, double* Ky,
                                                             unsigned* bar) {
-    const int64_t total = (int64_t)lc.nfields * lc.ncells;
-    const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e0 == 0 && bar) zero_barrier(bar);
-    for (int64_t e = e0; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int f = (int)(e / lc.ncells);
-        if (f == 0) faces_at(g, e, T, th, Kx, Ky);
+    const int f = (int)blockIdx.y;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f == 0 && i0 == 0 && bar) zero_barrier(bar);
+    for (int64_t i = i0; i < lc.ncells; i += (int64_t)gridDim.x * blockDim.x) {
+        if (f == 0) faces_at(g, i, T, th, Kx, Ky);
         double acc[LC_MAX_OUT];
-#pragma unroll
-        for (int p = 0; p < LC_MAX_OUT; ++p) acc[p] = 0.0;
-        const double sc = lc.smask ? lc.scale[e - (int64_t)f * lc.ncells] : 1.0;
-        for (int t = 0; t < lc.nterms; ++t) {
-            if (f >= lc.nf[t]) continue;
-            double v = lc.X[t][e];
-            if ((lc.smask >> t) & 1u) v *= sc;
-#pragma unroll
-            for (int p = 0; p < LC_MAX_OUT; ++p)
-                if (p < lc.nout) acc[p] += lc.W[p][t] * v;
-        }
+        lincomb_element(lc, f, i, acc);
+        const int64_t e = (int64_t)f * lc.ncells + i;
 #pragma unroll
         for (int p = 0; p < LC_MAX_OUT; ++p)
             if (p < lc.nout) lc.out[p][e] = acc[p];
@@ -313,6 +331,15 @@ GridDev grid_dev(const Grid& g) {
 
 }  // namespace
 
+// blocks of 256 cells along x (at most 65535; the kernels stride over the
+// rest), one field per y; x = 0 when the fields do not fit a grid's y range
+static dim3 lincomb_grid(const LinComb& lc) {
+    if (lc.nfields < 1 || lc.nfields > 65535) return dim3(0, 1, 1);
+    unsigned bx = grid_for(lc.ncells, 256);
+    if (bx > 65535u) bx = 65535u;
+    return dim3(bx, (unsigned)lc.nfields, 1);
+}
+
 int launch_copy(double* dst, const double* src, int64_t count, hipStream_t s) {
     if (count <= 0) return MISDC_OK;
     unsigned blocks = grid_for(count, 256);
@@ -365,9 +392,9 @@ int launch_lincomb_faces(const LinComb& lc, const Grid& g, const double* T_lag, 
                     lc.nout);
     if (lc.smask && !lc.scale) return fail(MISDC_EINVAL, "scaled terms without a scale array");
     if (lc.ncells != g.cells()) return fail(MISDC_EINVAL, "linear combination and grid differ");
-    unsigned blocks = grid_for(total, 256);
-    if (blocks > 65536u) blocks = 65536u;
-    hipLaunchKernelGGL(lincomb_faces_kernel, dim3(blocks), dim3(256), 0, s, lc, grid_dev(g), T_lag,
+    const dim3 grid = lincomb_grid(lc);
+    if (!grid.x) return fail(MISDC_EINVAL, "linear combination of %d fields", lc.nfields);
+    hipLaunchKernelGGL(lincomb_faces_kernel, grid, dim3(256), 0, s, lc, grid_dev(g), T_lag,
                        w.theta, w.Kx, w.Ky, w.barrier);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;
@@ -380,9 +407,9 @@ int launch_lincomb(const LinComb& lc, hipStream_t s) {
         return fail(MISDC_EINVAL, "linear combination too large (%d terms, %d outputs)", lc.nterms,
                     lc.nout);
     if (lc.smask && !lc.scale) return fail(MISDC_EINVAL, "scaled terms without a scale array");
-    unsigned blocks = grid_for(total, 256);
-    if (blocks > 65536u) blocks = 65536u;
-    hipLaunchKernelGGL(lincomb_kernel, dim3(blocks), dim3(256), 0, s, lc);
+    const dim3 grid = lincomb_grid(lc);
+    if (!grid.x) return fail(MISDC_EINVAL, "linear combination of %d fields", lc.nfields);
+    hipLaunchKernelGGL(lincomb_kernel, grid, dim3(256), 0, s, lc);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;
 }
