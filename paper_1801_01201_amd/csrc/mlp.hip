@@ -8,7 +8,7 @@
 // the plain guess leads to; only the iteration count can change.
 //
 // Every product runs on the matrix cores: BF16 operands with FP32
-// accumulation (16x16x16 MFMA), or FP32 operands (16x16x4 MFMA) in the FP32
+// accumulation (16x16x32 MFMA), or FP32 operands (16x16x4 MFMA) in the FP32
 // mode.  One tiled GEMM kernel serves all of them: C = A B with arbitrary
 // strides (transposed operands for the back-propagation), 128 x 128 output
 // tiles per 256-thread workgroup (each wavefront 4 x 4 MFMA tiles), K staged
@@ -29,7 +29,7 @@ namespace misdc {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // float -> bfloat16, round to nearest even (finite inputs)
 __device__ __forceinline__ uint16_t f2bf(float x) {
@@ -62,6 +62,7 @@ struct GemmArgs {
 // tile lies inside the matrix and the rows are 16-byte aligned, else one
 // element at a time with zero padding.
 constexpr int BM = 128, BN = 128, BK = 32, KP = BK + 8;    // LDS rows padded by 8 elements
+static_assert(BK % 32 == 0, "whole 16x16x32 BF16 products per K chunk");
 
 template <typename T>
 __device__ __forceinline__ void load_tile(T (*S)[KP], const T* X, int64_t s_row, int64_t s_k,
@@ -132,17 +133,20 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
         __syncthreads();
         if constexpr (sizeof(T) == 2) {
 #pragma unroll
-            for (int ks = 0; ks < BK; ks += 16) {
-                v4s a[4], b[4];
+            // gfx950's 16x16x32 BF16 product: each lane holds 8 consecutive k
+            // of its row (A) or column (B); A and B put the same k in the same
+            // slot, so the sum over the 32 slots is the dot product over k
+            for (int ks = 0; ks < BK; ks += 32) {
+                v8bf a[4], b[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) a[i] = *(const v4s*)&As[wr + 16 * i + li][ks + 4 * lk];
+                for (int i = 0; i < 4; ++i) a[i] = *(const v8bf*)&As[wr + 16 * i + li][ks + 8 * lk];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = *(const v4s*)&Bt[wc + 16 * j + li][ks + 4 * lk];
+                for (int j = 0; j < 4; ++j) b[j] = *(const v8bf*)&Bt[wc + 16 * j + li][ks + 8 * lk];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
             }
         } else {
 #pragma unroll
