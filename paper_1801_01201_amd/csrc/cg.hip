@@ -893,23 +893,32 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
     double r[NFD], u[NFD], w[NFD], zz[NFD], qq[NFD], ss[NFD], pp[NFD];
     unsigned kb = 0;
     // ---- r = b - A x0, u = M^-1 r (published), partial (b, b) ----
+    // every field's values are loaded before any is used, so the prologue
+    // waits for memory once (threads outside the grid load those of cell 0,
+    // which exist, and discard them)
+    {
+        double bv[NFD], xc[NFD], xe[NFD], xw[NFD], xn[NFD], xs[NFD];
 #pragma unroll
-    for (int d = 0; d < NFD; ++d) {
-        const size_t o = (size_t)a.fmap[d] * a.n;
-        const double* X = a.guess_in_x ? a.x + o : a.b + o;
-        r[d] = w[d] = zz[d] = qq[d] = ss[d] = pp[d] = 0.0;
-        xt[d * BS + threadIdx.x] = 0.0;
-        double bb = 0.0;
-        if (own) {
-            const double xi = X[cell];
-            const double Ax = xi - cf[d] * (ke * (X[ie] - xi) - kw * (xi - X[iw]) +
-                                            kn * (X[in_] - xi) - ks * (xi - X[is_]));
-            const double bi = a.b[o + cell];
-            xt[d * BS + threadIdx.x] = xi;
-            r[d] = bi - Ax;
-            bb = bi * bi;
+        for (int d = 0; d < NFD; ++d) {
+            const size_t o = (size_t)a.fmap[d] * a.n;
+            const double* X = a.guess_in_x ? a.x + o : a.b + o;
+            xc[d] = X[cell];
+            xe[d] = X[ie];
+            xw[d] = X[iw];
+            xn[d] = X[in_];
+            xs[d] = X[is_];
+            bv[d] = a.b[o + cell];
         }
-        wave_put<BS>(bb, red, d);
+#pragma unroll
+        for (int d = 0; d < NFD; ++d) {
+            const double xi = xc[d];
+            const double Ax = xi - cf[d] * (ke * (xe[d] - xi) - kw * (xi - xw[d]) +
+                                            kn * (xn[d] - xi) - ks * (xi - xs[d]));
+            w[d] = zz[d] = qq[d] = ss[d] = pp[d] = 0.0;
+            xt[d * BS + threadIdx.x] = own ? xi : 0.0;
+            r[d] = own ? bv[d] - Ax : 0.0;
+        }
+        wave_put_slots<BS, NFD>([&](int d) { return own ? bv[d] * bv[d] : 0.0; }, red);
     }
 #pragma unroll
     for (int d = 0; d < NFD; ++d) u[d] = 0.0;
@@ -1030,6 +1039,9 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
         // last one out adds them up, so nothing is waited for ----
         const int t = threadIdx.x;
         const bool inner = own && he && hw && hn && hs;
+        double bv[NFD];                               // loaded together (cell 0 off the grid)
+#pragma unroll
+        for (int d = 0; d < NFD; ++d) bv[d] = a.b[(size_t)a.fmap[d] * a.n + cell];
         wave_put_slots<BS, NFD>(
             [&](int d) {
                 if (!inner) return 0.0;
@@ -1038,7 +1050,7 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
                 const double Ax = xi - cf[d] * (ke * (Xt[t + 1] - xi) - kw * (xi - Xt[t - 1]) +
                                                 kn * (Xt[t + TILE_X] - xi) -
                                                 ks * (xi - Xt[t - TILE_X]));
-                const double res = a.b[(size_t)a.fmap[d] * a.n + cell] - Ax;
+                const double res = bv[d] - Ax;
                 return res * res;
             },
             red);
@@ -1076,21 +1088,37 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
         if (own) a.x[(size_t)a.fmap[d] * a.n + cell] = xt[d * BS + threadIdx.x];
     if (a.close && own) {
         // bath closure of this cell, then T and theta of the closed state
-        // (species in order, as a separate closure pass would take them)
+        // (species in order, as a separate closure pass would take them).
+        // The diffused fields are the N - 1 species other than the bath and
+        // h, so N = NFD here; the right-hand sides and the species tables
+        // are loaded together before they are used.
         const int t = threadIdx.x;
-        double sum = 0.0;
-        for (int k = 0; k < a.N; ++k) {
-            if (k == a.bath) continue;
-            sum += xt[a.dmap[k] * BS + t] - a.b[(size_t)k * a.n + cell];
+        double bk[NFD], hf_k[NFD], cp_k[NFD], iw_k[NFD];
+#pragma unroll
+        for (int k = 0; k < NFD; ++k) {
+            bk[k] = a.b[(size_t)k * a.n + cell];
+            hf_k[k] = a.hf[k];
+            cp_k[k] = a.cp[k];
+            iw_k[k] = a.invW[k];
         }
-        const double yb = a.b[(size_t)a.bath * a.n + cell] - sum;
+        double sum = 0.0, bb = 0.0;
+#pragma unroll
+        for (int k = 0; k < NFD; ++k) {
+            if (k == a.bath) {
+                bb = bk[k];
+                continue;
+            }
+            sum += xt[a.dmap[k] * BS + t] - bk[k];
+        }
+        const double yb = bb - sum;
         a.x[(size_t)a.bath * a.n + cell] = yb;
         if (a.T_out) {
             double hform = 0.0, cpm = 0.0;
-            for (int k = 0; k < a.N; ++k) {
+#pragma unroll
+            for (int k = 0; k < NFD; ++k) {
                 const double yk = (k == a.bath) ? yb : xt[a.dmap[k] * BS + t];
-                hform += yk * a.hf[k] * a.invW[k];
-                cpm += yk * a.cp[k] * a.invW[k];
+                hform += yk * hf_k[k] * iw_k[k];
+                cpm += yk * cp_k[k] * iw_k[k];
             }
             const double Ti = T_REF + (xt[a.dmap[a.N] * BS + t] - hform) / cpm;
             a.T_out[cell] = Ti;
