@@ -83,6 +83,12 @@ struct misdc_integ_s {
     std::vector<double*> phiAD, TAD, hatA, hatD;  // [M+1]
     std::vector<double*> C, CR;                   // [M+1] sweep constants (diffusion, reaction)
     double* rD = nullptr;                         // diffusion right-hand side (N+1 fields)
+    // split right-hand sides (split_rhs): every term but the lagged operators,
+    // one buffer per node parity, and the event that releases each
+    double* rP[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> evP;                  // [M+1]
+    std::vector<LagRhs> lagw;                     // [M+1] the second pass's weights
+    hipEvent_t ev_const = nullptr;                // the sweep constants are formed
     double* bR = nullptr;                         // reaction right-hand side (N fields)
     double* thD = nullptr;                        // theta work (diffusion stream)
     double* thR = nullptr;                        // theta work (reaction stream)
@@ -497,6 +503,55 @@ void diffusion_rhs(misdc_integ_s* I, int ell, int p, LC& b, double& cf_out,
     (void)M;
 }
 
+// Whether the right-hand side of the diffusion task at node p is formed in
+// two passes: every term but the lagged operators FA, FD at phi_AD^{p-1}
+// (eqs. initial_lagged_values_A/D) by a pass on the reaction stream while the
+// solve of node p-1 still runs, and those two terms (formed from phi_AD^{p-1}
+// itself, so no lag transport pass) with the face coefficients after it.
+// Concurrent scheme, first nested iteration, p >= 2, two-stream schedule, a
+// single grid: ensembles keep the one-pass form, which their persistent
+// stages (misdc_tune.fused) share, so that both give the same bits.
+bool split_rhs(const misdc_integ_s* I, int ell, int p) {
+    return I->opt.scheme == MISDC_SCHEME_CISDCQ && ell == 0 && p >= 2 && p <= I->M &&
+           !I->pipe && !I->fused && I->grid->n_flames == 0 && I->rP[0];
+}
+
+// The first pass of a split right-hand side (node p) on stream s: every term
+// but the lagged operators into rP[p & 1], and the initial guess.  Fills the
+// remaining terms' weights (qa, qd, scaled per cell or not) into lag.
+int partial_rhs(misdc_integ_s* I, int p, double dt, hipStream_t s, LagRhs& lag) {
+    const int NF = I->NF;
+    LC b(NF, I->n, dt, I->dtc);
+    double cf = 0.0;
+    const double* T_lag = nullptr;
+    diffusion_rhs(I, 0, p, b, cf, T_lag);
+    LinComb& lc = b.lc;
+    lc.out[0] = I->rP[p & 1];
+    lag = LagRhs();
+    for (int t = lc.nterms - 1; t >= 0; --t) {
+        const bool is_a = lc.X[t] == I->hatA[p - 1], is_d = lc.X[t] == I->hatD[p - 1];
+        if (!is_a && !is_d) continue;
+        if (lc.W[1][t] != 0.0) return fail(MISDC_EINVAL, "lagged operator in the guess");
+        (is_a ? lag.qa : lag.qd) = lc.W[0][t];
+        const bool scaled = (lc.smask >> t) & 1u;
+        if (scaled) lag.scale = I->dtc;
+        // drop term t
+        for (int u = t; u + 1 < lc.nterms; ++u) {
+            lc.X[u] = lc.X[u + 1];
+            lc.nf[u] = lc.nf[u + 1];
+            for (int q = 0; q < LC_MAX_OUT; ++q) lc.W[q][u] = lc.W[q][u + 1];
+        }
+        const unsigned low = lc.smask & ((1u << t) - 1u);
+        const unsigned high = (t + 1 < 32) ? ((lc.smask >> (t + 1)) << t) : 0u;
+        lc.smask = low | high;
+        --lc.nterms;
+    }
+    lag.src = I->phiAD[p - 1];
+    lag.part = I->rP[p & 1];
+    lag.T_lag = T_lag;
+    return launch_lincomb(lc, s);
+}
+
 int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     const int NF = I->NF;
     const int64_t n = I->n;
@@ -506,7 +561,15 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     LC b(NF, n, dt, I->dtc);
     diffusion_rhs(I, ell, p, b, cf, T_lag);
     int rc;
-    if (ell == 0 && p == 1 && I->d1_ready) {
+    if (split_rhs(I, ell, p)) {
+        // the first pass ran on the reaction stream (run_sweep); the lagged
+        // operators of node p-1 and the face coefficients now
+        MISDC_HIP(hipStreamWaitEvent(L.s, I->evP[p], 0));
+        LagRhs lag = I->lagw[p];
+        lag.th = L.th;
+        lag.out = L.rD;
+        if ((rc = launch_lag_rhs(*I->mech, *I->grid, lag, *L.dw, L.s))) return rc;
+    } else if (ell == 0 && p == 1 && I->d1_ready) {
         I->d1_ready = false;          // formed by the sweep constants' pass
     } else {
         // the same pass computes the face coefficients of the lagged operator
@@ -534,6 +597,7 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
 // reaction task of node p, which does not read them.
 int lag_transport(misdc_integ_s* I, int ell, int p) {
     if (I->opt.scheme != MISDC_SCHEME_CISDCQ || ell != 0 || p >= I->M) return MISDC_OK;
+    if (split_rhs(I, ell, p + 1)) return MISDC_OK;      // formed in D_{p+1}'s second pass
     const misdc_integ_s::DLane L = I->dlane(ell);
     return launch_transport(*I->mech, *I->grid, I->phiAD[p], I->TAD[p], I->hatA[p], I->hatD[p],
                             L.th, L.s, true);
@@ -858,6 +922,8 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
     }
     rc = sweep_constants(I, dt);
     if (rc) return rc;
+    // the first pass of D_2's split right-hand side reads the constants
+    if (split_rhs(I, 0, 2)) MISDC_HIP(hipEventRecord(I->ev_const, s0));
     if (I->opt.scheme == MISDC_SCHEME_IMEXQ) {
         for (int p = 1; p <= M; ++p)
             if ((rc = imexq_task(I, p, dt))) return rc;
@@ -902,6 +968,13 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
                     rc = reaction_task(I, ell, pr, dt);
                     if (rc) return rc;
                     MISDC_HIP(hipEventRecord(I->R_ev(ell + 1, pr), sr));
+                }
+                // the first pass of D_{s+2}'s split right-hand side, which
+                // reads R_s's outputs, while D_{s+1}'s solve runs
+                if (split_rhs(I, ell, s + 2)) {
+                    if (s == 0) MISDC_HIP(hipStreamWaitEvent(sr, I->ev_const, 0));
+                    if ((rc = partial_rhs(I, s + 2, dt, sr, I->lagw[s + 2]))) return rc;
+                    MISDC_HIP(hipEventRecord(I->evP[s + 2], sr));
                 }
             }
             if (adapt && ell + 1 < nu) {
@@ -1780,6 +1853,10 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
         if ((rc = dalloc(I, &I->CR[p], (size_t)N * n))) return bail(rc);
     }
     if ((rc = dalloc(I, &I->rD, (size_t)NF * n))) return bail(rc);
+    if (opts->scheme == MISDC_SCHEME_CISDCQ && M >= 2)
+        for (auto& r : I->rP)
+            if ((rc = dalloc(I, &r, (size_t)NF * n))) return bail(rc);
+    I->lagw.assign(M + 1, LagRhs());
     if ((rc = dalloc(I, &I->bR, (size_t)N * n))) return bail(rc);
     if ((rc = dalloc(I, &I->thD, (size_t)n))) return bail(rc);
     if ((rc = dalloc(I, &I->thR, (size_t)n))) return bail(rc);
@@ -1832,6 +1909,10 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_outR, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_const, hipEventDisableTiming);
+    I->evP.assign(M + 1, nullptr);
+    for (int p = 0; p <= M && e == hipSuccess; ++p)
+        e = hipEventCreateWithFlags(&I->evP[p], hipEventDisableTiming);
     if (e != hipSuccess) return bail(fail(MISDC_EDEVICE, "events: %s", hipGetErrorString(e)));
     if (opts->pipeline && (rc = create_lanes(I))) return bail(rc);
     if (opts->scheme == MISDC_SCHEME_IMEXQ && (rc = coupled_work_alloc(I->cw, mech->m, grid->g)))
@@ -1890,6 +1971,9 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (I->ev_outR) (void)hipEventDestroy(I->ev_outR);
     if (I->ev_fork) (void)hipEventDestroy(I->ev_fork);
     if (I->ev_join) (void)hipEventDestroy(I->ev_join);
+    if (I->ev_const) (void)hipEventDestroy(I->ev_const);
+    for (hipEvent_t ev : I->evP)
+        if (ev) (void)hipEventDestroy(ev);
     // only the streams the library created (a caller's streams stay theirs)
     if (I->sR2_own) (void)hipStreamDestroy(I->sR2_own);
     if (I->sRm) (void)hipStreamDestroy(I->sRm);

@@ -256,6 +256,23 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
 // with faces_ready
 int launch_lincomb_faces(const LinComb& lc, const Grid& g, const double* T_lag, DiffusionWork& w,
                          hipStream_t s);
+// The last step of a diffusion right-hand side split in two passes: out =
+// part + scale (qa FA(src) + qd FD(src)) for the N+1 fields of a state src
+// whose theta is th (the lagged operators of the concurrent scheme's first
+// nested iteration), with the face coefficients of the solve's lagged
+// operator at T_lag in the same pass, for a solve called with faces_ready.
+// part holds every other term, formed earlier by launch_lincomb; scale (may
+// be null) is the per-cell factor of dt-carrying terms.
+struct LagRhs {
+    const double* src = nullptr;
+    const double* th = nullptr;
+    const double* part = nullptr;
+    double* out = nullptr;
+    double qa = 0.0, qd = 0.0;
+    const double* scale = nullptr;
+    const double* T_lag = nullptr;
+};
+int launch_lag_rhs(const Mech& m, const Grid& g, const LagRhs& a, DiffusionWork& w, hipStream_t s);
 
 // max_i |a - b| and max_i |a| per field into out[2*f], out[2*f+1] (device);
 // partial holds nfields * partial_blocks * 2 doubles followed by a zeroed

@@ -170,6 +170,62 @@ __global__ void __launch_bounds__(256) lincomb_faces_kernel(LinComb lc, GridDev 
     }
 }
 
+// out = part + scale (qa FA + qd FD) of every field at one cell, FA and FD
+// at src (theta from th), the stencil values of all fields loaded before any
+// is used (as in transport_fields); the face coefficients of the lagged
+// operator at T in the same pass (see launch_lag_rhs)
+template <bool TWO_D>
+__device__ __forceinline__ void lag_rhs_cell(const Stencil& s, const MechDev& m, int64_t n,
+                                             const LagRhs& a, double sc, int64_t i) {
+    constexpr int CH = TRANSPORT_CHUNK;
+    const int NF = m.N + 1;
+    const double wa = sc * a.qa, wd = sc * a.qd;
+    double fd_sum = 0.0, fa_bath = 0.0, part_bath = 0.0;
+    for (int f0 = 0; f0 < NF; f0 += CH) {
+        double v[CH][9], pv[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int f = f0 + c < NF ? f0 + c : NF - 1;
+            load_stencil<TWO_D>(s, a.src + (size_t)f * n, i, v[c]);
+            pv[c] = a.part[(size_t)f * n + i];
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int f = f0 + c;
+            if (f >= NF) continue;
+            double fa, lap;
+            field_ops<TWO_D>(s, v[c], fa, lap);
+            if (f == m.bath) {
+                fa_bath = fa;
+                part_bath = pv[c];
+                continue;
+            }
+            const double fd = m.kappa0[f] * lap;
+            if (f < m.N) fd_sum += fd;
+            a.out[(size_t)f * n + i] = pv[c] + (wa * fa + wd * fd);
+        }
+    }
+    a.out[(size_t)m.bath * n + i] = part_bath + (wa * fa_bath + wd * -fd_sum);
+}
+
+__global__ void __launch_bounds__(256) lag_rhs_kernel(GridDev g, MechDev m, int64_t n, LagRhs a,
+                                                      double* th_out, double* Kx, double* Ky,
+                                                      unsigned* bar) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the persistent CG kernel that follows on this stream counts its grid
+    // barriers from zero
+    if (i == 0 && bar) zero_barrier(bar);
+    if (i >= n) return;
+    faces_at(g, i, a.T_lag, th_out, Kx, Ky);
+    auto theta = [&](int64_t j) { return a.th[j]; };
+    const Stencil s = stencil_at(g, i, a.th[i], theta);
+    const double sc = a.scale ? a.scale[i] : 1.0;
+    if (s.two_d)
+        lag_rhs_cell<true>(s, m, n, a, sc, i);
+    else
+        lag_rhs_cell<false>(s, m, n, a, sc, i);
+}
+
 // Cyclic tridiagonal solve of (I - cf L) y = r on one periodic 1-D system per
 // thread: Thomas' algorithm on the tridiagonal part plus a Sherman-Morrison
 // correction for the two corner entries.  Work arrays w1, w2 (same layout as
@@ -396,6 +452,17 @@ int launch_lincomb_faces(const LinComb& lc, const Grid& g, const double* T_lag, 
     if (!grid.x) return fail(MISDC_EINVAL, "linear combination of %d fields", lc.nfields);
     hipLaunchKernelGGL(lincomb_faces_kernel, grid, dim3(256), 0, s, lc, grid_dev(g), T_lag,
                        w.theta, w.Kx, w.Ky, w.barrier);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
+int launch_lag_rhs(const Mech& m, const Grid& g, const LagRhs& a, DiffusionWork& w, hipStream_t s) {
+    const int64_t n = g.cells();
+    if (n == 0) return MISDC_OK;
+    if (!a.src || !a.th || !a.part || !a.out || !a.T_lag)
+        return fail(MISDC_EINVAL, "split right-hand side: missing array");
+    hipLaunchKernelGGL(lag_rhs_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, grid_dev(g), m.dev,
+                       n, a, w.theta, w.Kx, w.Ky, w.barrier);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;
 }
