@@ -204,7 +204,11 @@ int launch_reaction_newton(const Mech& m, const NewtonArgs& a, hipStream_t s) {
             const int rc = launch_copy(a.h_out, a.h, a.n, s);
             if (rc) return rc;
         }
-        return launch_reaction_newton_wave(m, a, a.opt.lu, s);
+        if (a.th_out && !a.T)
+            return fail(MISDC_EINVAL, "theta of the reaction solve's result needs its T");
+        const int rc = launch_reaction_newton_wave(m, a, a.opt.lu, s);
+        if (rc || !a.th_out) return rc;
+        return launch_theta(a.n, a.T, a.th_out, s);
     }
     if (m.dev.N != 9)
         return fail(MISDC_EUNSUPPORTED, "per-thread reaction solve: %d species not built", m.dev.N);

@@ -307,6 +307,7 @@ __device__ __forceinline__ int newton_cell(const MechDev& m, const NewtonArgs& a
     const double Tc = temperature_of<NS>(m, Y, h);
     if (a.T) a.T[i] = Tc;
     if (a.h_out) a.h_out[i] = h;
+    if (a.th_out) a.th_out[i] = pow(Tc / T_DIFF_REF, THETA_EXP);
     if (a.FR) {
         double FR[NS], J[1][NS + 1];
         reaction_terms<NS, false>(m, Y, Tc, FR, J);

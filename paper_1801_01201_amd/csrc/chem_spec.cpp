@@ -376,6 +376,7 @@ std::string generate(const MechHost& m) {
     for (int q = 0; q < NR; ++q) emit(s, "    D[%d] = M[%d][NX];\n", rs[q], q);
     emit(s, "    D[%d] = db;\n}\n", b);
     emit(s, "#define WAVES_PER_EU %d\n", NEWTON_SPEC_WAVES_PER_EU);
+    emit(s, "constexpr double T_DIFF_REF = %.17g, THETA_EXP = %.17g;\n", T_DIFF_REF, THETA_EXP);
     emit(s, "constexpr int TILE_X = %d, TILE_Y = %d;\n", NEWTON_TILE_X, NEWTON_TILE_Y);
     emit(s, "constexpr int BUCKETS = %d, BUCKET_STRIDE = %d, HIST_SETS = %d, HIST_BINS = %d;\n",
          NEWTON_BUCKETS, NEWTON_BUCKET_STRIDE, NEWTON_HIST_SETS, NEWTON_HIST_BINS);
@@ -384,7 +385,7 @@ std::string generate(const MechHost& m) {
 extern "C" __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
 newton_spec(
         i64 n, const double* bY, i64 ldb, const double* hp, const double* cp, double c_scalar,
-        const double* guess, i64 ldg, double* Yo, i64 ldy, double* To, double* Ho, double* FRo, i64 ldf,
+        const double* guess, i64 ldg, double* Yo, i64 ldy, double* To, double* Ho, double* Tho, double* FRo, i64 ldf,
         int* iters, u64* buckets, u64* hist, int tile_nx, int tile_ny, double tol, int maxit,
         double dtau0, double dtau_max, double neg_slack) {
     i64 i;
@@ -462,6 +463,7 @@ newton_spec(
         const double Tc = temperature_of(Y, h);
         if (To) To[i] = Tc;
         if (Ho) Ho[i] = h;
+        if (Tho) Tho[i] = pow(Tc / T_DIFF_REF, THETA_EXP);
         if (FRo) {
             double F[NS];
             int kz;
@@ -622,6 +624,7 @@ int launch_newton_spec(const Mech& m, const NewtonArgs& a, hipStream_t s) {
     double* Yo = a.Y;
     double* To = a.T;
     double* Ho = a.h_out;
+    double* Tho = a.th_out;
     double* FRo = a.FR;
     int* iters = a.iters;
     unsigned long long* buckets = a.buckets;
@@ -629,7 +632,7 @@ int launch_newton_spec(const Mech& m, const NewtonArgs& a, hipStream_t s) {
     int tnx = a.tile_nx, tny = a.tile_ny;
     double tol = a.opt.tol, dtau0 = a.opt.dtau0, dtau_max = a.opt.dtau_max, slack = a.opt.neg_slack;
     int maxit = a.opt.maxit;
-    void* args[] = {&n, &bY, &ldb, &hp, &cp, &c_scalar, &guess, &ldg, &Yo, &ldy, &To, &Ho, &FRo, &ldf,
+    void* args[] = {&n, &bY, &ldb, &hp, &cp, &c_scalar, &guess, &ldg, &Yo, &ldy, &To, &Ho, &Tho, &FRo, &ldf,
                     &iters, &buckets, &hist, &tnx, &tny, &tol, &maxit, &dtau0, &dtau_max, &slack};
     MISDC_HIP(hipModuleLaunchKernel((hipFunction_t)m.spec_fn, (unsigned)blocks, 1, 1, 64, 1, 1, 0,
                                     s, args, nullptr));

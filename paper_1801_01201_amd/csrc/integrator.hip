@@ -88,6 +88,29 @@ struct misdc_integ_s {
     double* rP[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> evP;                  // [M+1]
     std::vector<LagRhs> lagw;                     // [M+1] the second pass's weights
+    // split sweep constants (split_constants): the next sweep's constants
+    // and D_1's right-hand side without the node-M terms, formed on the
+    // reaction stream during the last solve of a sweep; the node-M terms of
+    // C^1..C^M after R_M (cfin), those of D_1 in D_1's own pass (d1w) after
+    // R_M's Newton solve (ev_newtonM)
+    bool consts_ready = false, d1_split = false, const_on_r = false, prep_newton = false;
+    LinComb cfin;
+    LagRhs d1w;
+    hipEvent_t ev_newtonM = nullptr;
+    double* thM = nullptr;                        // theta of R_M's result (from its solve)
+    // R_M's transport operators, the node-M terms of C^1..C^M and the sweep
+    // increment, deferred until D_1's pass of the next sweep is issued (so
+    // that they do not run beside it); ev_d1 follows that pass
+    struct Deferred {
+        bool pending = false, cfin = false, inc = false;
+        NodeBuf out;
+        double* th = nullptr;
+        hipStream_t s = nullptr;
+        const double* inc_new = nullptr;
+        const double* inc_old = nullptr;
+        double* inc_out = nullptr;
+    } dfr;
+    hipEvent_t ev_d1 = nullptr;
     hipEvent_t ev_const = nullptr;                // the sweep constants are formed
     double* bR = nullptr;                         // reaction right-hand side (N fields)
     double* thD = nullptr;                        // theta work (diffusion stream)
@@ -516,6 +539,19 @@ bool split_rhs(const misdc_integ_s* I, int ell, int p) {
            !I->pipe && !I->fused && I->grid->n_flames == 0 && I->rP[0];
 }
 
+// Removes term t of a linear combination.
+void drop_term(LinComb& lc, int t) {
+    for (int u = t; u + 1 < lc.nterms; ++u) {
+        lc.X[u] = lc.X[u + 1];
+        lc.nf[u] = lc.nf[u + 1];
+        for (int q = 0; q < LC_MAX_OUT; ++q) lc.W[q][u] = lc.W[q][u + 1];
+    }
+    const unsigned low = lc.smask & ((1u << t) - 1u);
+    const unsigned high = (t + 1 < 32) ? ((lc.smask >> (t + 1)) << t) : 0u;
+    lc.smask = low | high;
+    --lc.nterms;
+}
+
 // The first pass of a split right-hand side (node p) on stream s: every term
 // but the lagged operators into rP[p & 1], and the initial guess.  Fills the
 // remaining terms' weights (qa, qd, scaled per cell or not) into lag.
@@ -535,16 +571,7 @@ int partial_rhs(misdc_integ_s* I, int p, double dt, hipStream_t s, LagRhs& lag) 
         (is_a ? lag.qa : lag.qd) = lc.W[0][t];
         const bool scaled = (lc.smask >> t) & 1u;
         if (scaled) lag.scale = I->dtc;
-        // drop term t
-        for (int u = t; u + 1 < lc.nterms; ++u) {
-            lc.X[u] = lc.X[u + 1];
-            lc.nf[u] = lc.nf[u + 1];
-            for (int q = 0; q < LC_MAX_OUT; ++q) lc.W[q][u] = lc.W[q][u + 1];
-        }
-        const unsigned low = lc.smask & ((1u << t) - 1u);
-        const unsigned high = (t + 1 < 32) ? ((lc.smask >> (t + 1)) << t) : 0u;
-        lc.smask = low | high;
-        --lc.nterms;
+        drop_term(lc, t);
     }
     lag.src = I->phiAD[p - 1];
     lag.part = I->rP[p & 1];
@@ -561,7 +588,15 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     LC b(NF, n, dt, I->dtc);
     diffusion_rhs(I, ell, p, b, cf, T_lag);
     int rc;
-    if (split_rhs(I, ell, p)) {
+    if (ell == 0 && p == 1 && I->d1_split) {
+        // the terms of node M (prepare_constants), once R_M's solve is done
+        I->d1_split = false;
+        MISDC_HIP(hipStreamWaitEvent(L.s, I->ev_newtonM, 0));
+        LagRhs d1 = I->d1w;
+        d1.out = L.rD;
+        if ((rc = launch_lag_rhs(*I->mech, *I->grid, d1, *L.dw, L.s))) return rc;
+        MISDC_HIP(hipEventRecord(I->ev_d1, L.s));
+    } else if (split_rhs(I, ell, p)) {
         // the first pass ran on the reaction stream (run_sweep); the lagged
         // operators of node p-1 and the face coefficients now
         MISDC_HIP(hipStreamWaitEvent(L.s, I->evP[p], 0));
@@ -686,6 +721,8 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
         a.tile_ny = (int)I->grid->ny;
     }
     a.opt = I->opt.newton;
+    const bool last_prep = (p == I->M && I->prep_newton);
+    if (last_prep) a.th_out = I->thM;
     // staggered: the Newton solve of node p starts once the diffusion solve
     // of node p+1 (issued just before this task) is about to start, so that
     // the persistent solve's workgroups take their CUs before the Newton
@@ -696,6 +733,11 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
     rc = launch_reaction_newton(*I->mech, a, L.s);
     if (rc) return rc;
     timing_end(I, t0, L.s, 1);
+    if (last_prep) {
+        // the next sweep's first diffusion pass needs this solve's outputs only
+        MISDC_HIP(hipEventRecord(I->ev_newtonM, L.s));
+        I->prep_newton = false;
+    }
     if (I->rec_buf && I->rec_count < I->rec_cap) {
         // record (b_Y, h, c, Y) of this reaction task
         double* slot = I->rec_buf + (size_t)I->rec_count * (2 * N + 2) * n;
@@ -704,6 +746,14 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
         if ((rc = launch_fill_c(n, I->dtc, c_scalar, slot + (size_t)(N + 1) * n, L.s))) return rc;
         if ((rc = launch_copy(slot + (size_t)(N + 2) * n, out.phi, (int64_t)N * n, L.s))) return rc;
         ++I->rec_count;
+    }
+    if (last_prep) {
+        // after the next sweep's first diffusion pass (flush_deferred)
+        I->dfr.pending = true;
+        I->dfr.out = out;
+        I->dfr.th = L.th;
+        I->dfr.s = L.s;
+        return MISDC_OK;
     }
     rc = eval_ops(I, out, L.th, L.s, false);
     (void)NF;
@@ -749,7 +799,9 @@ int imexq_task(misdc_integ_s* I, int p, double dt) {
 }
 
 // sweep-start constants (all terms of sweep k)
-int sweep_constants(misdc_integ_s* I, double dt) {
+// The sweep constants C^1..C^M as one linear combination of the state at
+// node 0 and F at the nodes of lev[0] (the sweep just finished).
+LC constants_lc(misdc_integ_s* I, double dt) {
     const int M = I->M, N = I->N, NF = I->NF;
     const int64_t n = I->n;
     const Tables& t = I->tab;
@@ -783,6 +835,15 @@ int sweep_constants(misdc_integ_s* I, double dt) {
             }
         }
     }
+    return b;
+}
+
+int sweep_constants(misdc_integ_s* I, double dt) {
+    const int M = I->M, N = I->N;
+    const int64_t n = I->n;
+    const Tables& t = I->tab;
+    auto& L0 = I->lev[0];
+    LC b = constants_lc(I, dt);
     int rc;
     if (I->opt.scheme == MISDC_SCHEME_MISDCQ) {
         LC r(N, n, dt, I->dtc);
@@ -810,6 +871,82 @@ int sweep_constants(misdc_integ_s* I, double dt) {
         }
     }
     return launch_lincomb(b.lc, I->dlane(0).s);
+}
+
+// Whether the next sweep's constants are formed in the split form
+// (prepare_constants); the same conditions as split right-hand sides, a
+// fixed number of nested iterations, and C^1..C^M, D_1's right-hand side and
+// its guess in one pass.
+bool split_constants(const misdc_integ_s* I) {
+    return split_rhs(I, 0, 2) && !(I->opt.nu_tol > 0 && I->nu >= 3) && I->M + 2 <= LC_MAX_OUT &&
+           !I->dtc;
+}
+
+// Issued on the reaction stream s before R_M of the sweep's last nested
+// iteration (whose results are lev[lv]): the next sweep's constants and
+// D_1's right-hand side (C^1 folded in) and guess, without the terms of node
+// M.  Those terms follow: C^1..C^M's in cfin (after R_M), D_1's in its own
+// pass (d1w, after R_M's Newton solve).  Leaves consts_ready false where the
+// terms do not fit one pass.
+int prepare_constants(misdc_integ_s* I, double dt, int lv, hipStream_t s) {
+    const int M = I->M, NF = I->NF;
+    // the next sweep's view of the levels (undone below)
+    for (int p = 1; p <= M; ++p) std::swap(I->lev[0][p], I->lev[lv][p]);
+    LC b = constants_lc(I, dt);
+    LC f = b;
+    f.fold = true;
+    double cf = 0.0;
+    const double* T_lag = nullptr;
+    diffusion_rhs(I, 0, 1, f, cf, T_lag);
+    const NodeBuf bM = I->lev[0][M];
+    for (int p = 1; p <= M; ++p) std::swap(I->lev[0][p], I->lev[lv][p]);
+    LinComb& lc = f.lc;
+    if (lc.nterms > LC_MAX_TERMS || lc.nout > LC_MAX_OUT || lc.smask) return MISDC_OK;
+    int o1 = -1;
+    for (int o = 0; o < lc.nout; ++o)
+        if (lc.out[o] == I->dlane(0).rD) o1 = o;
+    if (o1 < 0) return MISDC_OK;
+    // the completion of C^p: C^p plus its node-M terms
+    LC c(NF, I->n, 1.0, nullptr);
+    for (int p = 1; p <= M; ++p) {
+        const int o = c.out(I->C[p]);
+        c.add(o, 1.0, I->C[p], NF);
+    }
+    LagRhs d1;
+    const double* node_m[3] = {bM.FA, bM.FD, bM.FR};
+    for (int t = lc.nterms - 1; t >= 0; --t) {
+        int k = -1;
+        for (int q = 0; q < 3; ++q)
+            if (lc.X[t] == node_m[q]) k = q;
+        if (k < 0) continue;
+        for (int o = 0; o < lc.nout; ++o) {
+            const double w = lc.W[o][t];
+            if (w == 0.0) continue;
+            if (o == o1) {
+                (k == 0 ? d1.qa : k == 1 ? d1.qd : d1.qr) = w;
+            } else if (o < M && lc.out[o] == I->C[o + 1]) {
+                c.add(o, w, lc.X[t], lc.nf[t]);
+            } else {
+                return fail(MISDC_EINVAL, "node-M term in output %d of the sweep constants", o);
+            }
+        }
+        drop_term(lc, t);
+    }
+    if (c.lc.nterms > LC_MAX_TERMS) return MISDC_OK;
+    lc.out[o1] = I->rP[1];
+    int rc = launch_lincomb(lc, s);
+    if (rc) return rc;
+    d1.src = bM.phi;
+    d1.th = I->thM;                   // written by R_M's solve
+    d1.fr = bM.FR;
+    d1.part = I->rP[1];
+    d1.T_lag = T_lag;
+    I->d1w = d1;
+    I->cfin = c.lc;
+    I->dfr.cfin = true;
+    I->consts_ready = true;
+    I->prep_newton = true;
+    return MISDC_OK;
 }
 
 // max over fields of max_i |new - old| / max_i |new| from the (difference,
@@ -906,7 +1043,30 @@ int fused_stage(misdc_integ_s* I, int ell, int s, double dt) {
     return MISDC_OK;
 }
 
-int run_sweep(misdc_integ_s* I, int k, double dt) {
+// Issues the work deferred from a sweep's R_M (see Deferred) on its stream,
+// after the event 'after' (may be null).
+int flush_deferred(misdc_integ_s* I, hipEvent_t after) {
+    auto& d = I->dfr;
+    if (!d.pending) return MISDC_OK;
+    d.pending = false;
+    if (after) MISDC_HIP(hipStreamWaitEvent(d.s, after, 0));
+    int rc = eval_ops(I, d.out, d.th, d.s, false);
+    if (rc) return rc;
+    if (d.cfin && (rc = launch_lincomb(I->cfin, d.s))) return rc;
+    d.cfin = false;
+    if (d.inc) {
+        d.inc = false;
+        rc = launch_field_diff_max(I->NF, I->n, d.inc_new, d.inc_old, I->inc_partial,
+                                   I->inc_blocks, d.inc_out, d.s);
+    }
+    return rc;
+}
+
+// prep_next: another sweep of this step may follow (its constants can be
+// prepared during this sweep's last solve); defer_inc: the sweep increment
+// may be deferred with R_M's work (not when the caller reads it between
+// sweeps)
+int run_sweep(misdc_integ_s* I, int k, double dt, bool prep_next, bool defer_inc) {
     const int M = I->M;
     const int nu = (I->opt.scheme == MISDC_SCHEME_CISDCQ) ? I->nu : 1;
     int done = nu;                    // nested iterations done in this sweep
@@ -915,15 +1075,24 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
     // pipelined passes they also wait for every lane's last work of it,
     // since this sweep's tasks overwrite buffers those lanes read
     const hipStream_t s0 = I->dlane(0).s;
-    MISDC_HIP(hipStreamWaitEvent(s0, I->R_ev(0, M), 0));
-    if (I->pipe && k > 0) {
-        MISDC_HIP(hipStreamWaitEvent(s0, I->pd_lane[1].end, 0));
-        for (auto& r : I->pr_lane) MISDC_HIP(hipStreamWaitEvent(s0, r.end, 0));
+    // constants prepared by the previous sweep (prepare_constants): they are
+    // complete on the reaction stream, which every later reader follows, and
+    // D_1 waits for R_M's solve only
+    const bool pre = I->consts_ready;
+    I->consts_ready = false;
+    I->const_on_r = pre;
+    I->d1_split = pre;
+    if (!pre) {
+        MISDC_HIP(hipStreamWaitEvent(s0, I->R_ev(0, M), 0));
+        if (I->pipe && k > 0) {
+            MISDC_HIP(hipStreamWaitEvent(s0, I->pd_lane[1].end, 0));
+            for (auto& r : I->pr_lane) MISDC_HIP(hipStreamWaitEvent(s0, r.end, 0));
+        }
+        rc = sweep_constants(I, dt);
+        if (rc) return rc;
+        // the first pass of D_2's split right-hand side reads the constants
+        if (split_rhs(I, 0, 2)) MISDC_HIP(hipEventRecord(I->ev_const, s0));
     }
-    rc = sweep_constants(I, dt);
-    if (rc) return rc;
-    // the first pass of D_2's split right-hand side reads the constants
-    if (split_rhs(I, 0, 2)) MISDC_HIP(hipEventRecord(I->ev_const, s0));
     if (I->opt.scheme == MISDC_SCHEME_IMEXQ) {
         for (int p = 1; p <= M; ++p)
             if ((rc = imexq_task(I, p, dt))) return rc;
@@ -961,9 +1130,16 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
                     rc = diffusion_task(I, ell, pd, dt);
                     if (rc) return rc;
                     MISDC_HIP(hipEventRecord(I->D_ev(ell + 1, pd), sd));
+                    // the previous sweep's deferred R_M work, after D_1's pass
+                    if (ell == 0 && pd == 1 && (rc = flush_deferred(I, I->ev_d1))) return rc;
                     if ((rc = lag_transport(I, ell, pd))) return rc;
                 }
                 if (pr >= 1) {
+                    // the next sweep's constants but for node M's terms, while
+                    // D_M's solve runs
+                    if (pr == M && prep_next && ell == nu - 1 && split_constants(I) &&
+                        (rc = prepare_constants(I, dt, ell + 1, sr)))
+                        return rc;
                     MISDC_HIP(hipStreamWaitEvent(sr, I->D_ev(ell + 1, pr), 0));
                     rc = reaction_task(I, ell, pr, dt);
                     if (rc) return rc;
@@ -972,7 +1148,7 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
                 // the first pass of D_{s+2}'s split right-hand side, which
                 // reads R_s's outputs, while D_{s+1}'s solve runs
                 if (split_rhs(I, ell, s + 2)) {
-                    if (s == 0) MISDC_HIP(hipStreamWaitEvent(sr, I->ev_const, 0));
+                    if (s == 0 && !I->const_on_r) MISDC_HIP(hipStreamWaitEvent(sr, I->ev_const, 0));
                     if ((rc = partial_rhs(I, s + 2, dt, sr, I->lagw[s + 2]))) return rc;
                     MISDC_HIP(hipEventRecord(I->evP[s + 2], sr));
                 }
@@ -1008,10 +1184,18 @@ int run_sweep(misdc_integ_s* I, int k, double dt) {
     // released before the increment below (which reads buffers that only
     // later work of this same stream overwrites)
     MISDC_HIP(hipEventRecord(I->R_ev(0, M), se));
-    // sweep increment at node M (reaction stream, after the last reaction task)
-    rc = launch_field_diff_max(I->NF, I->n, I->lev[lv][M].phi, I->lev[0][M].phi, I->inc_partial,
-                               I->inc_blocks, I->inc + (size_t)k * I->NF * 2, se);
-    if (rc) return rc;
+    // sweep increment at node M (reaction stream, after the last reaction
+    // task; deferred with R_M's transport when that is)
+    if (I->dfr.pending && defer_inc) {
+        I->dfr.inc = true;
+        I->dfr.inc_new = I->lev[lv][M].phi;
+        I->dfr.inc_old = I->lev[0][M].phi;
+        I->dfr.inc_out = I->inc + (size_t)k * I->NF * 2;
+    } else {
+        rc = launch_field_diff_max(I->NF, I->n, I->lev[lv][M].phi, I->lev[0][M].phi,
+                                   I->inc_partial, I->inc_blocks, I->inc + (size_t)k * I->NF * 2, se);
+        if (rc) return rc;
+    }
     if (I->pipe) {
         for (auto& d : I->pd_lane) MISDC_HIP(hipEventRecord(d.end, d.s));
         for (auto& r : I->pr_lane) MISDC_HIP(hipEventRecord(r.end, r.s));
@@ -1116,6 +1300,8 @@ int issue_begin(misdc_integ_s* I, double* state, double dt, const double* dtf, i
         for (hipStream_t s : I->lane_streams) MISDC_HIP(hipStreamWaitEvent(s, I->ev_fork, 0));
     }
     I->s_last = I->sR;
+    I->consts_ready = I->d1_split = I->const_on_r = I->prep_newton = false;
+    I->dfr = misdc_integ_s::Deferred();
     I->dtf = dtf;
     I->dtc = nullptr;
     if (dtf) {
@@ -1168,7 +1354,8 @@ int issue_begin(misdc_integ_s* I, double* state, double dt, const double* dtf, i
 // The end of a step: node M of the last sweep back into the state, and the
 // reaction stream joins sD.
 int issue_end(misdc_integ_s* I, double* state) {
-    int rc;
+    int rc = flush_deferred(I, nullptr);
+    if (rc) return rc;
     const hipStream_t se = I->s_last;         // after the last reaction task
     if ((rc = launch_copy(state, I->lev[0][I->M].phi, (int64_t)I->NF * I->n, se))) return rc;
     if (se != I->sD) {
@@ -1193,7 +1380,7 @@ int issue_step(misdc_integ_s* I, double* state, double dt, const double* dtf) {
     if (rc) return rc;
     for (int k = 0; k < I->opt.n_sweeps; ++k) {
         I->sweep_index = k;
-        if ((rc = run_sweep(I, k, dts))) return rc;
+        if ((rc = run_sweep(I, k, dts, k + 1 < I->opt.n_sweeps, true))) return rc;
     }
     return issue_end(I, state);
 }
@@ -1853,9 +2040,11 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
         if ((rc = dalloc(I, &I->CR[p], (size_t)N * n))) return bail(rc);
     }
     if ((rc = dalloc(I, &I->rD, (size_t)NF * n))) return bail(rc);
-    if (opts->scheme == MISDC_SCHEME_CISDCQ && M >= 2)
+    if (opts->scheme == MISDC_SCHEME_CISDCQ && M >= 2) {
         for (auto& r : I->rP)
             if ((rc = dalloc(I, &r, (size_t)NF * n))) return bail(rc);
+        if ((rc = dalloc(I, &I->thM, (size_t)n))) return bail(rc);
+    }
     I->lagw.assign(M + 1, LagRhs());
     if ((rc = dalloc(I, &I->bR, (size_t)N * n))) return bail(rc);
     if ((rc = dalloc(I, &I->thD, (size_t)n))) return bail(rc);
@@ -1910,6 +2099,8 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_const, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_newtonM, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_d1, hipEventDisableTiming);
     I->evP.assign(M + 1, nullptr);
     for (int p = 0; p <= M && e == hipSuccess; ++p)
         e = hipEventCreateWithFlags(&I->evP[p], hipEventDisableTiming);
@@ -1972,6 +2163,8 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (I->ev_fork) (void)hipEventDestroy(I->ev_fork);
     if (I->ev_join) (void)hipEventDestroy(I->ev_join);
     if (I->ev_const) (void)hipEventDestroy(I->ev_const);
+    if (I->ev_newtonM) (void)hipEventDestroy(I->ev_newtonM);
+    if (I->ev_d1) (void)hipEventDestroy(I->ev_d1);
     for (hipEvent_t ev : I->evP)
         if (ev) (void)hipEventDestroy(ev);
     // only the streams the library created (a caller's streams stay theirs)
@@ -2058,7 +2251,7 @@ int misdc_sweep(misdc_integ_t I, void* stream) {
     MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_in, 0));
     const int k = I->open_sweeps;
     I->sweep_index = k;
-    int rc = run_sweep(I, k, I->open_dt);
+    int rc = run_sweep(I, k, I->open_dt, true, false);
     if (rc) return rc;
     I->open_sweeps = k + 1;
     I->last_sweeps = k + 1;             // misdc_get_stats reports the sweeps done so far

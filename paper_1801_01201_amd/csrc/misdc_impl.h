@@ -127,6 +127,7 @@ struct NewtonArgs {
     double* T;                              // n out (closed form of (Y, h)), may be null
     double* h_out = nullptr;                // n out, may be null: a copy of h (the reaction
                                             // step leaves the enthalpy unchanged)
+    double* th_out = nullptr;               // n out, may be null: (T/300)^1.7 of the result
     double* FR; int64_t ldf;                // N fields out, may be null
     int32_t* iters;                         // n out, may be null
     int32_t* lu_info = nullptr;             // n out, may be null: FP32 solves | FP64 fallbacks << 16
@@ -183,6 +184,8 @@ struct LinComb {
 int launch_lincomb(const LinComb& lc, hipStream_t s);
 // device-side copy and fill (stream-ordered kernels, safe under graph capture)
 int launch_copy(double* dst, const double* src, int64_t count, hipStream_t s);
+// th = (T/300)^1.7 of n cells
+int launch_theta(int64_t n, const double* T, double* th, hipStream_t s);
 // copies narr source arrays (lengths len, every len > 0) into each of ndst
 // destination sets, in one launch
 struct Broadcast {
@@ -257,18 +260,23 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
 int launch_lincomb_faces(const LinComb& lc, const Grid& g, const double* T_lag, DiffusionWork& w,
                          hipStream_t s);
 // The last step of a diffusion right-hand side split in two passes: out =
-// part + scale (qa FA(src) + qd FD(src)) for the N+1 fields of a state src
-// whose theta is th (the lagged operators of the concurrent scheme's first
-// nested iteration), with the face coefficients of the solve's lagged
-// operator at T_lag in the same pass, for a solve called with faces_ready.
-// part holds every other term, formed earlier by launch_lincomb; scale (may
-// be null) is the per-cell factor of dt-carrying terms.
+// part + scale (qa FA(src) + qd FD(src) + qr FR) for the N+1 fields of a
+// state src whose theta is th (the lagged operators of the concurrent
+// scheme's first nested iteration; or the node-M terms of the first task's
+// right-hand side in the next sweep), with the face coefficients of the
+// solve's lagged operator at T_lag in the same pass, for a solve called with
+// faces_ready.  part holds every other term, formed earlier by
+// launch_lincomb; scale (may be null) is the per-cell factor of dt-carrying
+// terms.  With T_src set, theta is (T_src/300)^1.7 of the cells (th unused);
+// fr (may be null) holds the N species' FR.
 struct LagRhs {
     const double* src = nullptr;
     const double* th = nullptr;
+    const double* T_src = nullptr;
     const double* part = nullptr;
+    const double* fr = nullptr;
     double* out = nullptr;
-    double qa = 0.0, qd = 0.0;
+    double qa = 0.0, qd = 0.0, qr = 0.0;
     const double* scale = nullptr;
     const double* T_lag = nullptr;
 };

@@ -73,6 +73,11 @@ __global__ void __launch_bounds__(256) lincomb_kernel(LinComb lc) {
     }
 }
 
+__global__ void __launch_bounds__(256) theta_kernel(int64_t n, const double* T, double* th) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) th[i] = pow(T[i] / T_DIFF_REF, THETA_EXP);
+}
+
 __global__ void __launch_bounds__(256) copy_kernel(double* dst, const double* src, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -170,8 +175,8 @@ __global__ void __launch_bounds__(256) lincomb_faces_kernel(LinComb lc, GridDev 
     }
 }
 
-// out = part + scale (qa FA + qd FD) of every field at one cell, FA and FD
-// at src (theta from th), the stencil values of all fields loaded before any
+// out = part + scale (qa FA + qd FD + qr FR) of every field at one cell, FA
+// and FD at src, the stencil values of all fields loaded before any
 // is used (as in transport_fields); the face coefficients of the lagged
 // operator at T in the same pass (see launch_lag_rhs)
 template <bool TWO_D>
@@ -179,15 +184,17 @@ __device__ __forceinline__ void lag_rhs_cell(const Stencil& s, const MechDev& m,
                                              const LagRhs& a, double sc, int64_t i) {
     constexpr int CH = TRANSPORT_CHUNK;
     const int NF = m.N + 1;
-    const double wa = sc * a.qa, wd = sc * a.qd;
-    double fd_sum = 0.0, fa_bath = 0.0, part_bath = 0.0;
+    const double wa = sc * a.qa, wd = sc * a.qd, wr = sc * a.qr;
+    double fd_sum = 0.0, fa_bath = 0.0, part_bath = 0.0, fr_bath = 0.0;
     for (int f0 = 0; f0 < NF; f0 += CH) {
-        double v[CH][9], pv[CH];
+        double v[CH][9], pv[CH], rv[CH];
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             const int f = f0 + c < NF ? f0 + c : NF - 1;
             load_stencil<TWO_D>(s, a.src + (size_t)f * n, i, v[c]);
             pv[c] = a.part[(size_t)f * n + i];
+            // FR has the N species only (the enthalpy's entry stays unused)
+            rv[c] = a.fr ? a.fr[(size_t)(f < m.N ? f : m.N - 1) * n + i] : 0.0;
         }
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
@@ -195,17 +202,19 @@ __device__ __forceinline__ void lag_rhs_cell(const Stencil& s, const MechDev& m,
             if (f >= NF) continue;
             double fa, lap;
             field_ops<TWO_D>(s, v[c], fa, lap);
+            const double fr = f < m.N ? rv[c] : 0.0;
             if (f == m.bath) {
                 fa_bath = fa;
                 part_bath = pv[c];
+                fr_bath = fr;
                 continue;
             }
             const double fd = m.kappa0[f] * lap;
             if (f < m.N) fd_sum += fd;
-            a.out[(size_t)f * n + i] = pv[c] + (wa * fa + wd * fd);
+            a.out[(size_t)f * n + i] = pv[c] + (wa * fa + wd * fd + wr * fr);
         }
     }
-    a.out[(size_t)m.bath * n + i] = part_bath + (wa * fa_bath + wd * -fd_sum);
+    a.out[(size_t)m.bath * n + i] = part_bath + (wa * fa_bath + wd * -fd_sum + wr * fr_bath);
 }
 
 __global__ void __launch_bounds__(256) lag_rhs_kernel(GridDev g, MechDev m, int64_t n, LagRhs a,
@@ -217,8 +226,10 @@ __global__ void __launch_bounds__(256) lag_rhs_kernel(GridDev g, MechDev m, int6
     if (i == 0 && bar) zero_barrier(bar);
     if (i >= n) return;
     faces_at(g, i, a.T_lag, th_out, Kx, Ky);
-    auto theta = [&](int64_t j) { return a.th[j]; };
-    const Stencil s = stencil_at(g, i, a.th[i], theta);
+    auto theta = [&](int64_t j) {
+        return a.T_src ? pow(a.T_src[j] / T_DIFF_REF, THETA_EXP) : a.th[j];
+    };
+    const Stencil s = stencil_at(g, i, theta(i), theta);
     const double sc = a.scale ? a.scale[i] : 1.0;
     if (s.two_d)
         lag_rhs_cell<true>(s, m, n, a, sc, i);
@@ -356,15 +367,23 @@ __global__ void __launch_bounds__(256) diffmax_kernel(int nfields, int64_t n, co
     __syncthreads();
     if (!s_last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const int nblocks = (int)gridDim.x;
-    for (int g = threadIdx.x; g < nfields; g += blockDim.x) {
+    // one wavefront per field: its lanes take the blocks' partials, then a
+    // wavefront maximum (max is exact in any order)
+    const int nblocks = (int)gridDim.x, nw = (int)(blockDim.x / 64);
+    for (int g = wave; g < nfields; g += nw) {
         double gd = 0.0, ga = 0.0;
-        for (int bk = 0; bk < nblocks; ++bk) {
+        for (int bk = lane; bk < nblocks; bk += 64) {
             gd = fmax(gd, partial[((size_t)g * nblocks + bk) * 2 + 0]);
             ga = fmax(ga, partial[((size_t)g * nblocks + bk) * 2 + 1]);
         }
-        out[2 * g] = gd;
-        out[2 * g + 1] = ga;
+        for (int off = 32; off > 0; off >>= 1) {
+            gd = fmax(gd, __shfl_xor(gd, off));
+            ga = fmax(ga, __shfl_xor(ga, off));
+        }
+        if (lane == 0) {
+            out[2 * g] = gd;
+            out[2 * g + 1] = ga;
+        }
     }
     if (threadIdx.x == 0) *done = 0u;
 }
@@ -389,6 +408,13 @@ GridDev grid_dev(const Grid& g) {
 
 // blocks of 256 cells along x (at most 65535; the kernels stride over the
 // rest), one field per y; x = 0 when the fields do not fit a grid's y range
+int launch_theta(int64_t n, const double* T, double* th, hipStream_t s) {
+    if (n == 0) return MISDC_OK;
+    hipLaunchKernelGGL(theta_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, n, T, th);
+    MISDC_HIP(hipGetLastError());
+    return MISDC_OK;
+}
+
 static dim3 lincomb_grid(const LinComb& lc) {
     if (lc.nfields < 1 || lc.nfields > 65535) return dim3(0, 1, 1);
     unsigned bx = grid_for(lc.ncells, 256);
@@ -459,7 +485,7 @@ int launch_lincomb_faces(const LinComb& lc, const Grid& g, const double* T_lag, 
 int launch_lag_rhs(const Mech& m, const Grid& g, const LagRhs& a, DiffusionWork& w, hipStream_t s) {
     const int64_t n = g.cells();
     if (n == 0) return MISDC_OK;
-    if (!a.src || !a.th || !a.part || !a.out || !a.T_lag)
+    if (!a.src || !(a.th || a.T_src) || !a.part || !a.out || !a.T_lag)
         return fail(MISDC_EINVAL, "split right-hand side: missing array");
     hipLaunchKernelGGL(lag_rhs_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, grid_dev(g), m.dev,
                        n, a, w.theta, w.Kx, w.Ky, w.barrier);
