@@ -102,18 +102,23 @@ __global__ void __launch_bounds__(256) enthalpy_kernel(MechDev m, int64_t n, con
     hp[i] = h;
 }
 
+// T of every cell; with copy set (state layout, ldy = n), the N+1 fields of
+// the cell are copied there in the same pass
 __global__ void __launch_bounds__(256) temperature_kernel(MechDev m, int64_t n, const double* Yp,
                                                           int64_t ldy, const double* hp,
-                                                          double* Tp) {
+                                                          double* Tp, double* copy) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double hform = 0.0, cpm = 0.0;
     for (int k = 0; k < m.N; ++k) {
         const double y = Yp[k * ldy + i];
+        if (copy) copy[k * n + i] = y;
         hform += y * m.hf[k] * m.invW[k];
         cpm += y * m.cp[k] * m.invW[k];
     }
-    Tp[i] = T_REF + (hp[i] - hform) / cpm;
+    const double h = hp[i];
+    if (copy) copy[(int64_t)m.N * n + i] = h;
+    Tp[i] = T_REF + (h - hform) / cpm;
 }
 
 template <int NS>
@@ -151,16 +156,16 @@ int launch_temperature(const Mech& m, int64_t n, const double* Y, const double* 
                        hipStream_t s) {
     if (n == 0) return MISDC_OK;
     hipLaunchKernelGGL(temperature_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, n, Y,
-                       n, h, T);
+                       n, h, T, nullptr);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;
 }
 
 int launch_state_temperature(const Mech& m, int64_t n, const double* state, double* T,
-                             hipStream_t s) {
+                             hipStream_t s, double* copy) {
     if (n == 0) return MISDC_OK;
     hipLaunchKernelGGL(temperature_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, m.dev, n,
-                       state, n, state + (size_t)m.dev.N * n, T);
+                       state, n, state + (size_t)m.dev.N * n, T, copy);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;
 }

@@ -111,6 +111,7 @@ struct misdc_integ_s {
         double* inc_out = nullptr;
     } dfr;
     hipEvent_t ev_d1 = nullptr;
+    bool skip_final_ops = false;                  // the step's last R_M skips its transport
     hipEvent_t ev_const = nullptr;                // the sweep constants are formed
     double* bR = nullptr;                         // reaction right-hand side (N fields)
     double* thD = nullptr;                        // theta work (diffusion stream)
@@ -747,6 +748,7 @@ int reaction_task(misdc_integ_s* I, int ell, int p, double dt) {
         if ((rc = launch_copy(slot + (size_t)(N + 2) * n, out.phi, (int64_t)N * n, L.s))) return rc;
         ++I->rec_count;
     }
+    if (p == I->M && I->skip_final_ops && ell == I->nu - 1) return MISDC_OK;
     if (last_prep) {
         // after the next sweep's first diffusion pass (flush_deferred)
         I->dfr.pending = true;
@@ -1043,6 +1045,26 @@ int fused_stage(misdc_integ_s* I, int ell, int s, double dt) {
     return MISDC_OK;
 }
 
+// Sweep 0 of a step: every node of the "previous sweep" holds phi^n and
+// F(phi^n), so node 0's buffers stand for nodes 1..M (a sweep only reads
+// lev[0]); the real buffers are put back before the sweep's S7 swap, or when
+// the issue ends early.
+struct FirstSweepNodes {
+    misdc_integ_s* I;
+    std::vector<NodeBuf> saved;
+    FirstSweepNodes(misdc_integ_s* integ, bool on) : I(integ) {
+        if (!on) return;
+        auto& L0 = I->lev[0];
+        saved.assign(L0.begin() + 1, L0.end());
+        for (size_t p = 1; p < L0.size(); ++p) L0[p] = L0[0];
+    }
+    void restore() {
+        for (size_t p = 0; p < saved.size(); ++p) I->lev[0][p + 1] = saved[p];
+        saved.clear();
+    }
+    ~FirstSweepNodes() { restore(); }
+};
+
 // Issues the work deferred from a sweep's R_M (see Deferred) on its stream,
 // after the event 'after' (may be null).
 int flush_deferred(misdc_integ_s* I, hipEvent_t after) {
@@ -1071,6 +1093,10 @@ int run_sweep(misdc_integ_s* I, int k, double dt, bool prep_next, bool defer_inc
     const int nu = (I->opt.scheme == MISDC_SCHEME_CISDCQ) ? I->nu : 1;
     int done = nu;                    // nested iterations done in this sweep
     int rc;
+    FirstSweepNodes first(I, k == 0);
+    // the step's last R_M: its F_A, F_D are never read (the next step starts
+    // from the state)
+    I->skip_final_ops = !prep_next && defer_inc && !(I->opt.nu_tol > 0 && I->nu >= 3);
     // the constants read every reaction output of the previous sweep; with
     // pipelined passes they also wait for every lane's last work of it,
     // since this sweep's tasks overwrite buffers those lanes read
@@ -1201,6 +1227,8 @@ int run_sweep(misdc_integ_s* I, int k, double dt, bool prep_next, bool defer_inc
         for (auto& r : I->pr_lane) MISDC_HIP(hipEventRecord(r.end, r.s));
     }
     // S7: the last nested iteration becomes sweep k+1 (swap buffer sets)
+    first.restore();
+    I->skip_final_ops = false;
     for (int p = 1; p <= M; ++p) std::swap(I->lev[0][p], I->lev[lv][p]);
     return MISDC_OK;
 }
@@ -1309,40 +1337,28 @@ int issue_begin(misdc_integ_s* I, double* state, double dt, const double* dtf, i
         I->dtc = I->dt_cell;
         dt = 1.0;      // every dt-carrying term takes dtc[cell] (or dtf[flame])
     }
-    if ((rc = launch_zero(I->nstats, 8 * sizeof(unsigned long long), I->sD))) return rc;
-    if ((rc = launch_zero(I->nbuckets, sizeof(unsigned long long) * NEWTON_BUCKETS *
-                                           NEWTON_BUCKET_STRIDE, I->sD)))
-        return rc;
-    if ((rc = launch_zero(I->nhist, sizeof(unsigned long long) * zero_sweeps *
-                                        NEWTON_HIST_SETS * NEWTON_HIST_BINS, I->sD)))
-        return rc;
-    if ((rc = launch_zero(I->cgstats, 8 * sizeof(int32_t), I->sD))) return rc;
+    {
+        void* const dst[4] = {I->nstats, I->nbuckets, I->nhist, I->cgstats};
+        const int64_t bytes[4] = {
+            (int64_t)(8 * sizeof(unsigned long long)),
+            (int64_t)(sizeof(unsigned long long) * NEWTON_BUCKETS * NEWTON_BUCKET_STRIDE),
+            (int64_t)(sizeof(unsigned long long) * zero_sweeps * NEWTON_HIST_SETS *
+                      NEWTON_HIST_BINS),
+            (int64_t)(8 * sizeof(int32_t))};
+        if ((rc = launch_zero_many(dst, bytes, 4, I->sD))) return rc;
+    }
     I->cst = CoupledStats();
     if (I->pipe)
         for (auto& d : I->pd_lane)
             if ((rc = launch_zero(d.cgstats, 8 * sizeof(int32_t), I->sD))) return rc;
-    // I1, I2, I4: every node of sweep 0 holds phi^n and F(phi^n)
+    // I1, I2, I4: node 0 holds phi^n (copied in T's pass) and F(phi^n); every
+    // other node of sweep 0 holds the same, which sweep 0 reads from node 0's
+    // buffers (FirstSweepNodes), so nothing is copied to them
     NodeBuf& b0 = I->lev[0][0];
-    if ((rc = launch_copy(b0.phi, state, (int64_t)NF * n, I->sD))) return rc;
-    if ((rc = launch_state_temperature(*I->mech, n, b0.phi, b0.T, I->sD))) return rc;
+    if ((rc = launch_state_temperature(*I->mech, n, state, b0.T, I->sD, b0.phi))) return rc;
     if ((rc = eval_ops(I, b0, I->thD, I->sD, true))) return rc;
-    {
-        Broadcast bc;
-        bc.narr = 5;
-        const double* src[5] = {b0.phi, b0.T, b0.FA, b0.FD, b0.FR};
-        const int64_t len[5] = {(int64_t)NF * n, n, (int64_t)NF * n, (int64_t)NF * n, (int64_t)N * n};
-        for (int k = 0; k < 5; ++k) {
-            bc.src[k] = src[k];
-            bc.len[k] = len[k];
-        }
-        bc.ndst = M;
-        for (int p = 1; p <= M; ++p) {
-            NodeBuf& b = I->lev[0][p];
-            double* dst[5] = {b.phi, b.T, b.FA, b.FD, b.FR};
-            for (int k = 0; k < 5; ++k) bc.dst[p - 1][k] = dst[k];
-        }
-        if ((rc = launch_broadcast(bc, I->sD))) return rc;
-    }
+    (void)N;
+    (void)NF;
     // node 0 is shared by every nested-iteration level
     for (int l = 1; l < I->levels; ++l) I->lev[l][0] = b0;
     // "previous sweep finished" marker for the first sweep's constants

@@ -184,24 +184,18 @@ struct LinComb {
 int launch_lincomb(const LinComb& lc, hipStream_t s);
 // device-side copy and fill (stream-ordered kernels, safe under graph capture)
 int launch_copy(double* dst, const double* src, int64_t count, hipStream_t s);
+// clears up to four buffers (whole 32-bit words, bytes[k] each) in one launch
+int launch_zero_many(void* const* dst, const int64_t* bytes, int count, hipStream_t s);
 // th = (T/300)^1.7 of n cells
 int launch_theta(int64_t n, const double* T, double* th, hipStream_t s);
-// copies narr source arrays (lengths len, every len > 0) into each of ndst
-// destination sets, in one launch
-struct Broadcast {
-    static constexpr int MAX_ARR = 6, MAX_DST = 8;
-    int narr = 0, ndst = 0;
-    const double* src[MAX_ARR] = {};
-    int64_t len[MAX_ARR] = {};
-    double* dst[MAX_DST][MAX_ARR] = {};
-};
-int launch_broadcast(const Broadcast& b, hipStream_t s);
 int launch_zero(void* dst, int64_t bytes, hipStream_t s);
 // per-cell value of a per-flame array: out[i] = v[flame of cell i]
 int launch_expand_flames(const Grid& g, const double* v, double* out, hipStream_t s);
 
 // T (cells) from a state with N+1 fields
-int launch_state_temperature(const Mech& m, int64_t n, const double* state, double* T, hipStream_t s);
+// T of a state (N+1 fields); copy (may be null) receives the state in the same pass
+int launch_state_temperature(const Mech& m, int64_t n, const double* state, double* T, hipStream_t s,
+                             double* copy = nullptr);
 // FA and FD (N+1 fields) at a state whose temperature is T; either output may be null
 // (theta_ready: work_theta already holds (T/300)^1.7)
 int launch_transport(const Mech& m, const Grid& g, const double* state, const double* T,

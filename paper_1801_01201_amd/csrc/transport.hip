@@ -84,25 +84,23 @@ __global__ void __launch_bounds__(256) copy_kernel(double* dst, const double* sr
         dst[i] = src[i];
 }
 
-// every destination set receives a copy of the source arrays (one pass over
-// the sources)
-__global__ void __launch_bounds__(256) broadcast_kernel(Broadcast b) {
-    int64_t total = 0;
-    for (int k = 0; k < b.narr; ++k) total += b.len[k];
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        int k = 0;
-        int64_t o = e;
-        while (o >= b.len[k]) o -= b.len[k++];
-        const double v = b.src[k][o];
-        for (int d = 0; d < b.ndst; ++d) b.dst[d][k][o] = v;
-    }
-}
-
 __global__ void __launch_bounds__(256) zero_kernel(unsigned* dst, int64_t words) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
          i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = 0u;
+}
+
+struct ZeroMany {
+    unsigned* dst[4];
+    int64_t words[4];
+};
+// blockIdx.y picks the buffer
+__global__ void __launch_bounds__(256) zero_many_kernel(ZeroMany z) {
+    unsigned* d = z.dst[blockIdx.y];
+    const int64_t words = z.words[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = 0u;
 }
 
 __global__ void __launch_bounds__(256) expand_kernel(int n_flames, const int64_t* off,
@@ -431,15 +429,22 @@ int launch_copy(double* dst, const double* src, int64_t count, hipStream_t s) {
     return MISDC_OK;
 }
 
-int launch_broadcast(const Broadcast& b, hipStream_t s) {
-    if (b.narr < 1 || b.narr > Broadcast::MAX_ARR || b.ndst < 0 || b.ndst > Broadcast::MAX_DST)
-        return fail(MISDC_EINVAL, "broadcast: %d arrays to %d destinations", b.narr, b.ndst);
-    int64_t total = 0;
-    for (int k = 0; k < b.narr; ++k) total += b.len[k];
-    if (total <= 0 || b.ndst == 0) return MISDC_OK;
-    unsigned blocks = grid_for(total, 256);
+
+int launch_zero_many(void* const* dst, const int64_t* bytes, int count, hipStream_t s) {
+    if (count < 1 || count > 4) return fail(MISDC_EINVAL, "zero fill of %d buffers", count);
+    ZeroMany z;
+    int64_t most = 0;
+    for (int k = 0; k < count; ++k) {
+        if (bytes[k] < 0 || bytes[k] % 4)
+            return fail(MISDC_EINVAL, "zero fill of %lld bytes: not whole words", (long long)bytes[k]);
+        z.dst[k] = (unsigned*)dst[k];
+        z.words[k] = bytes[k] / 4;
+        most = z.words[k] > most ? z.words[k] : most;
+    }
+    if (most == 0) return MISDC_OK;
+    unsigned blocks = grid_for(most, 256);
     if (blocks > 8192u) blocks = 8192u;
-    hipLaunchKernelGGL(broadcast_kernel, dim3(blocks), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(zero_many_kernel, dim3(blocks, (unsigned)count), dim3(256), 0, s, z);
     MISDC_HIP(hipGetLastError());
     return MISDC_OK;
 }

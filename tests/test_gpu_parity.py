@@ -235,6 +235,10 @@ STEP_CASES = [
     ("flame2d_cisdcq1", 2, (20, 24), (0.01, 0.01), (100.0, 0.0), 5, 6, 1, "cisdcq", 1),
     ("flame2d_cisdcq2", 2, (29, 37), (0.01, 0.01), (100.0, -30.0), 5, 4, 1, "cisdcq", 2),
     ("flame2d_cisdcq1_3nodes", 2, (20, 24), (0.01, 0.01), (100.0, 0.0), 3, 4, 2, "cisdcq", 1),
+    # one and two sweeps: the first sweep is also the last (its constants come
+    # from the initial state, nothing is prepared for a next sweep)
+    ("flame2d_cisdcq1_1sweep", 2, (20, 24), (0.01, 0.01), (100.0, 0.0), 5, 1, 2, "cisdcq", 1),
+    ("flame2d_cisdcq1_2sweeps", 2, (20, 24), (0.01, 0.01), (100.0, 0.0), 5, 2, 2, "cisdcq", 1),
     # the comparison scheme IMEXQ: one coupled diffusion-reaction solve per node
     ("flame1d_64_imexq", 1, (64,), (0.01,), (100.0,), 3, 4, 3, "imexq", 1),
     ("flame2d_imexq", 2, (20, 24), (0.01, 0.01), (100.0, -30.0), 5, 4, 1, "imexq", 1),
