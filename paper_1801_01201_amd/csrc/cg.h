@@ -62,6 +62,22 @@ struct CGArgs {
     double* th_out;
     int32_t* cgstats;       // [0] iterations, [1] max, [2] failures, [3] solves, [4] timeouts,
                             // [5] tiled variants: results whose true residual failed the check
+    // tiled variants, lag_src set: the right-hand side is formed by the
+    // kernel itself, each thread for its cell: b = lag_part + (qa FA(lag_src)
+    // + qd FD(lag_src) + qr FR) of every field (theta of lag_src's T in
+    // lag_th, or from lag_Tsrc; FR from lag_fr, may be null) is written to
+    // b_w (= b), and the face coefficients come from theta of lag_T instead
+    // of Kx, Ky; the guess must be in x
+    const double* lag_src = nullptr;
+    const double* lag_th = nullptr;
+    const double* lag_Tsrc = nullptr;
+    const double* lag_part = nullptr;
+    const double* lag_fr = nullptr;
+    const double* lag_T = nullptr;
+    double lag_qa = 0.0, lag_qd = 0.0, lag_qr = 0.0;
+    double* b_w = nullptr;
+    const double* kappa0 = nullptr;   // N+1
+    double dx = 0.0, dy = 0.0, ux = 0.0, uy = 0.0;
 };
 
 // launches the CG kernel of a variant (0 global memory, 1/2/4 register

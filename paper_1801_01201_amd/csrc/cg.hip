@@ -54,6 +54,109 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, in
 
 
 
+// The right-hand side formed inside the tiled kernel (CGArgs lag_src): for
+// cell i, the four neighbours (periodic; nx, ny >= 2), the face coefficients
+// of the solve's operator from theta of lag_T (the values faces_at forms),
+// and b = lag_part + (qa FA + qd FD + qr FR) of every field, FA and FD at
+// lag_src from their stencils (fourth-order advection faces, the diffusion
+// operator with theta of lag_src's temperature, the bath's FD minus the sum
+// of the other species'); every field is written to b_w when the thread owns
+// the cell, and bd returns the diffused fields' values.  Fields are taken
+// CH at a time, each chunk's loads issued together.
+template <int NFD>
+__device__ __forceinline__ void fused_rhs(const CGArgs& a, int64_t i, bool own, int64_t& e,
+                                          int64_t& w, int64_t& nn, int64_t& s, double& ke,
+                                          double& kw, double& kn, double& ks, double (&bd)[NFD]) {
+    constexpr int NF = NFD + 1, CH = 5;
+    const int64_t nx = a.nx, ny = a.ny, n = a.n;
+    const int64_t iy = i / nx, ix = i - iy * nx, row = iy * nx;
+    auto wx = [&](int64_t k) { return k < 0 ? k + nx : (k >= nx ? k - nx : k); };
+    auto wy = [&](int64_t k) { return k < 0 ? k + ny : (k >= ny ? k - ny : k); };
+    const int64_t xm1 = row + wx(ix - 1), xm2 = row + wx(ix - 2);
+    const int64_t xp1 = row + wx(ix + 1), xp2 = row + wx(ix + 2);
+    const int64_t ym1 = wy(iy - 1) * nx + ix, ym2 = wy(iy - 2) * nx + ix;
+    const int64_t yp1 = wy(iy + 1) * nx + ix, yp2 = wy(iy + 2) * nx + ix;
+    e = xp1;
+    w = xm1;
+    nn = yp1;
+    s = ym1;
+    const double* TH = a.lag_Tsrc ? a.lag_Tsrc : a.lag_th;
+    const double T0 = a.lag_T[i], Te = a.lag_T[xp1], Tw = a.lag_T[xm1], Tn = a.lag_T[yp1],
+                 Ts = a.lag_T[ym1];
+    const double h0 = TH[i], he = TH[xp1], hw = TH[xm1], hn = TH[yp1], hs = TH[ym1];
+    // the solve's face coefficients, as faces_at forms Kx and Ky (kw = Kx of
+    // the west neighbour, ks = Ky of the south neighbour)
+    const double t0 = pow(T0 / T_DIFF_REF, THETA_EXP), te = pow(Te / T_DIFF_REF, THETA_EXP);
+    const double tw = pow(Tw / T_DIFF_REF, THETA_EXP), tn = pow(Tn / T_DIFF_REF, THETA_EXP);
+    const double ts = pow(Ts / T_DIFF_REF, THETA_EXP);
+    ke = 0.5 * (t0 + te) / (a.dx * a.dx);
+    kw = 0.5 * (tw + t0) / (a.dx * a.dx);
+    kn = 0.5 * (t0 + tn) / (a.dy * a.dy);
+    ks = 0.5 * (ts + t0) / (a.dy * a.dy);
+    // the lagged operators' coefficients (theta of lag_src)
+    auto th_of = [&](double x) { return a.lag_Tsrc ? pow(x / T_DIFF_REF, THETA_EXP) : x; };
+    const double g0 = th_of(h0);
+    const double idx2 = 1.0 / (a.dx * a.dx), idy2 = 1.0 / (a.dy * a.dy);
+    const double kxe = 0.5 * (g0 + th_of(he)) * idx2, kxw = 0.5 * (g0 + th_of(hw)) * idx2;
+    const double kyn = 0.5 * (g0 + th_of(hn)) * idy2, kys = 0.5 * (g0 + th_of(hs)) * idy2;
+    const double ax = a.ux / a.dx, ay = a.uy / a.dy;
+    double bf[NF];
+    double fd_sum = 0.0, fa_bath = 0.0, part_bath = 0.0, fr_bath = 0.0;
+#pragma unroll
+    for (int f0 = 0; f0 < NF; f0 += CH) {
+        double v[CH][9], pv[CH], rv[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int f = f0 + c < NF ? f0 + c : NF - 1;
+            const double* P = a.lag_src + (size_t)f * n;
+            v[c][0] = P[i];
+            v[c][1] = P[xm1];
+            v[c][2] = P[xm2];
+            v[c][3] = P[xp1];
+            v[c][4] = P[xp2];
+            v[c][5] = P[ym1];
+            v[c][6] = P[ym2];
+            v[c][7] = P[yp1];
+            v[c][8] = P[yp2];
+            pv[c] = a.lag_part[(size_t)f * n + i];
+            rv[c] = a.lag_fr ? a.lag_fr[(size_t)(f < a.N ? f : a.N - 1) * n + i] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int f = f0 + c;
+            if (f >= NF) continue;
+            const double c0 = v[c][0], w1 = v[c][1], w2 = v[c][2], e1 = v[c][3], e2 = v[c][4];
+            const double s1 = v[c][5], s2 = v[c][6], n1 = v[c][7], n2 = v[c][8];
+            // fourth-order face values, as the explicit operators take them
+            const double fe = (7.0 * (c0 + e1) - (w1 + e2)) / 12.0;
+            const double fw = (7.0 * (w1 + c0) - (w2 + e1)) / 12.0;
+            double fa = -ax * (fe - fw);
+            double lap = kxe * (e1 - c0) - kxw * (c0 - w1);
+            const double fn = (7.0 * (c0 + n1) - (s1 + n2)) / 12.0;
+            const double fs = (7.0 * (s1 + c0) - (s2 + n1)) / 12.0;
+            if (ay != 0.0) fa -= ay * (fn - fs);
+            lap += kyn * (n1 - c0) - kys * (c0 - s1);
+            const double fr = f < a.N ? rv[c] : 0.0;
+            if (f == a.bath) {
+                fa_bath = fa;
+                part_bath = pv[c];
+                fr_bath = fr;
+                bf[f] = 0.0;
+                continue;
+            }
+            const double fd = a.kappa0[f] * lap;
+            if (f < a.N) fd_sum += fd;
+            bf[f] = pv[c] + (a.lag_qa * fa + a.lag_qd * fd + a.lag_qr * fr);
+            if (own) a.b_w[(size_t)f * n + i] = bf[f];
+        }
+    }
+    if (own)
+        a.b_w[(size_t)a.bath * n + i] =
+            part_bath + (a.lag_qa * fa_bath + a.lag_qd * -fd_sum + a.lag_qr * fr_bath);
+#pragma unroll
+    for (int d = 0; d < NFD; ++d) bd[d] = d >= a.bath ? bf[d + 1] : bf[d];
+}
+
 // A_f v at cell i: v_i - cf (Ke (v_E - v_i) - Kw (v_i - v_W) + Kn (...) - Ks (...))
 __device__ __forceinline__ void stencil_at(const CGArgs& a, int64_t i, int64_t& e, int64_t& w,
                                            int64_t& nn, int64_t& s, double& ke, double& kw,
@@ -814,7 +917,7 @@ __device__ __forceinline__ void tile_precond(const double (&v)[NFD], double (&z)
     }
 }
 
-template <int NFD, int KSW>
+template <int NFD, int KSW, bool FUSED = false>
 __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
     static_assert(NFD == 9, "the edge buffer holds 9 fields per tile");
     constexpr int BS = TILE_BS;
@@ -844,7 +947,11 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
     const int64_t cell = own ? (int64_t)gy * a.nx + gx : 0;
     int64_t ie, iw, in_, is_;
     double ke, kw, kn, ks;
-    stencil_at(a, cell, ie, iw, in_, is_, ke, kw, kn, ks);
+    double bfz[NFD];                 // the right-hand side formed here (FUSED)
+    if (FUSED)
+        fused_rhs<NFD>(a, cell, own, ie, iw, in_, is_, ke, kw, kn, ks, bfz);
+    else
+        stencil_at(a, cell, ie, iw, in_, is_, ke, kw, kn, ks);
     // neighbours inside this tile (and inside the grid)
     const bool he = own && tx + 1 < TILE_X && gx + 1 < a.nx;
     const bool hw = own && tx > 0;
@@ -907,7 +1014,7 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
             xw[d] = X[iw];
             xn[d] = X[in_];
             xs[d] = X[is_];
-            bv[d] = a.b[o + cell];
+            bv[d] = FUSED ? bfz[d] : a.b[o + cell];
         }
 #pragma unroll
         for (int d = 0; d < NFD; ++d) {
@@ -1028,6 +1135,8 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
             w[d] = act ? w[d] - al * z1 : w[d];
         }
     }
+    {
+    double* part = a.partial + (size_t)(kb & 1u) * CG_MAX_BLOCKS * (CG_MAX_FIELDS * 4);
     if (a.cgstats) {
         // ---- the true residual |b - A x| of the result, against 10 rtol |b|
         // per field: the recurrences' residual can drift away from it, so a
@@ -1054,7 +1163,6 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
                 return res * res;
             },
             red);
-        double* part = a.partial + (size_t)(kb & 1u) * CG_MAX_BLOCKS * (CG_MAX_FIELDS * 4);
         __syncthreads();
         for (int q = threadIdx.x; q < NFD; q += BS) {
             double v = 0.0;
@@ -1062,16 +1170,22 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
             __hip_atomic_store(&part[(size_t)blockIdx.x * (CG_MAX_FIELDS * 4) + q], v,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (threadIdx.x == 0)
-            s_last = __hip_atomic_fetch_add(&a.bar[BAR_EXIT], 1u, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT) + 1u == gridDim.x;
-        __syncthreads();
-        if (s_last) {                                 // uniform over the workgroup
+    }
+    // every workgroup counts itself out (after its last grid wait); the last
+    // one adds up the residual check's partials and clears the barrier
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_last = __hip_atomic_fetch_add(&a.bar[BAR_EXIT], 1u, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT) + 1u == gridDim.x;
+    __syncthreads();
+    if (s_last) {                                     // uniform over the workgroup
+        if (a.cgstats) {
             stage[threadIdx.x] = group_partial(part, gridDim.x, NFD);
             __syncthreads();
-            if (threadIdx.x == 0) {
+        }
+        if (threadIdx.x == 0) {
+            if (a.cgstats) {
                 // a solve already failed at maxit is not counted twice; NaN fails
                 int bad = 0, open_fields = 0;
                 for (int d = 0; d < NFD; ++d) {
@@ -1079,9 +1193,22 @@ __global__ void __launch_bounds__(TILE_BS) cg_tile_kernel(CGArgs a) {
                     open_fields |= s_active[d];
                 }
                 a.cgstats[5] += (it == a.maxit && open_fields) ? 0 : bad;
+            }
+            {
+                // every barrier word back to zero for the next launch on this
+                // work space (all workgroups are past their last wait), so a
+                // solve that forms its own right-hand side needs no pass to
+                // clear them
+                __hip_atomic_store(&a.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&a.bar[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int g = 0; g < BAR_GROUPS; ++g)
+                    __hip_atomic_store(&a.bar[BAR_STRIDE * (1 + g)], 0u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&a.bar[BAR_GLOBAL], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&a.bar[BAR_EXIT], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+    }
     }
 #pragma unroll
     for (int d = 0; d < NFD; ++d)
@@ -1225,7 +1352,12 @@ int launch_cg(const CGArgs& a, int variant, int blocks, hipStream_t s) {
         case 1: hipLaunchKernelGGL((cg_regs_kernel<9, 1, 512>), dim3(blocks), dim3(512), 0, s, a); break;
         case 2: hipLaunchKernelGGL((cg_regs_kernel<9, 2, 256>), dim3(blocks), dim3(256), 0, s, a); break;
         case 4: hipLaunchKernelGGL((cg_regs_kernel<9, 4, 256>), dim3(blocks), dim3(256), 0, s, a); break;
-        case 101: hipLaunchKernelGGL((cg_tile_kernel<9, 1>), dim3(blocks), dim3(TILE_BS), 0, s, a); break;
+        case 101:
+            if (a.lag_src)
+                hipLaunchKernelGGL((cg_tile_kernel<9, 1, true>), dim3(blocks), dim3(TILE_BS), 0, s, a);
+            else
+                hipLaunchKernelGGL((cg_tile_kernel<9, 1>), dim3(blocks), dim3(TILE_BS), 0, s, a);
+            break;
         case 102: hipLaunchKernelGGL((cg_tile_kernel<9, 2>), dim3(blocks), dim3(TILE_BS), 0, s, a); break;
         case 103: hipLaunchKernelGGL((cg_tile_kernel<9, 3>), dim3(blocks), dim3(TILE_BS), 0, s, a); break;
         case 0: hipLaunchKernelGGL(cg_kernel, dim3(blocks), dim3(CG_THREADS), 0, s, a); break;

@@ -589,22 +589,24 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     LC b(NF, n, dt, I->dtc);
     diffusion_rhs(I, ell, p, b, cf, T_lag);
     int rc;
+    // the second pass of a split right-hand side, formed with the solve
+    // (launch_diffusion_solve)
+    LagRhs second;
+    bool split = false;
     if (ell == 0 && p == 1 && I->d1_split) {
         // the terms of node M (prepare_constants), once R_M's solve is done
         I->d1_split = false;
         MISDC_HIP(hipStreamWaitEvent(L.s, I->ev_newtonM, 0));
-        LagRhs d1 = I->d1w;
-        d1.out = L.rD;
-        if ((rc = launch_lag_rhs(*I->mech, *I->grid, d1, *L.dw, L.s))) return rc;
+        second = I->d1w;
+        split = true;
         MISDC_HIP(hipEventRecord(I->ev_d1, L.s));
     } else if (split_rhs(I, ell, p)) {
         // the first pass ran on the reaction stream (run_sweep); the lagged
         // operators of node p-1 and the face coefficients now
         MISDC_HIP(hipStreamWaitEvent(L.s, I->evP[p], 0));
-        LagRhs lag = I->lagw[p];
-        lag.th = L.th;
-        lag.out = L.rD;
-        if ((rc = launch_lag_rhs(*I->mech, *I->grid, lag, *L.dw, L.s))) return rc;
+        second = I->lagw[p];
+        second.th = L.th;
+        split = true;
     } else if (ell == 0 && p == 1 && I->d1_ready) {
         I->d1_ready = false;          // formed by the sweep constants' pass
     } else {
@@ -620,7 +622,8 @@ int diffusion_task(misdc_integ_s* I, int ell, int p, double dt) {
     const bool lag_init = (I->opt.scheme == MISDC_SCHEME_CISDCQ && ell == 0 && p < I->M);
     rc = launch_diffusion_solve(*I->mech, *I->grid, *L.dw, dt * cf, I->dtf, cf, T_lag, L.rD,
                                 I->phiAD[p], 1, I->opt.cg_rtol, I->opt.cg_maxit, L.s, t0, t1,
-                                I->TAD[p], L.cgstats, lag_init ? L.th : nullptr, true);
+                                I->TAD[p], L.cgstats, lag_init ? L.th : nullptr, true,
+                                split ? &second : nullptr);
     if (rc) return rc;
     if (t0 && t1) I->timed.push_back({t0, t1, 0});
     return MISDC_OK;

@@ -241,13 +241,15 @@ void diffusion_work_free(DiffusionWork& w);
 // Solves all N+1 fields (bath by closure); y may hold the guess (guess_in_y);
 // T_out (optional) receives T(y) and th_out (optional, with T_out) its
 // (T/300)^1.7; cgstats (optional, 2-D solves) accumulates the CG statistics
+struct LagRhs;
 int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, double c,
                            const double* dt_flame, double c_factor,
                            const double* T_lag, const double* rhs, double* y, int guess_in_y,
                            double rtol, int maxit, hipStream_t s,
                            hipEvent_t core_begin = nullptr, hipEvent_t core_end = nullptr,
                            double* T_out = nullptr, int32_t* cgstats = nullptr,
-                           double* th_out = nullptr, bool faces_ready = false);
+                           double* th_out = nullptr, bool faces_ready = false,
+                           const LagRhs* fused = nullptr);
 // right-hand side (a linear combination over the grid's cells) together with
 // the face coefficients of the lagged operator at T_lag, for a solve called
 // with faces_ready

@@ -681,11 +681,25 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
                            const double* dt_flame, double c_factor, const double* T_lag,
                            const double* rhs, double* y, int guess_in_y, double rtol, int maxit,
                            hipStream_t s, hipEvent_t core_begin, hipEvent_t core_end,
-                           double* T_out, int32_t* cgstats, double* th_out, bool faces_ready) {
+                           double* T_out, int32_t* cgstats, double* th_out, bool faces_ready,
+                           const LagRhs* fused) {
     const int64_t n = g.cells();
     if (n == 0) return MISDC_OK;
     const GridDev gd = grid_dev(g);
-    if (!faces_ready) {
+    // the second pass of a split right-hand side: formed by the tiled solve
+    // itself where it can (each thread for its cell, in the prologue),
+    // otherwise by a launch of its own before the solve
+    const bool single2d = !(g.dim == 1 || g.n_flames > 0);
+    const bool in_solve = fused && single2d && w.variant == 101 && guess_in_y && g.nx >= 2 &&
+                          g.ny >= 2 && !fused->scale && m.dev.N == 9 && T_lag == fused->T_lag;
+    if (fused && !in_solve) {
+        LagRhs l = *fused;
+        l.out = const_cast<double*>(rhs);
+        const int rc = launch_lag_rhs(m, g, l, w, s);
+        if (rc) return rc;
+        faces_ready = true;
+    }
+    if (!faces_ready && !in_solve) {
         hipLaunchKernelGGL(faces_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, gd, n, T_lag,
                            w.theta, w.Kx, w.Ky, w.barrier);
         MISDC_HIP(hipGetLastError());
@@ -743,6 +757,23 @@ int launch_diffusion_solve(const Mech& m, const Grid& g, DiffusionWork& w, doubl
         a.T_out = T_out;
         a.th_out = T_out ? th_out : nullptr;
         a.cgstats = cgstats;
+        if (in_solve) {
+            a.lag_src = fused->src;
+            a.lag_th = fused->th;
+            a.lag_Tsrc = fused->T_src;
+            a.lag_part = fused->part;
+            a.lag_fr = fused->fr;
+            a.lag_T = fused->T_lag;
+            a.lag_qa = fused->qa;
+            a.lag_qd = fused->qd;
+            a.lag_qr = fused->qr;
+            a.b_w = const_cast<double*>(rhs);
+            a.kappa0 = m.dev.kappa0;
+            a.dx = g.dx;
+            a.dy = g.dy;
+            a.ux = g.ux;
+            a.uy = g.uy;
+        }
         int rc = launch_cg(a, w.variant, w.blocks, s);
         if (rc) return rc;
         if (a.close) {
