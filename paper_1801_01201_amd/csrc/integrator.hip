@@ -113,6 +113,9 @@ struct misdc_integ_s {
     hipEvent_t ev_d1 = nullptr;
     bool skip_final_ops = false;                  // the step's last R_M skips its transport
     hipEvent_t ev_const = nullptr;                // the sweep constants are formed
+    // step start: node 0's state is written (ev_state) and F_R at it, formed
+    // on the reaction stream beside F_A, F_D (ev_source)
+    hipEvent_t ev_state = nullptr, ev_source = nullptr;
     double* bR = nullptr;                         // reaction right-hand side (N fields)
     double* thD = nullptr;                        // theta work (diffusion stream)
     double* thR = nullptr;                        // theta work (reaction stream)
@@ -1359,7 +1362,18 @@ int issue_begin(misdc_integ_s* I, double* state, double dt, const double* dtf, i
     // buffers (FirstSweepNodes), so nothing is copied to them
     NodeBuf& b0 = I->lev[0][0];
     if ((rc = launch_state_temperature(*I->mech, n, state, b0.T, I->sD, b0.phi))) return rc;
-    if ((rc = eval_ops(I, b0, I->thD, I->sD, true))) return rc;
+    if (I->sR != I->sD) {
+        // F_R on the reaction stream while F_A, F_D are formed
+        MISDC_HIP(hipEventRecord(I->ev_state, I->sD));
+        MISDC_HIP(hipStreamWaitEvent(I->sR, I->ev_state, 0));
+        rc = launch_reaction_source(*I->mech, n, b0.phi, b0.phi + (size_t)N * n, b0.FR, I->sR);
+        if (rc) return rc;
+        MISDC_HIP(hipEventRecord(I->ev_source, I->sR));
+        if ((rc = eval_ops(I, b0, I->thD, I->sD, false))) return rc;
+        MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_source, 0));
+    } else if ((rc = eval_ops(I, b0, I->thD, I->sD, true))) {
+        return rc;
+    }
     (void)N;
     (void)NF;
     // node 0 is shared by every nested-iteration level
@@ -2118,6 +2132,8 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_const, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_state, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_source, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_newtonM, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_d1, hipEventDisableTiming);
     I->evP.assign(M + 1, nullptr);
@@ -2179,6 +2195,8 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (I->ev_in) (void)hipEventDestroy(I->ev_in);
     if (I->ev_outD) (void)hipEventDestroy(I->ev_outD);
     if (I->ev_outR) (void)hipEventDestroy(I->ev_outR);
+    if (I->ev_state) (void)hipEventDestroy(I->ev_state);
+    if (I->ev_source) (void)hipEventDestroy(I->ev_source);
     if (I->ev_fork) (void)hipEventDestroy(I->ev_fork);
     if (I->ev_join) (void)hipEventDestroy(I->ev_join);
     if (I->ev_const) (void)hipEventDestroy(I->ev_const);
