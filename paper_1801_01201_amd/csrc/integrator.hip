@@ -113,9 +113,9 @@ struct misdc_integ_s {
     hipEvent_t ev_d1 = nullptr;
     bool skip_final_ops = false;                  // the step's last R_M skips its transport
     hipEvent_t ev_const = nullptr;                // the sweep constants are formed
-    // step start: node 0's state is written (ev_state) and F_R at it, formed
-    // on the reaction stream beside F_A, F_D (ev_source)
-    hipEvent_t ev_state = nullptr, ev_source = nullptr;
+    // step start: F_R at the state, formed on the reaction stream beside
+    // F_A, F_D
+    hipEvent_t ev_source = nullptr;
     double* bR = nullptr;                         // reaction right-hand side (N fields)
     double* thD = nullptr;                        // theta work (diffusion stream)
     double* thR = nullptr;                        // theta work (reaction stream)
@@ -1351,7 +1351,9 @@ int issue_begin(misdc_integ_s* I, double* state, double dt, const double* dtf, i
             (int64_t)(sizeof(unsigned long long) * zero_sweeps * NEWTON_HIST_SETS *
                       NEWTON_HIST_BINS),
             (int64_t)(8 * sizeof(int32_t))};
-        if ((rc = launch_zero_many(dst, bytes, 4, I->sD))) return rc;
+        // on the reaction stream when there is one: every task of the step
+        // follows its F_R pass below
+        if ((rc = launch_zero_many(dst, bytes, 4, I->sR))) return rc;
     }
     I->cst = CoupledStats();
     if (I->pipe)
@@ -1361,18 +1363,18 @@ int issue_begin(misdc_integ_s* I, double* state, double dt, const double* dtf, i
     // other node of sweep 0 holds the same, which sweep 0 reads from node 0's
     // buffers (FirstSweepNodes), so nothing is copied to them
     NodeBuf& b0 = I->lev[0][0];
-    if ((rc = launch_state_temperature(*I->mech, n, state, b0.T, I->sD, b0.phi))) return rc;
     if (I->sR != I->sD) {
-        // F_R on the reaction stream while F_A, F_D are formed
-        MISDC_HIP(hipEventRecord(I->ev_state, I->sD));
-        MISDC_HIP(hipStreamWaitEvent(I->sR, I->ev_state, 0));
-        rc = launch_reaction_source(*I->mech, n, b0.phi, b0.phi + (size_t)N * n, b0.FR, I->sR);
+        // F_R on the reaction stream, from the state itself (the source forms
+        // T from h), while node 0's copy, T, F_A and F_D are formed
+        rc = launch_reaction_source(*I->mech, n, state, state + (size_t)N * n, b0.FR, I->sR);
         if (rc) return rc;
         MISDC_HIP(hipEventRecord(I->ev_source, I->sR));
+        if ((rc = launch_state_temperature(*I->mech, n, state, b0.T, I->sD, b0.phi))) return rc;
         if ((rc = eval_ops(I, b0, I->thD, I->sD, false))) return rc;
         MISDC_HIP(hipStreamWaitEvent(I->sD, I->ev_source, 0));
-    } else if ((rc = eval_ops(I, b0, I->thD, I->sD, true))) {
-        return rc;
+    } else {
+        if ((rc = launch_state_temperature(*I->mech, n, state, b0.T, I->sD, b0.phi))) return rc;
+        if ((rc = eval_ops(I, b0, I->thD, I->sD, true))) return rc;
     }
     (void)N;
     (void)NF;
@@ -2132,7 +2134,6 @@ int misdc_integ_create(misdc_mech_t mech, misdc_grid_t grid, const misdc_opts* o
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_const, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_state, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_source, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_newtonM, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_d1, hipEventDisableTiming);
@@ -2195,7 +2196,6 @@ int misdc_integ_destroy(misdc_integ_t I) {
     if (I->ev_in) (void)hipEventDestroy(I->ev_in);
     if (I->ev_outD) (void)hipEventDestroy(I->ev_outD);
     if (I->ev_outR) (void)hipEventDestroy(I->ev_outR);
-    if (I->ev_state) (void)hipEventDestroy(I->ev_state);
     if (I->ev_source) (void)hipEventDestroy(I->ev_source);
     if (I->ev_fork) (void)hipEventDestroy(I->ev_fork);
     if (I->ev_join) (void)hipEventDestroy(I->ev_join);
